@@ -1,0 +1,220 @@
+/*
+ * sv.h -- C ABI of the MI355X state-vector sweep library (libsvmi.so).
+ *
+ * The library applies a quantum circuit to a 2^n complex amplitude vector in
+ * place, Schroedinger style: every gate updates the 2^{n-k} disjoint sets of
+ * 2^k amplitudes whose indices agree outside the gate's k qubits (Sec. 3,
+ * "Fast Schroedinger simulation").  It starts from the basis vector
+ * (1,0,...,0) (Sec. 2) and keeps every amplitude ("strong simulation").
+ *
+ * Conventions
+ *   - Qubit q is bit q of the amplitude index (little-endian), as in the
+ *     paper's bitmask examples (Sec. 4.3, Fig. reorder).
+ *   - A gate's local index is l = sum_t bit(j, q[t]) * 2^t, so q[0] is the
+ *     least significant bit of its matrix index.  CNOT: q[0] control,
+ *     q[1] target (defined by action, Sec. 2).
+ *   - Amplitudes are interleaved (re, im): SV_C64 = two floats (8 bytes),
+ *     SV_C128 = two doubles (16 bytes), the layout of torch.complex64 /
+ *     torch.complex128.
+ *   - A context may hold a batch of B states of the same width stored back
+ *     to back (state b at element offset b * 2^n); one circuit is applied to
+ *     all of them, with per-state parameter vectors.
+ *
+ * Ownership
+ *   - Device buffers (states, adjoint scratch) belong to the caller.  The
+ *     library borrows the raw device pointers, never frees them, and needs
+ *     them to stay valid for the lifetime of the context.
+ *   - The library owns the context, its plan cache and small device
+ *     work areas (plans, reduction partials), released by sv_destroy.
+ *   - Host arrays passed to a call are read during the call only.
+ *
+ * Errors
+ *   - Every entry point validates its arguments synchronously and returns a
+ *     non-SV_OK status with a message (sv_last_error) without touching the
+ *     state when validation fails.
+ *   - Kernels run asynchronously on the context's HIP stream.  A device
+ *     fault surfaces as SV_EDEVICE from the next call that synchronises
+ *     (sv_expect, sv_norm, sv_adjoint_grad, sv_sync, sv_apply_batch).
+ *   - No C++ exception crosses this boundary.  A context is not thread-safe;
+ *     separate contexts are independent.
+ */
+#ifndef SV_H_
+#define SV_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SV_OK = 0,
+    SV_EINVAL = 1,        /* bad argument (qubit range, sizes, alignment, op code, ...) */
+    SV_ENOMEM = 2,        /* device or host allocation failed */
+    SV_EDEVICE = 3,       /* HIP runtime / kernel error */
+    SV_EUNSUPPORTED = 4   /* valid request this build does not support */
+} sv_status;
+
+typedef enum { SV_C64 = 1, SV_C128 = 2 } sv_dtype;
+
+/* Gate vocabulary.  Sec. 2 defines NOT (X), H, Z, CNOT, CZ, P = Z^(1/2) (S),
+ * X^(1/2), Y^(1/2) and T; Sec. 4.3 adds P = T^2, Z = T^4.  sqrt(Y) is the
+ * principal square root (it squares to Y).  Rotations are exp(-i theta P/2),
+ * SV_OP_P is diag(1, e^{i theta}), SV_OP_CP is diag(1,1,1,e^{i theta}).
+ * SV_OP_MAT is an explicit 2^nq x 2^nq matrix (nq <= 6) from sv_circuit.mats. */
+typedef enum {
+    SV_OP_I = 0, SV_OP_H = 1, SV_OP_X = 2, SV_OP_Y = 3, SV_OP_Z = 4,
+    SV_OP_S = 5, SV_OP_SDG = 6, SV_OP_T = 7, SV_OP_TDG = 8,
+    SV_OP_SQRTX = 9, SV_OP_SQRTY = 10, SV_OP_SQRTW = 11,
+    SV_OP_SQRTXDG = 12, SV_OP_SQRTYDG = 13, SV_OP_SQRTWDG = 14,
+    SV_OP_RX = 15, SV_OP_RY = 16, SV_OP_RZ = 17, SV_OP_P = 18,
+    SV_OP_CZ = 19, SV_OP_CNOT = 20, SV_OP_SWAP = 21, SV_OP_CP = 22,
+    SV_OP_MAT = 23,
+    SV_OP_COUNT_ = 24
+} sv_op;
+
+/* One gate.  nq: number of qubits (1..6).  param: index into the parameter
+ * vector for angle gates (theta used when param < 0).  mat: offset, in
+ * doubles, of the gate's matrix in sv_circuit.mats (SV_OP_MAT only); the
+ * matrix is row-major, interleaved complex, 2^nq x 2^nq. */
+typedef struct {
+    int32_t op;
+    int32_t nq;
+    int32_t q[6];
+    int32_t param;
+    int32_t mat;
+    double theta;
+} sv_gate;
+
+typedef struct {
+    int32_t n_qubits;
+    int32_t n_gates;
+    const sv_gate* gates;
+    int64_t n_mat_doubles;
+    const double* mats;
+    int32_t n_params;
+} sv_circuit;
+
+/* Observable sum_k coeff[k] * P_k with P_k = i^{|x&z|} X^x Z^z (Y = iXZ on a
+ * qubit whose x and z bits are both set).  Host arrays of n_terms entries. */
+typedef struct {
+    int32_t n_terms;
+    const double* coeff;
+    const uint64_t* x_mask;
+    const uint64_t* z_mask;
+} sv_pauli_sum;
+
+typedef struct {
+    int32_t max_fuse_k;    /* widest fused dense block, 1..6 (default 4) */
+    int32_t tile_bits;     /* local qubits per tile pass, 0 = default */
+    int32_t low_bits;      /* contiguous low bits per tile segment, 0 = default */
+    int32_t plain;         /* 1 = one kernel per gate, no reordering or fusion */
+    int32_t threads;       /* workgroup size of tile passes, 0 = default */
+    int32_t product_init;  /* 1 = fold leading one-qubit gates into the init of |0..0> */
+    int32_t structured;    /* 1 = multiply-free kernels for +-1/+-i structured gates */
+    int32_t reserved[5];
+} sv_opts;
+
+typedef struct {
+    int32_t gates_in;       /* gates in the circuit */
+    int32_t passes;         /* full-state read+write sweeps (tile passes + plain kernels) */
+    int32_t phases;         /* LDS register phases over all passes */
+    int32_t dense_ops;      /* dense blocks applied */
+    int32_t diag_ops;       /* diagonal (phase/sign) ops applied */
+    int32_t launches;       /* kernel launches */
+    int32_t folded_init;    /* gates folded into the product-state init */
+    int32_t reserved;
+    double plan_ms;         /* host planning time (0 on a plan-cache hit) */
+    double hbm_bytes;       /* algorithmic HBM bytes moved by the sweep */
+    double flops;           /* algorithmic floating-point operations */
+} sv_stats;
+
+typedef struct sv_ctx_s* sv_ctx;
+
+enum { SV_INIT_ZERO = 0, SV_INIT_BASIS = 1, SV_INIT_UNIFORM = 2 };
+
+/* Fill *opts with the defaults. */
+void sv_opts_default(sv_opts* opts);
+
+/* Create a context over caller-owned device memory.
+ *   n_qubits   1..34 (SV_C64) or 1..33 (SV_C128)
+ *   batch      number of states (>= 1) stored back to back in d_state
+ *   d_state    device pointer, 16-byte (c64) / 32-byte (c128) aligned
+ *   state_bytes must equal batch * 2^n * bytes-per-amplitude
+ *   hip_stream hipStream_t to launch on (NULL = default stream)
+ *   opts       NULL = defaults
+ * Errors: SV_EINVAL on bad sizes/alignment/null pointers, SV_ENOMEM. */
+sv_status sv_create(sv_ctx* out, int32_t n_qubits, sv_dtype dtype, int32_t batch,
+                    void* d_state, size_t state_bytes, void* hip_stream, const sv_opts* opts);
+sv_status sv_destroy(sv_ctx ctx);
+sv_status sv_set_stream(sv_ctx ctx, void* hip_stream);
+sv_status sv_set_opts(sv_ctx ctx, const sv_opts* opts);
+
+/* Initialise every state of the batch: SV_INIT_ZERO (|0..0>), SV_INIT_BASIS
+ * (|basis_index>), SV_INIT_UNIFORM (all amplitudes 2^{-n/2}, the result of a
+ * Hadamard layer on |0..0>, Sec. 4.5 footnote). */
+sv_status sv_init(sv_ctx ctx, int32_t kind, uint64_t basis_index);
+
+/* Apply a circuit to every state of the batch.  params: host FP64 array of
+ * batch * n_params values (row b = state b), may be NULL when the circuit has
+ * no parameterised gates.  stats may be NULL.  Gates are validated (qubit
+ * range and distinctness, nq <= 6, op codes, param < n_params, matrix range)
+ * before any kernel is launched. */
+sv_status sv_apply_circuit(sv_ctx ctx, const sv_circuit* circuit, const double* params,
+                           sv_stats* stats);
+
+/* out[b] = sum_k coeff_k Re <psi_b|P_k|psi_b>, accumulated in FP64 on the
+ * device with a fixed reduction order.  Synchronises the stream. */
+sv_status sv_expect(sv_ctx ctx, const sv_pauli_sum* obs, double* out);
+
+/* out[b] = ||psi_b||^2 in FP64 (norm check of Sec. 4.1).  Synchronises. */
+sv_status sv_norm(sv_ctx ctx, double* out);
+
+/* Adjoint gradient of E_b = <psi_b|H|psi_b> with psi_b = U(theta_b) psi_b^in,
+ * where psi_b^in is the current state.  Runs the forward sweep, forms
+ * lambda = H psi in d_scratch (caller-owned, >= state_bytes), then sweeps
+ * back through the gates, un-computing both vectors and accumulating
+ * grad[p] = sum over gates l using p of Im <lambda_l|G_l|psi_l> (G_l the
+ * generator of exp(-i theta G_l / 2)) in FP64.
+ * energy_out: host, batch values; grad_out: host, batch * n_params values.
+ * On return the state holds U^dagger U psi^in (psi^in up to rounding). */
+sv_status sv_adjoint_grad(sv_ctx ctx, const sv_circuit* circuit, const double* params,
+                          const sv_pauli_sum* obs, void* d_scratch, size_t scratch_bytes,
+                          double* energy_out, double* grad_out, sv_stats* stats);
+
+/* One item of a heterogeneous batch (circuits of different widths). */
+typedef struct {
+    const sv_circuit* circuit;
+    const double* params;        /* host, circuit->n_params values (may be NULL) */
+    void* d_state;               /* device, 2^n amplitudes of dtype, holds the input state */
+    void* d_lambda;              /* device scratch of the same size (gradients only) */
+    const sv_pauli_sum* observable;
+} sv_batch_item;
+
+enum { SV_BATCH_FORWARD = 1, SV_BATCH_GRAD = 2, SV_BATCH_INIT_ZERO = 4 };
+
+/* Heterogeneous batch in ONE persistent kernel launch: every item's forward
+ * sweep (and, with SV_BATCH_GRAD, its adjoint gradient) is executed by a
+ * grid of resident workgroups pulling (item, pass, tile) work from a device
+ * queue.  energies: host, count values; grads: host, concatenation of every
+ * item's n_params gradients (may be NULL without SV_BATCH_GRAD).
+ * Synchronises the stream. */
+sv_status sv_apply_batch(int32_t count, const sv_batch_item* items, sv_dtype dtype,
+                         void* hip_stream, int32_t flags, double* energies, double* grads,
+                         const sv_opts* opts, sv_stats* stats);
+
+/* Wait for the context's stream and report any device error. */
+sv_status sv_sync(sv_ctx ctx);
+
+/* Thread-local description of the last non-OK status ("" if none). */
+const char* sv_last_error(void);
+
+/* Library version string. */
+const char* sv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SV_H_ */

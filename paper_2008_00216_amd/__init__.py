@@ -1,0 +1,339 @@
+"""Python binding of libsvmi, the MI355X state-vector sweep library.
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels behind the C ABI declared in include/sv.h.  PyTorch supplies device
+memory (the state tensors) and the HIP stream.  If the shared library has not
+been built, importing this package raises ImportError; there is no CPU
+fallback.
+
+Circuits are passed duck-typed: any object with ``n``, ``gates`` (items with
+``op``, ``qubits``, ``param``, ``theta``, ``mat``) and ``n_params``; Pauli sums
+with ``coeff``, ``x_mask``, ``z_mask`` arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime before libsvmi)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsvmi.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_2008_00216_amd/build.py "
+                      "(or __graft_entry__.build()) first")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+SV_OK, SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_EUNSUPPORTED = 0, 1, 2, 3, 4
+SV_C64, SV_C128 = 1, 2
+INIT_ZERO, INIT_BASIS, INIT_UNIFORM = 0, 1, 2
+BATCH_FORWARD, BATCH_GRAD, BATCH_INIT_ZERO = 1, 2, 4
+
+OPS = {
+    "I": 0, "H": 1, "X": 2, "Y": 3, "Z": 4, "S": 5, "SDG": 6, "T": 7, "TDG": 8,
+    "SQRTX": 9, "SQRTY": 10, "SQRTW": 11, "SQRTXDG": 12, "SQRTYDG": 13, "SQRTWDG": 14,
+    "RX": 15, "RY": 16, "RZ": 17, "P": 18, "CZ": 19, "CNOT": 20, "SWAP": 21, "CP": 22, "MAT": 23,
+}
+
+
+class SvGate(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("nq", ctypes.c_int32), ("q", ctypes.c_int32 * 6),
+                ("param", ctypes.c_int32), ("mat", ctypes.c_int32), ("theta", ctypes.c_double)]
+
+
+class SvCircuit(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int32), ("n_gates", ctypes.c_int32),
+                ("gates", ctypes.POINTER(SvGate)), ("n_mat_doubles", ctypes.c_int64),
+                ("mats", ctypes.POINTER(ctypes.c_double)), ("n_params", ctypes.c_int32)]
+
+
+class SvPauliSum(ctypes.Structure):
+    _fields_ = [("n_terms", ctypes.c_int32), ("coeff", ctypes.POINTER(ctypes.c_double)),
+                ("x_mask", ctypes.POINTER(ctypes.c_uint64)), ("z_mask", ctypes.POINTER(ctypes.c_uint64))]
+
+
+class SvOpts(ctypes.Structure):
+    _fields_ = [("max_fuse_k", ctypes.c_int32), ("tile_bits", ctypes.c_int32),
+                ("low_bits", ctypes.c_int32), ("plain", ctypes.c_int32), ("threads", ctypes.c_int32),
+                ("product_init", ctypes.c_int32), ("structured", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
+
+
+class SvStats(ctypes.Structure):
+    _fields_ = [("gates_in", ctypes.c_int32), ("passes", ctypes.c_int32), ("phases", ctypes.c_int32),
+                ("dense_ops", ctypes.c_int32), ("diag_ops", ctypes.c_int32), ("launches", ctypes.c_int32),
+                ("folded_init", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("plan_ms", ctypes.c_double), ("hbm_bytes", ctypes.c_double), ("flops", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class SvBatchItem(ctypes.Structure):
+    _fields_ = [("circuit", ctypes.POINTER(SvCircuit)), ("params", ctypes.POINTER(ctypes.c_double)),
+                ("d_state", ctypes.c_void_p), ("d_lambda", ctypes.c_void_p),
+                ("observable", ctypes.POINTER(SvPauliSum))]
+
+
+_vp, _dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+_lib.sv_opts_default.argtypes = [ctypes.POINTER(SvOpts)]
+_lib.sv_opts_default.restype = None
+_lib.sv_last_error.restype = ctypes.c_char_p
+_lib.sv_version.restype = ctypes.c_char_p
+_lib.sv_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp,
+                           ctypes.c_size_t, _vp, ctypes.POINTER(SvOpts)]
+_lib.sv_destroy.argtypes = [_vp]
+_lib.sv_set_stream.argtypes = [_vp, _vp]
+_lib.sv_set_opts.argtypes = [_vp, ctypes.POINTER(SvOpts)]
+_lib.sv_init.argtypes = [_vp, ctypes.c_int32, ctypes.c_uint64]
+_lib.sv_apply_circuit.argtypes = [_vp, ctypes.POINTER(SvCircuit), _dp, ctypes.POINTER(SvStats)]
+_lib.sv_expect.argtypes = [_vp, ctypes.POINTER(SvPauliSum), _dp]
+_lib.sv_norm.argtypes = [_vp, _dp]
+_lib.sv_adjoint_grad.argtypes = [_vp, ctypes.POINTER(SvCircuit), _dp, ctypes.POINTER(SvPauliSum), _vp,
+                                 ctypes.c_size_t, _dp, _dp, ctypes.POINTER(SvStats)]
+_lib.sv_apply_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(SvBatchItem), ctypes.c_int32, _vp, ctypes.c_int32,
+                                _dp, _dp, ctypes.POINTER(SvOpts), ctypes.POINTER(SvStats)]
+_lib.sv_sync.argtypes = [_vp]
+for _f in ("sv_create", "sv_destroy", "sv_set_stream", "sv_set_opts", "sv_init", "sv_apply_circuit",
+           "sv_expect", "sv_norm", "sv_adjoint_grad", "sv_apply_batch", "sv_sync"):
+    getattr(_lib, _f).restype = ctypes.c_int32
+
+EXPORTED = ("sv_opts_default", "sv_create", "sv_destroy", "sv_set_stream", "sv_set_opts", "sv_init",
+            "sv_apply_circuit", "sv_expect", "sv_norm", "sv_adjoint_grad", "sv_apply_batch", "sv_sync",
+            "sv_last_error", "sv_version")
+
+
+class SvError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+def _check(st: int):
+    if st != SV_OK:
+        raise SvError(st, _lib.sv_last_error().decode())
+
+
+def version() -> str:
+    return _lib.sv_version().decode()
+
+
+def make_opts(**kw) -> SvOpts:
+    o = SvOpts()
+    _lib.sv_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, int(v))
+    return o
+
+
+class CircuitABI:
+    """ctypes view of a circuit (keeps its arrays alive)."""
+
+    def __init__(self, circ):
+        gates = list(circ.gates)
+        self.n = int(circ.n)
+        self.n_params = int(circ.n_params)
+        arr = (SvGate * max(1, len(gates)))()
+        mats = []
+        moff = 0
+        for i, g in enumerate(gates):
+            if g.op not in OPS:
+                raise KeyError(f"unknown gate {g.op}")
+            a = arr[i]
+            a.op = OPS[g.op]
+            a.nq = len(g.qubits)
+            for t, q in enumerate(g.qubits):
+                a.q[t] = int(q)
+            a.param = int(g.param)
+            a.theta = float(g.theta)
+            a.mat = -1
+            if g.op == "MAT":
+                m = np.ascontiguousarray(g.mat, np.complex128).view(np.float64).ravel()
+                a.mat = moff
+                mats.append(m)
+                moff += m.size
+        self._gates = arr
+        self._mats = np.concatenate(mats) if mats else np.zeros(1, np.float64)
+        self.c = SvCircuit(self.n, len(gates), arr, int(moff),
+                           self._mats.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.n_params)
+
+
+class PauliABI:
+    def __init__(self, pauli):
+        self._c = np.ascontiguousarray(pauli.coeff, np.float64)
+        self._x = np.ascontiguousarray(pauli.x_mask, np.uint64)
+        self._z = np.ascontiguousarray(pauli.z_mask, np.uint64)
+        self.p = SvPauliSum(int(self._c.size), self._c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                            self._x.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                            self._z.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+
+
+def _as_circuit(circ):
+    return circ if isinstance(circ, CircuitABI) else CircuitABI(circ)
+
+
+def _as_pauli(p):
+    return p if isinstance(p, PauliABI) else PauliABI(p)
+
+
+def _params_ptr(params, batch, n_params):
+    if params is None or n_params == 0:
+        return None, None
+    p = np.ascontiguousarray(np.asarray(params, np.float64).reshape(batch, n_params))
+    return p, p.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class StateVector:
+    """A batch of 2^n-amplitude states in a torch tensor, driven through libsvmi."""
+
+    def __init__(self, n: int, dtype=torch.complex64, batch: int = 1, device="cuda",
+                 opts: Optional[SvOpts] = None, tensor: Optional[torch.Tensor] = None):
+        if dtype not in (torch.complex64, torch.complex128):
+            raise TypeError("dtype must be complex64 or complex128")
+        self.n, self.batch, self.dtype = int(n), int(batch), dtype
+        if tensor is None:
+            tensor = torch.empty((batch, 1 << n), dtype=dtype, device=device)
+        if tensor.dtype != dtype or not tensor.is_cuda or not tensor.is_contiguous():
+            raise ValueError("state tensor must be a contiguous CUDA tensor of the given dtype")
+        self.tensor = tensor
+        self.opts = opts if opts is not None else make_opts()
+        h = ctypes.c_void_p()
+        _check(_lib.sv_create(ctypes.byref(h), self.n, SV_C64 if dtype == torch.complex64 else SV_C128,
+                              self.batch, ctypes.c_void_p(tensor.data_ptr()),
+                              tensor.numel() * tensor.element_size(), _stream_handle(),
+                              ctypes.byref(self.opts)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.sv_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        _check(_lib.sv_set_stream(self._h, _stream_handle()))
+
+    def set_opts(self, opts: SvOpts):
+        self.opts = opts
+        _check(_lib.sv_set_opts(self._h, ctypes.byref(opts)))
+
+    def init(self, kind: str = "zero", index: int = 0):
+        self._stream()
+        k = {"zero": INIT_ZERO, "basis": INIT_BASIS, "uniform": INIT_UNIFORM}[kind]
+        _check(_lib.sv_init(self._h, k, int(index)))
+        return self
+
+    def apply(self, circ, params=None) -> dict:
+        self._stream()
+        c = _as_circuit(circ)
+        _, pp = _params_ptr(params, self.batch, c.n_params)
+        st = SvStats()
+        _check(_lib.sv_apply_circuit(self._h, ctypes.byref(c.c), pp, ctypes.byref(st)))
+        return st.as_dict()
+
+    def expect(self, pauli) -> np.ndarray:
+        self._stream()
+        p = _as_pauli(pauli)
+        out = np.zeros(self.batch, np.float64)
+        _check(_lib.sv_expect(self._h, ctypes.byref(p.p), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def norm(self) -> np.ndarray:
+        self._stream()
+        out = np.zeros(self.batch, np.float64)
+        _check(_lib.sv_norm(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def adjoint_grad(self, circ, params, pauli, scratch: Optional[torch.Tensor] = None):
+        """Returns (energy[batch], grad[batch, n_params]); see sv_adjoint_grad."""
+        self._stream()
+        c = _as_circuit(circ)
+        p = _as_pauli(pauli)
+        _, pp = _params_ptr(params, self.batch, c.n_params)
+        if scratch is None:
+            scratch = torch.empty_like(self.tensor)
+        e = np.zeros(self.batch, np.float64)
+        g = np.zeros((self.batch, max(1, c.n_params)), np.float64)
+        st = SvStats()
+        _check(_lib.sv_adjoint_grad(self._h, ctypes.byref(c.c), pp, ctypes.byref(p.p),
+                                    ctypes.c_void_p(scratch.data_ptr()), scratch.numel() * scratch.element_size(),
+                                    e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(st)))
+        self.last_stats = st.as_dict()
+        return e, g[:, :c.n_params]
+
+    def sync(self):
+        _check(_lib.sv_sync(self._h))
+
+
+def apply_batch(circuits: Sequence, params: Sequence, states: Sequence[torch.Tensor],
+                observables: Sequence, lambdas: Optional[Sequence[torch.Tensor]] = None,
+                grad: bool = False, init_zero: bool = True, opts: Optional[SvOpts] = None):
+    """Heterogeneous batch through sv_apply_batch.  Returns (energies, grads list, stats)."""
+    count = len(circuits)
+    cabi = [_as_circuit(c) for c in circuits]
+    pabi = [_as_pauli(p) for p in observables]
+    dtype = states[0].dtype
+    items = (SvBatchItem * max(1, count))()
+    keep = []
+    for i in range(count):
+        pr = None
+        if cabi[i].n_params:
+            pr = np.ascontiguousarray(np.asarray(params[i], np.float64))
+            keep.append(pr)
+        items[i].circuit = ctypes.pointer(cabi[i].c)
+        items[i].params = pr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if pr is not None else None
+        items[i].d_state = states[i].data_ptr()
+        items[i].d_lambda = lambdas[i].data_ptr() if lambdas is not None else None
+        items[i].observable = ctypes.pointer(pabi[i].p)
+    ntot = sum(c.n_params for c in cabi)
+    energies = np.zeros(max(1, count), np.float64)
+    grads = np.zeros(max(1, ntot), np.float64)
+    flags = (BATCH_GRAD if grad else BATCH_FORWARD) | (BATCH_INIT_ZERO if init_zero else 0)
+    st = SvStats()
+    o = opts if opts is not None else make_opts()
+    _check(_lib.sv_apply_batch(count, items, SV_C64 if dtype == torch.complex64 else SV_C128,
+                               _stream_handle(), flags,
+                               energies.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               grads.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               ctypes.byref(o), ctypes.byref(st)))
+    out, off = [], 0
+    for c in cabi:
+        out.append(grads[off:off + c.n_params].copy())
+        off += c.n_params
+    return energies[:count], out, st.as_dict()
+
+
+class Energy(torch.autograd.Function):
+    """E(theta) = <psi(theta)|H|psi(theta)>, psi(theta) = U(theta)|0...0>, with the
+    gradient from the adjoint sweep (sv_adjoint_grad).  theta: [batch, n_params]
+    FP64 CPU tensor; returns [batch] FP64."""
+
+    @staticmethod
+    def forward(ctx, theta, sv: StateVector, circ, pauli):
+        th = theta.detach().cpu().numpy().astype(np.float64)
+        sv.init("zero")
+        e, g = sv.adjoint_grad(circ, th, pauli)
+        ctx.save_for_backward(torch.from_numpy(g))
+        return torch.from_numpy(e)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (g,) = ctx.saved_tensors
+        return grad_out.reshape(-1, 1).to(g.dtype) * g, None, None, None

@@ -1,0 +1,580 @@
+// C ABI of libsvmi: contexts, validation, plan cache, executor, reductions,
+// adjoint gradients and heterogeneous batches.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "host.h"
+#include "kernels.h"
+#include "sv.h"
+
+namespace svmi {
+sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dtype dtype, hipStream_t stream,
+                               int32_t flags, double* energies, double* grads, const sv_opts* opts,
+                               sv_stats* stats, std::string& err);
+}
+
+using namespace svmi;
+
+namespace {
+
+thread_local std::string g_err;
+
+sv_status fail(sv_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            return fail(e_ == hipErrorOutOfMemory ? SV_ENOMEM : SV_EDEVICE,                  \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+        }                                                                                    \
+    } while (0)
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+    hipError_t ensure(size_t need) {
+        if (need <= bytes) return hipSuccess;
+        if (p) { (void)hipFree(p); p = nullptr; bytes = 0; }
+        hipError_t e = hipMalloc(&p, need);
+        if (e == hipSuccess) bytes = need;
+        return e;
+    }
+};
+
+struct CachedPlan {
+    EncodedPlan ep;
+    DevBuf dev;
+    size_t o_pass = 0, o_phase = 0, o_op = 0, o_form = 0, o_pair = 0, o_etab = 0;
+    double plan_ms = 0.0;
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+hipError_t upload_plan(CachedPlan& cp, hipStream_t s) {
+    const EncodedPlan& e = cp.ep;
+    size_t o = 0;
+    cp.o_pass = o; o = align_up(o + e.passes.size() * sizeof(DPass), 256);
+    cp.o_phase = o; o = align_up(o + e.phases.size() * sizeof(DPhase), 256);
+    cp.o_op = o; o = align_up(o + e.ops.size() * sizeof(DOp), 256);
+    cp.o_form = o; o = align_up(o + e.forms.size() * sizeof(DForm), 256);
+    cp.o_pair = o; o = align_up(o + e.pairs.size() * sizeof(DPair), 256);
+    cp.o_etab = o; o = align_up(o + e.etab.size() * sizeof(uint16_t), 256);
+    o = std::max<size_t>(o, 256);
+    hipError_t er = cp.dev.ensure(o);
+    if (er != hipSuccess) return er;
+    std::vector<unsigned char> h(o, 0);
+    auto cpy = [&](size_t off, const void* src, size_t n) { if (n) std::memcpy(h.data() + off, src, n); };
+    cpy(cp.o_pass, e.passes.data(), e.passes.size() * sizeof(DPass));
+    cpy(cp.o_phase, e.phases.data(), e.phases.size() * sizeof(DPhase));
+    cpy(cp.o_op, e.ops.data(), e.ops.size() * sizeof(DOp));
+    cpy(cp.o_form, e.forms.data(), e.forms.size() * sizeof(DForm));
+    cpy(cp.o_pair, e.pairs.data(), e.pairs.size() * sizeof(DPair));
+    cpy(cp.o_etab, e.etab.data(), e.etab.size() * sizeof(uint16_t));
+    er = hipMemcpyAsync(cp.dev.p, h.data(), o, hipMemcpyHostToDevice, s);
+    if (er != hipSuccess) return er;
+    return hipStreamSynchronize(s);
+}
+
+}  // namespace
+
+struct sv_ctx_s {
+    int n = 0;
+    int dtype = SV_C64;
+    int batch = 1;
+    void* state = nullptr;
+    size_t state_bytes = 0;
+    hipStream_t stream = nullptr;
+    sv_opts opts{};
+    bool known_zero = false;
+    std::unordered_map<uint64_t, std::unique_ptr<CachedPlan>> cache;
+    DevBuf pool, red_part, red_out, pauli, gpart, gout, pinit;
+    std::vector<unsigned char> pool_host;
+    std::vector<double> host_out;
+};
+
+namespace {
+
+size_t amp_bytes(int dtype) { return dtype == SV_C64 ? 8 : 16; }
+
+PlanCfg cfg_for(const sv_ctx_s* c, bool two) {
+    PlanCfg p;
+    p.dtype = c->dtype;
+    const bool c64 = c->dtype == SV_C64;
+    int T = c->opts.tile_bits > 0 ? c->opts.tile_bits : (c64 ? (two ? 12 : 13) : (two ? 11 : 12));
+    T = std::max(4, std::min(T, kMaxTileBits));
+    if (!c64 && T > 13) T = 13;
+    p.T = T;
+    int L = c->opts.low_bits > 0 ? c->opts.low_bits : (c64 ? 5 : 4);
+    L = std::max(1, std::min(L, T - 1));
+    if (T - L > kMaxHigh) L = T - kMaxHigh;
+    p.L = L;
+    int nt = c->opts.threads > 0 ? c->opts.threads : ((c64 && !two) ? 512 : 256);
+    nt = nt >= 512 ? 512 : 256;
+    if (!c64 && two) nt = 256;
+    p.nt = nt;
+    p.max_fuse_k = c->opts.max_fuse_k > 0 ? c->opts.max_fuse_k : 4;
+    p.two = two;
+    return p;
+}
+
+uint64_t opts_key(const sv_ctx_s* c, bool two, bool pinit) {
+    uint64_t k = (uint64_t)c->dtype * 1315423911ull;
+    k ^= (uint64_t)c->batch * 2654435761ull;
+    k ^= ((uint64_t)c->opts.max_fuse_k << 1) ^ ((uint64_t)c->opts.tile_bits << 9) ^
+         ((uint64_t)c->opts.low_bits << 17) ^ ((uint64_t)c->opts.plain << 25) ^
+         ((uint64_t)c->opts.threads << 27) ^ ((uint64_t)c->opts.structured << 40) ^
+         ((uint64_t)two << 42) ^ ((uint64_t)pinit << 43);
+    return k;
+}
+
+bool use_plain(const sv_ctx_s* c) { return c->opts.plain != 0 || c->n < 4; }
+
+// Build (or fetch) the plan for a circuit; builds the IR with the current
+// parameters in `ir` and the product-init tables in `pi`.
+sv_status get_plan(sv_ctx_s* c, const sv_circuit* circ, const double* params, bool two,
+                   std::vector<IRGate>& ir, ProductInit& pi, CachedPlan*& out, double& plan_ms) {
+    BuildOpts bo;
+    bo.batch = c->batch;
+    bo.structured = c->opts.structured != 0 && !use_plain(c);
+    bo.fuse = !use_plain(c);
+    bo.backward = two;
+    bo.product_init = !two && !use_plain(c) && c->known_zero && c->opts.product_init != 0;
+    try {
+        ir = build_ir(circ, params, bo, &pi, c->n);
+    } catch (const std::exception& e) {
+        return fail(SV_EINVAL, std::string("IR build failed: ") + e.what());
+    }
+    const uint64_t key = circuit_hash(circ, opts_key(c, two, bo.product_init));
+    auto it = c->cache.find(key);
+    plan_ms = 0.0;
+    if (it != c->cache.end()) {
+        out = it->second.get();
+        return SV_OK;
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    auto cp = std::make_unique<CachedPlan>();
+    try {
+        if (use_plain(c)) plan_plain(ir, c->n, cfg_for(c, two), cp->ep);
+        else plan_fused(ir, c->n, cfg_for(c, two), cp->ep);
+    } catch (const std::exception& e) {
+        return fail(SV_EUNSUPPORTED, std::string("planning failed: ") + e.what());
+    }
+    HIPCHK(upload_plan(*cp, c->stream));
+    plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    cp->plan_ms = plan_ms;
+    out = cp.get();
+    c->cache[key] = std::move(cp);
+    return SV_OK;
+}
+
+// Execute a plan on psi (and lambda when `lam` is non-null).
+sv_status run_plan(sv_ctx_s* c, CachedPlan& cp, const std::vector<IRGate>& ir, void* psi, void* lam,
+                   double* gout, uint64_t gstride) {
+    const EncodedPlan& e = cp.ep;
+    const int dt = c->dtype;
+    const uint64_t bstride = 1ull << c->n;
+    const size_t ab = amp_bytes(dt);
+    // pool
+    fill_pool(e, ir, c->batch, c->pool_host);
+    HIPCHK(c->pool.ensure(std::max<size_t>(c->pool_host.size(), 256)));
+    HIPCHK(hipMemcpyAsync(c->pool.p, c->pool_host.data(), c->pool_host.size(), hipMemcpyHostToDevice, c->stream));
+    const uint64_t pool_bstride = e.pool_varies ? e.pool_size : 0;
+    const unsigned char* pool = reinterpret_cast<const unsigned char*>(c->pool.p);
+    // gradient partials
+    if (lam && e.gpart_size) HIPCHK(c->gpart.ensure(e.gpart_size * c->batch * sizeof(double)));
+    const unsigned char* plan = reinterpret_cast<const unsigned char*>(cp.dev.p);
+    void* states[2] = {psi, lam};
+    const int nstates = lam ? 2 : 1;
+    uint64_t gslot = 0;
+    for (const Step& st : e.steps) {
+        switch (st.type) {
+            case ST_TILE: {
+                const DPass& P = e.passes[st.pass];
+                TileArgs a{};
+                a.state = psi;
+                a.lam = lam;
+                a.pass = reinterpret_cast<const DPass*>(plan + cp.o_pass) + st.pass;
+                a.phases = reinterpret_cast<const DPhase*>(plan + cp.o_phase);
+                a.ops = reinterpret_cast<const DOp*>(plan + cp.o_op);
+                a.forms = reinterpret_cast<const DForm*>(plan + cp.o_form);
+                a.pairs = reinterpret_cast<const DPair*>(plan + cp.o_pair);
+                a.etab = reinterpret_cast<const uint16_t*>(plan + cp.o_etab);
+                a.pool = pool;
+                a.pool_bstride = pool_bstride;
+                a.state_bstride = bstride;
+                a.phase_tab = pool;
+                a.gpart = lam ? reinterpret_cast<double*>(c->gpart.p) + P.gpart_off * c->batch : nullptr;
+                a.ntile_log2 = (uint32_t)(c->n - (int)P.T);
+                a.nthreads = (uint32_t)e.cfg.nt;
+                const uint64_t nblocks = (uint64_t)c->batch << (c->n - P.T);
+                const size_t lds = tile_lds_bytes(dt, lam != nullptr, P.T, P.nform, P.ngrad, e.cfg.nt);
+                if (lds > 160 * 1024) return fail(SV_EUNSUPPORTED, "tile pass needs more LDS than available");
+                HIPCHK(launch_tile_pass(dt, lam != nullptr, e.cfg.nt, a, nblocks, lds, c->stream));
+                if (lam && P.ngrad) {
+                    HIPCHK(launch_grad_reduce(reinterpret_cast<double*>(c->gpart.p) + P.gpart_off * c->batch,
+                                              c->batch, 1ull << (c->n - P.T), P.ngrad, gout + gslot, gstride,
+                                              c->stream));
+                    gslot += P.ngrad;
+                }
+                break;
+            }
+            case ST_DENSE:
+                for (int s = 0; s < nstates; ++s)
+                    HIPCHK(launch_dense_plain(dt, states[s], bstride, c->batch, c->n, st.k, st.tq,
+                                              pool + e.recipes[st.recipe].off * ab, pool_bstride, c->stream));
+                break;
+            case ST_MASKED:
+                for (int s = 0; s < nstates; ++s)
+                    HIPCHK(launch_masked_phase(dt, states[s], bstride, c->batch, c->n, st.mask, st.mode,
+                                               st.recipe >= 0 ? pool + e.recipes[st.recipe].off * ab : nullptr,
+                                               pool_bstride, c->stream));
+                break;
+            case ST_DIAG:
+                for (int s = 0; s < nstates; ++s)
+                    HIPCHK(launch_diag_plain(dt, states[s], bstride, c->batch, c->n, st.k, st.tq,
+                                             pool + e.recipes[st.recipe].off * ab, pool_bstride, c->stream));
+                break;
+            case ST_SWAP:
+                for (int s = 0; s < nstates; ++s)
+                    HIPCHK(launch_pair_swap(dt, states[s], bstride, c->batch, c->n, st.mask, st.ones, st.flip,
+                                            st.mode, c->stream));
+                break;
+            case ST_GRAD: {
+                if (!lam) break;
+                HIPCHK(c->red_part.ensure(reduce_partials_size(c->n, c->batch) * sizeof(double)));
+                HIPCHK(launch_reduce(dt, 3, psi, lam, bstride, c->batch, c->n, nullptr, st.mode, st.mask,
+                                     reinterpret_cast<double*>(c->red_part.p), gout + st.slot, gstride, c->stream));
+                break;
+            }
+            default:
+                return fail(SV_EUNSUPPORTED, "unknown plan step");
+        }
+    }
+    return SV_OK;
+}
+
+void fill_stats(sv_stats* st, const sv_ctx_s* c, const CachedPlan& cp, const sv_circuit* circ, double plan_ms,
+                int folded, bool init_used) {
+    if (!st) return;
+    std::memset(st, 0, sizeof(*st));
+    const EncodedPlan& e = cp.ep;
+    st->gates_in = circ->n_gates;
+    st->passes = e.n_tile + e.n_plain + (int)e.steps.size() - e.n_tile - e.n_plain;
+    st->phases = e.n_phase;
+    st->dense_ops = e.n_dense;
+    st->diag_ops = e.n_diag;
+    st->launches = (int)e.steps.size() + (init_used ? 1 : 0);
+    st->folded_init = folded;
+    st->plan_ms = plan_ms;
+    const double N = std::ldexp(1.0, c->n) * c->batch;
+    const double ab = (double)amp_bytes(c->dtype);
+    double bytes = 0.0;
+    for (const Step& s : e.steps) {
+        if (s.type == ST_TILE || s.type == ST_DENSE || s.type == ST_DIAG || s.type == ST_SWAP)
+            bytes += 2.0 * N * ab * (s.type == ST_SWAP ? std::ldexp(1.0, -__builtin_popcountll(s.mask | s.ones)) * 2 : 1.0);
+        else if (s.type == ST_MASKED)
+            bytes += 2.0 * N * ab * std::ldexp(1.0, -__builtin_popcountll(s.mask));
+    }
+    if (init_used) bytes += N * ab;
+    st->hbm_bytes = bytes;
+    st->flops = e.flops * c->batch;
+}
+
+sv_status upload_pauli(sv_ctx_s* c, const sv_pauli_sum* h, PauliDev& pd) {
+    if (!h || h->n_terms < 0) return fail(SV_EINVAL, "observable is NULL or has n_terms < 0");
+    if (h->n_terms > 0 && (!h->coeff || !h->x_mask || !h->z_mask)) return fail(SV_EINVAL, "observable arrays are NULL");
+    const uint64_t qm = c->n >= 64 ? ~0ull : ((1ull << c->n) - 1ull);
+    std::vector<uint64_t> xs;
+    std::vector<std::vector<int>> grp;
+    for (int t = 0; t < h->n_terms; ++t) {
+        if ((h->x_mask[t] | h->z_mask[t]) & ~qm) return fail(SV_EINVAL, "Pauli term acts outside the register");
+        if (!std::isfinite(h->coeff[t])) return fail(SV_EINVAL, "non-finite Pauli coefficient");
+        size_t g = 0;
+        for (; g < xs.size(); ++g) if (xs[g] == h->x_mask[t]) break;
+        if (g == xs.size()) { xs.push_back(h->x_mask[t]); grp.emplace_back(); }
+        grp[g].push_back(t);
+    }
+    const size_t ng = xs.size();
+    const size_t nt = (size_t)h->n_terms;
+    std::vector<uint64_t> z;
+    std::vector<double> cf;
+    std::vector<uint32_t> ph, g0;
+    for (size_t g = 0; g < ng; ++g) {
+        g0.push_back((uint32_t)z.size());
+        for (int t : grp[g]) {
+            z.push_back(h->z_mask[t]);
+            cf.push_back(h->coeff[t]);
+            ph.push_back((uint32_t)(__builtin_popcountll(h->x_mask[t] & h->z_mask[t]) & 3));
+        }
+    }
+    g0.push_back((uint32_t)z.size());
+    const size_t ox = 0, og = align_up(ox + ng * 8, 64), oz = align_up(og + (ng + 1) * 4, 64),
+                 oc = align_up(oz + nt * 8, 64), oph = align_up(oc + nt * 8, 64), tot = align_up(oph + nt * 4 + 64, 64);
+    std::vector<unsigned char> buf(tot, 0);
+    std::memcpy(buf.data() + ox, xs.data(), ng * 8);
+    std::memcpy(buf.data() + og, g0.data(), (ng + 1) * 4);
+    std::memcpy(buf.data() + oz, z.data(), nt * 8);
+    std::memcpy(buf.data() + oc, cf.data(), nt * 8);
+    std::memcpy(buf.data() + oph, ph.data(), nt * 4);
+    HIPCHK(c->pauli.ensure(tot));
+    HIPCHK(hipMemcpyAsync(c->pauli.p, buf.data(), tot, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    unsigned char* d = reinterpret_cast<unsigned char*>(c->pauli.p);
+    pd.x = reinterpret_cast<const uint64_t*>(d + ox);
+    pd.g0 = reinterpret_cast<const uint32_t*>(d + og);
+    pd.z = reinterpret_cast<const uint64_t*>(d + oz);
+    pd.c = reinterpret_cast<const double*>(d + oc);
+    pd.ph = reinterpret_cast<const uint32_t*>(d + oph);
+    pd.ngroup = (uint32_t)ng;
+    return SV_OK;
+}
+
+sv_status apply_internal(sv_ctx_s* c, const sv_circuit* circ, const double* params, sv_stats* stats) {
+    std::vector<IRGate> ir;
+    ProductInit pi;
+    CachedPlan* cp = nullptr;
+    double plan_ms = 0.0;
+    sv_status st = get_plan(c, circ, params, false, ir, pi, cp, plan_ms);
+    if (st != SV_OK) return st;
+    if (pi.used) {
+        const size_t nlo = pi.lo.size(), nhi = pi.hi.size();
+        HIPCHK(c->pinit.ensure((nlo + nhi) * 16));
+        HIPCHK(hipMemcpyAsync(c->pinit.p, pi.lo.data(), nlo * 16, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(reinterpret_cast<unsigned char*>(c->pinit.p) + nlo * 16, pi.hi.data(), nhi * 16,
+                              hipMemcpyHostToDevice, c->stream));
+        const double* lo = reinterpret_cast<const double*>(c->pinit.p);
+        HIPCHK(launch_init_product(c->dtype, c->state, 1ull << c->n, c->batch, c->n, pi.nlo, lo, lo + 2 * nlo,
+                                   c->stream));
+    }
+    st = run_plan(c, *cp, ir, c->state, nullptr, nullptr, 0);
+    if (st != SV_OK) return st;
+    c->known_zero = false;
+    fill_stats(stats, c, *cp, circ, plan_ms, pi.folded, pi.used);
+    return SV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sv_opts_default(sv_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->max_fuse_k = 4;
+    o->product_init = 1;
+    o->structured = 1;
+}
+
+const char* sv_last_error(void) { return g_err.c_str(); }
+const char* sv_version(void) { return "svmi 0.1 (gfx950)"; }
+
+sv_status sv_create(sv_ctx* out, int32_t n, sv_dtype dt, int32_t batch, void* d_state, size_t state_bytes,
+                    void* hip_stream, const sv_opts* opts) {
+    g_err.clear();
+    if (!out) return fail(SV_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (dt != SV_C64 && dt != SV_C128) return fail(SV_EINVAL, "dtype must be SV_C64 or SV_C128");
+    const int nmax = dt == SV_C64 ? 34 : 33;
+    if (n < 1 || n > nmax) {
+        std::ostringstream s;
+        s << "n_qubits " << n << " out of range [1," << nmax << "]";
+        return fail(SV_EINVAL, s.str());
+    }
+    if (batch < 1 || batch > 65535) return fail(SV_EINVAL, "batch must be in [1, 65535]");
+    if (!d_state) return fail(SV_EINVAL, "d_state is NULL");
+    const size_t ab = amp_bytes(dt);
+    if (((uintptr_t)d_state) % (2 * ab / 1) % ab != 0 || ((uintptr_t)d_state % 16) != 0)
+        return fail(SV_EINVAL, "d_state must be 16-byte aligned");
+    const size_t need = (size_t)batch * ((size_t)1 << n) * ab;
+    if (state_bytes != need) {
+        std::ostringstream s;
+        s << "state_bytes " << state_bytes << " != batch * 2^n * " << ab << " = " << need;
+        return fail(SV_EINVAL, s.str());
+    }
+    auto c = new (std::nothrow) sv_ctx_s();
+    if (!c) return fail(SV_ENOMEM, "context allocation failed");
+    c->n = n;
+    c->dtype = dt;
+    c->batch = batch;
+    c->state = d_state;
+    c->state_bytes = state_bytes;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    if (opts) c->opts = *opts; else sv_opts_default(&c->opts);
+    if (c->opts.max_fuse_k < 0 || c->opts.max_fuse_k > 6) { delete c; return fail(SV_EINVAL, "max_fuse_k must be 0..6"); }
+    if (c->opts.tile_bits < 0 || c->opts.tile_bits > kMaxTileBits) { delete c; return fail(SV_EINVAL, "tile_bits must be 0..14"); }
+    static std::once_flag once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(once, [] { attr_err = tile_pass_set_attrs(160 * 1024); });
+    if (attr_err != hipSuccess) {
+        delete c;
+        return fail(SV_EDEVICE, std::string("hipFuncSetAttribute: ") + hipGetErrorString(attr_err));
+    }
+    *out = c;
+    return SV_OK;
+}
+
+sv_status sv_destroy(sv_ctx c) {
+    if (!c) return fail(SV_EINVAL, "ctx is NULL");
+    (void)hipStreamSynchronize(c->stream);
+    delete c;
+    return SV_OK;
+}
+
+sv_status sv_set_stream(sv_ctx c, void* s) {
+    if (!c) return fail(SV_EINVAL, "ctx is NULL");
+    c->stream = reinterpret_cast<hipStream_t>(s);
+    return SV_OK;
+}
+
+sv_status sv_set_opts(sv_ctx c, const sv_opts* o) {
+    if (!c || !o) return fail(SV_EINVAL, "ctx or opts is NULL");
+    if (o->max_fuse_k < 0 || o->max_fuse_k > 6) return fail(SV_EINVAL, "max_fuse_k must be 0..6");
+    if (o->tile_bits < 0 || o->tile_bits > kMaxTileBits) return fail(SV_EINVAL, "tile_bits must be 0..14");
+    c->opts = *o;
+    c->cache.clear();
+    return SV_OK;
+}
+
+sv_status sv_init(sv_ctx c, int32_t kind, uint64_t basis_index) {
+    if (!c) return fail(SV_EINVAL, "ctx is NULL");
+    if (kind != SV_INIT_ZERO && kind != SV_INIT_BASIS && kind != SV_INIT_UNIFORM)
+        return fail(SV_EINVAL, "unknown init kind");
+    if (kind == SV_INIT_BASIS && basis_index >= (1ull << c->n)) return fail(SV_EINVAL, "basis index out of range");
+    const double v = kind == SV_INIT_UNIFORM ? std::ldexp(1.0, -c->n / 2) * ((c->n & 1) ? std::sqrt(0.5) : 1.0) : 0.0;
+    HIPCHK(launch_init(c->dtype, c->state, 1ull << c->n, c->batch, c->n, kind == SV_INIT_UNIFORM ? 2 : 1,
+                       kind == SV_INIT_ZERO ? 0 : basis_index, v, c->stream));
+    c->known_zero = kind == SV_INIT_ZERO;
+    return SV_OK;
+}
+
+sv_status sv_apply_circuit(sv_ctx c, const sv_circuit* circ, const double* params, sv_stats* stats) {
+    if (!c) return fail(SV_EINVAL, "ctx is NULL");
+    std::string v = validate_circuit(circ, c->n);
+    if (!v.empty()) return fail(SV_EINVAL, v);
+    bool has_param = false;
+    for (int i = 0; i < circ->n_gates; ++i) has_param |= circ->gates[i].param >= 0;
+    if (has_param && !params) return fail(SV_EINVAL, "circuit has parameterised gates but params is NULL");
+    if (params)
+        for (int64_t i = 0; i < (int64_t)c->batch * circ->n_params; ++i)
+            if (!std::isfinite(params[i])) return fail(SV_EINVAL, "non-finite parameter");
+    return apply_internal(c, circ, params, stats);
+}
+
+sv_status sv_norm(sv_ctx c, double* out) {
+    if (!c || !out) return fail(SV_EINVAL, "ctx or out is NULL");
+    HIPCHK(c->red_part.ensure(reduce_partials_size(c->n, c->batch) * sizeof(double)));
+    HIPCHK(c->red_out.ensure((size_t)c->batch * sizeof(double)));
+    HIPCHK(launch_reduce(c->dtype, 0, c->state, nullptr, 1ull << c->n, c->batch, c->n, nullptr, 0, 0,
+                         reinterpret_cast<double*>(c->red_part.p), reinterpret_cast<double*>(c->red_out.p), 1,
+                         c->stream));
+    HIPCHK(hipMemcpyAsync(out, c->red_out.p, (size_t)c->batch * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return SV_OK;
+}
+
+sv_status sv_expect(sv_ctx c, const sv_pauli_sum* h, double* out) {
+    if (!c || !out) return fail(SV_EINVAL, "ctx or out is NULL");
+    PauliDev pd{};
+    sv_status st = upload_pauli(c, h, pd);
+    if (st != SV_OK) return st;
+    HIPCHK(c->red_part.ensure(reduce_partials_size(c->n, c->batch) * sizeof(double)));
+    HIPCHK(c->red_out.ensure((size_t)c->batch * sizeof(double)));
+    HIPCHK(launch_reduce(c->dtype, 2, c->state, nullptr, 1ull << c->n, c->batch, c->n, &pd, 0, 0,
+                         reinterpret_cast<double*>(c->red_part.p), reinterpret_cast<double*>(c->red_out.p), 1,
+                         c->stream));
+    HIPCHK(hipMemcpyAsync(out, c->red_out.p, (size_t)c->batch * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return SV_OK;
+}
+
+sv_status sv_adjoint_grad(sv_ctx c, const sv_circuit* circ, const double* params, const sv_pauli_sum* h,
+                          void* d_scratch, size_t scratch_bytes, double* energy_out, double* grad_out,
+                          sv_stats* stats) {
+    if (!c) return fail(SV_EINVAL, "ctx is NULL");
+    std::string v = validate_circuit(circ, c->n);
+    if (!v.empty()) return fail(SV_EINVAL, v);
+    if (!d_scratch || scratch_bytes < c->state_bytes) return fail(SV_EINVAL, "scratch must hold batch * 2^n amplitudes");
+    if (((uintptr_t)d_scratch % 16) != 0) return fail(SV_EINVAL, "d_scratch must be 16-byte aligned");
+    if (!energy_out) return fail(SV_EINVAL, "energy_out is NULL");
+    if (circ->n_params > 0 && (!params || !grad_out)) return fail(SV_EINVAL, "params and grad_out are required");
+    for (int64_t i = 0; params && i < (int64_t)c->batch * circ->n_params; ++i)
+        if (!std::isfinite(params[i])) return fail(SV_EINVAL, "non-finite parameter");
+    PauliDev pd{};
+    sv_status st = upload_pauli(c, h, pd);
+    if (st != SV_OK) return st;
+    // forward sweep (the product-init shortcut is not used: the input state is arbitrary)
+    const bool kz = c->known_zero;
+    c->known_zero = false;
+    st = apply_internal(c, circ, params, stats);
+    (void)kz;
+    if (st != SV_OK) return st;
+    // lambda = H psi, energy = Re <psi|lambda>
+    HIPCHK(launch_hpsi(c->dtype, c->state, d_scratch, 1ull << c->n, c->batch, c->n, pd, c->stream));
+    HIPCHK(c->red_part.ensure(reduce_partials_size(c->n, c->batch) * sizeof(double)));
+    const int ntot_slots = 0;
+    (void)ntot_slots;
+    // backward plan
+    std::vector<IRGate> ir;
+    ProductInit pi;
+    CachedPlan* cp = nullptr;
+    double plan_ms = 0.0;
+    st = get_plan(c, circ, params, true, ir, pi, cp, plan_ms);
+    if (st != SV_OK) return st;
+    const int ns = cp->ep.ngrad_total;
+    const size_t gbytes = (size_t)c->batch * (size_t)(ns + 1) * sizeof(double);
+    HIPCHK(c->gout.ensure(gbytes));
+    double* gdev = reinterpret_cast<double*>(c->gout.p);
+    // energy goes in column ns of the (batch x (ns+1)) output block
+    HIPCHK(launch_reduce(c->dtype, 1, c->state, d_scratch, 1ull << c->n, c->batch, c->n, nullptr, 0, 0,
+                         reinterpret_cast<double*>(c->red_part.p), gdev + ns, (uint64_t)ns + 1, c->stream));
+    st = run_plan(c, *cp, ir, c->state, d_scratch, gdev, (uint64_t)ns + 1);
+    if (st != SV_OK) return st;
+    c->host_out.resize((size_t)c->batch * (ns + 1));
+    HIPCHK(hipMemcpyAsync(c->host_out.data(), gdev, gbytes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int np = circ->n_params;
+    for (int b = 0; b < c->batch; ++b) {
+        const double* row = c->host_out.data() + (size_t)b * (ns + 1);
+        energy_out[b] = row[ns];
+        if (np > 0) {
+            double* g = grad_out + (size_t)b * np;
+            for (int p = 0; p < np; ++p) g[p] = 0.0;
+            for (int s = 0; s < ns; ++s) g[cp->ep.grad_param[s]] += row[s];
+        }
+    }
+    if (stats) stats->plan_ms += plan_ms;
+    return SV_OK;
+}
+
+sv_status sv_sync(sv_ctx c) {
+    if (!c) return fail(SV_EINVAL, "ctx is NULL");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return SV_OK;
+}
+
+sv_status sv_apply_batch(int32_t count, const sv_batch_item* items, sv_dtype dtype, void* hip_stream, int32_t flags,
+                         double* energies, double* grads, const sv_opts* opts, sv_stats* stats) {
+    g_err.clear();
+    std::string err;
+    sv_status st = run_batch_persistent(count, items, dtype, reinterpret_cast<hipStream_t>(hip_stream), flags,
+                                        energies, grads, opts, stats, err);
+    if (st != SV_OK) return fail(st, err);
+    return SV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,75 @@
+// Shared device helpers for the HIP kernels (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace svmi {
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <class R>
+struct alignas(2 * sizeof(R)) V2 {
+    R x, y;
+};
+
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// acc += u * v (complex)
+template <class R>
+__device__ __forceinline__ void cmac(V2<R>& acc, V2<R> u, V2<R> v) {
+    acc.x = fma_(u.x, v.x, acc.x);
+    acc.x = fma_(-u.y, v.y, acc.x);
+    acc.y = fma_(u.x, v.y, acc.y);
+    acc.y = fma_(u.y, v.x, acc.y);
+}
+
+template <class R>
+__device__ __forceinline__ V2<R> cmul(V2<R> u, V2<R> v) {
+    V2<R> r;
+    r.x = fma_(-u.y, v.y, u.x * v.x);
+    r.y = fma_(u.y, v.x, u.x * v.y);
+    return r;
+}
+
+// Deposit the low bits of l into the set bits of MASK (compile time).
+__host__ __device__ constexpr int dep4(int mask, int l) {
+    int out = 0, t = 0;
+    for (int b = 0; b < 4; ++b)
+        if ((mask >> b) & 1) {
+            if ((l >> t) & 1) out |= 1 << b;
+            ++t;
+        }
+    return out;
+}
+
+// XOR-linear LDS swizzle (amplitude units).  It only flips low index bits
+// as a function of higher bits, so swz(a ^ b) == swz(a) ^ swz(b); the c64
+// variant keeps bit 0 so that the two amplitudes of a 16-byte chunk stay
+// adjacent.
+template <class R>
+__host__ __device__ inline uint32_t swz(uint32_t l);
+template <>
+__host__ __device__ inline uint32_t swz<float>(uint32_t l) {
+    return l ^ ((((l >> 6) ^ (l >> 11)) & 31u) << 1);
+}
+template <>
+__host__ __device__ inline uint32_t swz<double>(uint32_t l) {
+    return l ^ (((l >> 4) ^ (l >> 8) ^ (l >> 12)) & 15u);
+}
+
+__device__ __forceinline__ uint32_t rfl(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Flip the sign of both parts of an amplitude when `flip` is 1 (exact).
+__device__ __forceinline__ void sign_flip(V2<float>& a, uint32_t flip) {
+    uint32_t m = flip << 31;
+    a.x = __uint_as_float(__float_as_uint(a.x) ^ m);
+    a.y = __uint_as_float(__float_as_uint(a.y) ^ m);
+}
+__device__ __forceinline__ void sign_flip(V2<double>& a, uint32_t flip) {
+    unsigned long long m = (unsigned long long)flip << 63;
+    a.x = __longlong_as_double(__double_as_longlong(a.x) ^ (long long)m);
+    a.y = __longlong_as_double(__double_as_longlong(a.y) ^ (long long)m);
+}
+
+}  // namespace svmi

@@ -1,0 +1,504 @@
+// Gate table, validation, circuit -> IR conversion and one-qubit fusion.
+//
+// Gate definitions follow Sec. 2 of the paper (NOT, H, Z, CNOT, CZ, P = S,
+// sqrt(X), T) and Sec. 4.3 (P = T^2, Z = T^4).  sqrt(Y) is the principal
+// square root (the printed matrix squares to -Y).  sqrt(W) is the principal
+// root of W = (X + Y)/sqrt(2).  Rotations are exp(-i theta G / 2).
+//
+// Classification follows the paper's split of gates by kind (Sec. 4.2):
+// diagonal gates with 8th-root phases (T, S, Z, CZ and inverses) become terms
+// of a phase form, general diagonals (RZ, P, CP) stay diagonal, everything
+// else is a dense (non-diagonal) gate.  With `structured`, H, sqrt(X),
+// sqrt(Y) and sqrt(W) keep their factored multiply-free form (Sec. 4.4).
+#include <cmath>
+#include <cstring>
+#include <sstream>
+
+#include "host.h"
+
+namespace svmi {
+
+namespace {
+
+const double kR = std::sqrt(0.5);
+
+int op_arity(int op) {
+    switch (op) {
+        case SV_OP_CZ: case SV_OP_CNOT: case SV_OP_SWAP: case SV_OP_CP: return 2;
+        case SV_OP_MAT: return -1;
+        default: return 1;
+    }
+}
+
+bool op_takes_angle(int op) {
+    return op == SV_OP_RX || op == SV_OP_RY || op == SV_OP_RZ || op == SV_OP_P || op == SV_OP_CP;
+}
+
+int diag8_alpha(int op) {
+    switch (op) {
+        case SV_OP_I: return 0;
+        case SV_OP_Z: return 4;
+        case SV_OP_S: return 2;
+        case SV_OP_SDG: return 6;
+        case SV_OP_T: return 1;
+        case SV_OP_TDG: return 7;
+        default: return -1;
+    }
+}
+
+void conj_transpose(std::vector<cd>& m, int d) {
+    std::vector<cd> t(m.size());
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) t[(size_t)c * d + r] = std::conj(m[(size_t)r * d + c]);
+    m.swap(t);
+}
+
+// C = A * B (d x d)
+void matmul(const cd* a, const cd* b, cd* c, int d) {
+    for (int r = 0; r < d; ++r)
+        for (int col = 0; col < d; ++col) {
+            cd s = 0.0;
+            for (int t = 0; t < d; ++t) s += a[(size_t)r * d + t] * b[(size_t)t * d + col];
+            c[(size_t)r * d + col] = s;
+        }
+}
+
+}  // namespace
+
+void gate_matrix(int op, double theta, const double* mat, int nq, std::vector<cd>& m) {
+    const cd I(0.0, 1.0);
+    auto set2 = [&](cd a, cd b, cd c, cd d) { m = {a, b, c, d}; };
+    switch (op) {
+        case SV_OP_I: set2(1, 0, 0, 1); break;
+        case SV_OP_H: set2(kR, kR, kR, -kR); break;
+        case SV_OP_X: set2(0, 1, 1, 0); break;
+        case SV_OP_Y: set2(0, -I, I, 0); break;
+        case SV_OP_Z: set2(1, 0, 0, -1); break;
+        case SV_OP_S: set2(1, 0, 0, I); break;
+        case SV_OP_SDG: set2(1, 0, 0, -I); break;
+        case SV_OP_T: set2(1, 0, 0, cd(kR, kR)); break;
+        case SV_OP_TDG: set2(1, 0, 0, cd(kR, -kR)); break;
+        case SV_OP_SQRTX: case SV_OP_SQRTXDG:
+            set2(cd(0.5, 0.5), cd(0.5, -0.5), cd(0.5, -0.5), cd(0.5, 0.5));
+            if (op == SV_OP_SQRTXDG) conj_transpose(m, 2);
+            break;
+        case SV_OP_SQRTY: case SV_OP_SQRTYDG:
+            set2(cd(0.5, 0.5), cd(-0.5, -0.5), cd(0.5, 0.5), cd(0.5, 0.5));
+            if (op == SV_OP_SQRTYDG) conj_transpose(m, 2);
+            break;
+        case SV_OP_SQRTW: case SV_OP_SQRTWDG:
+            set2(cd(0.5, 0.5), cd(0.0, -kR), cd(kR, 0.0), cd(0.5, 0.5));
+            if (op == SV_OP_SQRTWDG) conj_transpose(m, 2);
+            break;
+        case SV_OP_RX: {
+            const double c = std::cos(theta / 2), s = std::sin(theta / 2);
+            set2(c, cd(0, -s), cd(0, -s), c);
+            break;
+        }
+        case SV_OP_RY: {
+            const double c = std::cos(theta / 2), s = std::sin(theta / 2);
+            set2(c, -s, s, c);
+            break;
+        }
+        case SV_OP_RZ: {
+            const double c = std::cos(theta / 2), s = std::sin(theta / 2);
+            set2(cd(c, -s), 0, 0, cd(c, s));
+            break;
+        }
+        case SV_OP_P: set2(1, 0, 0, cd(std::cos(theta), std::sin(theta))); break;
+        case SV_OP_CZ:
+            m.assign(16, 0.0);
+            m[0] = m[5] = m[10] = 1.0;
+            m[15] = -1.0;
+            break;
+        case SV_OP_CP:
+            m.assign(16, 0.0);
+            m[0] = m[5] = m[10] = 1.0;
+            m[15] = cd(std::cos(theta), std::sin(theta));
+            break;
+        case SV_OP_CNOT:  // control = local bit 0, target = local bit 1: 1 <-> 3
+            m.assign(16, 0.0);
+            m[0 * 4 + 0] = 1.0;
+            m[2 * 4 + 2] = 1.0;
+            m[3 * 4 + 1] = 1.0;
+            m[1 * 4 + 3] = 1.0;
+            break;
+        case SV_OP_SWAP:  // 1 <-> 2
+            m.assign(16, 0.0);
+            m[0] = 1.0;
+            m[3 * 4 + 3] = 1.0;
+            m[2 * 4 + 1] = 1.0;
+            m[1 * 4 + 2] = 1.0;
+            break;
+        case SV_OP_MAT: {
+            const int d = 1 << nq;
+            m.resize((size_t)d * d);
+            for (int i = 0; i < d * d; ++i) m[i] = cd(mat[2 * i], mat[2 * i + 1]);
+            break;
+        }
+        default: m.clear(); break;
+    }
+}
+
+std::string validate_circuit(const sv_circuit* c, int n_qubits) {
+    std::ostringstream e;
+    if (!c) return "circuit is NULL";
+    if (c->n_qubits != n_qubits) {
+        e << "circuit has " << c->n_qubits << " qubits, context has " << n_qubits;
+        return e.str();
+    }
+    if (c->n_gates < 0) return "n_gates < 0";
+    if (c->n_gates > 0 && !c->gates) return "gates is NULL";
+    if (c->n_params < 0) return "n_params < 0";
+    for (int i = 0; i < c->n_gates; ++i) {
+        const sv_gate& g = c->gates[i];
+        if (g.op < 0 || g.op >= SV_OP_COUNT_) {
+            e << "gate " << i << ": unknown op " << g.op;
+            return e.str();
+        }
+        const int want = op_arity(g.op);
+        if (g.nq < 1 || g.nq > 6 || (want > 0 && g.nq != want)) {
+            e << "gate " << i << ": op " << g.op << " with nq=" << g.nq;
+            return e.str();
+        }
+        uint64_t seen = 0;
+        for (int t = 0; t < g.nq; ++t) {
+            if (g.q[t] < 0 || g.q[t] >= n_qubits) {
+                e << "gate " << i << ": qubit " << g.q[t] << " out of range [0," << n_qubits << ")";
+                return e.str();
+            }
+            if ((seen >> g.q[t]) & 1ull) {
+                e << "gate " << i << ": duplicate qubit " << g.q[t];
+                return e.str();
+            }
+            seen |= 1ull << g.q[t];
+        }
+        if (g.param >= 0) {
+            if (!op_takes_angle(g.op)) {
+                e << "gate " << i << ": op " << g.op << " takes no parameter";
+                return e.str();
+            }
+            if (g.param >= c->n_params) {
+                e << "gate " << i << ": param " << g.param << " >= n_params " << c->n_params;
+                return e.str();
+            }
+        }
+        if (g.op == SV_OP_MAT) {
+            const int64_t need = 2ll * (1ll << g.nq) * (1ll << g.nq);
+            if (!c->mats || g.mat < 0 || (int64_t)g.mat + need > c->n_mat_doubles) {
+                e << "gate " << i << ": matrix offset " << g.mat << " out of range";
+                return e.str();
+            }
+        }
+        if (!std::isfinite(g.theta)) {
+            e << "gate " << i << ": non-finite angle";
+            return e.str();
+        }
+    }
+    return "";
+}
+
+uint64_t circuit_hash(const sv_circuit* c, uint64_t seed) {
+    uint64_t h = 1469598103934665603ull ^ seed;
+    auto mix = [&](uint64_t v) {
+        for (int i = 0; i < 8; ++i) {
+            h ^= (v >> (8 * i)) & 255u;
+            h *= 1099511628211ull;
+        }
+    };
+    mix((uint64_t)c->n_qubits);
+    mix((uint64_t)c->n_gates);
+    mix((uint64_t)c->n_params);
+    for (int i = 0; i < c->n_gates; ++i) {
+        const sv_gate& g = c->gates[i];
+        mix((uint64_t)g.op | ((uint64_t)g.nq << 8) | ((uint64_t)(uint32_t)g.param << 16));
+        for (int t = 0; t < g.nq; ++t) mix((uint64_t)g.q[t]);
+    }
+    return h;
+}
+
+namespace {
+
+int gen_of(int op) {
+    switch (op) {
+        case SV_OP_RX: return GEN_X;
+        case SV_OP_RY: return GEN_Y;
+        case SV_OP_RZ: case SV_OP_P: return GEN_Z;
+        case SV_OP_CP: return GEN_P11;
+        default: return 0;
+    }
+}
+
+int perm_of(int op) {
+    switch (op) {
+        case SV_OP_X: return PK_X;
+        case SV_OP_Y: return PK_Y;
+        case SV_OP_CNOT: return PK_CNOT;
+        case SV_OP_SWAP: return PK_SWAP;
+        default: return PK_NONE;
+    }
+}
+
+int skind_of(int op) {
+    switch (op) {
+        case SV_OP_H: return OP_HP;
+        case SV_OP_SQRTX: return OP_XP;
+        case SV_OP_SQRTY: return OP_YP;
+        case SV_OP_SQRTW: return OP_WP;
+        default: return 0;
+    }
+}
+
+// One IR gate from a circuit gate (inverse = conjugate transpose when `inv`).
+IRGate make_ir(const sv_circuit* c, int gi, const double* params, const BuildOpts& o, bool inv) {
+    const sv_gate& g = c->gates[gi];
+    IRGate r;
+    r.k = g.nq;
+    for (int t = 0; t < g.nq; ++t) r.q[t] = g.q[t];
+    r.src = gi;
+    r.param = g.param;
+    r.gen = gen_of(g.op);
+    const int a8 = diag8_alpha(g.op);
+    if (a8 >= 0 || g.op == SV_OP_CZ) {
+        r.kind = K_DIAG8;
+        if (g.op == SV_OP_CZ) r.beta = 4;
+        else r.alpha[0] = inv ? (8 - a8) & 7 : a8;
+        return r;
+    }
+    const bool diag = g.op == SV_OP_RZ || g.op == SV_OP_P || g.op == SV_OP_CP;
+    r.kind = diag ? K_DIAGG : K_DENSE;
+    if (!diag && o.structured && !inv) r.skind = skind_of(g.op);
+    r.perm = inv && g.op == SV_OP_Y ? PK_Y : perm_of(g.op);
+    const int d = 1 << g.nq;
+    const int nb = (g.param >= 0) ? o.batch : 1;
+    r.m.d = d;
+    r.m.nb = nb;
+    r.m.diag = diag;
+    r.m.v.resize((size_t)nb * (diag ? d : d * d));
+    std::vector<cd> m;
+    for (int b = 0; b < nb; ++b) {
+        const double th = g.param >= 0 ? params[(size_t)b * c->n_params + g.param] : g.theta;
+        gate_matrix(g.op, th, g.op == SV_OP_MAT ? c->mats + g.mat : nullptr, g.nq, m);
+        if (inv) conj_transpose(m, d);
+        cd* dst = r.m.at(b);
+        if (diag)
+            for (int i = 0; i < d; ++i) dst[i] = m[(size_t)i * d + i];
+        else
+            std::copy(m.begin(), m.end(), dst);
+    }
+    return r;
+}
+
+// Dense 2x2 matrix of a one-qubit IR gate (any kind), per state.
+MatB as_dense1(const IRGate& g) {
+    MatB r;
+    r.d = 2;
+    r.diag = false;
+    if (g.kind == K_DIAG8) {
+        r.nb = 1;
+        r.v = {1.0, 0.0, 0.0, 1.0};
+        switch (g.alpha[0] & 7) {
+            case 1: r.v[3] = cd(kR, kR); break;
+            case 2: r.v[3] = cd(0, 1); break;
+            case 3: r.v[3] = cd(-kR, kR); break;
+            case 4: r.v[3] = -1.0; break;
+            case 5: r.v[3] = cd(-kR, -kR); break;
+            case 6: r.v[3] = cd(0, -1); break;
+            case 7: r.v[3] = cd(kR, -kR); break;
+            default: break;
+        }
+        return r;
+    }
+    if (g.kind == K_DIAGG) {
+        r.nb = g.m.nb;
+        r.v.resize((size_t)r.nb * 4);
+        for (int b = 0; b < r.nb; ++b) {
+            const cd* s = g.m.at(b);
+            cd* t = r.at(b);
+            t[0] = s[0]; t[1] = 0.0; t[2] = 0.0; t[3] = s[1];
+        }
+        return r;
+    }
+    return g.m;
+}
+
+// a := b * a for one-qubit matrices (per state)
+MatB mul1(const MatB& b, const MatB& a) {
+    MatB r;
+    r.d = 2;
+    r.diag = false;
+    r.nb = std::max(a.nb, b.nb);
+    r.v.resize((size_t)r.nb * 4);
+    for (int s = 0; s < r.nb; ++s) matmul(b.at(s), a.at(s), r.at(s), 2);
+    return r;
+}
+
+MatB diag_of(const IRGate& g) {
+    // diagonal entries (2) of a one-qubit diagonal gate
+    MatB r;
+    r.d = 2;
+    r.diag = true;
+    if (g.kind == K_DIAGG) return g.m;
+    MatB d = as_dense1(g);
+    r.nb = 1;
+    r.v = {d.v[0], d.v[3]};
+    return r;
+}
+
+}  // namespace
+
+std::vector<IRGate> build_ir(const sv_circuit* c, const double* params, const BuildOpts& o, ProductInit* pinit,
+                             int n) {
+    std::vector<IRGate> in;
+    in.reserve((size_t)c->n_gates * (o.backward ? 2 : 1));
+    std::vector<char> consumed((size_t)c->n_gates, 0);
+
+    // Leading one-qubit gates on |0...0> become a product-state initialisation
+    // (the paper turns the initial Hadamard layer into a uniform initial state,
+    // Sec. 4.5 footnote and Sec. 6.1).
+    if (pinit) pinit->used = false;
+    if (!o.backward && o.product_init && pinit) {
+        std::vector<std::vector<cd>> v((size_t)n, std::vector<cd>{1.0, 0.0});
+        std::vector<char> leading((size_t)n, 1);
+        int folded = 0;
+        for (int i = 0; i < c->n_gates; ++i) {
+            const sv_gate& g = c->gates[i];
+            if (g.nq == 1 && leading[g.q[0]] && g.param < 0) {
+                std::vector<cd> m;
+                gate_matrix(g.op, g.theta, g.op == SV_OP_MAT ? c->mats + g.mat : nullptr, 1, m);
+                std::vector<cd>& x = v[g.q[0]];
+                const cd a = m[0] * x[0] + m[1] * x[1], b = m[2] * x[0] + m[3] * x[1];
+                x = {a, b};
+                consumed[i] = 1;
+                ++folded;
+            } else {
+                for (int t = 0; t < g.nq; ++t) leading[g.q[t]] = 0;
+            }
+        }
+        if (folded > 0) {
+            pinit->used = true;
+            pinit->folded = folded;
+            pinit->nlo = n / 2;
+            const int nlo = pinit->nlo, nhi = n - nlo;
+            pinit->lo.assign((size_t)1 << nlo, 1.0);
+            pinit->hi.assign((size_t)1 << nhi, 1.0);
+            for (uint64_t i = 0; i < (1ull << nlo); ++i) {
+                cd p = 1.0;
+                for (int q = 0; q < nlo; ++q) p *= v[q][(i >> q) & 1];
+                pinit->lo[i] = p;
+            }
+            for (uint64_t i = 0; i < (1ull << nhi); ++i) {
+                cd p = 1.0;
+                for (int q = 0; q < nhi; ++q) p *= v[nlo + q][(i >> q) & 1];
+                pinit->hi[i] = p;
+            }
+        }
+    }
+
+    if (!o.backward) {
+        for (int i = 0; i < c->n_gates; ++i)
+            if (!consumed[i]) in.push_back(make_ir(c, i, params, o, false));
+    } else {
+        for (int i = c->n_gates - 1; i >= 0; --i) {
+            const sv_gate& g = c->gates[i];
+            if (g.param >= 0) {
+                IRGate gr;
+                gr.grad = 1;
+                gr.kind = K_DENSE;
+                gr.k = g.nq;
+                for (int t = 0; t < g.nq; ++t) gr.q[t] = g.q[t];
+                gr.param = g.param;
+                gr.gen = gen_of(g.op);
+                gr.src = i;
+                in.push_back(gr);
+            }
+            in.push_back(make_ir(c, i, params, o, true));
+        }
+    }
+    if (!o.fuse) return in;
+
+    // One-qubit fusion.  A chain on qubit q stays open while only diagonal
+    // gates touch q; a dense chain cannot absorb a dense gate once a
+    // multi-qubit diagonal has touched q ("blocked"), but diagonal one-qubit
+    // gates commute with those and may still join.
+    std::vector<IRGate> out;
+    out.reserve(in.size());
+    std::vector<char> alive;
+    std::vector<int> open((size_t)n, -1);
+    std::vector<char> open_diag((size_t)n, 0), blocked((size_t)n, 0);
+    auto is_diag = [](const IRGate& g) { return g.kind != K_DENSE; };
+    auto fusable = [&](const IRGate& g) {
+        if (g.grad || g.k != 1) return false;
+        if (o.backward && g.param >= 0) return false;
+        if (g.skind) return false;
+        if (o.structured && g.kind == K_DIAG8) return false;
+        return true;
+    };
+    for (IRGate& g : in) {
+        if (fusable(g)) {
+            const int q = g.q[0];
+            const int oi = open[q];
+            if (oi >= 0) {
+                IRGate& h = out[oi];
+                if (is_diag(g) && open_diag[q]) {
+                    if (g.kind == K_DIAG8 && h.kind == K_DIAG8) {
+                        h.alpha[0] = (h.alpha[0] + g.alpha[0]) & 7;
+                    } else {
+                        MatB a = diag_of(h), b = diag_of(g), r;
+                        r.d = 2; r.diag = true; r.nb = std::max(a.nb, b.nb);
+                        r.v.resize((size_t)r.nb * 2);
+                        for (int s = 0; s < r.nb; ++s) {
+                            r.at(s)[0] = a.at(s)[0] * b.at(s)[0];
+                            r.at(s)[1] = a.at(s)[1] * b.at(s)[1];
+                        }
+                        h.kind = K_DIAGG; h.m = r; h.perm = PK_NONE; h.param = -1; h.gen = 0;
+                    }
+                    continue;
+                }
+                if (open_diag[q]) {
+                    // dense g after a diagonal chain: move the chain to here
+                    IRGate f = g;
+                    f.m = mul1(as_dense1(g), as_dense1(h));
+                    f.kind = K_DENSE; f.perm = PK_NONE; f.param = -1; f.gen = 0; f.skind = 0;
+                    f.src = h.src;
+                    alive[oi] = 0;
+                    out.push_back(f);
+                    alive.push_back(1);
+                    open[q] = (int)out.size() - 1;
+                    open_diag[q] = 0;
+                    blocked[q] = 0;
+                    continue;
+                }
+                if (is_diag(g) || !blocked[q]) {
+                    h.m = mul1(as_dense1(g), h.m);
+                    h.kind = K_DENSE; h.perm = PK_NONE; h.param = -1; h.gen = 0; h.skind = 0;
+                    continue;
+                }
+            }
+            out.push_back(g);
+            alive.push_back(1);
+            open[q] = (int)out.size() - 1;
+            open_diag[q] = is_diag(g);
+            blocked[q] = 0;
+            continue;
+        }
+        if (!g.grad && g.kind != K_DENSE) {
+            for (int t = 0; t < g.k; ++t)
+                if (open[g.q[t]] >= 0 && !open_diag[g.q[t]]) blocked[g.q[t]] = 1;
+        } else {
+            for (int t = 0; t < g.k; ++t) open[g.q[t]] = -1;
+        }
+        // A diagonal one-qubit gate that cannot fuse (structured mode T) must
+        // still keep later dense gates from jumping over it.
+        if (g.k == 1 && g.kind != K_DENSE) open[g.q[0]] = -1;
+        out.push_back(g);
+        alive.push_back(1);
+    }
+    std::vector<IRGate> res;
+    res.reserve(out.size());
+    for (size_t i = 0; i < out.size(); ++i)
+        if (alive[i]) res.push_back(std::move(out[i]));
+    return res;
+}
+
+}  // namespace svmi

@@ -1,0 +1,85 @@
+// Host-side launch interface of the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "plan.h"
+
+namespace svmi {
+
+struct TileArgs {
+    void* state;             // batch element 0 of psi
+    void* lam;               // batch element 0 of lambda (adjoint sweep) or nullptr
+    const DPass* pass;
+    const DPhase* phases;
+    const DOp* ops;
+    const DForm* forms;
+    const DPair* pairs;
+    const uint16_t* etab;
+    const void* pool;        // matrix pool (state dtype, complex), batch element 0
+    uint64_t pool_bstride;   // elements between per-state pools (0 = shared)
+    uint64_t state_bstride;  // amplitudes between states
+    const void* phase_tab;   // 8 complex entries e^{i pi e / 4} in the state dtype
+    double* gpart;           // gradient partials
+    uint32_t ntile_log2;     // log2(tiles per state)
+    uint32_t nthreads;
+};
+
+// Dynamic LDS bytes a tile pass needs.
+size_t tile_lds_bytes(int dtype, bool two, uint32_t T, uint32_t nform, uint32_t ngrad, int nt);
+hipError_t launch_tile_pass(int dtype, bool two, int nt, const TileArgs& a, uint64_t nblocks,
+                            size_t lds, hipStream_t s);
+hipError_t tile_pass_set_attrs(size_t max_lds);
+
+// Plain (one kernel per gate) kernels; `batch` states spaced `bstride` amplitudes.
+// Dense k-qubit gate on ascending qubits tq[0..k), matrix row-major in that order.
+hipError_t launch_dense_plain(int dtype, void* state, uint64_t bstride, int batch, int n, int k,
+                             const int* tq, const void* mat, uint64_t mat_bstride, hipStream_t s);
+// Multiply every amplitude whose index has all bits of `mask` set by the
+// complex value at `val` (per state, spaced val_bstride); mode 0 general,
+// 1 sign flip (exact), 2 multiply by +i (exact), 3 by -i (exact).
+hipError_t launch_masked_phase(int dtype, void* state, uint64_t bstride, int batch, int n,
+                               uint64_t mask, int mode, const void* val, uint64_t val_bstride,
+                               hipStream_t s);
+// Diagonal on ascending qubits tq[0..k): amplitude j times d[loc(j)].
+hipError_t launch_diag_plain(int dtype, void* state, uint64_t bstride, int batch, int n, int k,
+                             const int* tq, const void* d, uint64_t d_bstride, hipStream_t s);
+// Exact pair permutation: for every index j with bits `zero_mask` clear and
+// `one_mask` set, exchange amplitudes j and j ^ flip.  mode 0: plain swap,
+// mode 1: Y-type swap (a0, a1) -> (-i a1, i a0).
+hipError_t launch_pair_swap(int dtype, void* state, uint64_t bstride, int batch, int n,
+                            uint64_t zero_mask, uint64_t one_mask, uint64_t flip, int mode,
+                            hipStream_t s);
+
+// Initialisation.  kind: 0 zero, 1 basis(index), 2 uniform(value).
+hipError_t launch_init(int dtype, void* state, uint64_t bstride, int batch, int n, int kind,
+                       uint64_t index, double value, hipStream_t s);
+// Product state psi[j] = lo[j & (2^nlo - 1)] * hi[j >> nlo] (FP64 tables).
+hipError_t launch_init_product(int dtype, void* state, uint64_t bstride, int batch, int n,
+                               int nlo, const double* lo, const double* hi, hipStream_t s);
+
+// FP64 reductions.  Partials need reduce_partials_size(...) doubles.
+size_t reduce_partials_size(int n, int batch);
+// kind 0: ||psi||^2; kind 1: Re<a|b> (b = second); kind 2: Pauli-sum
+// expectation; kind 3: Im<b|G|a> for a one/two-qubit generator G (gen,
+// qubit mask gmask) -- the adjoint gradient term with a = psi, b = lambda.
+// out[s * out_stride] receives state s's value.
+struct PauliDev {
+    const uint64_t* x;        // distinct x masks [ngroup]
+    const uint32_t* g0;       // first term of each group [ngroup + 1]
+    const uint64_t* z;        // z mask per term
+    const double* c;          // coefficient per term
+    const uint32_t* ph;       // i^{|x&z|} exponent per term
+    uint32_t ngroup;
+};
+hipError_t launch_reduce(int dtype, int kind, const void* a, const void* b, uint64_t bstride,
+                         int batch, int n, const PauliDev* pd, int gen, uint64_t gmask,
+                         double* partials, double* out, uint64_t out_stride, hipStream_t s);
+// lambda = H psi (FP64 accumulation, rounded once).
+hipError_t launch_hpsi(int dtype, const void* psi, void* lam, uint64_t bstride, int batch, int n,
+                       const PauliDev& pd, hipStream_t s);
+// out[b * out_stride + j] = sum_t part[(b * ntile + t) * nslot + j], t ascending
+hipError_t launch_grad_reduce(const double* part, int batch, uint64_t ntile, uint32_t nslot,
+                              double* out, uint64_t out_stride, hipStream_t s);
+
+}  // namespace svmi

@@ -1,0 +1,271 @@
+// One-kernel-per-gate ("plain") kernels, initialisation and the adjoint's
+// gradient reduction.
+//
+// The plain kernels are the baseline of Sec. 3: a gate on k qubits updates
+// each of the 2^{n-k} disjoint amplitude sets independently.  Diagonal gates
+// whose matrix is the identity except for one entry (CZ, Z, S, T, P, CP)
+// touch only the amplitudes whose index has every gate bit set (the paper's
+// "j & mask == mask" test, Sec. 3), and the permutation gates (NOT, CNOT,
+// SWAP, Y) exchange amplitude pairs without arithmetic, so both are exact.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace svmi {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ uint64_t insert_zeros(uint64_t s, const int* tq, int k) {
+    for (int t = 0; t < k; ++t) {
+        const int p = tq[t];
+        s = ((s >> p) << (p + 1)) | (s & ((1ull << p) - 1ull));
+    }
+    return s;
+}
+
+__device__ __forceinline__ uint64_t insert_zeros_mask(uint64_t s, uint64_t mask) {
+    while (mask) {
+        const int p = __builtin_ctzll(mask);
+        s = ((s >> p) << (p + 1)) | (s & ((1ull << p) - 1ull));
+        mask &= mask - 1;
+    }
+    return s;
+}
+
+struct Targets {
+    int q[6];
+};
+
+template <class R, int K>
+__global__ __launch_bounds__(kBlock) void k_dense(V2<R>* state, uint64_t bstride, int n, Targets tg,
+                                                  const V2<R>* __restrict__ mat, uint64_t mat_bstride,
+                                                  uint64_t nsets) {
+    constexpr int D = 1 << K;
+    const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t b = blockIdx.y;
+    if (gid >= nsets) return;
+    V2<R>* psi = state + (uint64_t)b * bstride;
+    const V2<R>* u = mat + (uint64_t)b * mat_bstride;
+    const uint64_t base = insert_zeros(gid, tg.q, K);
+    uint64_t off[D];
+#pragma unroll
+    for (int l = 0; l < D; ++l) {
+        uint64_t o = 0;
+#pragma unroll
+        for (int t = 0; t < K; ++t)
+            if ((l >> t) & 1) o |= 1ull << tg.q[t];
+        off[l] = base | o;
+    }
+    V2<R> in[D];
+#pragma unroll
+    for (int l = 0; l < D; ++l) in[l] = psi[off[l]];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+        V2<R> acc{R(0), R(0)};
+#pragma unroll
+        for (int c = 0; c < D; ++c) cmac(acc, u[r * D + c], in[c]);
+        psi[off[r]] = acc;
+    }
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_masked_phase(V2<R>* state, uint64_t bstride, uint64_t mask,
+                                                         int mode, const V2<R>* __restrict__ val,
+                                                         uint64_t val_bstride, uint64_t count) {
+    const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t b = blockIdx.y;
+    if (gid >= count) return;
+    V2<R>* psi = state + (uint64_t)b * bstride;
+    const uint64_t j = insert_zeros_mask(gid, mask) | mask;
+    V2<R> a = psi[j];
+    if (mode == 1) {
+        sign_flip(a, 1u);
+    } else if (mode == 2) {          // times +i
+        a = V2<R>{-a.y, a.x};
+    } else if (mode == 3) {          // times -i
+        a = V2<R>{a.y, -a.x};
+    } else {
+        a = cmul(val[(uint64_t)b * val_bstride], a);
+    }
+    psi[j] = a;
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_diag(V2<R>* state, uint64_t bstride, int k, Targets tg,
+                                                 const V2<R>* __restrict__ d, uint64_t d_bstride,
+                                                 uint64_t count) {
+    const uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t b = blockIdx.y;
+    if (j >= count) return;
+    V2<R>* psi = state + (uint64_t)b * bstride;
+    uint32_t loc = 0;
+    for (int t = 0; t < k; ++t) loc |= (uint32_t)((j >> tg.q[t]) & 1ull) << t;
+    psi[j] = cmul(d[(uint64_t)b * d_bstride + loc], psi[j]);
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_pair_swap(V2<R>* state, uint64_t bstride, uint64_t fixed,
+                                                      uint64_t ones, uint64_t flip, int mode,
+                                                      uint64_t count) {
+    const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t b = blockIdx.y;
+    if (gid >= count) return;
+    V2<R>* psi = state + (uint64_t)b * bstride;
+    const uint64_t j0 = insert_zeros_mask(gid, fixed) | ones;
+    const uint64_t j1 = j0 ^ flip;
+    const V2<R> a0 = psi[j0], a1 = psi[j1];
+    if (mode == 0) {
+        psi[j0] = a1;
+        psi[j1] = a0;
+    } else {  // Y: (a0, a1) -> (-i a1, i a0)
+        psi[j0] = V2<R>{a1.y, -a1.x};
+        psi[j1] = V2<R>{-a0.y, a0.x};
+    }
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_init(V2<R>* state, uint64_t bstride, uint64_t count, int kind,
+                                                 uint64_t index, R value) {
+    const uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t b = blockIdx.y;
+    if (j >= count) return;
+    V2<R> v{R(0), R(0)};
+    if (kind == 2) v.x = value;
+    else if (j == index) v.x = R(1);
+    state[(uint64_t)b * bstride + j] = v;
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_init_product(V2<R>* state, uint64_t bstride, uint64_t count,
+                                                         int nlo, const double* __restrict__ lo,
+                                                         const double* __restrict__ hi) {
+    const uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t b = blockIdx.y;
+    if (j >= count) return;
+    const uint64_t a = j & ((1ull << nlo) - 1ull), h = j >> nlo;
+    const double ar = lo[2 * a], ai = lo[2 * a + 1], br = hi[2 * h], bi = hi[2 * h + 1];
+    state[(uint64_t)b * bstride + j] = V2<R>{R(ar * br - ai * bi), R(ar * bi + ai * br)};
+}
+
+__global__ __launch_bounds__(kBlock) void k_grad_reduce(const double* __restrict__ part, uint64_t ntile,
+                                                        uint32_t nslot, double* __restrict__ out,
+                                                        uint64_t out_stride) {
+    const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t b = blockIdx.y;
+    if (j >= nslot) return;
+    const double* p = part + (uint64_t)b * ntile * nslot + j;
+    double s = 0.0;
+    for (uint64_t t = 0; t < ntile; ++t) s += p[t * nslot];
+    out[(uint64_t)b * out_stride + j] = s;
+}
+
+inline dim3 grid_for(uint64_t count, int batch) {
+    return dim3((uint32_t)((count + kBlock - 1) / kBlock), (uint32_t)batch);
+}
+
+}  // namespace
+
+template <class R>
+static hipError_t dense_plain_t(void* state, uint64_t bstride, int batch, int n, int k, const int* tq,
+                                const void* mat, uint64_t mat_bstride, hipStream_t s) {
+    Targets tg{};
+    for (int t = 0; t < k; ++t) tg.q[t] = tq[t];
+    const uint64_t nsets = 1ull << (n - k);
+    auto* st = reinterpret_cast<V2<R>*>(state);
+    auto* m = reinterpret_cast<const V2<R>*>(mat);
+    const dim3 g = grid_for(nsets, batch);
+    switch (k) {
+        case 1: hipLaunchKernelGGL((k_dense<R, 1>), g, dim3(kBlock), 0, s, st, bstride, n, tg, m, mat_bstride, nsets); break;
+        case 2: hipLaunchKernelGGL((k_dense<R, 2>), g, dim3(kBlock), 0, s, st, bstride, n, tg, m, mat_bstride, nsets); break;
+        case 3: hipLaunchKernelGGL((k_dense<R, 3>), g, dim3(kBlock), 0, s, st, bstride, n, tg, m, mat_bstride, nsets); break;
+        case 4: hipLaunchKernelGGL((k_dense<R, 4>), g, dim3(kBlock), 0, s, st, bstride, n, tg, m, mat_bstride, nsets); break;
+        case 5: hipLaunchKernelGGL((k_dense<R, 5>), g, dim3(kBlock), 0, s, st, bstride, n, tg, m, mat_bstride, nsets); break;
+        case 6: hipLaunchKernelGGL((k_dense<R, 6>), g, dim3(kBlock), 0, s, st, bstride, n, tg, m, mat_bstride, nsets); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_plain(int dtype, void* state, uint64_t bstride, int batch, int n, int k,
+                              const int* tq, const void* mat, uint64_t mat_bstride, hipStream_t s) {
+    return dtype == 1 ? dense_plain_t<float>(state, bstride, batch, n, k, tq, mat, mat_bstride, s)
+                      : dense_plain_t<double>(state, bstride, batch, n, k, tq, mat, mat_bstride, s);
+}
+
+hipError_t launch_masked_phase(int dtype, void* state, uint64_t bstride, int batch, int n, uint64_t mask,
+                               int mode, const void* val, uint64_t val_bstride, hipStream_t s) {
+    const uint64_t count = 1ull << (n - __builtin_popcountll(mask));
+    const dim3 g = grid_for(count, batch);
+    if (dtype == 1)
+        hipLaunchKernelGGL(k_masked_phase<float>, g, dim3(kBlock), 0, s, reinterpret_cast<V2<float>*>(state),
+                           bstride, mask, mode, reinterpret_cast<const V2<float>*>(val), val_bstride, count);
+    else
+        hipLaunchKernelGGL(k_masked_phase<double>, g, dim3(kBlock), 0, s, reinterpret_cast<V2<double>*>(state),
+                           bstride, mask, mode, reinterpret_cast<const V2<double>*>(val), val_bstride, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_plain(int dtype, void* state, uint64_t bstride, int batch, int n, int k,
+                             const int* tq, const void* d, uint64_t d_bstride, hipStream_t s) {
+    Targets tg{};
+    for (int t = 0; t < k; ++t) tg.q[t] = tq[t];
+    const uint64_t count = 1ull << n;
+    const dim3 g = grid_for(count, batch);
+    if (dtype == 1)
+        hipLaunchKernelGGL(k_diag<float>, g, dim3(kBlock), 0, s, reinterpret_cast<V2<float>*>(state), bstride,
+                           k, tg, reinterpret_cast<const V2<float>*>(d), d_bstride, count);
+    else
+        hipLaunchKernelGGL(k_diag<double>, g, dim3(kBlock), 0, s, reinterpret_cast<V2<double>*>(state), bstride,
+                           k, tg, reinterpret_cast<const V2<double>*>(d), d_bstride, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_swap(int dtype, void* state, uint64_t bstride, int batch, int n, uint64_t zero_mask,
+                            uint64_t one_mask, uint64_t flip, int mode, hipStream_t s) {
+    const uint64_t fixed = zero_mask | one_mask;
+    const uint64_t count = 1ull << (n - __builtin_popcountll(fixed));
+    const dim3 g = grid_for(count, batch);
+    if (dtype == 1)
+        hipLaunchKernelGGL(k_pair_swap<float>, g, dim3(kBlock), 0, s, reinterpret_cast<V2<float>*>(state),
+                           bstride, fixed, one_mask, flip, mode, count);
+    else
+        hipLaunchKernelGGL(k_pair_swap<double>, g, dim3(kBlock), 0, s, reinterpret_cast<V2<double>*>(state),
+                           bstride, fixed, one_mask, flip, mode, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(int dtype, void* state, uint64_t bstride, int batch, int n, int kind, uint64_t index,
+                       double value, hipStream_t s) {
+    const uint64_t count = 1ull << n;
+    const dim3 g = grid_for(count, batch);
+    if (dtype == 1)
+        hipLaunchKernelGGL(k_init<float>, g, dim3(kBlock), 0, s, reinterpret_cast<V2<float>*>(state), bstride,
+                           count, kind, index, (float)value);
+    else
+        hipLaunchKernelGGL(k_init<double>, g, dim3(kBlock), 0, s, reinterpret_cast<V2<double>*>(state), bstride,
+                           count, kind, index, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_product(int dtype, void* state, uint64_t bstride, int batch, int n, int nlo,
+                               const double* lo, const double* hi, hipStream_t s) {
+    const uint64_t count = 1ull << n;
+    const dim3 g = grid_for(count, batch);
+    if (dtype == 1)
+        hipLaunchKernelGGL(k_init_product<float>, g, dim3(kBlock), 0, s, reinterpret_cast<V2<float>*>(state),
+                           bstride, count, nlo, lo, hi);
+    else
+        hipLaunchKernelGGL(k_init_product<double>, g, dim3(kBlock), 0, s, reinterpret_cast<V2<double>*>(state),
+                           bstride, count, nlo, lo, hi);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const double* part, int batch, uint64_t ntile, uint32_t nslot, double* out,
+                              uint64_t out_stride, hipStream_t s) {
+    const dim3 g((nslot + kBlock - 1) / kBlock, (uint32_t)batch);
+    hipLaunchKernelGGL(k_grad_reduce, g, dim3(kBlock), 0, s, part, ntile, nslot, out, out_stride);
+    return hipGetLastError();
+}
+
+}  // namespace svmi

@@ -1,0 +1,90 @@
+// Device-visible simulation plan.
+//
+// The host planner turns a circuit into a "simulation plan" (Sec. 4.5: the
+// schedule of gate sets handled by the kernels) made of tile passes.  A tile
+// pass streams the whole state once: every workgroup gathers one tile of 2^T
+// amplitudes (T "local" qubits: the L lowest index bits, contiguous in memory,
+// plus H higher bits) into LDS, applies a list of register phases, and writes
+// the tile back.  A register phase gives each thread the 16 amplitudes that
+// differ in 4 chosen local bits ("register slots") and runs an op list on
+// them in registers: dense blocks on up to 4 slots, diagonals, the 8th-root
+// phase form of clustered T/S/Z/CZ gates (Sec. 4.3) and, for the adjoint
+// sweep, gradient reductions.
+//
+// All structures are plain data; the planner fills them on the host and
+// copies them to one device buffer per plan.
+#pragma once
+#include <stdint.h>
+
+namespace svmi {
+
+constexpr int kRegBits = 4;           // register slots per phase
+constexpr int kRegAmps = 1 << kRegBits;
+constexpr int kMaxTileBits = 14;      // local qubits per tile pass
+constexpr int kMaxHigh = 12;          // high local bits per pass
+constexpr int kMaxGradPerPass = 128;  // gradient slots reduced per pass
+
+enum OpType : uint32_t {
+    OP_DENSE = 1,   // k <= 4 slots (mask in `mask`), matrix at `arg` (pool elements)
+    OP_DIAGR = 2,   // diagonal on slots `mask`, 2^k entries at `arg`
+    OP_PHASE8 = 3,  // quadratic 8th-root phase form `arg`
+    OP_SIGN = 4,    // same with every exponent in {0, 4}
+    OP_GRAD = 5,    // Im<lambda|G|psi> over slots `mask`, generator `k`, pass-local slot `arg`
+    OP_SCALE = 6,   // multiply by the real scalar at pool element `arg` (.x)
+    OP_HP = 7,      // H' = [[1,1],[1,-1]] on slot (multiply-free)
+    OP_XP = 8,      // sqrt(X)' = [[1+i,1-i],[1-i,1+i]]
+    OP_YP = 9,      // sqrt(Y)' = [[1+i,-1-i],[1+i,1+i]]
+    OP_WP = 10,     // sqrt(2) sqrt(W) = [[w, -i],[1, w]], w = e^{i pi/4}
+};
+
+enum GradGen : uint32_t { GEN_X = 1, GEN_Y = 2, GEN_Z = 3, GEN_P11 = 4 };
+
+struct DOp {
+    uint32_t type;
+    uint32_t k;      // arity (dense/diag) or generator (grad)
+    uint32_t mask;   // register-slot bitmask (4 bits)
+    uint32_t arg;
+};
+
+enum PhaseKind : uint32_t { PH_REG = 0 };
+
+struct DPhase {
+    uint32_t kind;
+    uint32_t rpos;       // register positions in the tile-local index, 4 x 8 bits, ascending
+    uint32_t op0, nop;
+    uint16_t soff[kRegAmps];  // swizzled LDS offsets of the 16 slots (amplitude units)
+};
+
+// 8th-root phase form relative to one pass/phase (see kernels for the
+// decomposition into tile, thread and register parts).
+struct DForm {
+    uint64_t mc[kMaxTileBits][3];   // per local bit a: nonlocal partner masks, bit c of beta
+    uint64_t ka[3];                 // nonlocal linear terms, bit c of alpha
+    uint32_t konst;                 // constant exponent
+    uint32_t has_tile;              // 1 if any tile-dependent term exists
+    uint32_t q0, nq;                // nonlocal pair list [q0, q0+nq) in the pass's pair table
+    uint32_t etab;                  // offset of the per-thread-group table (uint16 entries)
+    uint32_t a_lo, a_hi;            // register-slot table A[16], 3 bits each (48 bits)
+    uint32_t lam_const[3];          // Lambda_c when has_tile == 0
+    uint32_t slot;                  // index of this form among the pass's forms
+    uint32_t pad;
+};
+
+// Nonlocal-nonlocal pair entry: for nonlocal bit `b`, masks of nonlocal
+// partners b' < b with bit c of beta(b, b') set.
+struct DPair {
+    uint64_t m[3];
+    uint32_t b;
+    uint32_t pad;
+};
+
+struct DPass {
+    uint32_t L, H, T;
+    uint32_t nphase, phase0;
+    uint32_t nform, form0;
+    uint32_t ngrad;
+    uint64_t gpart_off;   // offset of this pass's gradient partials (doubles)
+    uint32_t hpos[16];
+};
+
+}  // namespace svmi

@@ -1,0 +1,795 @@
+// Simulation planner: IR gates -> tile passes -> register phases -> ops.
+//
+// Pass formation reuses the reordering scan of Sec. 4.5.  Walking the
+// remaining gates in order, every qubit is "unobstructed" until a gate that
+// cannot be executed touches it; then it is "obstructed" and no later gate on
+// it may move ahead.  Diagonal gates commute with each other (Sec. 4.2), so a
+// pending diagonal only obstructs later non-diagonal gates.  For a candidate
+// set S of local qubits, a gate is executable in the pass when it is
+// unobstructed and either diagonal with 8th-root phases (any qubits: the
+// kernel knows every amplitude's full index) or all its qubits are in S.  The
+// planner picks S by greedy demand and then a swap-based local search on the
+// number of gates executed.  Register phases inside a pass are chosen the
+// same way over 4-subsets of the local bits.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <stdexcept>
+
+#include "device_common.h"
+#include "host.h"
+
+namespace svmi {
+
+namespace {
+
+enum Cls { C_FREE = 0, C_LOCAL = 1, C_BIG = 2 };
+
+struct GInfo {
+    uint64_t qm = 0;
+    int cls = C_LOCAL;
+    bool diag = false;   // commutes with other diagonals
+    double w = 1.0;
+};
+
+GInfo info_of(const IRGate& g) {
+    GInfo r;
+    r.qm = g.qmask();
+    if (g.kind == K_DIAG8 && !g.grad) {
+        r.cls = C_FREE;
+        r.diag = true;
+        r.w = 0.05;
+        return r;
+    }
+    if (g.grad) {
+        r.cls = C_LOCAL;
+        r.w = 0.5;
+        return r;
+    }
+    if (g.kind == K_DIAGG) {
+        r.cls = g.k <= kRegBits ? C_LOCAL : C_BIG;
+        r.diag = true;
+        r.w = 0.3;
+        return r;
+    }
+    r.cls = g.k <= kRegBits ? C_LOCAL : C_BIG;
+    r.w = g.skind ? 0.7 : (double)(1 << (g.k - 1));
+    return r;
+}
+
+// Obstruction scan.  `allowed` = qubits (bits) executable for C_LOCAL gates.
+// Returns score; fills `exec` if non-null.
+double scan(const std::vector<int>& rem, const std::vector<GInfo>& inf, uint64_t allowed, uint64_t all,
+            std::vector<int>* exec, int limit_local_fail = 1 << 30) {
+    uint64_t bND = 0, bD = 0;
+    double score = 0.0;
+    int fails = 0;
+    for (int id : rem) {
+        const GInfo& g = inf[id];
+        if (g.cls == C_FREE) {
+            if (g.qm & bND) { bD |= g.qm; continue; }
+            score += g.w;
+            if (exec) exec->push_back(id);
+            continue;
+        }
+        if (g.cls == C_BIG) {
+            if (g.diag) bD |= g.qm; else bND |= g.qm;
+        } else if (g.qm & (g.diag ? bND : (bND | bD))) {
+            if (g.diag) bD |= g.qm; else bND |= g.qm;
+        } else if ((g.qm & ~allowed) == 0) {
+            score += g.w;
+            if (exec) exec->push_back(id);
+            continue;
+        } else {
+            if (g.diag) bD |= g.qm; else bND |= g.qm;
+            if (++fails > limit_local_fail) break;
+        }
+        if ((bND & all) == all) break;
+    }
+    return score;
+}
+
+int popc(uint64_t x) { return __builtin_popcountll(x); }
+
+// ---------------------------------------------------------------- forms
+
+struct Form {
+    int alpha[64];
+    std::map<std::pair<int, int>, int> beta;  // (a<b) -> exponent mod 8
+    int konst = 0;
+    Form() { std::memset(alpha, 0, sizeof(alpha)); }
+    bool empty() const {
+        if (konst & 7) return false;
+        for (int i = 0; i < 64; ++i) if (alpha[i] & 7) return false;
+        for (auto& kv : beta) if (kv.second & 7) return false;
+        return true;
+    }
+    bool depends(uint64_t qm) const {
+        for (int i = 0; i < 64; ++i) if (((qm >> i) & 1) && (alpha[i] & 7)) return true;
+        for (auto& kv : beta)
+            if ((kv.second & 7) && (((qm >> kv.first.first) & 1) || ((qm >> kv.first.second) & 1))) return true;
+        return false;
+    }
+    bool sign_only() const {
+        if (konst & 3) return false;
+        for (int i = 0; i < 64; ++i) if (alpha[i] & 3) return false;
+        for (auto& kv : beta) if (kv.second & 3) return false;
+        return true;
+    }
+    void add(const IRGate& g) {
+        if (g.k == 1) {
+            alpha[g.q[0]] = (alpha[g.q[0]] + g.alpha[0]) & 7;
+        } else {
+            alpha[g.q[0]] = (alpha[g.q[0]] + g.alpha[0]) & 7;
+            alpha[g.q[1]] = (alpha[g.q[1]] + g.alpha[1]) & 7;
+            int a = g.q[0], b = g.q[1];
+            if (a > b) std::swap(a, b);
+            int& v = beta[{a, b}];
+            v = (v + g.beta) & 7;
+        }
+    }
+    int beta_of(int a, int b) const {
+        if (a > b) std::swap(a, b);
+        auto it = beta.find({a, b});
+        return it == beta.end() ? 0 : it->second & 7;
+    }
+    void clear() {
+        std::memset(alpha, 0, sizeof(alpha));
+        beta.clear();
+        konst = 0;
+    }
+};
+
+struct PassGeom {
+    int L = 0, H = 0, T = 0;
+    int hpos[16] = {0};
+    int lpos[64];            // global qubit -> local position or -1
+    int gq[kMaxTileBits];    // local position -> global qubit
+};
+
+PassGeom make_geom(int n, int L, uint64_t S) {
+    PassGeom g;
+    g.L = L;
+    for (int q = 0; q < 64; ++q) g.lpos[q] = -1;
+    int t = 0;
+    for (int q = 0; q < L; ++q) { g.lpos[q] = q; g.gq[q] = q; }
+    for (int q = L; q < n; ++q)
+        if ((S >> q) & 1) {
+            g.hpos[t] = q;
+            g.lpos[q] = L + t;
+            g.gq[L + t] = q;
+            ++t;
+        }
+    g.H = t;
+    g.T = L + t;
+    return g;
+}
+
+template <class R>
+void soff_for(const int r[4], uint16_t* soff) {
+    for (int i = 0; i < kRegAmps; ++i) {
+        uint32_t l = 0;
+        for (int s = 0; s < 4; ++s)
+            if ((i >> s) & 1) l |= 1u << r[s];
+        soff[i] = (uint16_t)swz<R>(l);
+    }
+}
+
+uint32_t deposit_skip(uint32_t x, const int r[4]) {
+    for (int s = 0; s < 4; ++s) {
+        const int p = r[s];
+        x = ((x >> p) << (p + 1)) | (x & ((1u << p) - 1u));
+    }
+    return x;
+}
+
+// Encode a form for (pass geometry, phase registers) into out.
+int encode_form(const Form& F, const PassGeom& G, const int r[4], int n, EncodedPlan& out, uint32_t slot) {
+    DForm D;
+    std::memset(&D, 0, sizeof(D));
+    D.konst = (uint32_t)(F.konst & 7);
+    D.slot = slot;
+    const uint64_t localmask = [&] {
+        uint64_t m = 0;
+        for (int a = 0; a < G.T; ++a) m |= 1ull << G.gq[a];
+        return m;
+    }();
+    // register table A[i]
+    uint64_t A = 0;
+    for (int i = 0; i < kRegAmps; ++i) {
+        int e = 0;
+        for (int s = 0; s < 4; ++s) {
+            if (!((i >> s) & 1)) continue;
+            e += F.alpha[G.gq[r[s]]];
+            for (int s2 = s + 1; s2 < 4; ++s2)
+                if ((i >> s2) & 1) e += F.beta_of(G.gq[r[s]], G.gq[r[s2]]);
+        }
+        A |= (uint64_t)(e & 7) << (3 * i);
+    }
+    D.a_lo = (uint32_t)A;
+    D.a_hi = (uint32_t)(A >> 32);
+    bool tile = false;
+    // nonlocal linear terms and local <-> nonlocal pairs
+    for (int q = 0; q < n; ++q) {
+        if ((localmask >> q) & 1) continue;
+        const int al = F.alpha[q] & 7;
+        for (int c = 0; c < 3; ++c)
+            if ((al >> c) & 1) { D.ka[c] |= 1ull << q; tile = true; }
+    }
+    for (auto& kv : F.beta) {
+        const int v = kv.second & 7;
+        if (!v) continue;
+        const int a = kv.first.first, b = kv.first.second;
+        const bool la = (localmask >> a) & 1, lb = (localmask >> b) & 1;
+        if (la && lb) continue;
+        tile = true;
+        if (la != lb) {
+            const int loc = la ? a : b, nl = la ? b : a;
+            const int pa = G.lpos[loc];
+            for (int c = 0; c < 3; ++c)
+                if ((v >> c) & 1) D.mc[pa][c] |= 1ull << nl;
+        }
+    }
+    // nonlocal-nonlocal pairs
+    D.q0 = (uint32_t)out.pairs.size();
+    std::map<int, DPair> pl;
+    for (auto& kv : F.beta) {
+        const int v = kv.second & 7;
+        if (!v) continue;
+        const int a = kv.first.first, b = kv.first.second;  // a < b
+        if (((localmask >> a) & 1) || ((localmask >> b) & 1)) continue;
+        DPair& p = pl[b];
+        p.b = (uint32_t)b;
+        for (int c = 0; c < 3; ++c)
+            if ((v >> c) & 1) p.m[c] |= 1ull << a;
+    }
+    for (auto& kv : pl) out.pairs.push_back(kv.second);
+    D.nq = (uint32_t)(out.pairs.size() - D.q0);
+    D.has_tile = tile ? 1u : 0u;
+    // thread-group table
+    D.etab = (uint32_t)out.etab.size();
+    const uint32_t ng = 1u << (G.T - kRegBits);
+    std::vector<int> tau;
+    for (int a = 0; a < G.T; ++a)
+        if (a != r[0] && a != r[1] && a != r[2] && a != r[3]) tau.push_back(a);
+    for (uint32_t gg = 0; gg < ng; ++gg) {
+        const uint32_t lb = deposit_skip(gg, r);
+        int e = 0;
+        int d[4] = {0, 0, 0, 0};
+        for (size_t i = 0; i < tau.size(); ++i) {
+            const int a = tau[i];
+            if (!((lb >> a) & 1)) continue;
+            const int qa = G.gq[a];
+            e += F.alpha[qa];
+            for (size_t j = i + 1; j < tau.size(); ++j) {
+                const int a2 = tau[j];
+                if ((lb >> a2) & 1) e += F.beta_of(qa, G.gq[a2]);
+            }
+            for (int s = 0; s < 4; ++s) d[s] += F.beta_of(G.gq[r[s]], qa);
+        }
+        uint32_t v = (uint32_t)(e & 7);
+        for (int s = 0; s < 4; ++s) v |= (uint32_t)(d[s] & 7) << (3 + 3 * s);
+        out.etab.push_back((uint16_t)v);
+    }
+    out.forms.push_back(D);
+    return (int)out.forms.size() - 1;
+}
+
+// Matrix slot permutation for a gate whose qubits sit on register slots.
+void slot_perm(const IRGate& g, const int* slot_of_q, Recipe& rc, uint32_t& mask) {
+    int s[6];
+    mask = 0;
+    for (int t = 0; t < g.k; ++t) {
+        s[t] = slot_of_q[t];
+        mask |= 1u << s[t];
+    }
+    // new local bit j <- the gate bit whose slot is the j-th smallest
+    int order[6];
+    for (int t = 0; t < g.k; ++t) order[t] = t;
+    std::sort(order, order + g.k, [&](int a, int b) { return s[a] < s[b]; });
+    for (int j = 0; j < g.k; ++j) rc.perm[j] = order[j];
+    rc.k = g.k;
+}
+
+uint64_t add_recipe(EncodedPlan& out, Recipe rc, const std::vector<IRGate>& ir) {
+    if (rc.type == Recipe::DENSE) {
+        const int d = 1 << rc.k;
+        rc.size = (uint64_t)d * d;
+        rc.varies = ir[rc.gate].m.nb > 1;
+    } else if (rc.type == Recipe::DIAG) {
+        rc.size = (uint64_t)1 << rc.k;
+        rc.varies = ir[rc.gate].m.nb > 1;
+    } else if (rc.type == Recipe::PHASETAB) {
+        rc.size = 8;
+    } else {
+        rc.size = 1;
+    }
+    // keep matrices 16-byte friendly: no special alignment needed for V2
+    rc.off = out.pool_size;
+    out.pool_size += rc.size;
+    if (rc.varies) out.pool_varies = true;
+    out.recipes.push_back(rc);
+    return rc.off;
+}
+
+double op_cost(const IRGate& g) {
+    if (g.kind == K_DIAG8) return 0.0;
+    if (g.grad) return 6.0;
+    if (g.kind == K_DIAGG) return 6.0;
+    if (g.skind) return g.skind == OP_WP ? 12.0 : (g.skind == OP_HP ? 4.0 : 8.0);
+    return 8.0 * (double)(1 << g.k);
+}
+
+}  // namespace
+
+void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, EncodedPlan& out) {
+    out = EncodedPlan();
+    out.cfg = cfg;
+    out.n = n;
+    const bool c64 = cfg.dtype == SV_C64;
+    // phase table e^{i pi e/4} at pool offset 0
+    {
+        Recipe r;
+        r.type = Recipe::PHASETAB;
+        add_recipe(out, r, ir);
+    }
+    std::vector<GInfo> inf(ir.size());
+    for (size_t i = 0; i < ir.size(); ++i) inf[i] = info_of(ir[i]);
+    const int T = std::min(cfg.T, n);
+    const int L = std::min(cfg.L, T);
+    const uint64_t all = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
+    const uint64_t low = (1ull << L) - 1ull;
+    std::vector<int> rem(ir.size());
+    for (size_t i = 0; i < ir.size(); ++i) rem[i] = (int)i;
+    uint64_t grad_base = 0;
+
+    while (!rem.empty()) {
+        // ---- choose the local set S (|S| = T, low bits always local)
+        uint64_t S = low;
+        {
+            uint64_t bND = 0, bD = 0;
+            for (int id : rem) {
+                const GInfo& g = inf[id];
+                if (g.cls == C_FREE) {
+                    if (g.qm & bND) bD |= g.qm;
+                    continue;
+                }
+                const uint64_t blk = g.diag ? bND : (bND | bD);
+                if (g.cls == C_LOCAL && !(g.qm & blk) && popc(S | g.qm) <= T) {
+                    S |= g.qm;
+                    continue;
+                }
+                if (g.diag) bD |= g.qm; else bND |= g.qm;
+                if ((bND & all) == all || popc(S) >= T) break;
+            }
+            // fill up with qubits that have pending local work, then any
+            if (popc(S) < T) {
+                std::vector<int> cnt((size_t)n, 0);
+                for (int id : rem)
+                    if (inf[id].cls == C_LOCAL)
+                        for (int q = 0; q < n; ++q) if ((inf[id].qm >> q) & 1) cnt[q]++;
+                while (popc(S) < T) {
+                    int best = -1;
+                    for (int q = 0; q < n; ++q)
+                        if (!((S >> q) & 1) && (best < 0 || cnt[q] > cnt[best])) best = q;
+                    if (best < 0) break;
+                    S |= 1ull << best;
+                }
+            }
+        }
+        double best = scan(rem, inf, S, all, nullptr);
+        // local search: swap one high local qubit for one non-local qubit
+        for (int round = 0; round < 6 && T < n; ++round) {
+            bool improved = false;
+            uint64_t bestS = S;
+            for (int a = L; a < n; ++a) {
+                if (!((S >> a) & 1)) continue;
+                for (int b = L; b < n; ++b) {
+                    if ((S >> b) & 1) continue;
+                    const uint64_t S2 = (S & ~(1ull << a)) | (1ull << b);
+                    const double sc = scan(rem, inf, S2, all, nullptr);
+                    if (sc > best + 1e-9) { best = sc; bestS = S2; improved = true; }
+                }
+            }
+            S = bestS;
+            if (!improved) break;
+        }
+        std::vector<int> ex;
+        scan(rem, inf, S, all, &ex);
+        if (ex.empty()) {
+            // the frontier is a gate wider than a register phase: plain kernel
+            const int id = rem[0];
+            if (inf[id].cls != C_BIG) throw std::runtime_error("planner: no progress");
+            const IRGate& g = ir[id];
+            Step st;
+            if (g.kind == K_DIAGG) {
+                st.type = ST_DIAG;
+            } else {
+                st.type = ST_DENSE;
+            }
+            int order[6];
+            for (int t = 0; t < g.k; ++t) order[t] = t;
+            std::sort(order, order + g.k, [&](int x, int y) { return g.q[x] < g.q[y]; });
+            Recipe rc;
+            rc.type = g.kind == K_DIAGG ? Recipe::DIAG : Recipe::DENSE;
+            rc.gate = id;
+            rc.k = g.k;
+            for (int j = 0; j < g.k; ++j) { rc.perm[j] = order[j]; st.tq[j] = g.q[order[j]]; }
+            st.k = g.k;
+            add_recipe(out, rc, ir);
+            st.recipe = (int)out.recipes.size() - 1;
+            out.steps.push_back(st);
+            out.n_plain++;
+            out.flops += 8.0 * (double)(1 << g.k) * (double)(1ull << n);
+            rem.erase(std::find(rem.begin(), rem.end(), id));
+            continue;
+        }
+        // ---- build the pass
+        PassGeom G = make_geom(n, L, S);
+        DPass P;
+        std::memset(&P, 0, sizeof(P));
+        P.L = (uint32_t)G.L;
+        P.H = (uint32_t)G.H;
+        P.T = (uint32_t)G.T;
+        for (int t = 0; t < G.H; ++t) P.hpos[t] = (uint32_t)G.hpos[t];
+        P.phase0 = (uint32_t)out.phases.size();
+        P.form0 = (uint32_t)out.forms.size();
+        uint32_t nform = 0, ngrad = 0;
+
+        // phases
+        std::vector<int> prem = ex;
+        std::vector<GInfo> linf(ir.size());
+        Form pending;
+        int scale_p = 0;   // accumulated power of 1/sqrt(2) from structured ops
+        std::vector<int> combos;
+        for (int a = 0; a < G.T; ++a)
+            for (int b = a + 1; b < G.T; ++b)
+                for (int c = b + 1; c < G.T; ++c)
+                    for (int d = c + 1; d < G.T; ++d) combos.push_back(a | (b << 8) | (c << 16) | (d << 24));
+        // local-position masks for the phase scan (non-local qubits never
+        // obstruct anything inside a pass, so they are dropped)
+        std::vector<GInfo> pinf = inf;
+        for (int id : prem) {
+            uint64_t m = 0;
+            for (int t = 0; t < ir[id].k; ++t) {
+                const int lp = G.lpos[ir[id].q[t]];
+                if (lp >= 0) m |= 1ull << lp;
+            }
+            pinf[id].qm = m;
+        }
+        const uint64_t lall = (1ull << G.T) - 1ull;
+        while (!prem.empty()) {
+            double bs = -1.0;
+            int bc = combos.empty() ? 0 : combos[0];
+            for (int cmb : combos) {
+                const uint64_t R = (1ull << (cmb & 255)) | (1ull << ((cmb >> 8) & 255)) |
+                                   (1ull << ((cmb >> 16) & 255)) | (1ull << (cmb >> 24));
+                const double sc = scan(prem, pinf, R, lall, nullptr);
+                if (sc > bs + 1e-9) { bs = sc; bc = cmb; }
+            }
+            int r[4] = {bc & 255, (bc >> 8) & 255, (bc >> 16) & 255, bc >> 24};
+            const uint64_t R = (1ull << r[0]) | (1ull << r[1]) | (1ull << r[2]) | (1ull << r[3]);
+            std::vector<int> pex;
+            scan(prem, pinf, R, lall, &pex);
+            if (pex.empty()) throw std::runtime_error("planner: empty register phase");
+            DPhase Ph;
+            std::memset(&Ph, 0, sizeof(Ph));
+            Ph.kind = PH_REG;
+            Ph.rpos = (uint32_t)(r[0] | (r[1] << 8) | (r[2] << 16) | (r[3] << 24));
+            if (c64) soff_for<float>(r, Ph.soff); else soff_for<double>(r, Ph.soff);
+            Ph.op0 = (uint32_t)out.ops.size();
+            auto flush = [&](bool force) {
+                if (pending.empty()) { pending.clear(); return; }
+                (void)force;
+                const bool so = pending.sign_only();
+                const int fi = encode_form(pending, G, r, n, out, nform++);
+                DOp op{so ? (uint32_t)OP_SIGN : (uint32_t)OP_PHASE8, 0u, 0u, (uint32_t)fi};
+                out.ops.push_back(op);
+                out.n_diag++;
+                out.flops += (so ? 2.0 : 6.0) * (double)(1ull << n) * (cfg.two ? 2 : 1);
+                pending.clear();
+            };
+            for (int id : pex) {
+                const IRGate& g = ir[id];
+                if (inf[id].cls == C_FREE) {
+                    pending.add(g);
+                    continue;
+                }
+                if (pending.depends(g.qmask())) flush(false);
+                int slot_of_q[6];
+                for (int t = 0; t < g.k; ++t) {
+                    const int lp = G.lpos[g.q[t]];
+                    int s = -1;
+                    for (int u = 0; u < 4; ++u) if (r[u] == lp) s = u;
+                    slot_of_q[t] = s;
+                }
+                if (g.grad) {
+                    uint32_t mask = 0;
+                    for (int t = 0; t < g.k; ++t) mask |= 1u << slot_of_q[t];
+                    DOp op{(uint32_t)OP_GRAD, (uint32_t)g.gen, mask, ngrad};
+                    out.ops.push_back(op);
+                    out.grad_param.push_back(g.param);
+                    ++ngrad;
+                    continue;
+                }
+                Recipe rc;
+                rc.gate = id;
+                uint32_t mask = 0;
+                slot_perm(g, slot_of_q, rc, mask);
+                if (g.skind) {
+                    DOp op{(uint32_t)g.skind, 1u, mask, 0u};
+                    out.ops.push_back(op);
+                    scale_p += (g.skind == OP_XP || g.skind == OP_YP) ? 2 : 1;
+                    out.n_dense++;
+                    out.flops += op_cost(g) * 0.5 * (double)(1ull << n) * (cfg.two ? 2 : 1);
+                    continue;
+                }
+                if (g.kind == K_DIAGG) {
+                    rc.type = Recipe::DIAG;
+                    const uint64_t off = add_recipe(out, rc, ir);
+                    DOp op{(uint32_t)OP_DIAGR, (uint32_t)g.k, mask, (uint32_t)off};
+                    out.ops.push_back(op);
+                    out.n_diag++;
+                    out.flops += 6.0 * (double)(1ull << n) * (cfg.two ? 2 : 1);
+                } else {
+                    rc.type = Recipe::DENSE;
+                    const uint64_t off = add_recipe(out, rc, ir);
+                    DOp op{(uint32_t)OP_DENSE, (uint32_t)g.k, mask, (uint32_t)off};
+                    out.ops.push_back(op);
+                    out.n_dense++;
+                    out.flops += 8.0 * (double)(1 << g.k) * (double)(1ull << n) * (cfg.two ? 2 : 1);
+                }
+            }
+            // drop executed gates from prem
+            {
+                std::vector<char> done(ir.size(), 0);
+                for (int id : pex) done[id] = 1;
+                std::vector<int> nr;
+                for (int id : prem) if (!done[id]) nr.push_back(id);
+                prem.swap(nr);
+            }
+            if (prem.empty()) {
+                flush(true);
+                if (scale_p) {
+                    Recipe rc;
+                    rc.type = Recipe::SCALE;
+                    rc.scale = std::ldexp(1.0, -(scale_p / 2)) * ((scale_p & 1) ? std::sqrt(0.5) : 1.0);
+                    const uint64_t off = add_recipe(out, rc, ir);
+                    DOp op{(uint32_t)OP_SCALE, 0u, 0u, (uint32_t)off};
+                    out.ops.push_back(op);
+                }
+            }
+            Ph.nop = (uint32_t)(out.ops.size() - Ph.op0);
+            out.phases.push_back(Ph);
+            out.n_phase++;
+        }
+        P.nphase = (uint32_t)(out.phases.size() - P.phase0);
+        P.nform = nform;
+        P.ngrad = ngrad;
+        P.gpart_off = out.gpart_size;   // per state; the executor scales by the batch
+        out.grad_slot_off.push_back(grad_base);
+        grad_base += ngrad;
+        out.gpart_size += (uint64_t)ngrad << (n - G.T);
+        out.passes.push_back(P);
+        Step st;
+        st.type = ST_TILE;
+        st.pass = (int)out.passes.size() - 1;
+        out.steps.push_back(st);
+        out.n_tile++;
+        // remove executed gates
+        {
+            std::vector<char> done(ir.size(), 0);
+            for (int id : ex) done[id] = 1;
+            std::vector<int> nr;
+            for (int id : rem) if (!done[id]) nr.push_back(id);
+            rem.swap(nr);
+        }
+    }
+    out.ngrad_total = (int)grad_base;
+}
+
+void plan_plain(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, EncodedPlan& out) {
+    out = EncodedPlan();
+    out.cfg = cfg;
+    out.n = n;
+    {
+        Recipe r;
+        r.type = Recipe::PHASETAB;
+        add_recipe(out, r, ir);
+    }
+    const double N = (double)(1ull << n);
+    int grad_slot = 0;
+    for (size_t id = 0; id < ir.size(); ++id) {
+        const IRGate& g = ir[id];
+        Step st;
+        if (g.grad) {
+            st.type = ST_GRAD;
+            st.k = g.k;
+            for (int t = 0; t < g.k; ++t) st.tq[t] = g.q[t];
+            st.mask = g.qmask();
+            st.mode = g.gen;
+            st.slot = grad_slot++;
+            out.grad_param.push_back(g.param);
+            out.steps.push_back(st);
+            continue;
+        }
+        if (g.kind == K_DIAG8) {
+            uint64_t mask = 0;
+            int e = 0;
+            if (g.k == 1) {
+                mask = 1ull << g.q[0];
+                e = g.alpha[0] & 7;
+            } else {
+                mask = (1ull << g.q[0]) | (1ull << g.q[1]);
+                e = g.beta & 7;
+                if ((g.alpha[0] & 7) || (g.alpha[1] & 7)) {
+                    // general two-qubit 8th-root diagonal: use the diagonal kernel
+                    e = -1;
+                }
+            }
+            if (e < 0) throw std::runtime_error("planner: unfused two-qubit phase with linear terms");
+            if (e == 0) continue;
+            st.type = ST_MASKED;
+            st.mask = mask;
+            st.mode = e == 4 ? 1 : (e == 2 ? 2 : (e == 6 ? 3 : 0));
+            if (st.mode == 0) {
+                Recipe rc;
+                rc.type = Recipe::VALUE;
+                const double a = std::atan2(1.0, 1.0) * e;  // pi/4 * e
+                rc.value = cd(std::cos(a), std::sin(a));
+                if (e == 1) rc.value = cd(std::sqrt(0.5), std::sqrt(0.5));
+                if (e == 7) rc.value = cd(std::sqrt(0.5), -std::sqrt(0.5));
+                if (e == 3) rc.value = cd(-std::sqrt(0.5), std::sqrt(0.5));
+                if (e == 5) rc.value = cd(-std::sqrt(0.5), -std::sqrt(0.5));
+                add_recipe(out, rc, ir);
+                st.recipe = (int)out.recipes.size() - 1;
+            }
+            out.steps.push_back(st);
+            out.n_diag++;
+            out.flops += 2.0 * N / (double)(1ull << popc(mask));
+            continue;
+        }
+        int order[6];
+        for (int t = 0; t < g.k; ++t) order[t] = t;
+        std::sort(order, order + g.k, [&](int x, int y) { return g.q[x] < g.q[y]; });
+        if (g.kind == K_DIAGG) {
+            // one entry differs from 1 for every state -> masked multiply
+            const int d = g.m.d;
+            bool unit = true;
+            for (int b = 0; b < g.m.nb && unit; ++b)
+                for (int i = 0; i + 1 < d; ++i)
+                    if (g.m.at(b)[i] != cd(1.0, 0.0)) { unit = false; break; }
+            Recipe rc;
+            rc.gate = (int)id;
+            rc.k = g.k;
+            for (int j = 0; j < g.k; ++j) { rc.perm[j] = order[j]; st.tq[j] = g.q[order[j]]; }
+            st.k = g.k;
+            if (unit) {
+                st.type = ST_MASKED;
+                st.mask = g.qmask();
+                st.mode = 0;
+                rc.type = Recipe::VALUE;
+                rc.value = cd(0.0, 0.0);  // taken from the gate per state (last entry)
+                rc.varies = g.m.nb > 1;
+                rc.k = -1;                // marks "last diagonal entry of gate"
+            } else {
+                st.type = ST_DIAG;
+                rc.type = Recipe::DIAG;
+            }
+            add_recipe(out, rc, ir);
+            st.recipe = (int)out.recipes.size() - 1;
+            out.steps.push_back(st);
+            out.n_diag++;
+            out.flops += 6.0 * N;
+            continue;
+        }
+        if (g.perm != PK_NONE) {
+            st.type = ST_SWAP;
+            if (g.perm == PK_X || g.perm == PK_Y) {
+                st.mask = 1ull << g.q[0];
+                st.ones = 0;
+                st.flip = 1ull << g.q[0];
+                st.mode = g.perm == PK_Y ? 1 : 0;
+            } else if (g.perm == PK_CNOT) {
+                st.mask = 1ull << g.q[1];
+                st.ones = 1ull << g.q[0];
+                st.flip = 1ull << g.q[1];
+            } else {
+                st.mask = 1ull << g.q[1];
+                st.ones = 1ull << g.q[0];
+                st.flip = (1ull << g.q[0]) | (1ull << g.q[1]);
+            }
+            out.steps.push_back(st);
+            out.n_plain++;
+            continue;
+        }
+        st.type = ST_DENSE;
+        Recipe rc;
+        rc.type = Recipe::DENSE;
+        rc.gate = (int)id;
+        rc.k = g.k;
+        for (int j = 0; j < g.k; ++j) { rc.perm[j] = order[j]; st.tq[j] = g.q[order[j]]; }
+        st.k = g.k;
+        add_recipe(out, rc, ir);
+        st.recipe = (int)out.recipes.size() - 1;
+        out.steps.push_back(st);
+        out.n_plain++;
+        out.n_dense++;
+        out.flops += 8.0 * (double)(1 << g.k) * N;
+    }
+    out.ngrad_total = grad_slot;
+}
+
+namespace {
+template <class R>
+void fill_pool_t(const EncodedPlan& p, const std::vector<IRGate>& ir, int batch, std::vector<unsigned char>& bytes) {
+    const int nb = p.pool_varies ? batch : 1;
+    bytes.assign((size_t)nb * p.pool_size * 2 * sizeof(R), 0);
+    R* base = reinterpret_cast<R*>(bytes.data());
+    const double c = std::sqrt(0.5);
+    const cd tab[8] = {cd(1, 0), cd(c, c), cd(0, 1), cd(-c, c), cd(-1, 0), cd(-c, -c), cd(0, -1), cd(c, -c)};
+    for (int b = 0; b < nb; ++b) {
+        R* pb = base + (size_t)b * p.pool_size * 2;
+        for (const Recipe& rc : p.recipes) {
+            R* dst = pb + rc.off * 2;
+            switch (rc.type) {
+                case Recipe::PHASETAB:
+                    for (int e = 0; e < 8; ++e) { dst[2 * e] = (R)tab[e].real(); dst[2 * e + 1] = (R)tab[e].imag(); }
+                    break;
+                case Recipe::SCALE:
+                    dst[0] = (R)rc.scale;
+                    dst[1] = 0;
+                    break;
+                case Recipe::VALUE: {
+                    cd v = rc.value;
+                    if (rc.k == -1) {
+                        const IRGate& g = ir[rc.gate];
+                        v = g.m.at(b)[g.m.d - 1];
+                    }
+                    dst[0] = (R)v.real();
+                    dst[1] = (R)v.imag();
+                    break;
+                }
+                case Recipe::DENSE: {
+                    const IRGate& g = ir[rc.gate];
+                    const int d = 1 << rc.k;
+                    const cd* m = g.m.at(b);
+                    for (int r = 0; r < d; ++r)
+                        for (int col = 0; col < d; ++col) {
+                            int orr = 0, oc = 0;
+                            for (int j = 0; j < rc.k; ++j) {
+                                if ((r >> j) & 1) orr |= 1 << rc.perm[j];
+                                if ((col >> j) & 1) oc |= 1 << rc.perm[j];
+                            }
+                            const cd v = m[(size_t)orr * d + oc];
+                            dst[2 * (r * d + col)] = (R)v.real();
+                            dst[2 * (r * d + col) + 1] = (R)v.imag();
+                        }
+                    break;
+                }
+                case Recipe::DIAG: {
+                    const IRGate& g = ir[rc.gate];
+                    const int d = 1 << rc.k;
+                    const cd* m = g.m.at(b);
+                    for (int r = 0; r < d; ++r) {
+                        int orr = 0;
+                        for (int j = 0; j < rc.k; ++j)
+                            if ((r >> j) & 1) orr |= 1 << rc.perm[j];
+                        dst[2 * r] = (R)m[orr].real();
+                        dst[2 * r + 1] = (R)m[orr].imag();
+                    }
+                    break;
+                }
+            }
+        }
+    }
+}
+}  // namespace
+
+void fill_pool(const EncodedPlan& p, const std::vector<IRGate>& ir, int batch, std::vector<unsigned char>& bytes) {
+    if (p.cfg.dtype == SV_C64) fill_pool_t<float>(p, ir, batch, bytes);
+    else fill_pool_t<double>(p, ir, batch, bytes);
+}
+
+}  // namespace svmi

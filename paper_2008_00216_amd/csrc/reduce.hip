@@ -1,0 +1,182 @@
+// FP64 reductions over the state: the norm check of Sec. 4.1 (accumulated in
+// double precision, as the paper recommends for a float state), inner
+// products, Pauli-sum expectations and lambda = H psi for the adjoint sweep.
+//
+// Every reduction uses a fixed grid and a fixed tree, so results are
+// bit-reproducible run to run.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace svmi {
+
+namespace {
+
+constexpr int kRB = 256;         // threads per reduction block
+constexpr uint32_t kMaxRBlk = 512; // blocks per state
+
+inline uint32_t nblk_for(int n) {
+    const uint64_t N = 1ull << n;
+    uint64_t b = (N + 4 * kRB - 1) / (4 * kRB);
+    if (b > kMaxRBlk) b = kMaxRBlk;
+    if (b < 1) b = 1;
+    return (uint32_t)b;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((tid & 63) == 0) sh[tid >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (tid == 0) {
+#pragma unroll
+        for (int w = 0; w < kRB / 64; ++w) s += sh[w];
+    }
+    return s;
+}
+
+template <class R>
+__device__ __forceinline__ double term_value(const PauliDev& pd, uint64_t j, const V2<R>* psi, double ar,
+                                             double ai) {
+    double acc = 0.0;
+    for (uint32_t g = 0; g < pd.ngroup; ++g) {
+        const uint64_t x = pd.x[g];
+        const uint64_t jx = j ^ x;
+        const V2<R> bq = psi[jx];
+        const double br = bq.x, bi = bq.y;
+        const double pr = ar * br + ai * bi;   // Re conj(a) b
+        const double pi = ar * bi - ai * br;   // Im conj(a) b
+        const uint32_t t1 = pd.g0[g + 1];
+        for (uint32_t t = pd.g0[g]; t < t1; ++t) {
+            const double s = (__popcll(jx & pd.z[t]) & 1) ? -1.0 : 1.0;
+            const uint32_t ph = pd.ph[t];
+            const double v = (ph & 1) ? pi : pr;
+            const double sg = (ph == 1 || ph == 2) ? -1.0 : 1.0;
+            acc += pd.c[t] * s * sg * v;
+        }
+    }
+    return acc;
+}
+
+template <class R>
+__global__ __launch_bounds__(kRB) void k_reduce(int kind, const V2<R>* __restrict__ a,
+                                                const V2<R>* __restrict__ b2, uint64_t bstride, uint64_t N,
+                                                PauliDev pd, int gen, uint64_t gmask,
+                                                double* __restrict__ partials) {
+    __shared__ double sh[kRB / 64];
+    const uint32_t b = blockIdx.y;
+    const V2<R>* pa = a + (uint64_t)b * bstride;
+    const V2<R>* pb = b2 ? b2 + (uint64_t)b * bstride : nullptr;
+    double acc = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * kRB;
+    for (uint64_t j = (uint64_t)blockIdx.x * kRB + threadIdx.x; j < N; j += stride) {
+        const V2<R> v = pa[j];
+        const double vr = v.x, vi = v.y;
+        if (kind == 0) {
+            acc += vr * vr + vi * vi;
+        } else if (kind == 1) {
+            const V2<R> w = pb[j];
+            acc += vr * (double)w.x + vi * (double)w.y;
+        } else if (kind == 2) {
+            acc += term_value<R>(pd, j, pa, vr, vi);
+        } else {
+            // Im <lambda|G|psi>: a = psi, b = lambda
+            const V2<R> l = pb[j];
+            const double lr = l.x, li = l.y;
+            if (gen == GEN_Z) {
+                const double s = (j & gmask) ? -1.0 : 1.0;
+                acc += s * (lr * vi - li * vr);
+            } else if (gen == GEN_P11) {
+                if ((j & gmask) == gmask) acc += -2.0 * (lr * vi - li * vr);
+            } else {
+                const V2<R> w = pa[j ^ gmask];
+                const double wr = w.x, wi = w.y;
+                if (gen == GEN_X) {
+                    acc += lr * wi - li * wr;
+                } else {  // Y: (Y psi)_j = -+ i psi_{j^m}
+                    const double s = (j & gmask) ? 1.0 : -1.0;
+                    acc += s * (lr * wr + li * wi);
+                }
+            }
+        }
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[(uint64_t)b * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ void k_final(const double* __restrict__ partials, uint32_t nb, double* __restrict__ out,
+                        uint64_t out_stride) {
+    const uint32_t b = blockIdx.x;
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (uint32_t i = 0; i < nb; ++i) s += partials[(uint64_t)b * nb + i];
+        out[(uint64_t)b * out_stride] = s;
+    }
+}
+
+template <class R>
+__global__ __launch_bounds__(kRB) void k_hpsi(const V2<R>* __restrict__ psi, V2<R>* __restrict__ lam,
+                                              uint64_t bstride, uint64_t N, PauliDev pd) {
+    const uint64_t j = (uint64_t)blockIdx.x * kRB + threadIdx.x;
+    const uint32_t b = blockIdx.y;
+    if (j >= N) return;
+    const V2<R>* p = psi + (uint64_t)b * bstride;
+    double lr = 0.0, li = 0.0;
+    for (uint32_t g = 0; g < pd.ngroup; ++g) {
+        const uint64_t jx = j ^ pd.x[g];
+        const V2<R> v = p[jx];
+        const double vr = v.x, vi = v.y;
+        const uint32_t t1 = pd.g0[g + 1];
+        for (uint32_t t = pd.g0[g]; t < t1; ++t) {
+            const double s = ((__popcll(jx & pd.z[t]) & 1) ? -1.0 : 1.0) * pd.c[t];
+            // multiply (vr + i vi) by s * i^{ph}
+            const uint32_t ph = pd.ph[t];
+            double xr = vr, xi = vi;
+            if (ph & 1) { const double tmp = xr; xr = -xi; xi = tmp; }
+            if (ph & 2) { xr = -xr; xi = -xi; }
+            lr += s * xr;
+            li += s * xi;
+        }
+    }
+    lam[(uint64_t)b * bstride + j] = V2<R>{R(lr), R(li)};
+}
+
+}  // namespace
+
+size_t reduce_partials_size(int n, int batch) { return (size_t)nblk_for(n) * (size_t)batch; }
+
+hipError_t launch_reduce(int dtype, int kind, const void* a, const void* b, uint64_t bstride, int batch, int n,
+                         const PauliDev* pd, int gen, uint64_t gmask, double* partials, double* out,
+                         uint64_t out_stride, hipStream_t s) {
+    const uint32_t nb = nblk_for(n);
+    const uint64_t N = 1ull << n;
+    PauliDev p{};
+    if (pd) p = *pd;
+    const dim3 g(nb, (uint32_t)batch);
+    if (dtype == 1)
+        hipLaunchKernelGGL(k_reduce<float>, g, dim3(kRB), 0, s, kind, reinterpret_cast<const V2<float>*>(a),
+                           reinterpret_cast<const V2<float>*>(b), bstride, N, p, gen, gmask, partials);
+    else
+        hipLaunchKernelGGL(k_reduce<double>, g, dim3(kRB), 0, s, kind, reinterpret_cast<const V2<double>*>(a),
+                           reinterpret_cast<const V2<double>*>(b), bstride, N, p, gen, gmask, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_final, dim3((uint32_t)batch), dim3(64), 0, s, partials, nb, out, out_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_hpsi(int dtype, const void* psi, void* lam, uint64_t bstride, int batch, int n,
+                       const PauliDev& pd, hipStream_t s) {
+    const uint64_t N = 1ull << n;
+    const dim3 g((uint32_t)((N + kRB - 1) / kRB), (uint32_t)batch);
+    if (dtype == 1)
+        hipLaunchKernelGGL(k_hpsi<float>, g, dim3(kRB), 0, s, reinterpret_cast<const V2<float>*>(psi),
+                           reinterpret_cast<V2<float>*>(lam), bstride, N, pd);
+    else
+        hipLaunchKernelGGL(k_hpsi<double>, g, dim3(kRB), 0, s, reinterpret_cast<const V2<double>*>(psi),
+                           reinterpret_cast<V2<double>*>(lam), bstride, N, pd);
+    return hipGetLastError();
+}
+
+}  // namespace svmi

@@ -1,0 +1,189 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: complex64 max-abs 1e-5 and L2 1e-4, complex128 max-abs and L2
+1e-12; sign/permutation-only circuits must agree exactly (numeric equality,
+so +0 and -0 compare equal)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from tests.gpu_util import check_close, round_c64, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+def lib():
+    import paper_2008_00216_amd as m
+    return m
+
+
+DTYPES = [torch.complex64, torch.complex128]
+ALL_OPS = ("H", "X", "Y", "Z", "S", "SDG", "T", "TDG", "SQRTX", "SQRTY", "SQRTW",
+           "SQRTXDG", "SQRTYDG", "SQRTWDG", "RX", "RY", "RZ", "P", "CZ", "CNOT", "SWAP", "CP")
+EXACT_OPS = ("X", "Y", "Z", "S", "SDG", "CZ", "CNOT", "SWAP")
+
+
+def run(circ, psi0, dtype, params=None, **opts):
+    m = lib()
+    t = to_dev(psi0, dtype)
+    s = m.StateVector(circ.n, dtype, batch=t.shape[0], tensor=t, opts=m.make_opts(**opts))
+    st = s.apply(circ, params)
+    out = to_host(t)
+    s.close()
+    return out, st
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_init_kinds(dtype):
+    m = lib()
+    n = 9
+    s = m.StateVector(n, dtype)
+    s.init("zero")
+    got = to_host(s.tensor)[0]
+    assert got[0] == 1 and np.count_nonzero(got) == 1
+    s.init("basis", 301)
+    got = to_host(s.tensor)[0]
+    assert got[301] == 1 and np.count_nonzero(got) == 1
+    s.init("uniform")
+    got = to_host(s.tensor)[0]
+    np.testing.assert_allclose(got, np.full(1 << n, 2.0 ** (-n / 2)), rtol=1e-7 if dtype == torch.complex64 else 1e-15)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("op", ALL_OPS)
+def test_single_gate_plain_and_fused(dtype, op):
+    n = 10
+    rng = np.random.default_rng(sum(map(ord, op)))
+    k = W.ARITY[op]
+    for trial in range(3):
+        qs = tuple(int(x) for x in rng.permutation(n)[:k])
+        if trial == 1:
+            qs = tuple(range(n - k, n)) if k == 1 else (n - 1, 0)    # highest / straddling
+        g = W.Gate(op, qs, theta=0.7317 if op in W.PARAMETRIC else 0.0)
+        c = W.Circuit(n, [g])
+        psi0 = round_c64(W.random_state(n, trial + 3))
+        ref = oracle.simulate(c, psi0=psi0)
+        for plain in (1, 0):
+            got, _ = run(c, psi0, dtype, plain=plain)
+            if op in EXACT_OPS:
+                assert np.array_equal(got[0], ref), f"{op} {qs} plain={plain} not exact"
+            else:
+                check_close(got[0], ref, dtype, f"{op} {qs} plain={plain}")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("seed", range(4))
+def test_random_circuits_fused(dtype, seed):
+    n = [6, 9, 14, 16][seed]
+    c = W.random_circuit(n, 150, seed, ops=ALL_OPS, mat_k=(1, 2, 3, 4))
+    params = W.uniform_params(1, c.n_params, seed)[0]
+    psi0 = round_c64(W.random_state(n, seed + 11))
+    ref = oracle.simulate(c, params, psi0)
+    for structured in (1, 0):
+        got, st = run(c, psi0, dtype, params, structured=structured)
+        check_close(got[0], ref, dtype, f"random n={n} structured={structured}")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_wide_matrix_gates(dtype):
+    n = 12
+    c = W.random_circuit(n, 20, 5, ops=("H", "CZ", "T"), mat_k=(5, 6))
+    psi0 = round_c64(W.random_state(n, 2))
+    ref = oracle.simulate(c, psi0=psi0)
+    got, _ = run(c, psi0, dtype)
+    check_close(got[0], ref, dtype, "k=5,6 matrices")
+
+
+@pytest.mark.parametrize("plain", [1, 0])
+def test_exact_circuits_bit_exact(plain):
+    for seed in range(3):
+        n = 13
+        c = W.random_circuit(n, 300, seed, ops=EXACT_OPS)
+        psi0 = round_c64(W.random_state(n, seed))
+        ref = oracle.simulate(c, psi0=psi0)
+        got, _ = run(c, psi0, torch.complex64, plain=plain)
+        assert np.array_equal(got[0], ref), f"seed {seed}: sign/perm circuit not exact"
+
+
+@pytest.mark.parametrize("tile_bits,low_bits", [(13, 5), (12, 4), (14, 7), (10, 3)])
+def test_tile_geometries(tile_bits, low_bits):
+    c = W.grid_circuit(3, 6, 6, seed=9)
+    n = c.n
+    ref = oracle.simulate(c)
+    for dtype in DTYPES:
+        if dtype == torch.complex128 and tile_bits > 13:
+            continue
+        got, st = run(c, np.eye(1, 1 << n, 0)[0].astype(np.complex128), dtype, tile_bits=tile_bits,
+                      low_bits=low_bits, product_init=0)
+        check_close(got[0], ref, dtype, f"T={tile_bits} L={low_bits}")
+
+
+def test_line_circuit_gate_by_gate_c128():
+    c = W.line_circuit()
+    ref = oracle.simulate(c)
+    m = lib()
+    s = m.StateVector(c.n, torch.complex128, opts=m.make_opts(plain=1))
+    s.init("zero")
+    st = s.apply(c)
+    got = to_host(s.tensor)[0]
+    check_close(got, ref, torch.complex128, "line circuit plain")
+    assert st["launches"] >= 170
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_grid_product_init(dtype):
+    c = W.grid_circuit(4, 5, 8, seed=3)
+    ref = oracle.simulate(c)
+    m = lib()
+    s = m.StateVector(c.n, dtype)
+    s.init("zero")
+    st = s.apply(c)
+    got = to_host(s.tensor)[0]
+    check_close(got, ref, dtype, "grid 20q")
+    assert st["folded_init"] >= c.n
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_batch_of_states(dtype):
+    n = 12
+    c = W.ansatz_circuit(n, 3)
+    B = 5
+    params = W.uniform_params(B, c.n_params, 4)
+    psi0 = np.stack([round_c64(W.random_state(n, 20 + b)) for b in range(B)])
+    got, _ = run(c, psi0, dtype, params)
+    for b in range(B):
+        ref = oracle.simulate(c, params[b], psi0[b])
+        check_close(got[b], ref, dtype, f"batch {b}")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_norm_and_expect(dtype):
+    m = lib()
+    n = 14
+    B = 3
+    psi0 = np.stack([round_c64(W.random_state(n, 40 + b)) for b in range(B)])
+    t = to_dev(psi0, dtype)
+    s = m.StateVector(n, dtype, batch=B, tensor=t)
+    h = W.pauli_sum([(0.7, {0: "Z", 5: "Z"}), (-1.3, {3: "X"}), (0.25, {2: "Y", 9: "X", 13: "Z"}),
+                     (0.5, {}), (1.1, {1: "Y"})])
+    nrm = s.norm()
+    e = s.expect(h)
+    tol = 1e-6 if dtype == torch.complex64 else 1e-12
+    for b in range(B):
+        x = psi0[b] if dtype == torch.complex128 else psi0[b]
+        assert abs(nrm[b] - oracle.norm2(x)) < tol
+        assert abs(e[b] - oracle.expect(x, h)) < tol
+
+
+def test_mirror_returns_to_zero():
+    c = W.grid_circuit(3, 5, 12, seed=7)
+    mirror = W.concat(c, W.inverse(c))
+    m = lib()
+    s = m.StateVector(c.n, torch.complex64)
+    s.init("zero")
+    s.apply(mirror)
+    got = to_host(s.tensor)[0]
+    assert abs(got[0] - 1) < 1e-5 and np.max(np.abs(got[1:])) < 1e-5
