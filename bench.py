@@ -1,0 +1,227 @@
+#!/usr/bin/env python
+"""Benchmark: Schroedinger sweep of the 33-qubit 3x11 grid circuit (40 cycles,
+1873 gates) in complex64 on one MI355X, plus the adjoint-gradient leg (20
+qubits, 400 parameters, 64 parameter sets) against finite differences with
+the plain per-gate kernels.
+
+A step = initialise |0...0> + apply the whole circuit + the FP64 norm check,
+with the 64 GiB state resident in HBM.  Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E, GB/s
+FP32_VALU_PEAK_TFLOPS = 78.6          # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA), no packed FP32
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--qubits", type=int, default=33, help="grid 3 x (qubits/3); 33 = headline")
+    p.add_argument("--cycles", type=int, default=40)
+    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--no-adjoint", action="store_true")
+    p.add_argument("--calib-copy-gib", type=float, default=0.0,
+                   help="run a device copy of this size first (counter calibration)")
+    p.add_argument("--structured", type=int, default=1)
+    p.add_argument("--tile-bits", type=int, default=0)
+    p.add_argument("--low-bits", type=int, default=0)
+    p.add_argument("--threads", type=int, default=0)
+    return p.parse_args()
+
+
+def cpu_baseline(circ, budget_s=20.0):
+    """The FP64 oracle on the host cores, on a cut of the same circuit: the
+    first `cut` qubits (gates entirely inside them).  Reported as amplitude
+    updates/s and as the equivalent gates/s at the full width."""
+    import numpy as np
+    import oracle
+    nthreads = oracle.max_threads()
+    cut = 24
+    sub = circ.cut(cut)
+    # time a prefix of the cut circuit, bounded by budget_s
+    psi = np.zeros(1 << cut, np.complex128)
+    psi[0] = 1.0
+    t0 = time.time()
+    done = 0
+    for g in sub.gates:
+        oracle.apply_matrix(psi, cut, g.qubits, oracle.gate_matrix(g, None), nthreads)
+        done += 1
+        if time.time() - t0 > budget_s:
+            break
+    dt = time.time() - t0
+    amp_updates = done * (1 << cut) / dt
+    return {
+        "value": amp_updates / float(1 << circ.n),
+        "unit": "gates/s (33-qubit equivalent)",
+        "amp_updates_per_s": amp_updates,
+        "cores": nthreads,
+        "kind": "oracle",
+        "sample": f"FP64 oracle, gate by gate, first {done} gates of the {cut}-qubit cut (qubits 0-{cut - 1}) "
+                  f"of the same grid circuit, {dt:.1f} s on {nthreads} threads; value = amp-updates/s / 2^{circ.n}",
+    }
+
+
+def adjoint_leg(sv, W, torch, np):
+    """cfg: 20 qubits, 10 layers RY/RZ + CZ ladder, 400 params, batch 64."""
+    n, B = 20, 64
+    c = W.ansatz_circuit(n, 10)
+    h = W.ansatz_observable(n)
+    th = W.uniform_params(B, c.n_params, 3003)
+    s = sv.StateVector(n, torch.complex64, batch=B)
+    scratch = torch.empty_like(s.tensor)
+    # warm up (plans)
+    s.init("zero")
+    s.adjoint_grad(c, th, h, scratch)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.time()
+    for _ in range(reps):
+        s.init("zero")
+        e, g = s.adjoint_grad(c, th, h, scratch)
+    torch.cuda.synchronize()
+    t_adj = (time.time() - t0) / reps
+    # finite differences with the plain per-gate kernels on the same GPU
+    sp = sv.StateVector(n, torch.complex64, batch=B, opts=sv.make_opts(plain=1))
+    hstep = 1e-3
+    sample = [0, 137, 262, 399]
+    sp.init("zero"); sp.apply(c, th); sp.expect(h)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    fd = np.zeros((B, len(sample)))
+    for j, p in enumerate(sample):
+        vals = []
+        for sgn in (1, -1):
+            tt = th.copy()
+            tt[:, p] += sgn * hstep
+            sp.init("zero")
+            sp.apply(c, tt)
+            vals.append(sp.expect(h))
+        fd[:, j] = (vals[0] - vals[1]) / (2 * hstep)
+    t_fd_sample = time.time() - t0
+    t_fd_full = t_fd_sample / len(sample) * c.n_params      # 2 sweeps per parameter
+    err_fd = float(np.max(np.abs(g[:, sample] - fd)))
+    return {
+        "workload": "ansatz20q-10layers-400params-batch64-c64",
+        "adjoint_s": t_adj,
+        "grad_vectors_per_s": B / t_adj,
+        "param_grads_per_s": B * c.n_params / t_adj,
+        "fd_plain_s_extrapolated": t_fd_full,
+        "fd_sample": f"{len(sample)} params x 2 plain sweeps x {B} sets, h={hstep}",
+        "speedup_vs_fd_plain": t_fd_full / t_adj,
+        "max_abs_diff_vs_fd": err_fd,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(every GPU box here has a single MI355X).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2008_00216_amd as sv
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    if args.calib_copy_gib > 0:
+        nb = int(args.calib_copy_gib * (1 << 30))
+        a = torch.empty(nb // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        torch.cuda.empty_cache()
+
+    cols = args.qubits // 3
+    circ = W.grid_circuit(3, cols, args.cycles, seed=1002)
+    n = circ.n
+    opts = sv.make_opts(timing=1, structured=args.structured, tile_bits=args.tile_bits,
+                        low_bits=args.low_bits, threads=args.threads)
+    s = sv.StateVector(n, torch.complex64, opts=opts)
+    cabi = sv.CircuitABI(circ)
+    st = None
+    for _ in range(args.warmup):
+        s.init("zero")
+        st = s.apply(cabi)
+        s.norm()
+    s.timing()  # reset counters
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    norms = []
+    for _ in range(args.steps):
+        s.init("zero")
+        st = s.apply(cabi)
+        norms.append(float(s.norm()[0]))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tile_ms, tile_launches, tile_bytes = s.timing()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    gates = len(circ.gates)
+    gates_per_s = gates / (ms_per_step / 1e3)
+    amp_upd = gates * float(1 << n) / (ms_per_step / 1e3)
+
+    per_launch_ms = tile_ms / max(1, tile_launches)
+    bytes_per_launch = tile_bytes / max(1, tile_launches)
+    achieved_gbs = bytes_per_launch / (per_launch_ms / 1e3) / 1e9
+    flops_tile = st["flops"]                       # algorithmic flops of the sweep (all tile passes)
+    achieved_tf = flops_tile * args.steps / (tile_ms / 1e3) / 1e12
+    hbm_frac = achieved_gbs / HBM_PEAK_GBS
+    alu_frac = achieved_tf / FP32_VALU_PEAK_TFLOPS
+    roofline_hbm = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(hbm_frac, 4), "traffic": None}
+    roofline_alu = {"bound": "alu", "achieved": round(achieved_tf, 2), "peak": FP32_VALU_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(alu_frac, 4)}
+    roofline = roofline_hbm if hbm_frac >= alu_frac else dict(roofline_alu, traffic=None)
+
+    out = {
+        "metric": "gates/s & %HBM peak at 33q complex64; adjoint grads/s vs plain at stated error",
+        "value": gates_per_s,
+        "unit": "gates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": f"grid3x{cols}-{args.cycles}cycles-{n}q-c64", "qubits": n, "gates": gates,
+                   "state_gib": (1 << n) * 8 / 2 ** 30, "parallelism": "1 GPU"},
+        "amp_updates_per_s": amp_upd,
+        "passes": st["passes"], "phases": st["phases"], "plan_ms_first": None,
+        "sweep_hbm_bytes": st["hbm_bytes"],
+        "sweep_GBps_algorithmic": st["hbm_bytes"] / (ms_per_step / 1e3) / 1e9,
+        "hbm_frac_whole_step": st["hbm_bytes"] / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS,
+        "tile_kernel": {"launches": tile_launches, "avg_ms": per_launch_ms,
+                        "bytes_per_launch": bytes_per_launch},
+        "roofline": roofline,
+        "roofline_hbm": roofline_hbm,
+        "roofline_alu": roofline_alu,
+        "norm_error": max(abs(x - 1.0) for x in norms),
+    }
+    del s
+    torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(sv, W, torch, np)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(circ)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

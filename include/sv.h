@@ -113,7 +113,9 @@ typedef struct {
     int32_t threads;       /* workgroup size of tile passes, 0 = default */
     int32_t product_init;  /* 1 = fold leading one-qubit gates into the init of |0..0> */
     int32_t structured;    /* 1 = multiply-free kernels for +-1/+-i structured gates */
-    int32_t reserved[5];
+    int32_t timing;        /* 1 = time every tile-pass launch with HIP events (sv_timing) */
+    int32_t jit;           /* run-time specialised tile passes: 0 auto (n >= 18), 1 always, -1 never */
+    int32_t reserved[3];
 } sv_opts;
 
 typedef struct {
@@ -203,6 +205,19 @@ enum { SV_BATCH_FORWARD = 1, SV_BATCH_GRAD = 2, SV_BATCH_INIT_ZERO = 4 };
 sv_status sv_apply_batch(int32_t count, const sv_batch_item* items, sv_dtype dtype,
                          void* hip_stream, int32_t flags, double* energies, double* grads,
                          const sv_opts* opts, sv_stats* stats);
+
+/* Accumulated tile-pass kernel time since the last call (needs opts.timing):
+ * total milliseconds, number of launches and the algorithmic HBM bytes of
+ * those launches (one read and one write of every amplitude per launch).
+ * Synchronises the stream and resets the counters. */
+sv_status sv_timing(sv_ctx ctx, double* tile_ms, int64_t* tile_launches, double* tile_bytes);
+
+/* Plan a circuit on the host only (no device work) and report its shape in
+ * *stats (passes, phases, dense/diagonal ops, plan time, algorithmic bytes
+ * and flops for one state).  `adjoint` = 1 plans the backward sweep.
+ * Usable without a GPU. */
+sv_status sv_plan_info(const sv_circuit* circuit, sv_dtype dtype, int32_t adjoint, const sv_opts* opts,
+                       sv_stats* stats);
 
 /* Wait for the context's stream and report any device error. */
 sv_status sv_sync(sv_ctx ctx);

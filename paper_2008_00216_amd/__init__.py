@@ -60,7 +60,7 @@ class SvOpts(ctypes.Structure):
     _fields_ = [("max_fuse_k", ctypes.c_int32), ("tile_bits", ctypes.c_int32),
                 ("low_bits", ctypes.c_int32), ("plain", ctypes.c_int32), ("threads", ctypes.c_int32),
                 ("product_init", ctypes.c_int32), ("structured", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("timing", ctypes.c_int32), ("jit", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class SvStats(ctypes.Structure):
@@ -98,13 +98,16 @@ _lib.sv_adjoint_grad.argtypes = [_vp, ctypes.POINTER(SvCircuit), _dp, ctypes.POI
 _lib.sv_apply_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(SvBatchItem), ctypes.c_int32, _vp, ctypes.c_int32,
                                 _dp, _dp, ctypes.POINTER(SvOpts), ctypes.POINTER(SvStats)]
 _lib.sv_sync.argtypes = [_vp]
+_lib.sv_timing.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_int64), _dp]
+_lib.sv_plan_info.argtypes = [ctypes.POINTER(SvCircuit), ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(SvOpts),
+                              ctypes.POINTER(SvStats)]
 for _f in ("sv_create", "sv_destroy", "sv_set_stream", "sv_set_opts", "sv_init", "sv_apply_circuit",
-           "sv_expect", "sv_norm", "sv_adjoint_grad", "sv_apply_batch", "sv_sync"):
+           "sv_expect", "sv_norm", "sv_adjoint_grad", "sv_apply_batch", "sv_sync", "sv_timing", "sv_plan_info"):
     getattr(_lib, _f).restype = ctypes.c_int32
 
 EXPORTED = ("sv_opts_default", "sv_create", "sv_destroy", "sv_set_stream", "sv_set_opts", "sv_init",
             "sv_apply_circuit", "sv_expect", "sv_norm", "sv_adjoint_grad", "sv_apply_batch", "sv_sync",
-            "sv_last_error", "sv_version")
+            "sv_timing", "sv_plan_info", "sv_last_error", "sv_version")
 
 
 class SvError(RuntimeError):
@@ -280,6 +283,24 @@ class StateVector:
 
     def sync(self):
         _check(_lib.sv_sync(self._h))
+
+    def timing(self):
+        """(tile-pass ms, launches, algorithmic bytes) since the last call."""
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        by = ctypes.c_double()
+        _check(_lib.sv_timing(self._h, ctypes.byref(ms), ctypes.byref(cnt), ctypes.byref(by)))
+        return ms.value, cnt.value, by.value
+
+
+def plan_info(circ, dtype=torch.complex64, adjoint=False, opts: Optional[SvOpts] = None) -> dict:
+    """Host-only planning statistics (no GPU needed)."""
+    c = _as_circuit(circ)
+    st = SvStats()
+    o = opts if opts is not None else make_opts()
+    _check(_lib.sv_plan_info(ctypes.byref(c.c), SV_C64 if dtype == torch.complex64 else SV_C128,
+                             1 if adjoint else 0, ctypes.byref(o), ctypes.byref(st)))
+    return st.as_dict()
 
 
 def apply_batch(circuits: Sequence, params: Sequence, states: Sequence[torch.Tensor],

@@ -32,13 +32,32 @@ def _compile(src):
     return obj
 
 
+JIT_HEADERS = ("device_common", "plan", "tile_ops", "tile_frame")
+
+
+def _embed_headers():
+    """Headers compiled again at run time by hiprtc, embedded as strings."""
+    out = os.path.join(BUILD, "jit_headers.cpp")
+    parts = []
+    for h in JIT_HEADERS:
+        text = open(os.path.join(CSRC, h + ".h")).read()
+        assert ")SVJIT\"" not in text
+        parts.append(f'extern "C" const char* svmi_jit_header_{h} = R"SVJIT({text})SVJIT";\n')
+    data = "".join(parts)
+    if not os.path.exists(out) or open(out).read() != data:
+        with open(out, "w") as f:
+            f.write(data)
+    return out
+
+
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
+    srcs.append(_embed_headers())
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = OUT + ".tmp"
-    cmd = ["hipcc", "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
+    cmd = ["hipcc", "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-lhiprtc"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

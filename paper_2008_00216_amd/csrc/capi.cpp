@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "host.h"
+#include "jit.h"
 #include "kernels.h"
 #include "sv.h"
 
@@ -59,6 +60,8 @@ struct DevBuf {
 struct CachedPlan {
     EncodedPlan ep;
     DevBuf dev;
+    std::shared_ptr<JitModule> jit;
+    bool jit_tried = false;
     size_t o_pass = 0, o_phase = 0, o_op = 0, o_form = 0, o_pair = 0, o_etab = 0;
     double plan_ms = 0.0;
 };
@@ -105,6 +108,14 @@ struct sv_ctx_s {
     DevBuf pool, red_part, red_out, pauli, gpart, gout, pinit;
     std::vector<unsigned char> pool_host;
     std::vector<double> host_out;
+    // tile-pass timing (opts.timing)
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<double> ev_bytes;
+    double t_ms = 0.0, t_bytes = 0.0;
+    int64_t t_count = 0;
+    ~sv_ctx_s() {
+        for (auto& e : ev) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    }
 };
 
 namespace {
@@ -138,7 +149,7 @@ uint64_t opts_key(const sv_ctx_s* c, bool two, bool pinit) {
     k ^= ((uint64_t)c->opts.max_fuse_k << 1) ^ ((uint64_t)c->opts.tile_bits << 9) ^
          ((uint64_t)c->opts.low_bits << 17) ^ ((uint64_t)c->opts.plain << 25) ^
          ((uint64_t)c->opts.threads << 27) ^ ((uint64_t)c->opts.structured << 40) ^
-         ((uint64_t)two << 42) ^ ((uint64_t)pinit << 43);
+         ((uint64_t)two << 42) ^ ((uint64_t)pinit << 43) ^ ((uint64_t)(c->opts.jit + 2) << 45);
     return k;
 }
 
@@ -200,6 +211,18 @@ sv_status run_plan(sv_ctx_s* c, CachedPlan& cp, const std::vector<IRGate>& ir, v
     const unsigned char* plan = reinterpret_cast<const unsigned char*>(cp.dev.p);
     void* states[2] = {psi, lam};
     const int nstates = lam ? 2 : 1;
+    // plan-specialised kernels for large states
+    if (!cp.jit_tried && !e.passes.empty()) {
+        cp.jit_tried = true;
+        bool eligible = jit_enabled() && c->opts.jit >= 0 && (c->opts.jit > 0 || c->n >= 18);
+        for (const DPass& P : e.passes)
+            if ((1u << (P.T - kRegBits)) < (uint32_t)e.cfg.nt) eligible = false;
+        if (eligible) {
+            std::string jerr;
+            cp.jit = jit_get(e, dt, lam != nullptr, e.cfg.nt, jerr);
+            if (!cp.jit && c->opts.jit > 0) return fail(SV_EDEVICE, "run-time specialisation failed: " + jerr);
+        }
+    }
     uint64_t gslot = 0;
     for (const Step& st : e.steps) {
         switch (st.type) {
@@ -224,7 +247,20 @@ sv_status run_plan(sv_ctx_s* c, CachedPlan& cp, const std::vector<IRGate>& ir, v
                 const uint64_t nblocks = (uint64_t)c->batch << (c->n - P.T);
                 const size_t lds = tile_lds_bytes(dt, lam != nullptr, P.T, P.nform, P.ngrad, e.cfg.nt);
                 if (lds > 160 * 1024) return fail(SV_EUNSUPPORTED, "tile pass needs more LDS than available");
-                HIPCHK(launch_tile_pass(dt, lam != nullptr, e.cfg.nt, a, nblocks, lds, c->stream));
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (c->opts.timing) {
+                    HIPCHK(hipEventCreate(&e0));
+                    HIPCHK(hipEventCreate(&e1));
+                    HIPCHK(hipEventRecord(e0, c->stream));
+                }
+                if (cp.jit) HIPCHK(jit_launch(*cp.jit, st.pass, a, nblocks, e.cfg.nt, lds, c->stream));
+                else HIPCHK(launch_tile_pass(dt, lam != nullptr, e.cfg.nt, a, nblocks, lds, c->stream));
+                if (c->opts.timing) {
+                    HIPCHK(hipEventRecord(e1, c->stream));
+                    c->ev.emplace_back(e0, e1);
+                    c->ev_bytes.push_back(2.0 * (double)ab * (double)c->batch * std::ldexp(1.0, c->n) *
+                                          (lam ? 2.0 : 1.0));
+                }
                 if (lam && P.ngrad) {
                     HIPCHK(launch_grad_reduce(reinterpret_cast<double*>(c->gpart.p) + P.gpart_off * c->batch,
                                               c->batch, 1ull << (c->n - P.T), P.ngrad, gout + gslot, gstride,
@@ -558,6 +594,74 @@ sv_status sv_adjoint_grad(sv_ctx c, const sv_circuit* circ, const double* params
         }
     }
     if (stats) stats->plan_ms += plan_ms;
+    return SV_OK;
+}
+
+sv_status sv_timing(sv_ctx c, double* tile_ms, int64_t* tile_launches, double* tile_bytes) {
+    if (!c) return fail(SV_EINVAL, "ctx is NULL");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < c->ev.size(); ++i) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, c->ev[i].first, c->ev[i].second));
+        c->t_ms += ms;
+        c->t_bytes += c->ev_bytes[i];
+        c->t_count += 1;
+        (void)hipEventDestroy(c->ev[i].first);
+        (void)hipEventDestroy(c->ev[i].second);
+    }
+    c->ev.clear();
+    c->ev_bytes.clear();
+    if (tile_ms) *tile_ms = c->t_ms;
+    if (tile_launches) *tile_launches = c->t_count;
+    if (tile_bytes) *tile_bytes = c->t_bytes;
+    c->t_ms = 0.0;
+    c->t_bytes = 0.0;
+    c->t_count = 0;
+    return SV_OK;
+}
+
+sv_status sv_plan_info(const sv_circuit* circ, sv_dtype dtype, int32_t adjoint, const sv_opts* opts,
+                       sv_stats* stats) {
+    if (!circ || !stats) return fail(SV_EINVAL, "circuit or stats is NULL");
+    if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "bad dtype");
+    std::string v = validate_circuit(circ, circ->n_qubits);
+    if (!v.empty()) return fail(SV_EINVAL, v);
+    sv_ctx_s c;
+    c.n = circ->n_qubits;
+    c.dtype = dtype;
+    c.batch = 1;
+    if (opts) c.opts = *opts; else sv_opts_default(&c.opts);
+    c.known_zero = !adjoint;
+    std::vector<double> params((size_t)std::max(1, circ->n_params), 0.0);
+    std::vector<IRGate> ir;
+    ProductInit pi;
+    BuildOpts bo;
+    bo.batch = 1;
+    bo.structured = c.opts.structured != 0 && !use_plain(&c);
+    bo.fuse = !use_plain(&c);
+    bo.backward = adjoint != 0;
+    bo.product_init = !adjoint && !use_plain(&c) && c.opts.product_init != 0;
+    auto t0 = std::chrono::steady_clock::now();
+    EncodedPlan ep;
+    try {
+        ir = build_ir(circ, params.data(), bo, &pi, c.n);
+        if (use_plain(&c)) plan_plain(ir, c.n, cfg_for(&c, adjoint != 0), ep);
+        else plan_fused(ir, c.n, cfg_for(&c, adjoint != 0), ep);
+    } catch (const std::exception& e) {
+        return fail(SV_EUNSUPPORTED, std::string("planning failed: ") + e.what());
+    }
+    CachedPlan cp;
+    cp.ep = std::move(ep);
+    const double plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (c.opts.jit > 0 && !use_plain(&c)) {
+        // compile the specialised kernels too (host only)
+        std::string jerr;
+        if (!jit_compile_only(cp.ep, dtype, adjoint != 0, cp.ep.cfg.nt, jerr))
+            return fail(SV_EUNSUPPORTED, "run-time specialisation failed: " + jerr);
+    }
+    fill_stats(stats, &c, cp, circ, 0.0, pi.folded, pi.used);
+    stats->plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    stats->reserved = (int32_t)plan_ms;
     return SV_OK;
 }
 

@@ -1,7 +1,18 @@
-// Shared device helpers for the HIP kernels (gfx950).
+// Shared device helpers for the HIP kernels (gfx950).  Also compiled at run
+// time by hiprtc for plan-specialised tile passes, so it avoids host headers
+// when __HIPCC_RTC__ is defined.
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#else
+typedef unsigned char uint8_t;
+typedef unsigned short uint16_t;
+typedef unsigned int uint32_t;
+typedef int int32_t;
+typedef unsigned long long uint64_t;
+typedef long long int64_t;
+#endif
 
 namespace svmi {
 
@@ -43,33 +54,45 @@ __host__ __device__ constexpr int dep4(int mask, int l) {
     return out;
 }
 
+// Extract the MASK bits of i into a dense index (compile time).
+__host__ __device__ constexpr int ext4(int mask, int i) {
+    int out = 0, t = 0;
+    for (int b = 0; b < 4; ++b)
+        if ((mask >> b) & 1) {
+            if ((i >> b) & 1) out |= 1 << t;
+            ++t;
+        }
+    return out;
+}
+
 // XOR-linear LDS swizzle (amplitude units).  It only flips low index bits
 // as a function of higher bits, so swz(a ^ b) == swz(a) ^ swz(b); the c64
 // variant keeps bit 0 so that the two amplitudes of a 16-byte chunk stay
 // adjacent.
 template <class R>
-__host__ __device__ inline uint32_t swz(uint32_t l);
+__host__ __device__ inline constexpr uint32_t swz(uint32_t l);
 template <>
-__host__ __device__ inline uint32_t swz<float>(uint32_t l) {
+__host__ __device__ inline constexpr uint32_t swz<float>(uint32_t l) {
     return l ^ ((((l >> 6) ^ (l >> 11)) & 31u) << 1);
 }
 template <>
-__host__ __device__ inline uint32_t swz<double>(uint32_t l) {
+__host__ __device__ inline constexpr uint32_t swz<double>(uint32_t l) {
     return l ^ (((l >> 4) ^ (l >> 8) ^ (l >> 12)) & 15u);
 }
 
 __device__ __forceinline__ uint32_t rfl(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Flip the sign of both parts of an amplitude when `flip` is 1 (exact).
-__device__ __forceinline__ void sign_flip(V2<float>& a, uint32_t flip) {
-    uint32_t m = flip << 31;
+// Flip the sign of both parts of an amplitude when bit 31 of `m` is set (exact).
+__device__ __forceinline__ void sign_flip_mask(V2<float>& a, uint32_t m) {
     a.x = __uint_as_float(__float_as_uint(a.x) ^ m);
     a.y = __uint_as_float(__float_as_uint(a.y) ^ m);
 }
-__device__ __forceinline__ void sign_flip(V2<double>& a, uint32_t flip) {
-    unsigned long long m = (unsigned long long)flip << 63;
-    a.x = __longlong_as_double(__double_as_longlong(a.x) ^ (long long)m);
-    a.y = __longlong_as_double(__double_as_longlong(a.y) ^ (long long)m);
+__device__ __forceinline__ void sign_flip_mask(V2<double>& a, uint32_t m) {
+    const long long mm = (long long)((unsigned long long)m << 32);
+    a.x = __longlong_as_double(__double_as_longlong(a.x) ^ mm);
+    a.y = __longlong_as_double(__double_as_longlong(a.y) ^ mm);
 }
+__device__ __forceinline__ void sign_flip(V2<float>& a, uint32_t flip) { sign_flip_mask(a, flip << 31); }
+__device__ __forceinline__ void sign_flip(V2<double>& a, uint32_t flip) { sign_flip_mask(a, flip << 31); }
 
 }  // namespace svmi

@@ -4,26 +4,11 @@
 #include <stdint.h>
 
 #include "plan.h"
+#include "tile_frame.h"
 
 namespace svmi {
 
-struct TileArgs {
-    void* state;             // batch element 0 of psi
-    void* lam;               // batch element 0 of lambda (adjoint sweep) or nullptr
-    const DPass* pass;
-    const DPhase* phases;
-    const DOp* ops;
-    const DForm* forms;
-    const DPair* pairs;
-    const uint16_t* etab;
-    const void* pool;        // matrix pool (state dtype, complex), batch element 0
-    uint64_t pool_bstride;   // elements between per-state pools (0 = shared)
-    uint64_t state_bstride;  // amplitudes between states
-    const void* phase_tab;   // 8 complex entries e^{i pi e / 4} in the state dtype
-    double* gpart;           // gradient partials
-    uint32_t ntile_log2;     // log2(tiles per state)
-    uint32_t nthreads;
-};
+
 
 // Dynamic LDS bytes a tile pass needs.
 size_t tile_lds_bytes(int dtype, bool two, uint32_t T, uint32_t nform, uint32_t ngrad, int nt);

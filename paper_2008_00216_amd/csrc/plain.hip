@@ -15,6 +15,7 @@ namespace svmi {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr uint64_t kMaxBlocks = 1u << 20;   // grid-stride beyond 2^28 threads per state
 
 __device__ __forceinline__ uint64_t insert_zeros(uint64_t s, const int* tq, int k) {
     for (int t = 0; t < k; ++t) {
@@ -42,11 +43,11 @@ __global__ __launch_bounds__(kBlock) void k_dense(V2<R>* state, uint64_t bstride
                                                   const V2<R>* __restrict__ mat, uint64_t mat_bstride,
                                                   uint64_t nsets) {
     constexpr int D = 1 << K;
-    const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     const uint32_t b = blockIdx.y;
-    if (gid >= nsets) return;
     V2<R>* psi = state + (uint64_t)b * bstride;
     const V2<R>* u = mat + (uint64_t)b * mat_bstride;
+    for (uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x; gid < nsets;
+         gid += (uint64_t)gridDim.x * kBlock) {
     const uint64_t base = insert_zeros(gid, tg.q, K);
     uint64_t off[D];
 #pragma unroll
@@ -67,16 +68,17 @@ __global__ __launch_bounds__(kBlock) void k_dense(V2<R>* state, uint64_t bstride
         for (int c = 0; c < D; ++c) cmac(acc, u[r * D + c], in[c]);
         psi[off[r]] = acc;
     }
+    }
 }
 
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_masked_phase(V2<R>* state, uint64_t bstride, uint64_t mask,
                                                          int mode, const V2<R>* __restrict__ val,
                                                          uint64_t val_bstride, uint64_t count) {
-    const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     const uint32_t b = blockIdx.y;
-    if (gid >= count) return;
     V2<R>* psi = state + (uint64_t)b * bstride;
+    for (uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x; gid < count;
+         gid += (uint64_t)gridDim.x * kBlock) {
     const uint64_t j = insert_zeros_mask(gid, mask) | mask;
     V2<R> a = psi[j];
     if (mode == 1) {
@@ -89,29 +91,30 @@ __global__ __launch_bounds__(kBlock) void k_masked_phase(V2<R>* state, uint64_t 
         a = cmul(val[(uint64_t)b * val_bstride], a);
     }
     psi[j] = a;
+    }
 }
 
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_diag(V2<R>* state, uint64_t bstride, int k, Targets tg,
                                                  const V2<R>* __restrict__ d, uint64_t d_bstride,
                                                  uint64_t count) {
-    const uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     const uint32_t b = blockIdx.y;
-    if (j >= count) return;
     V2<R>* psi = state + (uint64_t)b * bstride;
-    uint32_t loc = 0;
-    for (int t = 0; t < k; ++t) loc |= (uint32_t)((j >> tg.q[t]) & 1ull) << t;
-    psi[j] = cmul(d[(uint64_t)b * d_bstride + loc], psi[j]);
+    for (uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < count; j += (uint64_t)gridDim.x * kBlock) {
+        uint32_t loc = 0;
+        for (int t = 0; t < k; ++t) loc |= (uint32_t)((j >> tg.q[t]) & 1ull) << t;
+        psi[j] = cmul(d[(uint64_t)b * d_bstride + loc], psi[j]);
+    }
 }
 
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_pair_swap(V2<R>* state, uint64_t bstride, uint64_t fixed,
                                                       uint64_t ones, uint64_t flip, int mode,
                                                       uint64_t count) {
-    const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     const uint32_t b = blockIdx.y;
-    if (gid >= count) return;
     V2<R>* psi = state + (uint64_t)b * bstride;
+    for (uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x; gid < count;
+         gid += (uint64_t)gridDim.x * kBlock) {
     const uint64_t j0 = insert_zeros_mask(gid, fixed) | ones;
     const uint64_t j1 = j0 ^ flip;
     const V2<R> a0 = psi[j0], a1 = psi[j1];
@@ -122,30 +125,31 @@ __global__ __launch_bounds__(kBlock) void k_pair_swap(V2<R>* state, uint64_t bst
         psi[j0] = V2<R>{a1.y, -a1.x};
         psi[j1] = V2<R>{-a0.y, a0.x};
     }
+    }
 }
 
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_init(V2<R>* state, uint64_t bstride, uint64_t count, int kind,
                                                  uint64_t index, R value) {
-    const uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     const uint32_t b = blockIdx.y;
-    if (j >= count) return;
-    V2<R> v{R(0), R(0)};
-    if (kind == 2) v.x = value;
-    else if (j == index) v.x = R(1);
-    state[(uint64_t)b * bstride + j] = v;
+    for (uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < count; j += (uint64_t)gridDim.x * kBlock) {
+        V2<R> v{R(0), R(0)};
+        if (kind == 2) v.x = value;
+        else if (j == index) v.x = R(1);
+        state[(uint64_t)b * bstride + j] = v;
+    }
 }
 
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_init_product(V2<R>* state, uint64_t bstride, uint64_t count,
                                                          int nlo, const double* __restrict__ lo,
                                                          const double* __restrict__ hi) {
-    const uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     const uint32_t b = blockIdx.y;
-    if (j >= count) return;
-    const uint64_t a = j & ((1ull << nlo) - 1ull), h = j >> nlo;
-    const double ar = lo[2 * a], ai = lo[2 * a + 1], br = hi[2 * h], bi = hi[2 * h + 1];
-    state[(uint64_t)b * bstride + j] = V2<R>{R(ar * br - ai * bi), R(ar * bi + ai * br)};
+    for (uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < count; j += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t a = j & ((1ull << nlo) - 1ull), h = j >> nlo;
+        const double ar = lo[2 * a], ai = lo[2 * a + 1], br = hi[2 * h], bi = hi[2 * h + 1];
+        state[(uint64_t)b * bstride + j] = V2<R>{R(ar * br - ai * bi), R(ar * bi + ai * br)};
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_grad_reduce(const double* __restrict__ part, uint64_t ntile,
@@ -161,7 +165,9 @@ __global__ __launch_bounds__(kBlock) void k_grad_reduce(const double* __restrict
 }
 
 inline dim3 grid_for(uint64_t count, int batch) {
-    return dim3((uint32_t)((count + kBlock - 1) / kBlock), (uint32_t)batch);
+    uint64_t g = (count + kBlock - 1) / kBlock;
+    if (g > kMaxBlocks) g = kMaxBlocks;
+    return dim3((uint32_t)g, (uint32_t)batch);
 }
 
 }  // namespace

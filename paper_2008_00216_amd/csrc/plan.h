@@ -14,7 +14,9 @@
 // All structures are plain data; the planner fills them on the host and
 // copies them to one device buffer per plan.
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <stdint.h>
+#endif
 
 namespace svmi {
 
@@ -67,7 +69,7 @@ struct DForm {
     uint32_t a_lo, a_hi;            // register-slot table A[16], 3 bits each (48 bits)
     uint32_t lam_const[3];          // Lambda_c when has_tile == 0
     uint32_t slot;                  // index of this form among the pass's forms
-    uint32_t pad;
+    uint32_t abits;                 // bit i = bit 2 of A[i] (sign-only forms)
 };
 
 // Nonlocal-nonlocal pair entry: for nonlocal bit `b`, masks of nonlocal

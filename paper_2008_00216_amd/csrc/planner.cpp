@@ -209,6 +209,7 @@ int encode_form(const Form& F, const PassGeom& G, const int r[4], int n, Encoded
     }
     D.a_lo = (uint32_t)A;
     D.a_hi = (uint32_t)(A >> 32);
+    for (int i = 0; i < kRegAmps; ++i) D.abits |= (uint32_t)((A >> (3 * i + 2)) & 1u) << i;
     bool tile = false;
     // nonlocal linear terms and local <-> nonlocal pairs
     for (int q = 0; q < n; ++q) {

@@ -118,10 +118,9 @@ __global__ void k_final(const double* __restrict__ partials, uint32_t nb, double
 template <class R>
 __global__ __launch_bounds__(kRB) void k_hpsi(const V2<R>* __restrict__ psi, V2<R>* __restrict__ lam,
                                               uint64_t bstride, uint64_t N, PauliDev pd) {
-    const uint64_t j = (uint64_t)blockIdx.x * kRB + threadIdx.x;
     const uint32_t b = blockIdx.y;
-    if (j >= N) return;
     const V2<R>* p = psi + (uint64_t)b * bstride;
+    for (uint64_t j = (uint64_t)blockIdx.x * kRB + threadIdx.x; j < N; j += (uint64_t)gridDim.x * kRB) {
     double lr = 0.0, li = 0.0;
     for (uint32_t g = 0; g < pd.ngroup; ++g) {
         const uint64_t jx = j ^ pd.x[g];
@@ -140,6 +139,7 @@ __global__ __launch_bounds__(kRB) void k_hpsi(const V2<R>* __restrict__ psi, V2<
         }
     }
     lam[(uint64_t)b * bstride + j] = V2<R>{R(lr), R(li)};
+    }
 }
 
 }  // namespace
@@ -169,7 +169,9 @@ hipError_t launch_reduce(int dtype, int kind, const void* a, const void* b, uint
 hipError_t launch_hpsi(int dtype, const void* psi, void* lam, uint64_t bstride, int batch, int n,
                        const PauliDev& pd, hipStream_t s) {
     const uint64_t N = 1ull << n;
-    const dim3 g((uint32_t)((N + kRB - 1) / kRB), (uint32_t)batch);
+    uint64_t gx = (N + kRB - 1) / kRB;
+    if (gx > (1u << 20)) gx = 1u << 20;
+    const dim3 g((uint32_t)gx, (uint32_t)batch);
     if (dtype == 1)
         hipLaunchKernelGGL(k_hpsi<float>, g, dim3(kRB), 0, s, reinterpret_cast<const V2<float>*>(psi),
                            reinterpret_cast<V2<float>*>(lam), bstride, N, pd);

@@ -1,0 +1,212 @@
+// Frame of a tile pass: gather a tile into LDS, per-tile parts of the phase
+// forms, register-group load/store, gradient partials and the scatter back.
+// Shared by the runtime interpreter and the plan-specialised kernels.
+#pragma once
+#include "device_common.h"
+#include "plan.h"
+
+namespace svmi {
+
+struct TileArgs {
+    void* state;             // batch element 0 of psi
+    void* lam;               // batch element 0 of lambda (adjoint sweep) or nullptr
+    const DPass* pass;
+    const DPhase* phases;
+    const DOp* ops;
+    const DForm* forms;
+    const DPair* pairs;
+    const uint16_t* etab;
+    const void* pool;        // matrix pool (state dtype, complex), batch element 0
+    uint64_t pool_bstride;   // elements between per-state pools (0 = shared)
+    uint64_t state_bstride;  // amplitudes between states
+    const void* phase_tab;   // 8 complex entries e^{i pi e / 4} in the state dtype
+    double* gpart;           // gradient partials of this pass
+    uint32_t ntile_log2;     // log2(tiles per state)
+    uint32_t nthreads;
+};
+
+__device__ __forceinline__ uint32_t ins0(uint32_t x, uint32_t p) {
+    const uint32_t lo = x & ((1u << p) - 1u);
+    return ((x >> p) << (p + 1)) | lo;
+}
+
+// Global offset of tile-local index l (low L bits contiguous, then the high
+// positions hpos[0..H)).
+__device__ __forceinline__ uint64_t map_local(uint32_t l, uint32_t L, uint32_t H, const uint32_t* hpos) {
+    uint64_t o = l & ((1u << L) - 1u);
+    const uint32_t hi = l >> L;
+    for (uint32_t t = 0; t < H; ++t) o |= (uint64_t)((hi >> t) & 1u) << hpos[t];
+    return o;
+}
+
+template <class R, int NT, bool TWO>
+struct TileFrame {
+    using V = V2<R>;
+    static constexpr int NW = NT / 64;
+    uint32_t tid, b, T, NA, ngrad;
+    uint64_t g, base, ot;
+    V* psi;
+    V* lam;
+    const V* pool;
+    V* sA;
+    V* sB;
+    V* ptab;
+    uint32_t* fl;
+    double* red;
+
+    // Carve LDS, gather the tile, evaluate the per-tile form parts.
+    __device__ __forceinline__ void begin(const TileArgs& A, unsigned char* smem, uint32_t L, uint32_t H,
+                                          uint32_t Tn, const uint32_t* hpos, uint32_t nform, uint32_t form0,
+                                          uint32_t ngrad_) {
+        tid = threadIdx.x;
+        T = Tn;
+        NA = 1u << T;
+        ngrad = TWO ? ngrad_ : 0u;
+        const uint64_t blk = blockIdx.x;
+        b = (uint32_t)(blk >> A.ntile_log2);
+        g = blk & ((1ull << A.ntile_log2) - 1ull);
+        base = g << L;
+        for (uint32_t t = 0; t < H; ++t) {
+            const uint32_t h = hpos[t];
+            base = (base & ((1ull << h) - 1ull)) | ((base >> h) << (h + 1));
+        }
+        psi = reinterpret_cast<V*>(A.state) + (uint64_t)b * A.state_bstride;
+        lam = nullptr;
+        if constexpr (TWO) lam = reinterpret_cast<V*>(A.lam) + (uint64_t)b * A.state_bstride;
+        pool = reinterpret_cast<const V*>(A.pool) + (uint64_t)b * A.pool_bstride;
+        sA = reinterpret_cast<V*>(smem);
+        sB = sA + (TWO ? NA : 0);
+        ptab = sA + (TWO ? 2 * NA : NA);
+        fl = reinterpret_cast<uint32_t*>(ptab + 8);
+        red = reinterpret_cast<double*>(fl + ((4 * nform + 1) & ~1u));
+
+        if (tid < 8) ptab[tid] = reinterpret_cast<const V*>(A.phase_tab)[tid];
+        for (uint32_t i = tid; i < 4 * nform; i += NT) fl[i] = 0;
+        if constexpr (TWO)
+            for (uint32_t i = tid; i < ngrad * NW; i += NT) red[i] = 0.0;
+
+        constexpr uint32_t APC = 16 / sizeof(V);
+        const uint32_t nchunk = NA / APC;
+        ot = map_local(APC * tid, L, H, hpos);
+        for (uint32_t c0 = 0; c0 < nchunk; c0 += 8 * NT) {
+            u32x4 va[8];
+            u32x4 vb[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const uint32_t c = c0 + j * NT + tid;
+                if (c < nchunk) {
+                    const uint64_t gi = base + ot + map_local(APC * (c0 + j * NT), L, H, hpos);
+                    va[j] = *reinterpret_cast<const u32x4*>(psi + gi);
+                    if constexpr (TWO) vb[j] = *reinterpret_cast<const u32x4*>(lam + gi);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const uint32_t c = c0 + j * NT + tid;
+                if (c < nchunk) {
+                    const uint32_t s = swz<R>(APC * c);
+                    *reinterpret_cast<u32x4*>(sA + s) = va[j];
+                    if constexpr (TWO) *reinterpret_cast<u32x4*>(sB + s) = vb[j];
+                }
+            }
+        }
+        __syncthreads();
+
+        // per-tile form parts: Lambda_c (local bits whose nonlocal partner sum
+        // has bit c set) and the tile constant K
+        for (uint32_t w = tid; w < nform * 16; w += NT) {
+            const uint32_t f = w >> 4, a = w & 15u;
+            const DForm* F = A.forms + form0 + f;
+            if (!F->has_tile) {
+                if (a == 0) atomicAdd(&fl[4 * f + 3], F->konst);
+                continue;
+            }
+            if (a < T) {
+                const uint32_t lamv = __popcll(base & F->mc[a][0]) + 2u * __popcll(base & F->mc[a][1]) +
+                                      4u * __popcll(base & F->mc[a][2]);
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc)
+                    if ((lamv >> cc) & 1u) atomicOr(&fl[4 * f + cc], 1u << a);
+            }
+            if (a == 0) {
+                const uint32_t kv = F->konst + __popcll(base & F->ka[0]) + 2u * __popcll(base & F->ka[1]) +
+                                    4u * __popcll(base & F->ka[2]);
+                atomicAdd(&fl[4 * f + 3], kv);
+            }
+        }
+        for (uint32_t f = 0; f < nform; ++f) {
+            const DForm* F = A.forms + form0 + f;
+            const uint32_t nq = F->nq;
+            for (uint32_t e = tid; e < nq; e += NT) {
+                const DPair pr = A.pairs[F->q0 + e];
+                if ((base >> pr.b) & 1ull) {
+                    const uint32_t kv = __popcll(base & pr.m[0]) + 2u * __popcll(base & pr.m[1]) +
+                                        4u * __popcll(base & pr.m[2]);
+                    atomicAdd(&fl[4 * f + 3], kv);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    __device__ __forceinline__ void load_group(uint32_t sb, const uint32_t* soff, V* a, V* l, bool act) const {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            a[i] = act ? sA[sb ^ soff[i]] : V{R(0), R(0)};
+            if constexpr (TWO) l[i] = act ? sB[sb ^ soff[i]] : V{R(0), R(0)};
+        }
+    }
+    __device__ __forceinline__ void store_group(uint32_t sb, const uint32_t* soff, const V* a, const V* l,
+                                                bool act) const {
+        if (!act) return;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            sA[sb ^ soff[i]] = a[i];
+            if constexpr (TWO) sB[sb ^ soff[i]] = l[i];
+        }
+    }
+
+    // wave-reduced gradient partial into the per-wave slot
+    __device__ __forceinline__ void grad_add(uint32_t slot, double v) const {
+        v = wave_sum_(v);
+        if ((tid & 63u) == 0) red[slot * NW + (tid >> 6)] += v;
+    }
+    __device__ __forceinline__ static double wave_sum_(double v) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        return v;
+    }
+
+    // Gradient partials of this tile and the scatter back to HBM.
+    __device__ __forceinline__ void end(const TileArgs& A, uint32_t L, uint32_t H, const uint32_t* hpos) {
+        if constexpr (TWO) {
+            if (ngrad) {
+                const uint64_t ntile = 1ull << A.ntile_log2;
+                double* dst = A.gpart + ((uint64_t)b * ntile + g) * ngrad;
+                for (uint32_t j = tid; j < ngrad; j += NT) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) s += red[j * NW + w];
+                    dst[j] = s;
+                }
+            }
+        }
+        constexpr uint32_t APC = 16 / sizeof(V);
+        const uint32_t nchunk = NA / APC;
+        for (uint32_t c0 = 0; c0 < nchunk; c0 += 8 * NT) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const uint32_t c = c0 + j * NT + tid;
+                if (c < nchunk) {
+                    const uint32_t s = swz<R>(APC * c);
+                    const uint64_t gi = base + ot + map_local(APC * (c0 + j * NT), L, H, hpos);
+                    *reinterpret_cast<u32x4*>(psi + gi) = *reinterpret_cast<const u32x4*>(sA + s);
+                    if constexpr (TWO)
+                        *reinterpret_cast<u32x4*>(lam + gi) = *reinterpret_cast<const u32x4*>(sB + s);
+                }
+            }
+        }
+    }
+};
+
+}  // namespace svmi

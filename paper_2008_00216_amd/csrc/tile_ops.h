@@ -1,0 +1,180 @@
+// Register-phase operations of a tile pass.  Each operates on the 16
+// amplitudes a[0..15] that a thread holds in a register phase; bit s of the
+// register index is register slot s.  Shared by the runtime interpreter and
+// the plan-specialised kernels compiled with hiprtc.
+#pragma once
+#include "device_common.h"
+#include "plan.h"
+
+namespace svmi {
+
+// Dense 2^k x 2^k block on the slots of MASK (k = popcount(MASK) <= 4); the
+// matrix is row-major with local index bit t = the t-th lowest slot of MASK.
+// Each matrix element is loaded once and applied to every index set.
+template <class R, int MASK>
+__device__ __forceinline__ void op_dense(V2<R>* a, const V2<R>* __restrict__ u) {
+    constexpr int K = __builtin_popcount(MASK);
+    constexpr int D = 1 << K;
+    V2<R> out[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) out[i] = V2<R>{R(0), R(0)};
+#pragma unroll
+    for (int o = 0; o < D; ++o) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            const V2<R> m = u[o * D + c];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                if (r & MASK) continue;
+                cmac(out[r | dep4(MASK, o)], m, a[r | dep4(MASK, c)]);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) a[i] = out[i];
+}
+
+// Diagonal on the slots of MASK: a[i] *= d[ext(MASK, i)].
+template <class R, int MASK>
+__device__ __forceinline__ void op_diag(V2<R>* a, const V2<R>* __restrict__ d) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) a[i] = cmul(d[ext4(MASK, i)], a[i]);
+}
+
+// Multiply-free one-qubit kernels on slot S for the factored matrices of
+// Sec. 4.4 (entries +-1, +-i); the leading 1/sqrt(2) and 1/2 factors are
+// applied once per pass (op_scale).  WP is sqrt(2) sqrt(W) = [[w,-i],[1,w]]
+// with w = e^{i pi/4} = c (1 + i).
+template <class R, int S, uint32_t KIND>
+__device__ __forceinline__ void op_struct(V2<R>* a, R c) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (i & (1 << S)) continue;
+        const V2<R> x = a[i], y = a[i | (1 << S)];
+        V2<R> o0, o1;
+        if constexpr (KIND == OP_HP) {           // [[1,1],[1,-1]]
+            o0 = V2<R>{x.x + y.x, x.y + y.y};
+            o1 = V2<R>{x.x - y.x, x.y - y.y};
+        } else if constexpr (KIND == OP_XP) {    // [[1+i,1-i],[1-i,1+i]]: s +- i d
+            const V2<R> s{x.x + y.x, x.y + y.y}, d{x.x - y.x, x.y - y.y};
+            o0 = V2<R>{s.x - d.y, s.y + d.x};
+            o1 = V2<R>{s.x + d.y, s.y - d.x};
+        } else if constexpr (KIND == OP_YP) {    // [[1+i,-1-i],[1+i,1+i]]: (1+i)d, (1+i)s
+            const V2<R> s{x.x + y.x, x.y + y.y}, d{x.x - y.x, x.y - y.y};
+            o0 = V2<R>{d.x - d.y, d.x + d.y};
+            o1 = V2<R>{s.x - s.y, s.x + s.y};
+        } else {                                 // [[w,-i],[1,w]]
+            o0 = V2<R>{fma_(c, x.x - x.y, y.y), fma_(c, x.x + x.y, -y.x)};
+            o1 = V2<R>{fma_(c, y.x - y.y, x.x), fma_(c, y.x + y.y, x.y)};
+        }
+        a[i] = o0;
+        a[i | (1 << S)] = o1;
+    }
+}
+
+template <class R>
+__device__ __forceinline__ void op_scale(V2<R>* a, R s) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) { a[i].x *= s; a[i].y *= s; }
+}
+
+// ---- 8th-root phase forms (Sec. 4.3) --------------------------------------
+// Exponent of register amplitude i: e0 + sum_{s in i} d[s] + A_i (mod 8),
+// where e0 and d[] are per thread and A (3 bits per i) is uniform.
+
+// Per-thread parts from the per-tile masks (fl: Lambda_0..2 and K in LDS) and
+// the per-thread-group table entry et (3 bits Etau, then 3 bits per slot).
+__device__ __forceinline__ void form_thread(const uint32_t* fl, uint32_t et, uint32_t lb, uint32_t r0, uint32_t r1,
+                                            uint32_t r2, uint32_t r3, uint32_t& e0, uint32_t d[4]) {
+    const uint32_t L0 = fl[0], L1 = fl[1], L2 = fl[2], K = fl[3];
+    e0 = K + (et & 7u) + __popc(lb & L0) + 2u * __popc(lb & L1) + 4u * __popc(lb & L2);
+    const uint32_t rr[4] = {r0, r1, r2, r3};
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        d[s] = ((et >> (3 + 3 * s)) & 7u) + ((L0 >> rr[s]) & 1u) + 2u * ((L1 >> rr[s]) & 1u) +
+               4u * ((L2 >> rr[s]) & 1u);
+}
+
+// Sign-only form: every exponent is 0 or 4, so the sign bit of amplitude i is
+// the XOR of the bit-2's of its terms; build a 16-bit flip mask per thread.
+template <class R, bool TWO>
+__device__ __forceinline__ void op_sign(V2<R>* a, V2<R>* l, uint32_t e0, const uint32_t d[4], uint32_t abits) {
+    uint32_t m = abits;
+    m ^= ((e0 >> 2) & 1u) ? 0xFFFFu : 0u;
+    m ^= ((d[0] >> 2) & 1u) ? 0xAAAAu : 0u;
+    m ^= ((d[1] >> 2) & 1u) ? 0xCCCCu : 0u;
+    m ^= ((d[2] >> 2) & 1u) ? 0xF0F0u : 0u;
+    m ^= ((d[3] >> 2) & 1u) ? 0xFF00u : 0u;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const uint32_t f = (m << (31 - i)) & 0x80000000u;
+        sign_flip_mask(a[i], f);
+        if constexpr (TWO) sign_flip_mask(l[i], f);
+    }
+}
+
+// General form: multiply amplitude i by e^{i pi e_i / 4} from the LDS table.
+template <class R, bool TWO>
+__device__ __forceinline__ void op_phase8(V2<R>* a, V2<R>* l, uint32_t e0, const uint32_t d[4], uint64_t At,
+                                          const V2<R>* ptab) {
+    uint32_t e[16];
+    e[0] = e0;
+#pragma unroll
+    for (int i = 1; i < 16; ++i) e[i] = e[i & (i - 1)] + d[__builtin_ctz(i)];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const uint32_t ee = (e[i] + (uint32_t)(At >> (3 * i))) & 7u;
+        const V2<R> t = ptab[ee];
+        a[i] = cmul(t, a[i]);
+        if constexpr (TWO) l[i] = cmul(t, l[i]);
+    }
+}
+
+// ---- adjoint gradient terms -----------------------------------------------
+__device__ __forceinline__ double imcj(double ux, double uy, double vx, double vy) {
+    return ux * vy - uy * vx;  // Im(conj(u) v)
+}
+__device__ __forceinline__ double recj(double ux, double uy, double vx, double vy) {
+    return ux * vx + uy * vy;  // Re(conj(u) v)
+}
+
+// Im <lambda|G|psi> over the 16 register amplitudes (FP64), G = X, Y or Z on
+// slot S.
+template <class R, int S, uint32_t GEN>
+__device__ __forceinline__ double op_grad1(const V2<R>* p, const V2<R>* l) {
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (i & (1 << S)) continue;
+        const int j = i | (1 << S);
+        const double p0x = p[i].x, p0y = p[i].y, p1x = p[j].x, p1y = p[j].y;
+        const double l0x = l[i].x, l0y = l[i].y, l1x = l[j].x, l1y = l[j].y;
+        if constexpr (GEN == GEN_X) {
+            acc += imcj(l0x, l0y, p1x, p1y) + imcj(l1x, l1y, p0x, p0y);
+        } else if constexpr (GEN == GEN_Y) {
+            // (Y psi)_0 = -i psi_1, (Y psi)_1 = i psi_0
+            acc += -recj(l0x, l0y, p1x, p1y) + recj(l1x, l1y, p0x, p0y);
+        } else {
+            acc += imcj(l0x, l0y, p0x, p0y) - imcj(l1x, l1y, p1x, p1y);
+        }
+    }
+    return acc;
+}
+
+// Generator -2 |11><11| on the two slots of MASK (controlled phase).
+template <class R, int MASK>
+__device__ __forceinline__ double op_grad11(const V2<R>* p, const V2<R>* l) {
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        if ((i & MASK) == MASK) acc += -2.0 * imcj(l[i].x, l[i].y, p[i].x, p[i].y);
+    return acc;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+}  // namespace svmi

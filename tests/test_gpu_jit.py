@@ -1,0 +1,63 @@
+"""Plan-specialised (run-time compiled) tile passes against the oracle and
+against the runtime-interpreted kernel."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from tests.gpu_util import check_close, round_c64, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def lib():
+    import paper_2008_00216_amd as m
+    return m
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_jit_grid_matches_oracle_and_interpreter(dtype):
+    m = lib()
+    c = W.grid_circuit(3, 6, 14, seed=21)        # 18 qubits
+    ref = oracle.simulate(c)
+    outs = []
+    for jit in (1, -1):
+        s = m.StateVector(c.n, dtype, opts=m.make_opts(jit=jit))
+        s.init("zero")
+        s.apply(c)
+        got = to_host(s.tensor)[0]
+        check_close(got, ref, dtype, f"jit={jit}")
+        outs.append(got)
+    # both paths run the same op sequence on the same tiles
+    assert np.max(np.abs(outs[0] - outs[1])) < (2e-6 if dtype == torch.complex64 else 1e-13)
+
+
+def test_jit_random_circuit_all_ops():
+    m = lib()
+    n = 17
+    ops = ("H", "X", "Y", "Z", "S", "SDG", "T", "TDG", "SQRTX", "SQRTY", "SQRTW", "RX", "RY", "RZ",
+           "P", "CZ", "CNOT", "SWAP", "CP")
+    c = W.random_circuit(n, 160, 77, ops=ops, mat_k=(2, 3, 4))
+    params = W.uniform_params(1, c.n_params, 5)[0]
+    psi0 = round_c64(W.random_state(n, 3))
+    ref = oracle.simulate(c, params, psi0)
+    t = to_dev(psi0, torch.complex64)
+    s = m.StateVector(n, torch.complex64, tensor=t, opts=m.make_opts(jit=1))
+    s.apply(c, params)
+    check_close(to_host(t)[0], ref, torch.complex64, "jit random")
+
+
+def test_jit_adjoint():
+    m = lib()
+    n = 16
+    c = W.ansatz_circuit(n, 3)
+    h = W.ansatz_observable(n)
+    th = W.uniform_params(2, c.n_params, 9)
+    s = m.StateVector(n, torch.complex64, batch=2, opts=m.make_opts(jit=1))
+    s.init("zero")
+    e, g = s.adjoint_grad(c, th, h)
+    for b in range(2):
+        assert abs(e[b] - oracle.energy(c, th[b], h)) < 2e-4
+        ref = oracle.grad_param_shift(c, th[b], h, which=list(range(0, c.n_params, 9)))
+        np.testing.assert_allclose(g[b][::9], ref, atol=2e-4)
