@@ -155,7 +155,7 @@ def main():
     cabi = sv.CircuitABI(circ)
     st = None
     for _ in range(args.warmup):
-        s.init("zero")
+        s.init("zero_deferred")
         st = s.apply(cabi)
         s.norm()
     s.timing()  # reset counters
@@ -163,7 +163,7 @@ def main():
     t0 = time.perf_counter()
     norms = []
     for _ in range(args.steps):
-        s.init("zero")
+        s.init("zero_deferred")
         st = s.apply(cabi)
         norms.append(float(s.norm()[0]))
     torch.cuda.synchronize()

@@ -134,7 +134,7 @@ typedef struct {
 
 typedef struct sv_ctx_s* sv_ctx;
 
-enum { SV_INIT_ZERO = 0, SV_INIT_BASIS = 1, SV_INIT_UNIFORM = 2 };
+enum { SV_INIT_ZERO = 0, SV_INIT_BASIS = 1, SV_INIT_UNIFORM = 2, SV_INIT_ZERO_DEFERRED = 3 };
 
 /* Fill *opts with the defaults. */
 void sv_opts_default(sv_opts* opts);
@@ -155,7 +155,12 @@ sv_status sv_set_opts(sv_ctx ctx, const sv_opts* opts);
 
 /* Initialise every state of the batch: SV_INIT_ZERO (|0..0>), SV_INIT_BASIS
  * (|basis_index>), SV_INIT_UNIFORM (all amplitudes 2^{-n/2}, the result of a
- * Hadamard layer on |0..0>, Sec. 4.5 footnote). */
+ * Hadamard layer on |0..0>, Sec. 4.5 footnote).  SV_INIT_ZERO_DEFERRED
+ * records |0..0> without writing it: the next library call that reads the
+ * state writes it first, unless the next sweep starts with one-qubit gates
+ * that are folded into a product-state initialisation (then the state is
+ * written once).  Reading the buffer directly before such a call sees stale
+ * data. */
 sv_status sv_init(sv_ctx ctx, int32_t kind, uint64_t basis_index);
 
 /* Apply a circuit to every state of the batch.  params: host FP64 array of

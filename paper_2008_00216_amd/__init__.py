@@ -30,7 +30,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 SV_OK, SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_EUNSUPPORTED = 0, 1, 2, 3, 4
 SV_C64, SV_C128 = 1, 2
-INIT_ZERO, INIT_BASIS, INIT_UNIFORM = 0, 1, 2
+INIT_ZERO, INIT_BASIS, INIT_UNIFORM, INIT_ZERO_DEFERRED = 0, 1, 2, 3
 BATCH_FORWARD, BATCH_GRAD, BATCH_INIT_ZERO = 1, 2, 4
 
 OPS = {
@@ -238,7 +238,8 @@ class StateVector:
 
     def init(self, kind: str = "zero", index: int = 0):
         self._stream()
-        k = {"zero": INIT_ZERO, "basis": INIT_BASIS, "uniform": INIT_UNIFORM}[kind]
+        k = {"zero": INIT_ZERO, "basis": INIT_BASIS, "uniform": INIT_UNIFORM,
+             "zero_deferred": INIT_ZERO_DEFERRED}[kind]
         _check(_lib.sv_init(self._h, k, int(index)))
         return self
 

@@ -6,12 +6,22 @@
 // fallback path that the persistent path is checked against.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
+#include "batch.h"
 #include "host.h"
+#include "kernels.h"
 #include "sv.h"
 
 namespace svmi {
@@ -59,22 +69,414 @@ sv_status run_batch_loop(int32_t count, const sv_batch_item* items, sv_dtype dty
 
 namespace svmi {
 
+namespace {
+
+struct PlanKeyed {
+    EncodedPlan ep;
+};
+
+std::mutex g_plan_mu;
+std::unordered_map<uint64_t, std::shared_ptr<PlanKeyed>> g_plans;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+PlanCfg batch_cfg(int dtype, bool two, int n) {
+    PlanCfg p;
+    p.dtype = dtype;
+    const int T = dtype == SV_C64 ? 12 : (two ? 11 : 12);
+    p.T = std::min(T, n);
+    p.L = std::min(dtype == SV_C64 ? 5 : 4, p.T - 1);
+    p.nt = 256;
+    p.two = two;
+    return p;
+}
+
+std::shared_ptr<PlanKeyed> get_batch_plan(const sv_circuit* c, const std::vector<IRGate>& ir, int dtype, bool two) {
+    const uint64_t key = circuit_hash(c, 0x9e3779b97f4a7c15ull ^ ((uint64_t)dtype << 8) ^ ((uint64_t)two << 12));
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        auto it = g_plans.find(key);
+        if (it != g_plans.end()) return it->second;
+    }
+    auto pk = std::make_shared<PlanKeyed>();
+    plan_fused(ir, c->n_qubits, batch_cfg(dtype, two, c->n_qubits), pk->ep);
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    g_plans[key] = pk;
+    return pk;
+}
+
+struct DevMem {
+    void* p = nullptr;
+    ~DevMem() { if (p) (void)hipFree(p); }
+};
+
+struct ItemHost {
+    std::vector<IRGate> irf, irb;
+    std::shared_ptr<PlanKeyed> pf, pb;
+    std::vector<unsigned char> poolf, poolb;
+    std::string err;
+};
+
+}  // namespace
+
 sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dtype dtype, hipStream_t stream,
                                int32_t flags, double* energies, double* grads, const sv_opts* opts,
                                sv_stats* stats, std::string& err) {
     if (count < 0) { err = "count < 0"; return SV_EINVAL; }
     if (count > 0 && !items) { err = "items is NULL"; return SV_EINVAL; }
     if (dtype != SV_C64 && dtype != SV_C128) { err = "dtype must be SV_C64 or SV_C128"; return SV_EINVAL; }
-    if ((flags & SV_BATCH_GRAD) && (!energies || !grads)) { err = "energies and grads are required"; return SV_EINVAL; }
+    const bool grad = (flags & SV_BATCH_GRAD) != 0;
+    if (grad && (!energies || !grads)) { err = "energies and grads are required"; return SV_EINVAL; }
+    bool small = false;
     for (int32_t i = 0; i < count; ++i) {
-        if (!items[i].circuit || !items[i].d_state) { err = "item " + std::to_string(i) + ": NULL circuit or state"; return SV_EINVAL; }
-        if ((flags & SV_BATCH_GRAD) && (!items[i].d_lambda || !items[i].observable)) {
+        const sv_batch_item& it = items[i];
+        if (!it.circuit || !it.d_state) { err = "item " + std::to_string(i) + ": NULL circuit or state"; return SV_EINVAL; }
+        std::string v = validate_circuit(it.circuit, it.circuit->n_qubits);
+        if (!v.empty()) { err = "item " + std::to_string(i) + ": " + v; return SV_EINVAL; }
+        const int nmax = dtype == SV_C64 ? 34 : 33;
+        if (it.circuit->n_qubits < 1 || it.circuit->n_qubits > nmax) { err = "item " + std::to_string(i) + ": bad width"; return SV_EINVAL; }
+        if ((uintptr_t)it.d_state % 16) { err = "item " + std::to_string(i) + ": state not 16-byte aligned"; return SV_EINVAL; }
+        if (grad && (!it.d_lambda || !it.observable)) {
             err = "item " + std::to_string(i) + ": gradients need d_lambda and an observable";
             return SV_EINVAL;
         }
-        if (energies && !items[i].observable) { err = "item " + std::to_string(i) + ": energies need an observable"; return SV_EINVAL; }
+        if (energies && !it.observable) { err = "item " + std::to_string(i) + ": energies need an observable"; return SV_EINVAL; }
+        if (it.circuit->n_params > 0 && !it.params) { err = "item " + std::to_string(i) + ": params is NULL"; return SV_EINVAL; }
+        if (it.circuit->n_qubits < 4) small = true;
     }
-    return run_batch_loop(count, items, dtype, stream, flags, energies, grads, opts, stats, err);
+    if (count == 0) return SV_OK;
+    if (small || (opts && opts->plain)) return run_batch_loop(count, items, dtype, stream, flags, energies, grads, opts, stats, err);
+
+    auto t0 = std::chrono::steady_clock::now();
+    // ---- IR and plans (planned in parallel; plans are cached by structure)
+    std::vector<ItemHost> H((size_t)count);
+    {
+        std::atomic<int> next{0};
+        unsigned hw = std::thread::hardware_concurrency();
+        const int nthr = (int)std::max(1u, std::min<unsigned>(hw ? hw : 4, 16u));
+        std::vector<std::thread> th;
+        for (int t = 0; t < std::min(nthr, (int)count); ++t)
+            th.emplace_back([&] {
+                for (;;) {
+                    const int i = next++;
+                    if (i >= count) return;
+                    const sv_batch_item& it = items[i];
+                    try {
+                        BuildOpts bo;
+                        bo.batch = 1;
+                        bo.structured = !opts || opts->structured;
+                        bo.fuse = true;
+                        bo.product_init = false;
+                        H[i].irf = build_ir(it.circuit, it.params, bo, nullptr, it.circuit->n_qubits);
+                        H[i].pf = get_batch_plan(it.circuit, H[i].irf, dtype, false);
+                        fill_pool(H[i].pf->ep, H[i].irf, 1, H[i].poolf);
+                        if (grad) {
+                            bo.backward = true;
+                            H[i].irb = build_ir(it.circuit, it.params, bo, nullptr, it.circuit->n_qubits);
+                            H[i].pb = get_batch_plan(it.circuit, H[i].irb, dtype, true);
+                            fill_pool(H[i].pb->ep, H[i].irb, 1, H[i].poolb);
+                        }
+                    } catch (const std::exception& e) {
+                        H[i].err = e.what();
+                    }
+                }
+            });
+        for (auto& t : th) t.join();
+    }
+    for (int i = 0; i < count; ++i) {
+        if (!H[i].err.empty()) { err = "item " + std::to_string(i) + ": planning failed: " + H[i].err; return SV_EUNSUPPORTED; }
+        const EncodedPlan* eps[2] = {&H[i].pf->ep, grad ? &H[i].pb->ep : nullptr};
+        for (const EncodedPlan* e : eps)
+            if (e)
+                for (const Step& s : e->steps)
+                    if (s.type != ST_TILE)  // wide (k > 4) gates: run item by item
+                        return run_batch_loop(count, items, dtype, stream, flags, energies, grads, opts, stats, err);
+    }
+    const double plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+
+    // ---- device layout
+    const size_t ab = dtype == SV_C64 ? 8 : 16;
+    struct Off {
+        size_t f_pass, f_phase, f_op, f_form, f_pair, f_etab, f_pool;
+        size_t b_pass, b_phase, b_op, b_form, b_pair, b_etab, b_pool;
+        size_t px, pg0, pz, pc, pph;
+        size_t gpart, epart;
+        uint32_t ngroup, nterm;
+    };
+    std::vector<Off> off((size_t)count);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t r = o; o = align_up(o + std::max<size_t>(bytes, 1), 256); return r; };
+    std::vector<std::vector<uint64_t>> gx((size_t)count), gz((size_t)count);
+    std::vector<std::vector<uint32_t>> gg0((size_t)count), gph((size_t)count);
+    std::vector<std::vector<double>> gc((size_t)count);
+    std::vector<uint32_t> hT((size_t)count);
+    size_t lds = 0;
+    for (int i = 0; i < count; ++i) {
+        const EncodedPlan& F = H[i].pf->ep;
+        Off& f = off[i];
+        f.f_pass = take(F.passes.size() * sizeof(DPass));
+        f.f_phase = take(F.phases.size() * sizeof(DPhase));
+        f.f_op = take(F.ops.size() * sizeof(DOp));
+        f.f_form = take(F.forms.size() * sizeof(DForm));
+        f.f_pair = take(F.pairs.size() * sizeof(DPair));
+        f.f_etab = take(F.etab.size() * sizeof(uint16_t));
+        f.f_pool = take(H[i].poolf.size());
+        for (const DPass& P : F.passes) lds = std::max(lds, tile_lds_bytes(dtype, false, P.T, P.nform, 0, 256));
+        if (grad) {
+            const EncodedPlan& B = H[i].pb->ep;
+            f.b_pass = take(B.passes.size() * sizeof(DPass));
+            f.b_phase = take(B.phases.size() * sizeof(DPhase));
+            f.b_op = take(B.ops.size() * sizeof(DOp));
+            f.b_form = take(B.forms.size() * sizeof(DForm));
+            f.b_pair = take(B.pairs.size() * sizeof(DPair));
+            f.b_etab = take(B.etab.size() * sizeof(uint16_t));
+            f.b_pool = take(H[i].poolb.size());
+            f.gpart = take(B.gpart_size * sizeof(double));
+            for (const DPass& P : B.passes) lds = std::max(lds, tile_lds_bytes(dtype, true, P.T, P.nform, P.ngrad, 256));
+        }
+        // observable, grouped by x mask
+        const sv_pauli_sum* h = items[i].observable;
+        if (h) {
+            if (h->n_terms < 0 || (h->n_terms > 0 && (!h->coeff || !h->x_mask || !h->z_mask))) {
+                err = "item " + std::to_string(i) + ": bad observable";
+                return SV_EINVAL;
+            }
+            const int n = items[i].circuit->n_qubits;
+            const uint64_t qm = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+            std::vector<std::vector<int>> grp;
+            for (int t = 0; t < h->n_terms; ++t) {
+                if ((h->x_mask[t] | h->z_mask[t]) & ~qm) { err = "item " + std::to_string(i) + ": Pauli term outside the register"; return SV_EINVAL; }
+                size_t g = 0;
+                for (; g < gx[i].size(); ++g) if (gx[i][g] == h->x_mask[t]) break;
+                if (g == gx[i].size()) { gx[i].push_back(h->x_mask[t]); grp.emplace_back(); }
+                grp[g].push_back(t);
+            }
+            for (size_t g = 0; g < grp.size(); ++g) {
+                gg0[i].push_back((uint32_t)gz[i].size());
+                for (int t : grp[g]) {
+                    gz[i].push_back(h->z_mask[t]);
+                    gc[i].push_back(h->coeff[t]);
+                    gph[i].push_back((uint32_t)(__builtin_popcountll(h->x_mask[t] & h->z_mask[t]) & 3));
+                }
+            }
+            gg0[i].push_back((uint32_t)gz[i].size());
+        } else {
+            gg0[i].push_back(0);
+        }
+        f.ngroup = (uint32_t)gx[i].size();
+        f.nterm = (uint32_t)gz[i].size();
+        f.px = take(gx[i].size() * 8);
+        f.pg0 = take(gg0[i].size() * 4);
+        f.pz = take(gz[i].size() * 8);
+        f.pc = take(gc[i].size() * 8);
+        f.pph = take(gph[i].size() * 4);
+        const int n = items[i].circuit->n_qubits;
+        hT[i] = (uint32_t)std::min(n, 12);
+        f.epart = take(((size_t)1 << (n - hT[i])) * sizeof(double));
+    }
+    // records: stages per item
+    std::vector<std::vector<BRec>> stages((size_t)count);
+    for (int i = 0; i < count; ++i) {
+        const int n = items[i].circuit->n_qubits;
+        auto add = [&](uint32_t kind, uint32_t pass, uint32_t T) {
+            BRec r{};
+            r.item = (uint32_t)i;
+            r.kind = kind;
+            r.pass = pass;
+            r.T = T;
+            r.ntiles = 1u << (n - (int)T);
+            stages[i].push_back(r);
+        };
+        if (flags & SV_BATCH_INIT_ZERO) add(BK_INIT, 0, hT[i]);
+        const EncodedPlan& F = H[i].pf->ep;
+        for (size_t p = 0; p < F.passes.size(); ++p) add(BK_FWD, (uint32_t)p, F.passes[p].T);
+        if (grad) {
+            add(BK_HPSI, 0, hT[i]);
+            const EncodedPlan& B = H[i].pb->ep;
+            for (size_t p = 0; p < B.passes.size(); ++p) add(BK_BWD, (uint32_t)p, B.passes[p].T);
+        } else if (energies) {
+            add(BK_ENERGY, 0, hT[i]);
+        }
+    }
+    // queues: largest items first onto the least-loaded queue
+    std::vector<int> order((size_t)count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    auto cost = [&](int i) {
+        double c = 0.0;
+        for (const BRec& r : stages[i]) c += (double)r.ntiles * std::ldexp(1.0, (int)r.T) * (r.kind == BK_BWD ? 2.0 : 1.0);
+        return c;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    std::vector<std::vector<int>> qitems(kQueues);
+    double qload[kQueues] = {0};
+    for (int i : order) {
+        uint32_t best = 0;
+        for (uint32_t q = 1; q < kQueues; ++q) if (qload[q] < qload[best]) best = q;
+        qitems[best].push_back(i);
+        qload[best] += cost(i);
+    }
+    std::vector<BRec> recs;
+    BatchArgs BA{};
+    std::vector<std::vector<int32_t>> recid((size_t)count);
+    for (uint32_t q = 0; q < kQueues; ++q) {
+        BA.qrec0[q] = (uint32_t)recs.size();
+        std::vector<int> its = qitems[q];
+        std::sort(its.begin(), its.end());
+        uint64_t w = 0;
+        size_t maxl = 0;
+        for (int i : its) maxl = std::max(maxl, stages[i].size());
+        for (size_t lvl = 0; lvl < maxl; ++lvl)
+            for (int i : its) {
+                if (lvl >= stages[i].size()) continue;
+                BRec r = stages[i][lvl];
+                r.first_w = w;
+                r.dep = lvl ? recid[i][lvl - 1] : -1;
+                w += r.ntiles;
+                recid[i].push_back((int32_t)recs.size());
+                recs.push_back(r);
+            }
+        BA.qtotal[q] = w;
+        if (w >= (1ull << 31)) { err = "batch too large for one launch"; return SV_EUNSUPPORTED; }
+    }
+    BA.qrec0[kQueues] = (uint32_t)recs.size();
+    const size_t o_items = take((size_t)count * sizeof(BItem));
+    const size_t o_recs = take(recs.size() * sizeof(BRec));
+    const size_t o_cnt = take((kQueues + recs.size() + 1) * sizeof(uint32_t));
+    // reduction tasks: energies then gradient slots
+    struct Task { const double* src; uint64_t ntile; uint32_t nslot; uint32_t pad; double* dst; };
+    std::vector<Task> tasks;
+    size_t nout = (size_t)count;
+    std::vector<size_t> gslot0((size_t)count, 0);
+    for (int i = 0; i < count; ++i) {
+        gslot0[i] = nout;
+        if (grad) nout += (size_t)H[i].pb->ep.ngrad_total;
+    }
+    const size_t o_out = take(nout * sizeof(double));
+    const size_t o_tasks = take(((size_t)count * 64 + 16) * sizeof(Task));
+    const size_t total = o;
+
+    DevMem dm;
+    hipError_t he = hipMalloc(&dm.p, total);
+    if (he != hipSuccess) { err = std::string("hipMalloc: ") + hipGetErrorString(he); return SV_ENOMEM; }
+    unsigned char* D = reinterpret_cast<unsigned char*>(dm.p);
+    std::vector<unsigned char> h(total, 0);
+    auto put = [&](size_t at, const void* src, size_t n) { if (n) std::memcpy(h.data() + at, src, n); };
+    std::vector<BItem> bi((size_t)count);
+    for (int i = 0; i < count; ++i) {
+        const Off& f = off[i];
+        const EncodedPlan& F = H[i].pf->ep;
+        put(f.f_pass, F.passes.data(), F.passes.size() * sizeof(DPass));
+        put(f.f_phase, F.phases.data(), F.phases.size() * sizeof(DPhase));
+        put(f.f_op, F.ops.data(), F.ops.size() * sizeof(DOp));
+        put(f.f_form, F.forms.data(), F.forms.size() * sizeof(DForm));
+        put(f.f_pair, F.pairs.data(), F.pairs.size() * sizeof(DPair));
+        put(f.f_etab, F.etab.data(), F.etab.size() * sizeof(uint16_t));
+        put(f.f_pool, H[i].poolf.data(), H[i].poolf.size());
+        BItem& b = bi[i];
+        b.state = items[i].d_state;
+        b.lam = items[i].d_lambda;
+        b.n = (uint32_t)items[i].circuit->n_qubits;
+        b.fwd = BPlan{reinterpret_cast<const DPass*>(D + f.f_pass), reinterpret_cast<const DPhase*>(D + f.f_phase),
+                      reinterpret_cast<const DOp*>(D + f.f_op), reinterpret_cast<const DForm*>(D + f.f_form),
+                      reinterpret_cast<const DPair*>(D + f.f_pair), reinterpret_cast<const uint16_t*>(D + f.f_etab),
+                      D + f.f_pool};
+        if (grad) {
+            const EncodedPlan& B = H[i].pb->ep;
+            put(f.b_pass, B.passes.data(), B.passes.size() * sizeof(DPass));
+            put(f.b_phase, B.phases.data(), B.phases.size() * sizeof(DPhase));
+            put(f.b_op, B.ops.data(), B.ops.size() * sizeof(DOp));
+            put(f.b_form, B.forms.data(), B.forms.size() * sizeof(DForm));
+            put(f.b_pair, B.pairs.data(), B.pairs.size() * sizeof(DPair));
+            put(f.b_etab, B.etab.data(), B.etab.size() * sizeof(uint16_t));
+            put(f.b_pool, H[i].poolb.data(), H[i].poolb.size());
+            b.bwd = BPlan{reinterpret_cast<const DPass*>(D + f.b_pass), reinterpret_cast<const DPhase*>(D + f.b_phase),
+                          reinterpret_cast<const DOp*>(D + f.b_op), reinterpret_cast<const DForm*>(D + f.b_form),
+                          reinterpret_cast<const DPair*>(D + f.b_pair), reinterpret_cast<const uint16_t*>(D + f.b_etab),
+                          D + f.b_pool};
+            b.gpart = reinterpret_cast<double*>(D + f.gpart);
+        }
+        put(f.px, gx[i].data(), gx[i].size() * 8);
+        put(f.pg0, gg0[i].data(), gg0[i].size() * 4);
+        put(f.pz, gz[i].data(), gz[i].size() * 8);
+        put(f.pc, gc[i].data(), gc[i].size() * 8);
+        put(f.pph, gph[i].data(), gph[i].size() * 4);
+        b.pd.x = reinterpret_cast<const uint64_t*>(D + f.px);
+        b.pd.g0 = reinterpret_cast<const uint32_t*>(D + f.pg0);
+        b.pd.z = reinterpret_cast<const uint64_t*>(D + f.pz);
+        b.pd.c = reinterpret_cast<const double*>(D + f.pc);
+        b.pd.ph = reinterpret_cast<const uint32_t*>(D + f.pph);
+        b.pd.ngroup = f.ngroup;
+        b.epart = reinterpret_cast<double*>(D + f.epart);
+        const int n = items[i].circuit->n_qubits;
+        double* outp = reinterpret_cast<double*>(D + o_out);
+        if (energies) tasks.push_back(Task{b.epart, 1ull << (n - hT[i]), 1u, 0u, outp + i});
+        if (grad) {
+            const EncodedPlan& B = H[i].pb->ep;
+            size_t slot = gslot0[i];
+            for (const DPass& P : B.passes) {
+                if (!P.ngrad) continue;
+                tasks.push_back(Task{b.gpart + P.gpart_off, 1ull << (n - P.T), P.ngrad, 0u, outp + slot});
+                slot += P.ngrad;
+            }
+        }
+    }
+    if (tasks.size() > (size_t)count * 64 + 16) { err = "too many reduction tasks"; return SV_EUNSUPPORTED; }
+    put(o_items, bi.data(), bi.size() * sizeof(BItem));
+    put(o_recs, recs.data(), recs.size() * sizeof(BRec));
+    put(o_tasks, tasks.data(), tasks.size() * sizeof(Task));
+    he = hipMemcpyAsync(dm.p, h.data(), total, hipMemcpyHostToDevice, stream);
+    if (he != hipSuccess) { err = std::string("hipMemcpyAsync: ") + hipGetErrorString(he); return SV_EDEVICE; }
+    BA.items = reinterpret_cast<const BItem*>(D + o_items);
+    BA.recs = reinterpret_cast<const BRec*>(D + o_recs);
+    BA.head = reinterpret_cast<uint32_t*>(D + o_cnt);
+    BA.done = BA.head + kQueues;
+    BA.err = BA.done + recs.size();
+    BA.spin_limit = 1u << 21;
+    int bpc = 0;
+    he = batch_occupancy(dtype, lds, &bpc);
+    if (he != hipSuccess || bpc < 1) { err = std::string("occupancy query failed: ") + hipGetErrorString(he); return SV_EDEVICE; }
+    int dev = 0, ncu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    uint32_t nblocks = (uint32_t)(bpc * std::max(ncu, 1));
+    nblocks = std::max<uint32_t>(kQueues, nblocks / kQueues * kQueues);
+    he = launch_batch(dtype, BA, nblocks, lds, stream);
+    if (he != hipSuccess) { err = std::string("persistent launch: ") + hipGetErrorString(he); return SV_EDEVICE; }
+    he = launch_multi_sum(reinterpret_cast<const void*>(D + o_tasks), (uint32_t)tasks.size(), stream);
+    if (he != hipSuccess) { err = std::string("reduction launch: ") + hipGetErrorString(he); return SV_EDEVICE; }
+    std::vector<double> out(nout, 0.0);
+    uint32_t errflag = 0;
+    he = hipMemcpyAsync(out.data(), D + o_out, nout * sizeof(double), hipMemcpyDeviceToHost, stream);
+    if (he == hipSuccess) he = hipMemcpyAsync(&errflag, BA.err, 4, hipMemcpyDeviceToHost, stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(stream);
+    if (he != hipSuccess) { err = std::string("batch: ") + hipGetErrorString(he); return SV_EDEVICE; }
+    if (errflag) { err = "persistent batch: a dependency wait exceeded its spin limit"; return SV_EDEVICE; }
+    size_t goff = 0;
+    for (int i = 0; i < count; ++i) {
+        if (energies) energies[i] = out[i];
+        if (grad) {
+            const int np = items[i].circuit->n_params;
+            for (int p = 0; p < np; ++p) grads[goff + p] = 0.0;
+            const EncodedPlan& B = H[i].pb->ep;
+            for (int s = 0; s < B.ngrad_total; ++s) grads[goff + B.grad_param[s]] += out[gslot0[i] + s];
+            goff += (size_t)np;
+        }
+    }
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        for (int i = 0; i < count; ++i) {
+            stats->gates_in += items[i].circuit->n_gates;
+            stats->passes += (int32_t)H[i].pf->ep.passes.size() + (grad ? (int32_t)H[i].pb->ep.passes.size() : 0);
+        }
+        stats->launches = 2;
+        stats->plan_ms = plan_ms;
+        double bytes = 0.0;
+        for (int i = 0; i < count; ++i)
+            for (const BRec& r : stages[i])
+                bytes += (double)ab * std::ldexp(1.0, items[i].circuit->n_qubits) * (r.kind == BK_BWD ? 4.0 : 2.0);
+        stats->hbm_bytes = bytes;
+    }
+    return SV_OK;
 }
 
 }  // namespace svmi

@@ -1,0 +1,196 @@
+// Heterogeneous batch in one persistent launch.
+//
+// Every item (a circuit of its own width, its state, optional lambda scratch
+// and observable) is split into stages: [zero init], forward tile passes,
+// lambda = H psi with the energy partials (or the energy alone), [backward
+// tile passes with gradient partials].  A stage is a set of independent
+// tiles; stage s of an item may start only when all tiles of stage s-1 of the
+// same item are done.
+//
+// The host lays the (item, stage) records out in 8 queues (one per XCD,
+// workgroup w serves queue w % 8) in level order, so every dependency of a
+// record precedes it in its queue.  The grid holds only resident
+// workgroups; a workgroup pops a tile index with an atomic, finds its record,
+// waits (bounded spin) for the previous stage and runs the tile with the same
+// interpreter body as the single-circuit tile pass.  Waits can only be on
+// tiles popped earlier by running workgroups, so the queue always drains; a
+// wait that exceeds the spin limit sets an error flag and the workgroup
+// skips its work, so every wave still reaches the exit.
+#include "device_common.h"
+#include "kernels.h"
+#include "tile_frame.h"
+#include "tile_ops.h"
+#include "tile_interp.h"
+#include "batch.h"
+
+namespace svmi {
+
+namespace {
+
+constexpr int kBNT = 256;
+
+template <class R>
+__device__ void init_tile(const BItem& it, uint32_t tile, uint32_t Th) {
+    V2<R>* psi = reinterpret_cast<V2<R>*>(it.state);
+    const uint64_t j0 = (uint64_t)tile << Th;
+    const uint32_t cnt = 1u << Th;
+    for (uint32_t i = threadIdx.x; i < cnt; i += kBNT) {
+        V2<R> v{R(0), R(0)};
+        if (j0 + i == 0) v.x = R(1);
+        psi[j0 + i] = v;
+    }
+}
+
+// lambda = H psi on the tile's amplitudes (FP64 accumulation) and the tile's
+// partial of Re <psi|lambda>.  With `write` = false only the energy partial.
+template <class R>
+__device__ void hpsi_tile(const BItem& it, uint32_t tile, uint32_t Th, bool write, double* sh) {
+    const V2<R>* psi = reinterpret_cast<const V2<R>*>(it.state);
+    V2<R>* lam = reinterpret_cast<V2<R>*>(it.lam);
+    const PauliDev& pd = it.pd;
+    const uint64_t j0 = (uint64_t)tile << Th;
+    const uint32_t cnt = 1u << Th;
+    double acc = 0.0;
+    for (uint32_t i = threadIdx.x; i < cnt; i += kBNT) {
+        const uint64_t j = j0 + i;
+        double lr = 0.0, li = 0.0;
+        for (uint32_t g = 0; g < pd.ngroup; ++g) {
+            const uint64_t jx = j ^ pd.x[g];
+            const V2<R> v = psi[jx];
+            const double vr = v.x, vi = v.y;
+            const uint32_t t1 = pd.g0[g + 1];
+            for (uint32_t t = pd.g0[g]; t < t1; ++t) {
+                const double s = ((__popcll(jx & pd.z[t]) & 1) ? -1.0 : 1.0) * pd.c[t];
+                const uint32_t ph = pd.ph[t];
+                double xr = vr, xi = vi;
+                if (ph & 1) { const double tmp = xr; xr = -xi; xi = tmp; }
+                if (ph & 2) { xr = -xr; xi = -xi; }
+                lr += s * xr;
+                li += s * xi;
+            }
+        }
+        const V2<R> a = psi[j];
+        if (write) {
+            const V2<R> lv{R(lr), R(li)};
+            lam[j] = lv;
+            // energy from the rounded lambda, as the adjoint sweep sees it
+            acc += (double)a.x * (double)lv.x + (double)a.y * (double)lv.y;
+        } else {
+            acc += (double)a.x * lr + (double)a.y * li;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < kBNT / 64; ++w) s += sh[w];
+        it.epart[tile] = s;
+    }
+}
+
+template <class R>
+__global__ __launch_bounds__(kBNT) void k_batch(BatchArgs B) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t s_w;
+    __shared__ int32_t s_rec;
+    __shared__ uint32_t s_skip;
+    __shared__ double s_red[kBNT / 64];
+    const uint32_t q = blockIdx.x % kQueues;
+    const uint32_t rec0 = B.qrec0[q], rec1 = B.qrec0[q + 1];
+    const uint64_t total = B.qtotal[q];
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const uint32_t w = atomicAdd(&B.head[q], 1u);
+            s_w = w;
+            int32_t r = -1;
+            if (w < total) {
+                // binary search: last record with first_w <= w
+                uint32_t lo = rec0, hi = rec1;
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) / 2;
+                    if (B.recs[mid].first_w <= w) lo = mid; else hi = mid;
+                }
+                r = (int32_t)lo;
+            }
+            s_rec = r;
+            uint32_t skip = 0;
+            if (r >= 0) {
+                const int32_t dep = B.recs[r].dep;
+                if (dep >= 0) {
+                    const uint32_t need = B.recs[dep].ntiles;
+                    uint32_t spins = 0;
+                    while (__hip_atomic_load(&B.done[dep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                        if (__hip_atomic_load(B.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+                            ++spins > B.spin_limit) {
+                            atomicOr(B.err, 1u);
+                            skip = 1;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(8);
+                    }
+                }
+                __threadfence();
+            }
+            s_skip = skip;
+        }
+        __syncthreads();
+        const int32_t r = s_rec;
+        if (r < 0) break;
+        const BRec rc = B.recs[r];
+        const uint32_t tile = s_w - (uint32_t)rc.first_w;
+        if (!s_skip) {
+            const BItem& it = B.items[rc.item];
+            if (rc.kind == BK_INIT) {
+                init_tile<R>(it, tile, rc.T);
+            } else if (rc.kind == BK_HPSI || rc.kind == BK_ENERGY) {
+                hpsi_tile<R>(it, tile, rc.T, rc.kind == BK_HPSI, s_red);
+            } else {
+                const bool two = rc.kind == BK_BWD;
+                TileArgs A{};
+                const BPlan& pl = two ? it.bwd : it.fwd;
+                A.state = it.state;
+                A.lam = it.lam;
+                A.pass = pl.passes + rc.pass;
+                A.phases = pl.phases;
+                A.ops = pl.ops;
+                A.forms = pl.forms;
+                A.pairs = pl.pairs;
+                A.etab = pl.etab;
+                A.pool = pl.pool;
+                A.pool_bstride = 0;
+                A.state_bstride = 0;
+                A.phase_tab = pl.pool;
+                A.gpart = two ? it.gpart + A.pass->gpart_off : nullptr;
+                A.ntile_log2 = it.n - rc.T;
+                A.nthreads = kBNT;
+                if (two) tile_interp<R, kBNT, true>(A, smem, tile);
+                else tile_interp<R, kBNT, false>(A, smem, tile);
+            }
+        }
+        // publish this tile's global writes, then count it
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) atomicAdd(&B.done[r], 1u);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_batch(int dtype, const BatchArgs& a, uint32_t nblocks, size_t lds, hipStream_t s) {
+    if (dtype == 1)
+        hipLaunchKernelGGL(k_batch<float>, dim3(nblocks), dim3(kBNT), lds, s, a);
+    else
+        hipLaunchKernelGGL(k_batch<double>, dim3(nblocks), dim3(kBNT), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t batch_occupancy(int dtype, size_t lds, int* blocks_per_cu) {
+    const void* f = dtype == 1 ? (const void*)&k_batch<float> : (const void*)&k_batch<double>;
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, kBNT, lds);
+}
+
+}  // namespace svmi

@@ -104,6 +104,7 @@ struct sv_ctx_s {
     hipStream_t stream = nullptr;
     sv_opts opts{};
     bool known_zero = false;
+    bool zero_pending = false;   // |0..0> requested but not yet written
     std::unordered_map<uint64_t, std::unique_ptr<CachedPlan>> cache;
     DevBuf pool, red_part, red_out, pauli, gpart, gout, pinit;
     std::vector<unsigned char> pool_host;
@@ -380,6 +381,15 @@ sv_status upload_pauli(sv_ctx_s* c, const sv_pauli_sum* h, PauliDev& pd) {
     return SV_OK;
 }
 
+// Write a pending |0...0> (sv_init(ZERO) is deferred so that a following
+// product-state initialisation does not stream the state twice).
+sv_status materialise(sv_ctx_s* c) {
+    if (!c->zero_pending) return SV_OK;
+    HIPCHK(launch_init(c->dtype, c->state, 1ull << c->n, c->batch, c->n, 1, 0, 0.0, c->stream));
+    c->zero_pending = false;
+    return SV_OK;
+}
+
 sv_status apply_internal(sv_ctx_s* c, const sv_circuit* circ, const double* params, sv_stats* stats) {
     std::vector<IRGate> ir;
     ProductInit pi;
@@ -387,6 +397,11 @@ sv_status apply_internal(sv_ctx_s* c, const sv_circuit* circ, const double* para
     double plan_ms = 0.0;
     sv_status st = get_plan(c, circ, params, false, ir, pi, cp, plan_ms);
     if (st != SV_OK) return st;
+    if (!pi.used) {
+        st = materialise(c);
+        if (st != SV_OK) return st;
+    }
+    c->zero_pending = false;
     if (pi.used) {
         const size_t nlo = pi.lo.size(), nhi = pi.hi.size();
         HIPCHK(c->pinit.ensure((nlo + nhi) * 16));
@@ -488,10 +503,16 @@ sv_status sv_set_opts(sv_ctx c, const sv_opts* o) {
 
 sv_status sv_init(sv_ctx c, int32_t kind, uint64_t basis_index) {
     if (!c) return fail(SV_EINVAL, "ctx is NULL");
-    if (kind != SV_INIT_ZERO && kind != SV_INIT_BASIS && kind != SV_INIT_UNIFORM)
+    if (kind != SV_INIT_ZERO && kind != SV_INIT_BASIS && kind != SV_INIT_UNIFORM && kind != SV_INIT_ZERO_DEFERRED)
         return fail(SV_EINVAL, "unknown init kind");
     if (kind == SV_INIT_BASIS && basis_index >= (1ull << c->n)) return fail(SV_EINVAL, "basis index out of range");
     const double v = kind == SV_INIT_UNIFORM ? std::ldexp(1.0, -c->n / 2) * ((c->n & 1) ? std::sqrt(0.5) : 1.0) : 0.0;
+    if (kind == SV_INIT_ZERO_DEFERRED) {
+        c->zero_pending = true;
+        c->known_zero = true;
+        return SV_OK;
+    }
+    c->zero_pending = false;
     HIPCHK(launch_init(c->dtype, c->state, 1ull << c->n, c->batch, c->n, kind == SV_INIT_UNIFORM ? 2 : 1,
                        kind == SV_INIT_ZERO ? 0 : basis_index, v, c->stream));
     c->known_zero = kind == SV_INIT_ZERO;
@@ -513,6 +534,10 @@ sv_status sv_apply_circuit(sv_ctx c, const sv_circuit* circ, const double* param
 
 sv_status sv_norm(sv_ctx c, double* out) {
     if (!c || !out) return fail(SV_EINVAL, "ctx or out is NULL");
+    {
+        sv_status ms = materialise(c);
+        if (ms != SV_OK) return ms;
+    }
     HIPCHK(c->red_part.ensure(reduce_partials_size(c->n, c->batch) * sizeof(double)));
     HIPCHK(c->red_out.ensure((size_t)c->batch * sizeof(double)));
     HIPCHK(launch_reduce(c->dtype, 0, c->state, nullptr, 1ull << c->n, c->batch, c->n, nullptr, 0, 0,
@@ -525,6 +550,10 @@ sv_status sv_norm(sv_ctx c, double* out) {
 
 sv_status sv_expect(sv_ctx c, const sv_pauli_sum* h, double* out) {
     if (!c || !out) return fail(SV_EINVAL, "ctx or out is NULL");
+    {
+        sv_status ms = materialise(c);
+        if (ms != SV_OK) return ms;
+    }
     PauliDev pd{};
     sv_status st = upload_pauli(c, h, pd);
     if (st != SV_OK) return st;
@@ -553,11 +582,8 @@ sv_status sv_adjoint_grad(sv_ctx c, const sv_circuit* circ, const double* params
     PauliDev pd{};
     sv_status st = upload_pauli(c, h, pd);
     if (st != SV_OK) return st;
-    // forward sweep (the product-init shortcut is not used: the input state is arbitrary)
-    const bool kz = c->known_zero;
-    c->known_zero = false;
+    // forward sweep (folds leading one-qubit gates when the state is |0...0>)
     st = apply_internal(c, circ, params, stats);
-    (void)kz;
     if (st != SV_OK) return st;
     // lambda = H psi, energy = Re <psi|lambda>
     HIPCHK(launch_hpsi(c->dtype, c->state, d_scratch, 1ull << c->n, c->batch, c->n, pd, c->stream));
@@ -667,6 +693,10 @@ sv_status sv_plan_info(const sv_circuit* circ, sv_dtype dtype, int32_t adjoint, 
 
 sv_status sv_sync(sv_ctx c) {
     if (!c) return fail(SV_EINVAL, "ctx is NULL");
+    {
+        sv_status ms = materialise(c);
+        if (ms != SV_OK) return ms;
+    }
     HIPCHK(hipStreamSynchronize(c->stream));
     return SV_OK;
 }

@@ -67,4 +67,8 @@ hipError_t launch_hpsi(int dtype, const void* psi, void* lam, uint64_t bstride, 
 hipError_t launch_grad_reduce(const double* part, int batch, uint64_t ntile, uint32_t nslot,
                               double* out, uint64_t out_stride, hipStream_t s);
 
+// Tasks {const double* src; uint64 ntile; uint32 nslot; uint32 pad; double* dst}:
+// dst[j] = sum over t (ascending) of src[t * nslot + j]; one block per task.
+hipError_t launch_multi_sum(const void* tasks, uint32_t ntask, hipStream_t s);
+
 }  // namespace svmi

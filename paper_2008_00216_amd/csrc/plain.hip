@@ -145,10 +145,18 @@ __global__ __launch_bounds__(kBlock) void k_init_product(V2<R>* state, uint64_t 
                                                          int nlo, const double* __restrict__ lo,
                                                          const double* __restrict__ hi) {
     const uint32_t b = blockIdx.y;
-    for (uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < count; j += (uint64_t)gridDim.x * kBlock) {
+    // two consecutive amplitudes per thread (same high part when nlo >= 1)
+    const uint64_t pairs = count >> 1;
+    for (uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x; p < pairs; p += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t j = 2 * p;
         const uint64_t a = j & ((1ull << nlo) - 1ull), h = j >> nlo;
-        const double ar = lo[2 * a], ai = lo[2 * a + 1], br = hi[2 * h], bi = hi[2 * h + 1];
-        state[(uint64_t)b * bstride + j] = V2<R>{R(ar * br - ai * bi), R(ar * bi + ai * br)};
+        const double br = hi[2 * h], bi = hi[2 * h + 1];
+        const double ar0 = lo[2 * a], ai0 = lo[2 * a + 1], ar1 = lo[2 * a + 2], ai1 = lo[2 * a + 3];
+        V2<R> o[2] = {V2<R>{R(ar0 * br - ai0 * bi), R(ar0 * bi + ai0 * br)},
+                      V2<R>{R(ar1 * br - ai1 * bi), R(ar1 * bi + ai1 * br)}};
+        V2<R>* dst = state + (uint64_t)b * bstride + j;
+        dst[0] = o[0];
+        dst[1] = o[1];
     }
 }
 
@@ -162,6 +170,24 @@ __global__ __launch_bounds__(kBlock) void k_grad_reduce(const double* __restrict
     double s = 0.0;
     for (uint64_t t = 0; t < ntile; ++t) s += p[t * nslot];
     out[(uint64_t)b * out_stride + j] = s;
+}
+
+struct SumTask {
+    const double* src;
+    uint64_t ntile;
+    uint32_t nslot;
+    uint32_t pad;
+    double* dst;
+};
+
+// One block per task: dst[j] = sum_t src[t * nslot + j], t ascending.
+__global__ __launch_bounds__(kBlock) void k_multi_sum(const SumTask* __restrict__ tasks) {
+    const SumTask t = tasks[blockIdx.x];
+    for (uint32_t j = threadIdx.x; j < t.nslot; j += kBlock) {
+        double s = 0.0;
+        for (uint64_t k = 0; k < t.ntile; ++k) s += t.src[k * t.nslot + j];
+        t.dst[j] = s;
+    }
 }
 
 inline dim3 grid_for(uint64_t count, int batch) {
@@ -256,14 +282,21 @@ hipError_t launch_init(int dtype, void* state, uint64_t bstride, int batch, int 
 
 hipError_t launch_init_product(int dtype, void* state, uint64_t bstride, int batch, int n, int nlo,
                                const double* lo, const double* hi, hipStream_t s) {
+    if (nlo < 1 || n < 2) return hipErrorInvalidValue;
     const uint64_t count = 1ull << n;
-    const dim3 g = grid_for(count, batch);
+    const dim3 g = grid_for(count / 2, batch);
     if (dtype == 1)
         hipLaunchKernelGGL(k_init_product<float>, g, dim3(kBlock), 0, s, reinterpret_cast<V2<float>*>(state),
                            bstride, count, nlo, lo, hi);
     else
         hipLaunchKernelGGL(k_init_product<double>, g, dim3(kBlock), 0, s, reinterpret_cast<V2<double>*>(state),
                            bstride, count, nlo, lo, hi);
+    return hipGetLastError();
+}
+
+hipError_t launch_multi_sum(const void* tasks, uint32_t ntask, hipStream_t s) {
+    if (ntask == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_multi_sum, dim3(ntask), dim3(kBlock), 0, s, reinterpret_cast<const SumTask*>(tasks));
     return hipGetLastError();
 }
 

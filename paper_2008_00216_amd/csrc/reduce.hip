@@ -11,12 +11,12 @@ namespace svmi {
 
 namespace {
 
-constexpr int kRB = 256;         // threads per reduction block
-constexpr uint32_t kMaxRBlk = 512; // blocks per state
+constexpr int kRB = 256;            // threads per reduction block
+constexpr uint32_t kMaxRBlk = 8192;  // blocks per state (enough loads in flight to stream HBM)
 
 inline uint32_t nblk_for(int n) {
     const uint64_t N = 1ull << n;
-    uint64_t b = (N + 4 * kRB - 1) / (4 * kRB);
+    uint64_t b = (N + 8 * kRB - 1) / (8 * kRB);
     if (b > kMaxRBlk) b = kMaxRBlk;
     if (b < 1) b = 1;
     return (uint32_t)b;
@@ -70,7 +70,29 @@ __global__ __launch_bounds__(kRB) void k_reduce(int kind, const V2<R>* __restric
     const V2<R>* pb = b2 ? b2 + (uint64_t)b * bstride : nullptr;
     double acc = 0.0;
     const uint64_t stride = (uint64_t)gridDim.x * kRB;
-    for (uint64_t j = (uint64_t)blockIdx.x * kRB + threadIdx.x; j < N; j += stride) {
+    uint64_t j0 = (uint64_t)blockIdx.x * kRB + threadIdx.x;
+    if (kind <= 1) {
+        // four amplitudes in flight per thread, fixed order
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        for (; j0 + 3 * stride < N; j0 += 4 * stride) {
+            V2<R> v[4], w[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = pa[j0 + u * stride];
+            if (kind == 1) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) w[u] = pb[j0 + u * stride];
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) w[u] = v[u];
+            }
+            a0 += (double)v[0].x * (double)w[0].x + (double)v[0].y * (double)w[0].y;
+            a1 += (double)v[1].x * (double)w[1].x + (double)v[1].y * (double)w[1].y;
+            a2 += (double)v[2].x * (double)w[2].x + (double)v[2].y * (double)w[2].y;
+            a3 += (double)v[3].x * (double)w[3].x + (double)v[3].y * (double)w[3].y;
+        }
+        acc = (a0 + a1) + (a2 + a3);
+    }
+    for (uint64_t j = j0; j < N; j += stride) {
         const V2<R> v = pa[j];
         const double vr = v.x, vi = v.y;
         if (kind == 0) {

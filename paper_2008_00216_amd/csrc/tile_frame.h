@@ -58,11 +58,16 @@ struct TileFrame {
     __device__ __forceinline__ void begin(const TileArgs& A, unsigned char* smem, uint32_t L, uint32_t H,
                                           uint32_t Tn, const uint32_t* hpos, uint32_t nform, uint32_t form0,
                                           uint32_t ngrad_) {
+        begin_at(A, smem, L, H, Tn, hpos, nform, form0, ngrad_, blockIdx.x);
+    }
+    // blk = state * 2^ntile_log2 + tile
+    __device__ __forceinline__ void begin_at(const TileArgs& A, unsigned char* smem, uint32_t L, uint32_t H,
+                                             uint32_t Tn, const uint32_t* hpos, uint32_t nform, uint32_t form0,
+                                             uint32_t ngrad_, uint64_t blk) {
         tid = threadIdx.x;
         T = Tn;
         NA = 1u << T;
         ngrad = TWO ? ngrad_ : 0u;
-        const uint64_t blk = blockIdx.x;
         b = (uint32_t)(blk >> A.ntile_log2);
         g = blk & ((1ull << A.ntile_log2) - 1ull);
         base = g << L;

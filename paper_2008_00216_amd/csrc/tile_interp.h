@@ -1,0 +1,193 @@
+// Runtime-interpreted tile pass body: the op list of every register phase is
+// read from the plan and dispatched on its type and slot mask.  Used by the
+// single-circuit tile kernel and by the persistent batched kernel.
+#pragma once
+#include "device_common.h"
+#include "plan.h"
+#include "tile_frame.h"
+#include "tile_ops.h"
+
+namespace svmi {
+
+namespace {
+
+template <class R>
+__device__ __forceinline__ void dense_dispatch(V2<R>* a, uint32_t mask, const V2<R>* __restrict__ u) {
+    switch (mask) {
+        case 1: op_dense<R, 1>(a, u); break;
+        case 2: op_dense<R, 2>(a, u); break;
+        case 3: op_dense<R, 3>(a, u); break;
+        case 4: op_dense<R, 4>(a, u); break;
+        case 5: op_dense<R, 5>(a, u); break;
+        case 6: op_dense<R, 6>(a, u); break;
+        case 7: op_dense<R, 7>(a, u); break;
+        case 8: op_dense<R, 8>(a, u); break;
+        case 9: op_dense<R, 9>(a, u); break;
+        case 10: op_dense<R, 10>(a, u); break;
+        case 11: op_dense<R, 11>(a, u); break;
+        case 12: op_dense<R, 12>(a, u); break;
+        case 13: op_dense<R, 13>(a, u); break;
+        case 14: op_dense<R, 14>(a, u); break;
+        case 15: op_dense<R, 15>(a, u); break;
+        default: break;
+    }
+}
+
+template <class R>
+__device__ __forceinline__ void diag_dispatch(V2<R>* a, uint32_t mask, const V2<R>* __restrict__ d) {
+    switch (mask) {
+        case 1: op_diag<R, 1>(a, d); break;
+        case 2: op_diag<R, 2>(a, d); break;
+        case 3: op_diag<R, 3>(a, d); break;
+        case 4: op_diag<R, 4>(a, d); break;
+        case 5: op_diag<R, 5>(a, d); break;
+        case 6: op_diag<R, 6>(a, d); break;
+        case 7: op_diag<R, 7>(a, d); break;
+        case 8: op_diag<R, 8>(a, d); break;
+        case 9: op_diag<R, 9>(a, d); break;
+        case 10: op_diag<R, 10>(a, d); break;
+        case 11: op_diag<R, 11>(a, d); break;
+        case 12: op_diag<R, 12>(a, d); break;
+        case 13: op_diag<R, 13>(a, d); break;
+        case 14: op_diag<R, 14>(a, d); break;
+        case 15: op_diag<R, 15>(a, d); break;
+        default: break;
+    }
+}
+
+template <class R, uint32_t KIND>
+__device__ __forceinline__ void struct_dispatch(V2<R>* a, uint32_t mask, R c) {
+    switch (mask) {
+        case 1: op_struct<R, 0, KIND>(a, c); break;
+        case 2: op_struct<R, 1, KIND>(a, c); break;
+        case 4: op_struct<R, 2, KIND>(a, c); break;
+        case 8: op_struct<R, 3, KIND>(a, c); break;
+        default: break;
+    }
+}
+
+template <class R, uint32_t GEN>
+__device__ __forceinline__ double grad1_dispatch(const V2<R>* p, const V2<R>* l, uint32_t mask) {
+    switch (mask) {
+        case 1: return op_grad1<R, 0, GEN>(p, l);
+        case 2: return op_grad1<R, 1, GEN>(p, l);
+        case 4: return op_grad1<R, 2, GEN>(p, l);
+        case 8: return op_grad1<R, 3, GEN>(p, l);
+        default: return 0.0;
+    }
+}
+
+template <class R>
+__device__ __forceinline__ double grad_dispatch(const V2<R>* p, const V2<R>* l, uint32_t gen, uint32_t mask) {
+    switch (gen) {
+        case GEN_X: return grad1_dispatch<R, GEN_X>(p, l, mask);
+        case GEN_Y: return grad1_dispatch<R, GEN_Y>(p, l, mask);
+        case GEN_Z: return grad1_dispatch<R, GEN_Z>(p, l, mask);
+        default: break;
+    }
+    switch (mask) {
+        case 3: return op_grad11<R, 3>(p, l);
+        case 5: return op_grad11<R, 5>(p, l);
+        case 6: return op_grad11<R, 6>(p, l);
+        case 9: return op_grad11<R, 9>(p, l);
+        case 10: return op_grad11<R, 10>(p, l);
+        case 12: return op_grad11<R, 12>(p, l);
+        default: return 0.0;
+    }
+}
+
+}  // namespace
+
+// Interpreter body of one tile of one pass (blk = state * tiles + tile).
+template <class R, int NT, bool TWO>
+__device__ __forceinline__ void tile_interp(const TileArgs& A, unsigned char* smem, uint64_t blk) {
+    using V = V2<R>;
+    const DPass* __restrict__ P = A.pass;
+    const uint32_t L = P->L, H = P->H;
+    TileFrame<R, NT, TWO> F;
+    F.begin_at(A, smem, L, H, P->T, P->hpos, P->nform, P->form0, P->ngrad, blk);
+    const uint32_t tid = F.tid;
+    const uint32_t ngroups = F.NA >> kRegBits;
+    const uint32_t iters = (ngroups + NT - 1) / NT;
+    const uint32_t nphase = P->nphase;
+    for (uint32_t ph = 0; ph < nphase; ++ph) {
+        const DPhase* __restrict__ Ph = A.phases + P->phase0 + ph;
+        const uint32_t rpos = Ph->rpos;
+        const uint32_t r0 = rpos & 255u, r1 = (rpos >> 8) & 255u, r2 = (rpos >> 16) & 255u, r3 = rpos >> 24;
+        uint32_t soff[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) soff[i] = Ph->soff[i];
+        const uint32_t op0 = Ph->op0, nop = Ph->nop;
+        for (uint32_t it = 0; it < iters; ++it) {
+            const uint32_t gg = it * NT + tid;
+            const bool act = gg < ngroups;
+            const uint32_t lb = ins0(ins0(ins0(ins0(gg, r0), r1), r2), r3);
+            const uint32_t sb = swz<R>(lb);
+            V a[16];
+            V l[16];
+            F.load_group(sb, soff, a, l, act);
+            for (uint32_t o = op0; o < op0 + nop; ++o) {
+                const DOp op = A.ops[o];
+                const uint32_t type = rfl(op.type), mask = rfl(op.mask), arg = rfl(op.arg);
+                switch (type) {
+                    case OP_DENSE:
+                        dense_dispatch<R>(a, mask, F.pool + arg);
+                        if constexpr (TWO) dense_dispatch<R>(l, mask, F.pool + arg);
+                        break;
+                    case OP_DIAGR:
+                        diag_dispatch<R>(a, mask, F.pool + arg);
+                        if constexpr (TWO) diag_dispatch<R>(l, mask, F.pool + arg);
+                        break;
+                    case OP_HP:
+                        struct_dispatch<R, OP_HP>(a, mask, R(0));
+                        if constexpr (TWO) struct_dispatch<R, OP_HP>(l, mask, R(0));
+                        break;
+                    case OP_XP:
+                        struct_dispatch<R, OP_XP>(a, mask, R(0));
+                        if constexpr (TWO) struct_dispatch<R, OP_XP>(l, mask, R(0));
+                        break;
+                    case OP_YP:
+                        struct_dispatch<R, OP_YP>(a, mask, R(0));
+                        if constexpr (TWO) struct_dispatch<R, OP_YP>(l, mask, R(0));
+                        break;
+                    case OP_WP: {
+                        const R c = F.ptab[1].x;  // cos(pi/4) in the state dtype
+                        struct_dispatch<R, OP_WP>(a, mask, c);
+                        if constexpr (TWO) struct_dispatch<R, OP_WP>(l, mask, c);
+                        break;
+                    }
+                    case OP_SCALE: {
+                        const R s = F.pool[arg].x;
+                        op_scale<R>(a, s);
+                        if constexpr (TWO) op_scale<R>(l, s);
+                        break;
+                    }
+                    case OP_PHASE8:
+                    case OP_SIGN: {
+                        const DForm* __restrict__ Fm = A.forms + arg;
+                        const uint32_t et = act ? (uint32_t)A.etab[Fm->etab + gg] : 0u;
+                        uint32_t e0, d[4];
+                        form_thread(F.fl + 4 * Fm->slot, et, lb, r0, r1, r2, r3, e0, d);
+                        if (type == OP_SIGN) {
+                            op_sign<R, TWO>(a, l, e0, d, Fm->abits);
+                        } else {
+                            const uint64_t At = (uint64_t)Fm->a_lo | ((uint64_t)Fm->a_hi << 32);
+                            op_phase8<R, TWO>(a, l, e0, d, At, F.ptab);
+                        }
+                        break;
+                    }
+                    case OP_GRAD:
+                        if constexpr (TWO) F.grad_add(arg, grad_dispatch<R>(a, l, rfl(op.k), mask));
+                        break;
+                    default:
+                        break;
+                }
+            }
+            F.store_group(sb, soff, a, l, act);
+        }
+        __syncthreads();
+    }
+    F.end(A, L, H, P->hpos);
+}
+
+}  // namespace svmi
