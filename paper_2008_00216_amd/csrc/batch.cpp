@@ -431,7 +431,12 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
     BA.head = reinterpret_cast<uint32_t*>(D + o_cnt);
     BA.done = BA.head + kQueues;
     BA.err = BA.done + recs.size();
-    BA.spin_limit = 1u << 21;
+    {
+        int dev0 = 0, khz = 0;
+        (void)hipGetDevice(&dev0);
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev0) != hipSuccess || khz <= 0) khz = 100000;
+        BA.wait_ticks = (uint64_t)khz * 2000ull;   // 2 s per dependency wait
+    }
     int bpc = 0;
     he = batch_occupancy(dtype, lds, &bpc);
     if (he != hipSuccess || bpc < 1) { err = std::string("occupancy query failed: ") + hipGetErrorString(he); return SV_EDEVICE; }
@@ -450,7 +455,7 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
     if (he == hipSuccess) he = hipMemcpyAsync(&errflag, BA.err, 4, hipMemcpyDeviceToHost, stream);
     if (he == hipSuccess) he = hipStreamSynchronize(stream);
     if (he != hipSuccess) { err = std::string("batch: ") + hipGetErrorString(he); return SV_EDEVICE; }
-    if (errflag) { err = "persistent batch: a dependency wait exceeded its spin limit"; return SV_EDEVICE; }
+    if (errflag) { err = "persistent batch: a dependency wait exceeded its time budget"; return SV_EDEVICE; }
     size_t goff = 0;
     for (int i = 0; i < count; ++i) {
         if (energies) energies[i] = out[i];

@@ -47,8 +47,8 @@ struct BatchArgs {
     uint64_t qtotal[kQueues];      // tiles in queue q
     uint32_t* head;                // per-queue pop counters
     uint32_t* done;                // per-record finished tiles
-    uint32_t* err;                 // set when a dependency wait exceeds the spin limit
-    uint32_t spin_limit;
+    uint32_t* err;                 // set when a dependency wait exceeds its time budget
+    uint64_t wait_ticks;           // budget of one dependency wait, device wall-clock ticks
 };
 
 hipError_t launch_batch(int dtype, const BatchArgs& a, uint32_t nblocks, size_t lds, hipStream_t s);

@@ -11,11 +11,19 @@
 // workgroup w serves queue w % 8) in level order, so every dependency of a
 // record precedes it in its queue.  The grid holds only resident
 // workgroups; a workgroup pops a tile index with an atomic, finds its record,
-// waits (bounded spin) for the previous stage and runs the tile with the same
-// interpreter body as the single-circuit tile pass.  Waits can only be on
-// tiles popped earlier by running workgroups, so the queue always drains; a
-// wait that exceeds the spin limit sets an error flag and the workgroup
-// skips its work, so every wave still reaches the exit.
+// waits (bounded in wall-clock time) for the previous stage and runs the tile
+// with the same interpreter body as the single-circuit tile pass.  Waits can
+// only be on tiles popped earlier by running workgroups, so the queue always
+// drains; a wait that exceeds its time budget sets an error flag and the
+// workgroup skips its work, so every wave still reaches the exit.
+//
+// Control flow around the barriers is wave-uniform: wave 0 as a whole runs
+// the scheduling step (one lane does the atomics, the results are broadcast
+// with readlane/readfirstlane), the other waves skip it.  A lane-dependent
+// branch next to a barrier on the loop's back edge lets the compiler build an
+// inner loop that some lanes of a wave leave and others do not, which does
+// not terminate on SIMD hardware.  The completion count of a tile is added
+// by the same lane-0 step that pops the workgroup's next tile.
 #include "device_common.h"
 #include "kernels.h"
 #include "tile_frame.h"
@@ -90,89 +98,112 @@ __device__ void hpsi_tile(const BItem& it, uint32_t tile, uint32_t Th, bool writ
     }
 }
 
+__device__ __forceinline__ uint64_t rfl64(uint64_t v) {
+    return (uint64_t)rfl((uint32_t)v) | ((uint64_t)rfl((uint32_t)(v >> 32)) << 32);
+}
+
+template <class T>
+__device__ __forceinline__ T* uptr(T* p) {
+    return reinterpret_cast<T*>(rfl64(reinterpret_cast<uint64_t>(p)));
+}
+
 template <class R>
 __global__ __launch_bounds__(kBNT) void k_batch(BatchArgs B) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ uint32_t s_w;
-    __shared__ int32_t s_rec;
-    __shared__ uint32_t s_skip;
+    __shared__ uint32_t s_ctl[4];          // popped slot, record (-1: queue empty), skip
     __shared__ double s_red[kBNT / 64];
     const uint32_t q = blockIdx.x % kQueues;
     const uint32_t rec0 = B.qrec0[q], rec1 = B.qrec0[q + 1];
     const uint64_t total = B.qtotal[q];
+    const bool wave0 = threadIdx.x < 64;   // wave-uniform
+    const uint32_t lane = threadIdx.x & 63u;
+    int32_t prev = -1;                     // record of the tile finished in the previous round
     for (;;) {
-        if (threadIdx.x == 0) {
-            const uint32_t w = atomicAdd(&B.head[q], 1u);
-            s_w = w;
+        if (wave0) {
+            uint32_t wl = 0;
+            if (lane == 0) {
+                if (prev >= 0) __hip_atomic_fetch_add(&B.done[prev], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                wl = __hip_atomic_fetch_add(&B.head[q], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            const uint32_t w = __builtin_amdgcn_readlane(wl, 0);
             int32_t r = -1;
             if (w < total) {
                 // binary search: last record with first_w <= w
                 uint32_t lo = rec0, hi = rec1;
                 while (hi - lo > 1) {
                     const uint32_t mid = (lo + hi) / 2;
-                    if (B.recs[mid].first_w <= w) lo = mid; else hi = mid;
+                    if (rfl64(B.recs[mid].first_w) <= w) lo = mid; else hi = mid;
                 }
                 r = (int32_t)lo;
             }
-            s_rec = r;
             uint32_t skip = 0;
             if (r >= 0) {
-                const int32_t dep = B.recs[r].dep;
+                const int32_t dep = (int32_t)rfl((uint32_t)B.recs[r].dep);
                 if (dep >= 0) {
-                    const uint32_t need = B.recs[dep].ntiles;
-                    uint32_t spins = 0;
-                    while (__hip_atomic_load(&B.done[dep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                        if (__hip_atomic_load(B.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
-                            ++spins > B.spin_limit) {
-                            atomicOr(B.err, 1u);
+                    const uint32_t need = rfl(B.recs[dep].ntiles);
+                    const uint64_t t0 = wall_clock64();
+                    for (;;) {
+                        const uint32_t d = rfl(__hip_atomic_load(&B.done[dep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+                        if (d >= need) break;
+                        const uint32_t e = rfl(__hip_atomic_load(B.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                        if (e != 0u || wall_clock64() - t0 > B.wait_ticks) {
                             skip = 1;
                             break;
                         }
-                        __builtin_amdgcn_s_sleep(8);
+                        __builtin_amdgcn_s_sleep(4);
                     }
                 }
                 __threadfence();
             }
-            s_skip = skip;
+            if (lane == 0) {
+                if (skip) __hip_atomic_fetch_or(B.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_ctl[0] = w;
+                s_ctl[1] = (uint32_t)r;
+                s_ctl[2] = skip;
+            }
         }
         __syncthreads();
-        const int32_t r = s_rec;
+        const int32_t r = (int32_t)rfl(s_ctl[1]);
         if (r < 0) break;
+        const uint32_t skip = rfl(s_ctl[2]);
         const BRec rc = B.recs[r];
-        const uint32_t tile = s_w - (uint32_t)rc.first_w;
-        if (!s_skip) {
-            const BItem& it = B.items[rc.item];
-            if (rc.kind == BK_INIT) {
-                init_tile<R>(it, tile, rc.T);
-            } else if (rc.kind == BK_HPSI || rc.kind == BK_ENERGY) {
-                hpsi_tile<R>(it, tile, rc.T, rc.kind == BK_HPSI, s_red);
+        const uint32_t tile = rfl(s_ctl[0]) - (uint32_t)rfl64(rc.first_w);
+        const uint32_t kind = rfl(rc.kind);
+        if (!skip) {
+            const BItem& it = B.items[rfl(rc.item)];
+            if (kind == BK_INIT) {
+                init_tile<R>(it, tile, rfl(rc.T));
+            } else if (kind == BK_HPSI || kind == BK_ENERGY) {
+                hpsi_tile<R>(it, tile, rfl(rc.T), kind == BK_HPSI, s_red);
             } else {
-                const bool two = rc.kind == BK_BWD;
+                const bool two = kind == BK_BWD;
+                // the plan pointers are uniform: keep them in scalar registers so the
+                // interpreter's loop bounds stay scalar, as in the single-circuit kernel
                 TileArgs A{};
                 const BPlan& pl = two ? it.bwd : it.fwd;
-                A.state = it.state;
-                A.lam = it.lam;
-                A.pass = pl.passes + rc.pass;
-                A.phases = pl.phases;
-                A.ops = pl.ops;
-                A.forms = pl.forms;
-                A.pairs = pl.pairs;
-                A.etab = pl.etab;
-                A.pool = pl.pool;
+                A.state = uptr<void>(it.state);
+                A.lam = uptr<void>(it.lam);
+                A.pass = uptr<const DPass>(pl.passes) + rfl(rc.pass);
+                A.phases = uptr<const DPhase>(pl.phases);
+                A.ops = uptr<const DOp>(pl.ops);
+                A.forms = uptr<const DForm>(pl.forms);
+                A.pairs = uptr<const DPair>(pl.pairs);
+                A.etab = uptr<const uint16_t>(pl.etab);
+                A.pool = uptr<const void>(pl.pool);
                 A.pool_bstride = 0;
                 A.state_bstride = 0;
-                A.phase_tab = pl.pool;
-                A.gpart = two ? it.gpart + A.pass->gpart_off : nullptr;
-                A.ntile_log2 = it.n - rc.T;
+                A.phase_tab = A.pool;
+                A.gpart = two ? uptr<double>(it.gpart) + A.pass->gpart_off : nullptr;
+                A.ntile_log2 = rfl(it.n) - rfl(rc.T);
                 A.nthreads = kBNT;
                 if (two) tile_interp<R, kBNT, true>(A, smem, tile);
                 else tile_interp<R, kBNT, false>(A, smem, tile);
             }
         }
-        // publish this tile's global writes, then count it
+        // publish this tile's global writes; wave 0 counts it with its next pop
         __threadfence();
         __syncthreads();
-        if (threadIdx.x == 0) atomicAdd(&B.done[r], 1u);
+        prev = r;
     }
 }
 
@@ -188,7 +219,8 @@ hipError_t launch_batch(int dtype, const BatchArgs& a, uint32_t nblocks, size_t 
 
 hipError_t batch_occupancy(int dtype, size_t lds, int* blocks_per_cu) {
     const void* f = dtype == 1 ? (const void*)&k_batch<float> : (const void*)&k_batch<double>;
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    // 160 KiB of LDS per workgroup minus the kernel's static shared variables
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
     if (e != hipSuccess) return e;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, kBNT, lds);
 }

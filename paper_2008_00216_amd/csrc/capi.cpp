@@ -39,6 +39,7 @@ sv_status fail(sv_status st, const std::string& msg) {
     do {                                                                                     \
         hipError_t e_ = (expr);                                                              \
         if (e_ != hipSuccess) {                                                              \
+            (void)hipGetLastError(); /* do not leave the error for the caller's next call */ \
             return fail(e_ == hipErrorOutOfMemory ? SV_ENOMEM : SV_EDEVICE,                  \
                         std::string(#expr) + ": " + hipGetErrorString(e_));                  \
         }                                                                                    \
@@ -707,7 +708,10 @@ sv_status sv_apply_batch(int32_t count, const sv_batch_item* items, sv_dtype dty
     std::string err;
     sv_status st = run_batch_persistent(count, items, dtype, reinterpret_cast<hipStream_t>(hip_stream), flags,
                                         energies, grads, opts, stats, err);
-    if (st != SV_OK) return fail(st, err);
+    if (st != SV_OK) {
+        (void)hipGetLastError();
+        return fail(st, err);
+    }
     return SV_OK;
 }
 

@@ -103,15 +103,17 @@ template <class R, int NT, bool TWO>
 __device__ __forceinline__ void tile_interp(const TileArgs& A, unsigned char* smem, uint64_t blk) {
     using V = V2<R>;
     const DPass* __restrict__ P = A.pass;
-    const uint32_t L = P->L, H = P->H;
+    // pass fields are block-uniform; readfirstlane keeps every loop that
+    // contains a barrier on a scalar exit condition
+    const uint32_t L = rfl(P->L), H = rfl(P->H);
     TileFrame<R, NT, TWO> F;
-    F.begin_at(A, smem, L, H, P->T, P->hpos, P->nform, P->form0, P->ngrad, blk);
+    F.begin_at(A, smem, L, H, rfl(P->T), P->hpos, rfl(P->nform), rfl(P->form0), rfl(P->ngrad), blk);
     const uint32_t tid = F.tid;
     const uint32_t ngroups = F.NA >> kRegBits;
     const uint32_t iters = (ngroups + NT - 1) / NT;
-    const uint32_t nphase = P->nphase;
+    const uint32_t nphase = rfl(P->nphase);
     for (uint32_t ph = 0; ph < nphase; ++ph) {
-        const DPhase* __restrict__ Ph = A.phases + P->phase0 + ph;
+        const DPhase* __restrict__ Ph = A.phases + rfl(P->phase0) + ph;
         const uint32_t rpos = Ph->rpos;
         const uint32_t r0 = rpos & 255u, r1 = (rpos >> 8) & 255u, r2 = (rpos >> 16) & 255u, r3 = rpos >> 24;
         uint32_t soff[16];
