@@ -112,7 +112,8 @@ typedef struct {
     int32_t plain;         /* 1 = one kernel per gate, no reordering or fusion */
     int32_t threads;       /* workgroup size of tile passes, 0 = default */
     int32_t product_init;  /* 1 = fold leading one-qubit gates into the init of |0..0> */
-    int32_t structured;    /* 1 = multiply-free kernels for +-1/+-i structured gates */
+    int32_t structured;    /* 1 = H, sqrt(X), sqrt(Y), sqrt(W) and inverses as multiply-free H'
+                              butterflies with the diagonal phases applied lazily (default) */
     int32_t timing;        /* 1 = time every tile-pass launch with HIP events (sv_timing) */
     int32_t jit;           /* run-time specialised tile passes: 0 auto (n >= 18), 1 always, -1 never */
     int32_t reserved[3];
@@ -223,6 +224,27 @@ sv_status sv_timing(sv_ctx ctx, double* tile_ms, int64_t* tile_launches, double*
  * Usable without a GPU. */
 sv_status sv_plan_info(const sv_circuit* circuit, sv_dtype dtype, int32_t adjoint, const sv_opts* opts,
                        sv_stats* stats);
+
+/* Host-only trace of the fused plan of `circuit` (parameters of one state in
+ * `params`, NULL when n_params == 0): the operations the tile passes apply,
+ * in order, in global-qubit terms (Sec. 4.3 phase forms, Sec. 4.4 butterflies,
+ * dense and diagonal blocks, scales).  One text line per operation:
+ *   PASS q...            local qubits of a tile pass
+ *   PHASE q0 q1 q2 q3    qubits of a register phase
+ *   BF q m p...          (x, y) <- (x + t y, x - t y) on qubit q, y = bit set,
+ *                        t = e^{i pi m/4} (-1)^(sum of the bits of qubits p)
+ *   FORM c aQ:v... bA,B:v...  multiply amplitude j by e^{i pi e(j)/4},
+ *                        e = c + sum v j_Q + sum v j_A j_B
+ *   DENSE k q... (re im)...   row-major 2^k x 2^k matrix, local bit t = qubit q[t]
+ *   DIAG k q... (re im)...    2^k diagonal entries
+ *   SCALE s              multiply every amplitude by s
+ *   GRAD p gen s q...    adjoint plans: parameter p gains s * Im<lambda|G|psi>, G = X, Y,
+ *                        Z (gen 1, 2, 3) on q or -2|11><11| (gen 4) on q0 q1
+ * Product-state folding of leading gates is off for the trace.  Writes at
+ * most cap-1 bytes plus a NUL to buf and the full length to *len.  Usable
+ * without a GPU. */
+sv_status sv_plan_trace(const sv_circuit* circuit, const double* params, sv_dtype dtype, int32_t adjoint,
+                        const sv_opts* opts, char* buf, size_t cap, size_t* len);
 
 /* Wait for the context's stream and report any device error. */
 sv_status sv_sync(sv_ctx ctx);

@@ -101,13 +101,16 @@ _lib.sv_sync.argtypes = [_vp]
 _lib.sv_timing.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_int64), _dp]
 _lib.sv_plan_info.argtypes = [ctypes.POINTER(SvCircuit), ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(SvOpts),
                               ctypes.POINTER(SvStats)]
+_lib.sv_plan_trace.argtypes = [ctypes.POINTER(SvCircuit), _dp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(SvOpts),
+                               ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
 for _f in ("sv_create", "sv_destroy", "sv_set_stream", "sv_set_opts", "sv_init", "sv_apply_circuit",
-           "sv_expect", "sv_norm", "sv_adjoint_grad", "sv_apply_batch", "sv_sync", "sv_timing", "sv_plan_info"):
+           "sv_expect", "sv_norm", "sv_adjoint_grad", "sv_apply_batch", "sv_sync", "sv_timing", "sv_plan_info",
+           "sv_plan_trace"):
     getattr(_lib, _f).restype = ctypes.c_int32
 
 EXPORTED = ("sv_opts_default", "sv_create", "sv_destroy", "sv_set_stream", "sv_set_opts", "sv_init",
             "sv_apply_circuit", "sv_expect", "sv_norm", "sv_adjoint_grad", "sv_apply_batch", "sv_sync",
-            "sv_timing", "sv_plan_info", "sv_last_error", "sv_version")
+            "sv_timing", "sv_plan_info", "sv_plan_trace", "sv_last_error", "sv_version")
 
 
 class SvError(RuntimeError):
@@ -302,6 +305,22 @@ def plan_info(circ, dtype=torch.complex64, adjoint=False, opts: Optional[SvOpts]
     _check(_lib.sv_plan_info(ctypes.byref(c.c), SV_C64 if dtype == torch.complex64 else SV_C128,
                              1 if adjoint else 0, ctypes.byref(o), ctypes.byref(st)))
     return st.as_dict()
+
+
+def plan_trace(circ, params=None, dtype=torch.complex64, adjoint=False, opts: Optional[SvOpts] = None) -> str:
+    """Host-only trace of the fused plan (sv_plan_trace); no GPU needed."""
+    c = _as_circuit(circ)
+    pr = None
+    if c.n_params:
+        pr = np.ascontiguousarray(np.asarray(params, np.float64).reshape(-1))
+    o = opts if opts is not None else make_opts()
+    n = ctypes.c_size_t(0)
+    args = (ctypes.byref(c.c), pr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if pr is not None else None,
+            SV_C64 if dtype == torch.complex64 else SV_C128, 1 if adjoint else 0, ctypes.byref(o))
+    _check(_lib.sv_plan_trace(*args, None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value + 1)
+    _check(_lib.sv_plan_trace(*args, buf, n.value + 1, ctypes.byref(n)))
+    return buf.value.decode()
 
 
 def apply_batch(circuits: Sequence, params: Sequence, states: Sequence[torch.Tensor],

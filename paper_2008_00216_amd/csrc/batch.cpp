@@ -463,7 +463,8 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
             const int np = items[i].circuit->n_params;
             for (int p = 0; p < np; ++p) grads[goff + p] = 0.0;
             const EncodedPlan& B = H[i].pb->ep;
-            for (int s = 0; s < B.ngrad_total; ++s) grads[goff + B.grad_param[s]] += out[gslot0[i] + s];
+            for (int s = 0; s < B.ngrad_total; ++s)
+                grads[goff + B.grad_param[s]] += B.grad_scale[s] * out[gslot0[i] + s];
             goff += (size_t)np;
         }
     }

@@ -617,7 +617,7 @@ sv_status sv_adjoint_grad(sv_ctx c, const sv_circuit* circ, const double* params
         if (np > 0) {
             double* g = grad_out + (size_t)b * np;
             for (int p = 0; p < np; ++p) g[p] = 0.0;
-            for (int s = 0; s < ns; ++s) g[cp->ep.grad_param[s]] += row[s];
+            for (int s = 0; s < ns; ++s) g[cp->ep.grad_param[s]] += cp->ep.grad_scale[s] * row[s];
         }
     }
     if (stats) stats->plan_ms += plan_ms;
@@ -689,6 +689,42 @@ sv_status sv_plan_info(const sv_circuit* circ, sv_dtype dtype, int32_t adjoint, 
     fill_stats(stats, &c, cp, circ, 0.0, pi.folded, pi.used);
     stats->plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     stats->reserved = (int32_t)plan_ms;
+    return SV_OK;
+}
+
+sv_status sv_plan_trace(const sv_circuit* circ, const double* params, sv_dtype dtype, int32_t adjoint,
+                        const sv_opts* opts, char* buf, size_t cap, size_t* len) {
+    if (!circ || !len) return fail(SV_EINVAL, "circuit or len is NULL");
+    if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "bad dtype");
+    std::string v = validate_circuit(circ, circ->n_qubits);
+    if (!v.empty()) return fail(SV_EINVAL, v);
+    if (circ->n_params > 0 && !params) return fail(SV_EINVAL, "params is NULL");
+    sv_ctx_s c;
+    c.n = circ->n_qubits;
+    c.dtype = dtype;
+    c.batch = 1;
+    if (opts) c.opts = *opts; else sv_opts_default(&c.opts);
+    if (use_plain(&c)) return fail(SV_EUNSUPPORTED, "the plain path has no fused plan to trace");
+    BuildOpts bo;
+    bo.batch = 1;
+    bo.structured = c.opts.structured != 0;
+    bo.fuse = true;
+    bo.backward = adjoint != 0;
+    bo.product_init = false;
+    std::string tr;
+    try {
+        std::vector<IRGate> ir = build_ir(circ, params, bo, nullptr, c.n);
+        EncodedPlan ep;
+        plan_fused(ir, c.n, cfg_for(&c, adjoint != 0), ep, &tr);
+    } catch (const std::exception& e) {
+        return fail(SV_EUNSUPPORTED, std::string("planning failed: ") + e.what());
+    }
+    *len = tr.size();
+    if (buf && cap) {
+        const size_t m = std::min(cap - 1, tr.size());
+        std::memcpy(buf, tr.data(), m);
+        buf[m] = '\0';
+    }
     return SV_OK;
 }
 

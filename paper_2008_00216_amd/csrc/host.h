@@ -31,7 +31,8 @@ struct IRGate {
     int q[6] = {0, 0, 0, 0, 0, 0};
     int alpha[2] = {0, 0};     // DIAG8 linear exponents (mod 8) on q[0], q[1]
     int beta = 0;              // DIAG8 pair exponent on (q[0], q[1])
-    int skind = 0;             // structured op (OP_HP, OP_XP, OP_YP, OP_WP) or 0
+    int skind = 0;             // OP_BF: w^g diag(1, w^post) H' diag(1, w^pre) / sqrt(2), else 0
+    int bf_pre = 0, bf_post = 0, bf_g = 0;   // exponents of w = e^{i pi/4} (mod 8)
     int perm = PK_NONE;        // exact permutation gate (plain path)
     int src = -1;              // first source gate
     int param = -1;            // parameter index (unfused parameterised gate)
@@ -126,6 +127,7 @@ struct EncodedPlan {
     uint64_t gpart_size = 0;     // doubles per state (gradient partials)
     int ngrad_total = 0;
     std::vector<int> grad_param; // grad slot (global) -> parameter index
+    std::vector<double> grad_scale; // grad slot -> factor undoing the butterflies' growth at the reduction
     std::vector<uint64_t> grad_slot_off;  // per pass: first global grad slot
     // statistics
     int n_dense = 0, n_diag = 0, n_phase = 0, n_tile = 0, n_plain = 0;
@@ -133,7 +135,8 @@ struct EncodedPlan {
 };
 
 // Plan a fused sweep (tile passes) for an IR gate list.
-void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, EncodedPlan& out);
+void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, EncodedPlan& out,
+                std::string* trace = nullptr);
 // Plan a plain sweep (one kernel per gate).
 void plan_plain(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, EncodedPlan& out);
 

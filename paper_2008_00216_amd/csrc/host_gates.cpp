@@ -239,14 +239,36 @@ int perm_of(int op) {
     }
 }
 
-int skind_of(int op) {
+// The one-qubit gates of the benchmark family as one unnormalised butterfly
+// H' = [[1,1],[1,-1]] between 8th-root diagonals:  G = w^g diag(1, w^post)
+// H' diag(1, w^pre) / sqrt(2),  w = e^{i pi/4}.  With the principal roots
+// (sqrt(G) = ((1+i)/2) I + ((1-i)/2) G) and W = (X+Y)/sqrt(2) = T X T^dag:
+//   H = H'/sqrt(2);  sqrt(X) = w S^dag H S^dag;  sqrt(Y) = w H Z;
+//   sqrt(W) = T sqrt(X) T^dag = w (T S^dag) H (S^dag T^dag),
+// and the conjugate transposes for the adjoint sweep.  Returns false for
+// other gates.
+bool butterfly_form(int op, bool inv, int& pre, int& post, int& g) {
+    int a = -1, b = -1, c = 0;
     switch (op) {
-        case SV_OP_H: return OP_HP;
-        case SV_OP_SQRTX: return OP_XP;
-        case SV_OP_SQRTY: return OP_YP;
-        case SV_OP_SQRTW: return OP_WP;
-        default: return 0;
+        case SV_OP_H: a = 0; b = 0; c = 0; break;
+        case SV_OP_SQRTX: a = 6; b = 6; c = 1; break;
+        case SV_OP_SQRTY: a = 4; b = 0; c = 1; break;
+        case SV_OP_SQRTW: a = 5; b = 7; c = 1; break;
+        case SV_OP_SQRTXDG: a = 2; b = 2; c = 7; break;
+        case SV_OP_SQRTYDG: a = 0; b = 4; c = 7; break;
+        case SV_OP_SQRTWDG: a = 1; b = 3; c = 7; break;
+        default: return false;
     }
+    if (inv) {  // (w^c D_b H' D_a)^dag = w^-c D_-a H' D_-b
+        pre = (8 - b) & 7;
+        post = (8 - a) & 7;
+        g = (8 - c) & 7;
+    } else {
+        pre = a;
+        post = b;
+        g = c;
+    }
+    return true;
 }
 
 // One IR gate from a circuit gate (inverse = conjugate transpose when `inv`).
@@ -267,7 +289,7 @@ IRGate make_ir(const sv_circuit* c, int gi, const double* params, const BuildOpt
     }
     const bool diag = g.op == SV_OP_RZ || g.op == SV_OP_P || g.op == SV_OP_CP;
     r.kind = diag ? K_DIAGG : K_DENSE;
-    if (!diag && o.structured && !inv) r.skind = skind_of(g.op);
+    if (!diag && o.structured && butterfly_form(g.op, inv, r.bf_pre, r.bf_post, r.bf_g)) r.skind = OP_BF;
     r.perm = inv && g.op == SV_OP_Y ? PK_Y : perm_of(g.op);
     const int d = 1 << g.nq;
     const int nb = (g.param >= 0) ? o.batch : 1;

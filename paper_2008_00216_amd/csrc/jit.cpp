@@ -45,16 +45,6 @@ uint64_t fnv(const std::string& s) {
     return h;
 }
 
-const char* kOpName(uint32_t t) {
-    switch (t) {
-        case OP_HP: return "OP_HP";
-        case OP_XP: return "OP_XP";
-        case OP_YP: return "OP_YP";
-        case OP_WP: return "OP_WP";
-        default: return "0";
-    }
-}
-
 std::string pass_source(const EncodedPlan& ep, int pi, int dtype, bool two, int nt) {
     const DPass& P = ep.passes[pi];
     const char* R = dtype == SV_C64 ? "float" : "double";
@@ -101,10 +91,20 @@ std::string pass_source(const EncodedPlan& ep, int pi, int dtype, bool two, int 
                     o << "      op_diag<R, " << op.mask << ">(a, F.pool + " << op.arg << ");\n";
                     if (two) o << "      op_diag<R, " << op.mask << ">(l, F.pool + " << op.arg << ");\n";
                     break;
-                case OP_HP: case OP_XP: case OP_YP: case OP_WP: {
-                    const int s = __builtin_ctz(op.mask);
-                    o << "      op_struct<R, " << s << ", " << kOpName(op.type) << ">(a, cw);\n";
-                    if (two) o << "      op_struct<R, " << s << ", " << kOpName(op.type) << ">(l, cw);\n";
+                case OP_BF: {
+                    const uint32_t M = op.k & 7u, S = (op.k >> 4) & 3u, RM = op.k >> 8;
+                    const uint64_t gm = op.arg == kNoPair ? 0ull : ep.pairs[op.arg].m[0];
+                    const bool rt = op.mask != 0 || gm != 0;
+                    o << "      { ";
+                    if (rt)
+                        o << "const R s_ = bf_parity(lb, " << op.mask << "u, F.base, " << gm << "ull) ? R(-1) : R(1); ";
+                    else
+                        o << "const R s_ = R(1); ";
+                    const std::string targs = std::to_string(S) + ", " + std::to_string(M) + ", " + std::to_string(RM) +
+                                              ", " + (rt ? "true" : "false");
+                    o << "op_bf<R, " << targs << ">(a, s_, cw);";
+                    if (two) o << " op_bf<R, " << targs << ">(l, s_, cw);";
+                    o << " }\n";
                     break;
                 }
                 case OP_SCALE:

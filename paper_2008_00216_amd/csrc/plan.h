@@ -7,9 +7,11 @@
 // plus H higher bits) into LDS, applies a list of register phases, and writes
 // the tile back.  A register phase gives each thread the 16 amplitudes that
 // differ in 4 chosen local bits ("register slots") and runs an op list on
-// them in registers: dense blocks on up to 4 slots, diagonals, the 8th-root
-// phase form of clustered T/S/Z/CZ gates (Sec. 4.3) and, for the adjoint
-// sweep, gradient reductions.
+// them in registers: dense blocks on up to 4 slots, diagonals, twiddled H'
+// butterflies (Sec. 4.4's multiply-free one-qubit gates with the pending
+// diagonal phases of Sec. 4.3 folded in), the 8th-root phase form of
+// clustered T/S/Z/CZ gates (Sec. 4.3) and, for the adjoint sweep, gradient
+// reductions.
 //
 // All structures are plain data; the planner fills them on the host and
 // copies them to one device buffer per plan.
@@ -33,11 +35,17 @@ enum OpType : uint32_t {
     OP_SIGN = 4,    // same with every exponent in {0, 4}
     OP_GRAD = 5,    // Im<lambda|G|psi> over slots `mask`, generator `k`, pass-local slot `arg`
     OP_SCALE = 6,   // multiply by the real scalar at pool element `arg` (.x)
-    OP_HP = 7,      // H' = [[1,1],[1,-1]] on slot (multiply-free)
-    OP_XP = 8,      // sqrt(X)' = [[1+i,1-i],[1-i,1+i]]
-    OP_YP = 9,      // sqrt(Y)' = [[1+i,-1-i],[1+i,1+i]]
-    OP_WP = 10,     // sqrt(2) sqrt(W) = [[w, -i],[1, w]], w = e^{i pi/4}
+    OP_BF = 11,     // twiddled butterfly, see below
 };
+
+// OP_BF on register slot S: for every pair (x, y) of amplitudes that differ
+// only in slot S (y has the bit set),
+//     x <- x + t y,   y <- x - t y,   t = w^M (-1)^(parity of the index bits in
+// the partner set),  w = e^{i pi/4}.
+// Encoding: k = M | S << 4 | RM << 8 (RM: partner register slots); mask =
+// partner tile-local positions outside the registers; arg = index of a DPair
+// whose m[0] holds the partner nonlocal qubits, or kNoPair.
+constexpr uint32_t kNoPair = 0xffffffffu;
 
 enum GradGen : uint32_t { GEN_X = 1, GEN_Y = 2, GEN_Z = 3, GEN_P11 = 4 };
 

@@ -13,7 +13,9 @@
 // same way over 4-subsets of the local bits.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <string>
 #include <map>
 #include <stdexcept>
 
@@ -318,13 +320,53 @@ double op_cost(const IRGate& g) {
     if (g.kind == K_DIAG8) return 0.0;
     if (g.grad) return 6.0;
     if (g.kind == K_DIAGG) return 6.0;
-    if (g.skind) return g.skind == OP_WP ? 12.0 : (g.skind == OP_HP ? 4.0 : 8.0);
+    if (g.skind) return 4.0;
     return 8.0 * (double)(1 << g.k);
 }
 
 }  // namespace
 
-void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, EncodedPlan& out) {
+namespace {
+
+// Planner trace: the plan's arithmetic in global-qubit terms, one op per line
+// (pass/phase markers, butterflies with their twiddle and partner qubits,
+// flushed phase forms, dense and diagonal blocks with their matrices, pass
+// scales, gradient reductions).  Used to check the planner's algebra on the
+// host against an independent evaluation.
+void trace_matrix(std::string* tr, const char* tag, const IRGate& g) {
+    if (!tr) return;
+    char b[64];
+    *tr += tag;
+    std::snprintf(b, sizeof(b), " %d", g.k);
+    *tr += b;
+    for (int t = 0; t < g.k; ++t) { std::snprintf(b, sizeof(b), " %d", g.q[t]); *tr += b; }
+    const cd* m = g.m.at(0);
+    const size_t cnt = g.m.diag ? (size_t)g.m.d : (size_t)g.m.d * g.m.d;
+    for (size_t i = 0; i < cnt; ++i) {
+        std::snprintf(b, sizeof(b), " %.17g %.17g", m[i].real(), m[i].imag());
+        *tr += b;
+    }
+    *tr += "\n";
+}
+
+void trace_form(std::string* tr, const Form& F) {
+    if (!tr) return;
+    char b[64];
+    std::snprintf(b, sizeof(b), "FORM %d", F.konst & 7);
+    *tr += b;
+    for (int q = 0; q < 64; ++q)
+        if (F.alpha[q] & 7) { std::snprintf(b, sizeof(b), " a%d:%d", q, F.alpha[q] & 7); *tr += b; }
+    for (auto& kv : F.beta)
+        if (kv.second & 7) {
+            std::snprintf(b, sizeof(b), " b%d,%d:%d", kv.first.first, kv.first.second, kv.second & 7);
+            *tr += b;
+        }
+    *tr += "\n";
+}
+
+}  // namespace
+
+void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, EncodedPlan& out, std::string* tr) {
     out = EncodedPlan();
     out.cfg = cfg;
     out.n = n;
@@ -344,6 +386,11 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
     std::vector<int> rem(ir.size());
     for (size_t i = 0; i < ir.size(); ++i) rem[i] = (int)i;
     uint64_t grad_base = 0;
+    // Diagonal phases not applied yet (Sec. 4.3's clustered T/S/Z/CZ plus the
+    // side phases of the butterflies).  They stay pending across passes: a
+    // butterfly on qubit q takes over the part that depends on q as its
+    // twiddle, so most of them are never applied as separate ops.
+    Form pending;
 
     while (!rem.empty()) {
         // ---- choose the local set S (|S| = T, low bits always local)
@@ -422,6 +469,7 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
             st.recipe = (int)out.recipes.size() - 1;
             out.steps.push_back(st);
             out.n_plain++;
+            trace_matrix(tr, g.kind == K_DIAGG ? "DIAG" : "DENSE", g);
             out.flops += 8.0 * (double)(1 << g.k) * (double)(1ull << n);
             rem.erase(std::find(rem.begin(), rem.end(), id));
             continue;
@@ -437,12 +485,29 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
         P.phase0 = (uint32_t)out.phases.size();
         P.form0 = (uint32_t)out.forms.size();
         uint32_t nform = 0, ngrad = 0;
+        if (tr) {
+            *tr += "PASS";
+            for (int a = 0; a < G.T; ++a) *tr += " " + std::to_string(G.gq[a]);
+            *tr += "\n";
+        }
 
         // phases
         std::vector<int> prem = ex;
-        std::vector<GInfo> linf(ir.size());
-        Form pending;
-        int scale_p = 0;   // accumulated power of 1/sqrt(2) from structured ops
+        int scale_p = 0;   // accumulated power of 1/sqrt(2) from the butterflies
+        // pending phases must be applied at the end of this pass when no pass
+        // follows or a plain (wide-gate) step may come next
+        bool flush_at_end = false;
+        {
+            std::vector<char> inpass(ir.size(), 0);
+            for (int id : ex) inpass[id] = 1;
+            bool any_left = false;
+            for (int id : rem) {
+                if (inpass[id]) continue;
+                any_left = true;
+                if (inf[id].cls == C_BIG) flush_at_end = true;
+            }
+            if (!any_left) flush_at_end = true;
+        }
         std::vector<int> combos;
         for (int a = 0; a < G.T; ++a)
             for (int b = a + 1; b < G.T; ++b)
@@ -480,9 +545,13 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
             Ph.rpos = (uint32_t)(r[0] | (r[1] << 8) | (r[2] << 16) | (r[3] << 24));
             if (c64) soff_for<float>(r, Ph.soff); else soff_for<double>(r, Ph.soff);
             Ph.op0 = (uint32_t)out.ops.size();
+            if (tr)
+                *tr += "PHASE " + std::to_string(G.gq[r[0]]) + " " + std::to_string(G.gq[r[1]]) + " " +
+                       std::to_string(G.gq[r[2]]) + " " + std::to_string(G.gq[r[3]]) + "\n";
             auto flush = [&](bool force) {
                 if (pending.empty()) { pending.clear(); return; }
                 (void)force;
+                trace_form(tr, pending);
                 const bool so = pending.sign_only();
                 const int fi = encode_form(pending, G, r, n, out, nform++);
                 DOp op{so ? (uint32_t)OP_SIGN : (uint32_t)OP_PHASE8, 0u, 0u, (uint32_t)fi};
@@ -497,7 +566,6 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
                     pending.add(g);
                     continue;
                 }
-                if (pending.depends(g.qmask())) flush(false);
                 int slot_of_q[6];
                 for (int t = 0; t < g.k; ++t) {
                     const int lp = G.lpos[g.q[t]];
@@ -505,12 +573,68 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
                     for (int u = 0; u < 4; ++u) if (r[u] == lp) s = u;
                     slot_of_q[t] = s;
                 }
+                if (g.skind == OP_BF) {
+                    const int q = g.q[0];
+                    // the part of the pending phase that depends on q must be
+                    // w^m (-1)^(sum of partner bits): pair exponents 0 or 4
+                    for (auto& kv : pending.beta)
+                        if ((kv.second & 3) && (kv.first.first == q || kv.first.second == q)) {
+                            flush(false);
+                            break;
+                        }
+                    const int M = (pending.alpha[q] + g.bf_pre) & 7;
+                    uint32_t RM = 0, lmask = 0;
+                    uint64_t gmask = 0;
+                    std::string partners;
+                    for (auto it = pending.beta.begin(); it != pending.beta.end();) {
+                        const int a = it->first.first, b = it->first.second;
+                        if (a != q && b != q) { ++it; continue; }
+                        if (it->second & 7) {
+                            const int p = a == q ? b : a;
+                            partners += " " + std::to_string(p);
+                            const int lp = G.lpos[p];
+                            int su = -1;
+                            for (int u = 0; u < 4; ++u) if (r[u] == lp) su = u;
+                            if (lp < 0) gmask |= 1ull << p;
+                            else if (su >= 0) RM |= 1u << su;
+                            else lmask |= 1u << lp;
+                        }
+                        it = pending.beta.erase(it);
+                    }
+                    pending.alpha[q] = g.bf_post & 7;
+                    pending.konst = (pending.konst + g.bf_g) & 7;
+                    uint32_t pa = kNoPair;
+                    if (gmask) {
+                        DPair pr;
+                        std::memset(&pr, 0, sizeof(pr));
+                        pr.m[0] = gmask;
+                        pa = (uint32_t)out.pairs.size();
+                        out.pairs.push_back(pr);
+                    }
+                    DOp op{(uint32_t)OP_BF, (uint32_t)(M | (slot_of_q[0] << 4) | (RM << 8)), lmask, pa};
+                    out.ops.push_back(op);
+                    if (tr) *tr += "BF " + std::to_string(q) + " " + std::to_string(M) + partners + "\n";
+                    scale_p += 1;
+                    out.n_dense++;
+                    out.flops += ((M & 1) ? 5.0 : 2.0) * (double)(1ull << n) * (cfg.two ? 2 : 1);
+                    continue;
+                }
+                if (pending.depends(g.qmask())) flush(false);
                 if (g.grad) {
                     uint32_t mask = 0;
                     for (int t = 0; t < g.k; ++t) mask |= 1u << slot_of_q[t];
                     DOp op{(uint32_t)OP_GRAD, (uint32_t)g.gen, mask, ngrad};
                     out.ops.push_back(op);
+                    if (tr) {
+                        char b[64];
+                        std::snprintf(b, sizeof(b), "GRAD %d %d %.17g", g.param, g.gen, std::ldexp(1.0, -scale_p));
+                        *tr += b;
+                        for (int t = 0; t < g.k; ++t) *tr += " " + std::to_string(g.q[t]);
+                        *tr += "\n";
+                    }
                     out.grad_param.push_back(g.param);
+                    // psi and lambda both carry sqrt(2)^scale_p at this point of the pass
+                    out.grad_scale.push_back(std::ldexp(1.0, -scale_p));
                     ++ngrad;
                     continue;
                 }
@@ -518,19 +642,12 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
                 rc.gate = id;
                 uint32_t mask = 0;
                 slot_perm(g, slot_of_q, rc, mask);
-                if (g.skind) {
-                    DOp op{(uint32_t)g.skind, 1u, mask, 0u};
-                    out.ops.push_back(op);
-                    scale_p += (g.skind == OP_XP || g.skind == OP_YP) ? 2 : 1;
-                    out.n_dense++;
-                    out.flops += op_cost(g) * 0.5 * (double)(1ull << n) * (cfg.two ? 2 : 1);
-                    continue;
-                }
                 if (g.kind == K_DIAGG) {
                     rc.type = Recipe::DIAG;
                     const uint64_t off = add_recipe(out, rc, ir);
                     DOp op{(uint32_t)OP_DIAGR, (uint32_t)g.k, mask, (uint32_t)off};
                     out.ops.push_back(op);
+                    trace_matrix(tr, "DIAG", g);
                     out.n_diag++;
                     out.flops += 6.0 * (double)(1ull << n) * (cfg.two ? 2 : 1);
                 } else {
@@ -538,6 +655,7 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
                     const uint64_t off = add_recipe(out, rc, ir);
                     DOp op{(uint32_t)OP_DENSE, (uint32_t)g.k, mask, (uint32_t)off};
                     out.ops.push_back(op);
+                    trace_matrix(tr, "DENSE", g);
                     out.n_dense++;
                     out.flops += 8.0 * (double)(1 << g.k) * (double)(1ull << n) * (cfg.two ? 2 : 1);
                 }
@@ -551,7 +669,7 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
                 prem.swap(nr);
             }
             if (prem.empty()) {
-                flush(true);
+                if (flush_at_end) flush(true);
                 if (scale_p) {
                     Recipe rc;
                     rc.type = Recipe::SCALE;
@@ -559,6 +677,11 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
                     const uint64_t off = add_recipe(out, rc, ir);
                     DOp op{(uint32_t)OP_SCALE, 0u, 0u, (uint32_t)off};
                     out.ops.push_back(op);
+                    if (tr) {
+                        char b[64];
+                        std::snprintf(b, sizeof(b), "SCALE %.17g\n", rc.scale);
+                        *tr += b;
+                    }
                 }
             }
             Ph.nop = (uint32_t)(out.ops.size() - Ph.op0);
@@ -612,6 +735,7 @@ void plan_plain(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
             st.mode = g.gen;
             st.slot = grad_slot++;
             out.grad_param.push_back(g.param);
+            out.grad_scale.push_back(1.0);
             out.steps.push_back(st);
             continue;
         }

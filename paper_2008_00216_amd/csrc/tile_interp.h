@@ -55,13 +55,13 @@ __device__ __forceinline__ void diag_dispatch(V2<R>* a, uint32_t mask, const V2<
     }
 }
 
-template <class R, uint32_t KIND>
-__device__ __forceinline__ void struct_dispatch(V2<R>* a, uint32_t mask, R c) {
-    switch (mask) {
-        case 1: op_struct<R, 0, KIND>(a, c); break;
-        case 2: op_struct<R, 1, KIND>(a, c); break;
-        case 4: op_struct<R, 2, KIND>(a, c); break;
-        case 8: op_struct<R, 3, KIND>(a, c); break;
+template <class R>
+__device__ __forceinline__ void bf_dispatch(V2<R>* a, uint32_t slot, uint32_t M, uint32_t RM, R s, const V2<R>* ptab) {
+    switch (slot) {
+        case 0: op_bf_rt<R, 0>(a, M, RM, s, ptab); break;
+        case 1: op_bf_rt<R, 1>(a, M, RM, s, ptab); break;
+        case 2: op_bf_rt<R, 2>(a, M, RM, s, ptab); break;
+        case 3: op_bf_rt<R, 3>(a, M, RM, s, ptab); break;
         default: break;
     }
 }
@@ -140,22 +140,12 @@ __device__ __forceinline__ void tile_interp(const TileArgs& A, unsigned char* sm
                         diag_dispatch<R>(a, mask, F.pool + arg);
                         if constexpr (TWO) diag_dispatch<R>(l, mask, F.pool + arg);
                         break;
-                    case OP_HP:
-                        struct_dispatch<R, OP_HP>(a, mask, R(0));
-                        if constexpr (TWO) struct_dispatch<R, OP_HP>(l, mask, R(0));
-                        break;
-                    case OP_XP:
-                        struct_dispatch<R, OP_XP>(a, mask, R(0));
-                        if constexpr (TWO) struct_dispatch<R, OP_XP>(l, mask, R(0));
-                        break;
-                    case OP_YP:
-                        struct_dispatch<R, OP_YP>(a, mask, R(0));
-                        if constexpr (TWO) struct_dispatch<R, OP_YP>(l, mask, R(0));
-                        break;
-                    case OP_WP: {
-                        const R c = F.ptab[1].x;  // cos(pi/4) in the state dtype
-                        struct_dispatch<R, OP_WP>(a, mask, c);
-                        if constexpr (TWO) struct_dispatch<R, OP_WP>(l, mask, c);
+                    case OP_BF: {
+                        const uint32_t kk = rfl(op.k);
+                        const uint64_t gm = arg == kNoPair ? 0ull : A.pairs[arg].m[0];
+                        const R sg = bf_parity(lb, mask, F.base, gm) ? R(-1) : R(1);
+                        bf_dispatch<R>(a, (kk >> 4) & 3u, kk & 7u, kk >> 8, sg, F.ptab);
+                        if constexpr (TWO) bf_dispatch<R>(l, (kk >> 4) & 3u, kk & 7u, kk >> 8, sg, F.ptab);
                         break;
                     }
                     case OP_SCALE: {

@@ -41,35 +41,75 @@ __device__ __forceinline__ void op_diag(V2<R>* a, const V2<R>* __restrict__ d) {
     for (int i = 0; i < 16; ++i) a[i] = cmul(d[ext4(MASK, i)], a[i]);
 }
 
-// Multiply-free one-qubit kernels on slot S for the factored matrices of
-// Sec. 4.4 (entries +-1, +-i); the leading 1/sqrt(2) and 1/2 factors are
-// applied once per pass (op_scale).  WP is sqrt(2) sqrt(W) = [[w,-i],[1,w]]
-// with w = e^{i pi/4} = c (1 + i).
-template <class R, int S, uint32_t KIND>
-__device__ __forceinline__ void op_struct(V2<R>* a, R c) {
+// Twiddled butterfly on slot S (OP_BF): for each pair (x, y), y the member
+// with the slot bit set, x <- x + t y and y <- x - t y with
+// t = k w^M (-1)^(parity of the register slots RM in the pair index),
+// w = e^{i pi/4}.  k = +-1 is the thread's sign from partner bits outside the
+// registers (RT) or 1.  w^M y = i^(M/2) y for even M and
+// i^((M-1)/2) c (y.x - y.y, y.x + y.y) for odd M (c = cos(pi/4)), so an even
+// twiddle costs 4 adds or FMAs per pair and an odd one 6.  The 1/sqrt(2) of
+// every butterfly is applied once per pass (op_scale).
+template <class R, int S, int M, int RM, bool RT>
+__device__ __forceinline__ void op_bf(V2<R>* a, R s, R c) {
+    constexpr int j = (M >> 1) & 3;
+    constexpr bool odd = (M & 1) != 0;
+    const R kk = odd ? (RT ? s * c : c) : (RT ? s : R(1));
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         if (i & (1 << S)) continue;
         const V2<R> x = a[i], y = a[i | (1 << S)];
-        V2<R> o0, o1;
-        if constexpr (KIND == OP_HP) {           // [[1,1],[1,-1]]
-            o0 = V2<R>{x.x + y.x, x.y + y.y};
-            o1 = V2<R>{x.x - y.x, x.y - y.y};
-        } else if constexpr (KIND == OP_XP) {    // [[1+i,1-i],[1-i,1+i]]: s +- i d
-            const V2<R> s{x.x + y.x, x.y + y.y}, d{x.x - y.x, x.y - y.y};
-            o0 = V2<R>{s.x - d.y, s.y + d.x};
-            o1 = V2<R>{s.x + d.y, s.y - d.x};
-        } else if constexpr (KIND == OP_YP) {    // [[1+i,-1-i],[1+i,1+i]]: (1+i)d, (1+i)s
-            const V2<R> s{x.x + y.x, x.y + y.y}, d{x.x - y.x, x.y - y.y};
-            o0 = V2<R>{d.x - d.y, d.x + d.y};
-            o1 = V2<R>{s.x - s.y, s.x + s.y};
-        } else {                                 // [[w,-i],[1,w]]
-            o0 = V2<R>{fma_(c, x.x - x.y, y.y), fma_(c, x.x + x.y, -y.x)};
-            o1 = V2<R>{fma_(c, y.x - y.y, x.x), fma_(c, y.x + y.y, x.y)};
+        const bool neg = (__builtin_popcount(i & RM) & 1) != 0;
+        R z0, z1;
+        if constexpr (odd) {
+            z0 = y.x - y.y;
+            z1 = y.x + y.y;
+        } else {
+            z0 = y.x;
+            z1 = y.y;
         }
-        a[i] = o0;
-        a[i | (1 << S)] = o1;
+        // t y = (g0 p0, g1 p1) with g = +-k
+        R p0, p1;
+        bool n0, n1;
+        if constexpr (j == 0) { p0 = z0; p1 = z1; n0 = false; n1 = false; }
+        else if constexpr (j == 1) { p0 = z1; p1 = z0; n0 = true; n1 = false; }
+        else if constexpr (j == 2) { p0 = z0; p1 = z1; n0 = true; n1 = true; }
+        else { p0 = z1; p1 = z0; n0 = false; n1 = true; }
+        n0 = n0 != neg;
+        n1 = n1 != neg;
+        if constexpr (!odd && !RT) {
+            const R q0 = n0 ? -p0 : p0, q1 = n1 ? -p1 : p1;
+            a[i] = V2<R>{x.x + q0, x.y + q1};
+            a[i | (1 << S)] = V2<R>{x.x - q0, x.y - q1};
+        } else {
+            const R g0 = n0 ? -kk : kk, g1 = n1 ? -kk : kk;
+            a[i] = V2<R>{fma_(g0, p0, x.x), fma_(g1, p1, x.y)};
+            a[i | (1 << S)] = V2<R>{fma_(-g0, p0, x.x), fma_(-g1, p1, x.y)};
+        }
     }
+}
+
+// Same with M and RM known only at run time (interpreter): one complex
+// multiply by the twiddle w^M k from the phase table per pair.
+template <class R, int S>
+__device__ __forceinline__ void op_bf_rt(V2<R>* a, uint32_t M, uint32_t RM, R s, const V2<R>* ptab) {
+    const V2<R> w = ptab[M & 7u];
+    const V2<R> t0{s * w.x, s * w.y};
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (i & (1 << S)) continue;
+        const V2<R> x = a[i], y = a[i | (1 << S)];
+        const bool neg = (__builtin_popcount((uint32_t)i & RM) & 1) != 0;
+        const V2<R> t = neg ? V2<R>{-t0.x, -t0.y} : t0;
+        const V2<R> ty = cmul(t, y);
+        a[i] = V2<R>{x.x + ty.x, x.y + ty.y};
+        a[i | (1 << S)] = V2<R>{x.x - ty.x, x.y - ty.y};
+    }
+}
+
+// Thread sign of a butterfly: (-1)^(parity of the partner bits of the
+// thread's tile-local index lb and of the tile's global base).
+__device__ __forceinline__ uint32_t bf_parity(uint32_t lb, uint32_t lmask, uint64_t base, uint64_t gmask) {
+    return (uint32_t)(__popc(lb & lmask) + __popcll(base & gmask)) & 1u;
 }
 
 template <class R>

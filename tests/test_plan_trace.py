@@ -1,0 +1,84 @@
+"""The fused planner's algebra on the host: the plan trace evaluated from
+its definitions equals the gate-by-gate FP64 oracle (Sec. 4.5 reordering,
+Sec. 4.4 butterflies, Sec. 4.3 lazily applied phase forms)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests.trace_eval import apply_pauli_sum, evaluate
+
+
+def lib():
+    m = pytest.importorskip("paper_2008_00216_amd")
+    return m
+
+
+def _check(m, c, params=None, tile_bits=0, psi0=None, tol=1e-12, **kw):
+    opts = m.make_opts(tile_bits=tile_bits, **kw)
+    tr = m.plan_trace(c, params, opts=opts)
+    if psi0 is None:
+        psi0 = W.basis_state(c.n, 0)
+    got, _ = evaluate(tr, c.n, psi0)
+    ref = oracle.simulate(c, params, psi0=psi0)
+    assert np.max(np.abs(got - ref)) < tol, tr[:2000]
+    return tr
+
+
+def test_line_circuit_single_pass():
+    m = lib()
+    c = W.line_circuit(12, 10, seed=1000)
+    tr = _check(m, c)
+    # every non-diagonal one-qubit gate is one butterfly; T and CZ phases are
+    # absorbed into twiddles or applied once at the end
+    nbf = sum(1 for g in c.gates if g.op in ("H", "SQRTX", "SQRTY", "SQRTW"))
+    assert sum(1 for l in tr.splitlines() if l.startswith("BF ")) == nbf
+    assert tr.count("FORM") == 1
+
+
+@pytest.mark.parametrize("tile_bits", [6, 8, 10])
+def test_grid_multi_pass_carried_phases(tile_bits):
+    m = lib()
+    c = W.grid_circuit(3, 4, 12, seed=77)
+    tr = _check(m, c, tile_bits=tile_bits, low_bits=3)
+    assert tr.count("PASS") > 1
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_random_mixed_gates(seed):
+    m = lib()
+    c = W.random_circuit(9, 120, seed=seed, mat_k=(2, 3))
+    p = W.uniform_params(1, c.n_params, 50 + seed)[0]
+    psi0 = W.random_state(9, seed)
+    _check(m, c, p, tile_bits=7, low_bits=3, psi0=psi0)
+
+
+def test_wide_gates_force_flush_before_plain_steps():
+    m = lib()
+    c = W.random_circuit(8, 80, seed=9, ops=("H", "SQRTX", "SQRTY", "SQRTW", "T", "CZ", "S"), mat_k=(5, 6))
+    assert any(g.op == "MAT" and len(g.qubits) >= 5 for g in c.gates)
+    _check(m, c, tile_bits=6, low_bits=3, psi0=W.random_state(8, 5))
+
+
+def test_unstructured_mode_matches_too():
+    m = lib()
+    c = W.grid_circuit(3, 3, 8, seed=5)
+    tr = _check(m, c, tile_bits=6, low_bits=3, structured=0)
+    assert "BF" not in tr
+
+
+def test_adjoint_plan_is_the_inverse_sweep_with_shift_rule_gradients():
+    m = lib()
+    c = W.random_circuit(8, 90, seed=11, ops=("H", "SQRTX", "SQRTY", "SQRTW", "T", "TDG", "S", "CZ", "RY", "RZ",
+                                              "RX", "CP"), param_frac=1.0)
+    p = W.uniform_params(1, c.n_params, 12)[0]
+    h = W.pauli_sum([(1.0, {0: "Z", 1: "Z"}), (0.5, {2: "X"}), (-0.3, {1: "Y", 3: "Z"})])
+    tr = m.plan_trace(c, p, adjoint=True, opts=m.make_opts(tile_bits=6, low_bits=3))
+    psi0 = W.random_state(8, 3)
+    fwd = oracle.simulate(c, p, psi0=psi0)
+    (back, _), grads = evaluate(tr, 8, fwd, apply_pauli_sum(fwd, 8, h))
+    # the backward sweep un-computes psi
+    assert np.max(np.abs(back - psi0)) < 1e-12
+    ref = oracle.grad_param_shift(c, p, h, psi0)
+    got = np.array([grads[i] for i in range(c.n_params)])
+    np.testing.assert_allclose(got, ref, atol=1e-11)
