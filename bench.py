@@ -18,7 +18,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E, GB/s
-FP32_VALU_PEAK_TFLOPS = 78.6          # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA), no packed FP32
+# Vector ALU issue peak without packed FP32: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
+# = 39.3 T lane-instructions/s (an add, a multiply or an FMA each count once).
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def parse():
@@ -177,14 +179,14 @@ def main():
     per_launch_ms = tile_ms / max(1, tile_launches)
     bytes_per_launch = tile_bytes / max(1, tile_launches)
     achieved_gbs = bytes_per_launch / (per_launch_ms / 1e3) / 1e9
-    flops_tile = st["flops"]                       # algorithmic flops of the sweep (all tile passes)
-    achieved_tf = flops_tile * args.steps / (tile_ms / 1e3) / 1e12
+    ops_tile = st["alu_ops"]                       # algorithmic vector instructions per lane, all tile passes
+    achieved_tops = ops_tile * args.steps / (tile_ms / 1e3) / 1e12
     hbm_frac = achieved_gbs / HBM_PEAK_GBS
-    alu_frac = achieved_tf / FP32_VALU_PEAK_TFLOPS
+    alu_frac = achieved_tops / VALU_PEAK_TOPS
     roofline_hbm = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(hbm_frac, 4), "traffic": None}
-    roofline_alu = {"bound": "alu", "achieved": round(achieved_tf, 2), "peak": FP32_VALU_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(alu_frac, 4)}
+    roofline_alu = {"bound": "alu", "achieved": round(achieved_tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
+                    "unit": "TOP/s", "frac": round(alu_frac, 4)}
     roofline = roofline_hbm if hbm_frac >= alu_frac else dict(roofline_alu, traffic=None)
 
     out = {

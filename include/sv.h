@@ -130,7 +130,9 @@ typedef struct {
     int32_t reserved;
     double plan_ms;         /* host planning time (0 on a plan-cache hit) */
     double hbm_bytes;       /* algorithmic HBM bytes moved by the sweep */
-    double flops;           /* algorithmic floating-point operations */
+    double flops;           /* algorithmic floating-point operations (an FMA counts 2) */
+    double alu_ops;         /* algorithmic vector arithmetic instructions per lane of the
+                               tile passes (an FMA counts 1): the ALU-side roofline */
 } sv_stats;
 
 typedef struct sv_ctx_s* sv_ctx;

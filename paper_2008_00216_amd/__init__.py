@@ -67,7 +67,8 @@ class SvStats(ctypes.Structure):
     _fields_ = [("gates_in", ctypes.c_int32), ("passes", ctypes.c_int32), ("phases", ctypes.c_int32),
                 ("dense_ops", ctypes.c_int32), ("diag_ops", ctypes.c_int32), ("launches", ctypes.c_int32),
                 ("folded_init", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("plan_ms", ctypes.c_double), ("hbm_bytes", ctypes.c_double), ("flops", ctypes.c_double)]
+                ("plan_ms", ctypes.c_double), ("hbm_bytes", ctypes.c_double), ("flops", ctypes.c_double),
+                ("alu_ops", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

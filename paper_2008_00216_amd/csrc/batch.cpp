@@ -59,6 +59,7 @@ sv_status run_batch_loop(int32_t count, const sv_batch_item* items, sv_dtype dty
             stats->launches += s1.launches;
             stats->hbm_bytes += s1.hbm_bytes;
             stats->flops += s1.flops;
+            stats->alu_ops += s1.alu_ops;
             stats->plan_ms += s1.plan_ms;
         }
     }
@@ -85,7 +86,7 @@ PlanCfg batch_cfg(int dtype, bool two, int n) {
     p.dtype = dtype;
     const int T = dtype == SV_C64 ? 12 : (two ? 11 : 12);
     p.T = std::min(T, n);
-    p.L = std::min(dtype == SV_C64 ? 5 : 4, p.T - 1);
+    p.L = std::min(4, p.T - 1);   // same tile geometry as the single-circuit default
     p.nt = 256;
     p.two = two;
     return p;

@@ -132,7 +132,8 @@ PlanCfg cfg_for(const sv_ctx_s* c, bool two) {
     T = std::max(4, std::min(T, kMaxTileBits));
     if (!c64 && T > 13) T = 13;
     p.T = T;
-    int L = c->opts.low_bits > 0 ? c->opts.low_bits : (c64 ? 5 : 4);
+    // 2^L contiguous amplitudes per tile segment: 128 B (c64) or 256 B (c128)
+    int L = c->opts.low_bits > 0 ? c->opts.low_bits : 4;
     L = std::max(1, std::min(L, T - 1));
     if (T - L > kMaxHigh) L = T - kMaxHigh;
     p.L = L;
@@ -331,6 +332,7 @@ void fill_stats(sv_stats* st, const sv_ctx_s* c, const CachedPlan& cp, const sv_
     if (init_used) bytes += N * ab;
     st->hbm_bytes = bytes;
     st->flops = e.flops * c->batch;
+    st->alu_ops = e.alu_ops * c->batch;
 }
 
 sv_status upload_pauli(sv_ctx_s* c, const sv_pauli_sum* h, PauliDev& pd) {

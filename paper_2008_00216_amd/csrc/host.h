@@ -132,6 +132,7 @@ struct EncodedPlan {
     // statistics
     int n_dense = 0, n_diag = 0, n_phase = 0, n_tile = 0, n_plain = 0;
     double flops = 0.0;
+    double alu_ops = 0.0;        // vector arithmetic instructions per lane (an FMA counts once), tile passes
 };
 
 // Plan a fused sweep (tile passes) for an IR gate list.

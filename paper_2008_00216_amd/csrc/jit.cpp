@@ -50,8 +50,9 @@ std::string pass_source(const EncodedPlan& ep, int pi, int dtype, bool two, int 
     const char* R = dtype == SV_C64 ? "float" : "double";
     const char* TW = two ? "true" : "false";
     std::ostringstream o;
-    // c64 forward passes keep two workgroups per CU (4 waves per SIMD, <= 128 VGPRs)
-    const bool two_wg = dtype == SV_C64 && !two && nt == 512 && P.T <= 13;
+    // c64 forward passes: at least 4 waves per SIMD (<= 128 VGPRs), as many as
+    // the tile's LDS allows
+    const bool two_wg = dtype == SV_C64 && !two && P.T <= 13;
     o << "extern \"C\" __global__ __launch_bounds__(" << nt << ")"
       << (two_wg ? " __attribute__((amdgpu_waves_per_eu(4, 8)))" : "") << " void svp_" << pi
       << "(svmi::TileArgs A) {\n";

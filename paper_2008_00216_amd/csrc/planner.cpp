@@ -316,6 +316,10 @@ uint64_t add_recipe(EncodedPlan& out, Recipe rc, const std::vector<IRGate>& ir) 
     return rc.off;
 }
 
+// Butterflies between two applications of the accumulated 1/sqrt(2) factors
+// (a growth of 2^60 at most: amplitudes stay far from the FP32 range limits).
+constexpr int kScaleEvery = 120;
+
 double op_cost(const IRGate& g) {
     if (g.kind == K_DIAG8) return 0.0;
     if (g.grad) return 6.0;
@@ -391,6 +395,10 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
     // butterfly on qubit q takes over the part that depends on q as its
     // twiddle, so most of them are never applied as separate ops.
     Form pending;
+    // Each butterfly grows the state by sqrt(2); the factor 2^(-scale_p/2) is
+    // applied once every few passes (FP32 keeps the growth exactly) and
+    // before the state is handed back.
+    int scale_p = 0;
 
     while (!rem.empty()) {
         // ---- choose the local set S (|S| = T, low bits always local)
@@ -493,7 +501,6 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
 
         // phases
         std::vector<int> prem = ex;
-        int scale_p = 0;   // accumulated power of 1/sqrt(2) from the butterflies
         // pending phases must be applied at the end of this pass when no pass
         // follows or a plain (wide-gate) step may come next
         bool flush_at_end = false;
@@ -558,6 +565,7 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
                 out.ops.push_back(op);
                 out.n_diag++;
                 out.flops += (so ? 2.0 : 6.0) * (double)(1ull << n) * (cfg.two ? 2 : 1);
+                out.alu_ops += (so ? 1.0 : 4.0) * (double)(1ull << n) * (cfg.two ? 2 : 1);
                 pending.clear();
             };
             for (int id : pex) {
@@ -617,6 +625,7 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
                     scale_p += 1;
                     out.n_dense++;
                     out.flops += ((M & 1) ? 5.0 : 2.0) * (double)(1ull << n) * (cfg.two ? 2 : 1);
+                    out.alu_ops += ((M & 1) ? 3.0 : 2.0) * (double)(1ull << n) * (cfg.two ? 2 : 1);
                     continue;
                 }
                 if (pending.depends(g.qmask())) flush(false);
@@ -650,6 +659,7 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
                     trace_matrix(tr, "DIAG", g);
                     out.n_diag++;
                     out.flops += 6.0 * (double)(1ull << n) * (cfg.two ? 2 : 1);
+                    out.alu_ops += 4.0 * (double)(1ull << n) * (cfg.two ? 2 : 1);
                 } else {
                     rc.type = Recipe::DENSE;
                     const uint64_t off = add_recipe(out, rc, ir);
@@ -658,6 +668,7 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
                     trace_matrix(tr, "DENSE", g);
                     out.n_dense++;
                     out.flops += 8.0 * (double)(1 << g.k) * (double)(1ull << n) * (cfg.two ? 2 : 1);
+                    out.alu_ops += 4.0 * (double)(1 << g.k) * (double)(1ull << n) * (cfg.two ? 2 : 1);
                 }
             }
             // drop executed gates from prem
@@ -670,7 +681,7 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
             }
             if (prem.empty()) {
                 if (flush_at_end) flush(true);
-                if (scale_p) {
+                if (scale_p && (flush_at_end || scale_p >= kScaleEvery)) {
                     Recipe rc;
                     rc.type = Recipe::SCALE;
                     rc.scale = std::ldexp(1.0, -(scale_p / 2)) * ((scale_p & 1) ? std::sqrt(0.5) : 1.0);
@@ -682,6 +693,8 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
                         std::snprintf(b, sizeof(b), "SCALE %.17g\n", rc.scale);
                         *tr += b;
                     }
+                    scale_p = 0;
+                    out.alu_ops += 2.0 * (double)(1ull << n) * (cfg.two ? 2 : 1);
                 }
             }
             Ph.nop = (uint32_t)(out.ops.size() - Ph.op0);
