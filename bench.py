@@ -67,6 +67,7 @@ def parse():
     p.add_argument("--cycles", type=int, default=40)
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-adjoint", action="store_true")
+    p.add_argument("--no-batch", action="store_true")
     p.add_argument("--calib-copy-gib", type=float, default=0.0,
                    help="run a device copy of this size first (counter calibration)")
     p.add_argument("--structured", type=int, default=1)
@@ -159,6 +160,68 @@ def adjoint_leg(sv, W, torch, np):
     }
 
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def batch_leg(sv, W, torch, np, count=512):
+    """512 circuits, n ~ U{10..22}, 20..60 layers (RY + a random gate per qubit
+    + CZ), observable sum Z_i: energies and adjoint gradients of all of them
+    in one persistent launch, against the same work one circuit at a time."""
+    circs = W.batch_circuits(count, 10, 22, 20, 60, seed0=4000)
+    params = [W.uniform_params(1, c.n_params, 4000 + i)[0] for i, c in enumerate(circs)]
+    obs = [W.z_sum(c.n) for c in circs]
+    states = [torch.empty(1 << c.n, dtype=torch.complex64, device="cuda") for c in circs]
+    lams = [torch.empty_like(t) for t in states]
+    progress(f"batch: {count} circuits generated")
+    e, g, st = sv.apply_batch(circs, params, states, obs, lambdas=lams, grad=True, init_zero=True)
+    torch.cuda.synchronize()
+    progress("batch: first persistent launch done (plans built)")
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        e, g, st = sv.apply_batch(circs, params, states, obs, lambdas=lams, grad=True, init_zero=True)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    progress(f"batch: {t_batch * 1e3:.1f} ms per launch")
+    # one circuit at a time (per-circuit launches, same library)
+    sample = list(range(0, count, 8))
+    ctxs = {}
+    for i in sample:
+        c = circs[i]
+        s = sv.StateVector(c.n, torch.complex64, tensor=states[i].view(1, -1))
+        s.init("zero")
+        s.adjoint_grad(c, params[i][None, :], obs[i], lams[i].view(1, -1))
+        ctxs[i] = s
+    torch.cuda.synchronize()
+    progress("batch: one-at-a-time warm-up done")
+    t0 = time.perf_counter()
+    e_one = {}
+    for i in sample:
+        s = ctxs[i]
+        s.init("zero")
+        ee, gg = s.adjoint_grad(circs[i], params[i][None, :], obs[i], lams[i].view(1, -1))
+        e_one[i] = (ee[0], gg[0])
+    torch.cuda.synchronize()
+    t_one = (time.perf_counter() - t0) * count / len(sample)
+    err_e = max(abs(e[i] - e_one[i][0]) for i in sample)
+    err_g = max(float(np.max(np.abs(g[i] - e_one[i][1]))) for i in sample)
+    gates = sum(len(c.gates) for c in circs)
+    return {
+        "workload": f"{count} circuits, n 10..22, 20..60 layers, c64, forward + adjoint of sum Z",
+        "gates": gates,
+        "batch_s": t_batch,
+        "circuits_per_s": count / t_batch,
+        "gates_per_s": gates / t_batch,
+        "one_at_a_time_s_extrapolated": t_one,
+        "one_at_a_time_sample": f"{len(sample)} of {count} circuits, per-circuit launches",
+        "speedup_vs_one_at_a_time": t_one / t_batch,
+        "max_abs_diff_energy_vs_one_at_a_time": err_e,
+        "max_abs_diff_grad_vs_one_at_a_time": err_g,
+        "launches": st["launches"],
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -196,6 +259,7 @@ def main():
         st = s.apply(cabi)
         s.norm()
     s.timing()  # reset counters
+    progress("sweep: warm-up done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     norms = []
@@ -256,10 +320,15 @@ def main():
     }
     del s
     torch.cuda.empty_cache()
+    progress(f"sweep: {ms_per_step:.1f} ms per step")
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(sv, W, torch, np)
+        progress("adjoint leg done")
+    if not args.no_batch:
+        out["batch"] = batch_leg(sv, W, torch, np)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(circ)
+        progress("cpu baseline done")
     print(json.dumps(out), flush=True)
 
 

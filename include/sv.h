@@ -115,7 +115,8 @@ typedef struct {
     int32_t structured;    /* 1 = H, sqrt(X), sqrt(Y), sqrt(W) and inverses as multiply-free H'
                               butterflies with the diagonal phases applied lazily (default) */
     int32_t timing;        /* 1 = time every tile-pass launch with HIP events (sv_timing) */
-    int32_t jit;           /* run-time specialised tile passes: 0 auto (n >= 18), 1 always, -1 never */
+    int32_t jit;           /* run-time specialised tile passes: 0 auto (batch * 2^n >= 2^24),
+                              1 always, -1 never */
     int32_t reserved[3];
 } sv_opts;
 
@@ -238,6 +239,8 @@ sv_status sv_plan_info(const sv_circuit* circuit, sv_dtype dtype, int32_t adjoin
  *   FORM c aQ:v... bA,B:v...  multiply amplitude j by e^{i pi e(j)/4},
  *                        e = c + sum v j_Q + sum v j_A j_B
  *   DENSE k q... (re im)...   row-major 2^k x 2^k matrix, local bit t = qubit q[t]
+ *   DENSE1 1 q (re im)x4 [| p...]  (x, y) <- (u00 x + s u01 y, u10 x + s u11 y) on qubit q,
+ *                        s = (-1)^(sum of the bits of qubits p)
  *   DIAG k q... (re im)...    2^k diagonal entries
  *   SCALE s              multiply every amplitude by s
  *   GRAD p gen s q...    adjoint plans: parameter p gains s * Im<lambda|G|psi>, G = X, Y,

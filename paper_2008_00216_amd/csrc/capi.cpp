@@ -217,7 +217,10 @@ sv_status run_plan(sv_ctx_s* c, CachedPlan& cp, const std::vector<IRGate>& ir, v
     // plan-specialised kernels for large states
     if (!cp.jit_tried && !e.passes.empty()) {
         cp.jit_tried = true;
-        bool eligible = jit_enabled() && c->opts.jit >= 0 && (c->opts.jit > 0 || c->n >= 18);
+        // auto: specialise when every launch streams >= 2^24 amplitudes, where a
+        // few seconds of compilation (cached on disk) pay for themselves
+        const bool big = (uint64_t)c->batch << c->n >= (1ull << 24);
+        bool eligible = jit_enabled() && c->opts.jit >= 0 && (c->opts.jit > 0 || big);
         for (const DPass& P : e.passes)
             if ((1u << (P.T - kRegBits)) < (uint32_t)e.cfg.nt) eligible = false;
         if (eligible) {

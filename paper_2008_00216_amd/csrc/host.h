@@ -33,6 +33,7 @@ struct IRGate {
     int beta = 0;              // DIAG8 pair exponent on (q[0], q[1])
     int skind = 0;             // OP_BF: w^g diag(1, w^post) H' diag(1, w^pre) / sqrt(2), else 0
     int bf_pre = 0, bf_post = 0, bf_g = 0;   // exponents of w = e^{i pi/4} (mod 8)
+    bool real = false;         // the matrix is real for every parameter value
     int perm = PK_NONE;        // exact permutation gate (plain path)
     int src = -1;              // first source gate
     int param = -1;            // parameter index (unfused parameterised gate)
@@ -71,6 +72,9 @@ void gate_matrix(int op, double theta, const double* mat, int nq, std::vector<cd
 std::vector<IRGate> build_ir(const sv_circuit* c, const double* params, const BuildOpts& o,
                              ProductInit* pinit, int n_qubits);
 
+// True when the gate's matrix is real for every parameter value.
+bool real_gate(const IRGate& g);
+
 // Structural hash of a circuit for the plan cache.
 uint64_t circuit_hash(const sv_circuit* c, uint64_t seed);
 
@@ -92,6 +96,7 @@ struct Recipe {
     int perm[6] = {0, 1, 2, 3, 4, 5};  // slot order: new local bit t <- gate local bit perm[t]
     int k = 0;
     double scale = 1.0;          // SCALE
+    int twiddle = 0;             // DENSE k = 1: multiply column 1 by e^{i pi twiddle/4}
     cd value{1.0, 0.0};          // VALUE
     uint64_t off = 0;            // pool offset (complex elements)
     uint64_t size = 0;

@@ -18,6 +18,12 @@
 
 namespace svmi {
 
+// True when the gate's matrix is real (for every parameter value).
+bool real_gate(const IRGate& g) {
+    if (g.kind == K_DIAG8) return (g.alpha[0] & 3) == 0 && (g.alpha[1] & 3) == 0 && (g.beta & 3) == 0;
+    return g.real;
+}
+
 namespace {
 
 const double kR = std::sqrt(0.5);
@@ -308,8 +314,15 @@ IRGate make_ir(const sv_circuit* c, int gi, const double* params, const BuildOpt
         else
             std::copy(m.begin(), m.end(), dst);
     }
+    if (g.param >= 0) {
+        r.real = g.op == SV_OP_RY;   // real for every angle
+    } else {
+        r.real = true;
+        for (const cd& v : r.m.v) if (v.imag() != 0.0) r.real = false;
+    }
     return r;
 }
+
 
 // Dense 2x2 matrix of a one-qubit IR gate (any kind), per state.
 MatB as_dense1(const IRGate& g) {
@@ -473,6 +486,7 @@ std::vector<IRGate> build_ir(const sv_circuit* c, const double* params, const Bu
                             r.at(s)[0] = a.at(s)[0] * b.at(s)[0];
                             r.at(s)[1] = a.at(s)[1] * b.at(s)[1];
                         }
+                        h.real = real_gate(h) && real_gate(g);
                         h.kind = K_DIAGG; h.m = r; h.perm = PK_NONE; h.param = -1; h.gen = 0;
                     }
                     continue;
@@ -481,6 +495,7 @@ std::vector<IRGate> build_ir(const sv_circuit* c, const double* params, const Bu
                     // dense g after a diagonal chain: move the chain to here
                     IRGate f = g;
                     f.m = mul1(as_dense1(g), as_dense1(h));
+                    f.real = real_gate(g) && real_gate(h);
                     f.kind = K_DENSE; f.perm = PK_NONE; f.param = -1; f.gen = 0; f.skind = 0;
                     f.src = h.src;
                     alive[oi] = 0;
@@ -492,6 +507,7 @@ std::vector<IRGate> build_ir(const sv_circuit* c, const double* params, const Bu
                     continue;
                 }
                 if (is_diag(g) || !blocked[q]) {
+                    h.real = real_gate(g) && real_gate(h);
                     h.m = mul1(as_dense1(g), h.m);
                     h.kind = K_DENSE; h.perm = PK_NONE; h.param = -1; h.gen = 0; h.skind = 0;
                     continue;

@@ -108,6 +108,22 @@ std::string pass_source(const EncodedPlan& ep, int pi, int dtype, bool two, int 
                     o << " }\n";
                     break;
                 }
+                case OP_D1T: {
+                    const uint32_t S = op.k & 3u, RM = (op.k >> 2) & 15u, real = (op.k >> 6) & 1u, pk = op.k >> 7;
+                    const uint64_t gm = pk == 0 ? 0ull : ep.pairs[pk - 1].m[0];
+                    const bool rt = op.mask != 0 || gm != 0;
+                    o << "      { ";
+                    if (rt)
+                        o << "const R s_ = bf_parity(lb, " << op.mask << "u, F.base, " << gm << "ull) ? R(-1) : R(1); ";
+                    else
+                        o << "const R s_ = R(1); ";
+                    const std::string targs = std::to_string(S) + ", " + std::to_string(RM) + ", " +
+                                              (rt ? "true" : "false") + ", " + (real ? "true" : "false");
+                    o << "op_d1t<R, " << targs << ">(a, F.pool + " << op.arg << ", s_);";
+                    if (two) o << " op_d1t<R, " << targs << ">(l, F.pool + " << op.arg << ", s_);";
+                    o << " }\n";
+                    break;
+                }
                 case OP_SCALE:
                     o << "      { const R s_ = F.pool[" << op.arg << "].x; op_scale<R>(a, s_);";
                     if (two) o << " op_scale<R>(l, s_);";

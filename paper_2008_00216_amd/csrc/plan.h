@@ -36,6 +36,7 @@ enum OpType : uint32_t {
     OP_GRAD = 5,    // Im<lambda|G|psi> over slots `mask`, generator `k`, pass-local slot `arg`
     OP_SCALE = 6,   // multiply by the real scalar at pool element `arg` (.x)
     OP_BF = 11,     // twiddled butterfly, see below
+    OP_D1T = 12,    // one-qubit 2x2 matrix at `arg` with a +-1 input sign, see below
 };
 
 // OP_BF on register slot S: for every pair (x, y) of amplitudes that differ
@@ -47,6 +48,12 @@ enum OpType : uint32_t {
 // whose m[0] holds the partner nonlocal qubits, or kNoPair.
 constexpr uint32_t kNoPair = 0xffffffffu;
 
+// OP_D1T on slot S: (x, y) <- (u00 x + s u01 y, u10 x + s u11 y) with u the
+// 2x2 matrix at pool offset `arg` (the pending 8th-root phase of the qubit is
+// already folded into its second column) and s = (-1)^(parity of the
+// partner bits).  Encoding: k = S | RM << 2 | REAL << 6 | (pair + 1) << 7
+// (REAL: u is real; pair: DPair index of the partner nonlocal qubits, 0 =
+// none); mask = partner tile-local positions outside the registers.
 enum GradGen : uint32_t { GEN_X = 1, GEN_Y = 2, GEN_Z = 3, GEN_P11 = 4 };
 
 struct DOp {

@@ -337,7 +337,7 @@ namespace {
 // flushed phase forms, dense and diagonal blocks with their matrices, pass
 // scales, gradient reductions).  Used to check the planner's algebra on the
 // host against an independent evaluation.
-void trace_matrix(std::string* tr, const char* tag, const IRGate& g) {
+void trace_matrix(std::string* tr, const char* tag, const IRGate& g, const std::string& partners = "") {
     if (!tr) return;
     char b[64];
     *tr += tag;
@@ -350,6 +350,7 @@ void trace_matrix(std::string* tr, const char* tag, const IRGate& g) {
         std::snprintf(b, sizeof(b), " %.17g %.17g", m[i].real(), m[i].imag());
         *tr += b;
     }
+    if (!partners.empty()) *tr += " |" + partners;
     *tr += "\n";
 }
 
@@ -581,51 +582,85 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
                     for (int u = 0; u < 4; ++u) if (r[u] == lp) s = u;
                     slot_of_q[t] = s;
                 }
-                if (g.skind == OP_BF) {
-                    const int q = g.q[0];
-                    // the part of the pending phase that depends on q must be
-                    // w^m (-1)^(sum of partner bits): pair exponents 0 or 4
+                // Take the part of the pending phase that depends on qubit q:
+                // w^m (-1)^(sum of partner bits).  Needs every pair exponent on
+                // q to be 0 or 4; otherwise the whole form is applied first.
+                struct Tw { int m = 0; uint32_t RM = 0, lmask = 0, pair = kNoPair; std::string partners; };
+                auto take_twiddle = [&](int q) {
                     for (auto& kv : pending.beta)
                         if ((kv.second & 3) && (kv.first.first == q || kv.first.second == q)) {
                             flush(false);
                             break;
                         }
-                    const int M = (pending.alpha[q] + g.bf_pre) & 7;
-                    uint32_t RM = 0, lmask = 0;
+                    Tw t;
+                    t.m = pending.alpha[q] & 7;
                     uint64_t gmask = 0;
-                    std::string partners;
                     for (auto it = pending.beta.begin(); it != pending.beta.end();) {
                         const int a = it->first.first, b = it->first.second;
                         if (a != q && b != q) { ++it; continue; }
                         if (it->second & 7) {
                             const int p = a == q ? b : a;
-                            partners += " " + std::to_string(p);
+                            t.partners += " " + std::to_string(p);
                             const int lp = G.lpos[p];
                             int su = -1;
                             for (int u = 0; u < 4; ++u) if (r[u] == lp) su = u;
                             if (lp < 0) gmask |= 1ull << p;
-                            else if (su >= 0) RM |= 1u << su;
-                            else lmask |= 1u << lp;
+                            else if (su >= 0) t.RM |= 1u << su;
+                            else t.lmask |= 1u << lp;
                         }
                         it = pending.beta.erase(it);
                     }
-                    pending.alpha[q] = g.bf_post & 7;
-                    pending.konst = (pending.konst + g.bf_g) & 7;
-                    uint32_t pa = kNoPair;
+                    pending.alpha[q] = 0;
                     if (gmask) {
                         DPair pr;
                         std::memset(&pr, 0, sizeof(pr));
                         pr.m[0] = gmask;
-                        pa = (uint32_t)out.pairs.size();
+                        t.pair = (uint32_t)out.pairs.size();
                         out.pairs.push_back(pr);
                     }
-                    DOp op{(uint32_t)OP_BF, (uint32_t)(M | (slot_of_q[0] << 4) | (RM << 8)), lmask, pa};
+                    return t;
+                };
+                if (g.skind == OP_BF) {
+                    const int q = g.q[0];
+                    Tw t = take_twiddle(q);
+                    const int M = (t.m + g.bf_pre) & 7;
+                    pending.alpha[q] = g.bf_post & 7;
+                    pending.konst = (pending.konst + g.bf_g) & 7;
+                    DOp op{(uint32_t)OP_BF, (uint32_t)(M | (slot_of_q[0] << 4) | (t.RM << 8)), t.lmask, t.pair};
                     out.ops.push_back(op);
-                    if (tr) *tr += "BF " + std::to_string(q) + " " + std::to_string(M) + partners + "\n";
+                    if (tr) *tr += "BF " + std::to_string(q) + " " + std::to_string(M) + t.partners + "\n";
                     scale_p += 1;
                     out.n_dense++;
                     out.flops += ((M & 1) ? 5.0 : 2.0) * (double)(1ull << n) * (cfg.two ? 2 : 1);
                     out.alu_ops += ((M & 1) ? 3.0 : 2.0) * (double)(1ull << n) * (cfg.two ? 2 : 1);
+                    continue;
+                }
+                if (g.kind == K_DENSE && g.k == 1 && !g.grad) {
+                    // one-qubit matrix: the pending phase of q folds into its
+                    // second column, the partner signs into the kernel
+                    const int q = g.q[0];
+                    Tw t = take_twiddle(q);
+                    const bool real = real_gate(g) && (t.m & 3) == 0;
+                    Recipe rc;
+                    rc.type = Recipe::DENSE;
+                    rc.gate = id;
+                    rc.k = 1;
+                    rc.twiddle = t.m;
+                    const uint64_t off = add_recipe(out, rc, ir);
+                    const uint32_t pk = t.pair == kNoPair ? 0u : t.pair + 1u;
+                    DOp op{(uint32_t)OP_D1T, (uint32_t)(slot_of_q[0] | (t.RM << 2) | ((real ? 1u : 0u) << 6) | (pk << 7)),
+                           t.lmask, (uint32_t)off};
+                    out.ops.push_back(op);
+                    if (tr) {
+                        IRGate tg = g;
+                        tg.m = g.m;
+                        const cd w = std::polar(1.0, M_PI / 4.0 * t.m);
+                        for (int bb = 0; bb < tg.m.nb; ++bb) { tg.m.at(bb)[1] *= w; tg.m.at(bb)[3] *= w; }
+                        trace_matrix(tr, "DENSE1", tg, t.partners);
+                    }
+                    out.n_dense++;
+                    out.flops += (real ? 8.0 : 16.0) * (double)(1ull << n) * (cfg.two ? 2 : 1);
+                    out.alu_ops += (real ? 4.0 : 8.0) * (double)(1ull << n) * (cfg.two ? 2 : 1);
                     continue;
                 }
                 if (pending.depends(g.qmask())) flush(false);
@@ -900,7 +935,8 @@ void fill_pool_t(const EncodedPlan& p, const std::vector<IRGate>& ir, int batch,
                                 if ((r >> j) & 1) orr |= 1 << rc.perm[j];
                                 if ((col >> j) & 1) oc |= 1 << rc.perm[j];
                             }
-                            const cd v = m[(size_t)orr * d + oc];
+                            cd v = m[(size_t)orr * d + oc];
+                            if (rc.twiddle && (col & 1)) v *= tab[rc.twiddle & 7];
                             dst[2 * (r * d + col)] = (R)v.real();
                             dst[2 * (r * d + col) + 1] = (R)v.imag();
                         }

@@ -66,6 +66,17 @@ __device__ __forceinline__ void bf_dispatch(V2<R>* a, uint32_t slot, uint32_t M,
     }
 }
 
+template <class R>
+__device__ __forceinline__ void d1t_dispatch(V2<R>* a, uint32_t slot, const V2<R>* u, uint32_t RM, R s) {
+    switch (slot) {
+        case 0: op_d1t_rt<R, 0>(a, u, RM, s); break;
+        case 1: op_d1t_rt<R, 1>(a, u, RM, s); break;
+        case 2: op_d1t_rt<R, 2>(a, u, RM, s); break;
+        case 3: op_d1t_rt<R, 3>(a, u, RM, s); break;
+        default: break;
+    }
+}
+
 template <class R, uint32_t GEN>
 __device__ __forceinline__ double grad1_dispatch(const V2<R>* p, const V2<R>* l, uint32_t mask) {
     switch (mask) {
@@ -146,6 +157,15 @@ __device__ __forceinline__ void tile_interp(const TileArgs& A, unsigned char* sm
                         const R sg = bf_parity(lb, mask, F.base, gm) ? R(-1) : R(1);
                         bf_dispatch<R>(a, (kk >> 4) & 3u, kk & 7u, kk >> 8, sg, F.ptab);
                         if constexpr (TWO) bf_dispatch<R>(l, (kk >> 4) & 3u, kk & 7u, kk >> 8, sg, F.ptab);
+                        break;
+                    }
+                    case OP_D1T: {
+                        const uint32_t kk = rfl(op.k);
+                        const uint32_t pk = kk >> 7;
+                        const uint64_t gm = pk == 0 ? 0ull : A.pairs[pk - 1].m[0];
+                        const R sg = bf_parity(lb, mask, F.base, gm) ? R(-1) : R(1);
+                        d1t_dispatch<R>(a, kk & 3u, F.pool + arg, (kk >> 2) & 15u, sg);
+                        if constexpr (TWO) d1t_dispatch<R>(l, kk & 3u, F.pool + arg, (kk >> 2) & 15u, sg);
                         break;
                     }
                     case OP_SCALE: {

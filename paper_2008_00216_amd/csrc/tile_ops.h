@@ -106,6 +106,58 @@ __device__ __forceinline__ void op_bf_rt(V2<R>* a, uint32_t M, uint32_t RM, R s,
     }
 }
 
+// One-qubit matrix u (row-major 2x2 at u, the qubit's pending phase already
+// in its second column) on slot S with the input sign of y
+// s * (-1)^(parity of the register slots RM in the pair index) (OP_D1T).
+// REAL: u is real (8 multiply-adds per pair instead of 16).
+template <class R, int S, int RM, bool RT, bool REAL>
+__device__ __forceinline__ void op_d1t(V2<R>* a, const V2<R>* __restrict__ u, R s) {
+    const V2<R> u00 = u[0], u10 = u[2];
+    V2<R> u01 = u[1], u11 = u[3];
+    if constexpr (RT) {
+        u01 = V2<R>{s * u01.x, s * u01.y};
+        u11 = V2<R>{s * u11.x, s * u11.y};
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (i & (1 << S)) continue;
+        const V2<R> x = a[i], y = a[i | (1 << S)];
+        const bool neg = (__builtin_popcount(i & RM) & 1) != 0;
+        const R c01x = neg ? -u01.x : u01.x, c01y = neg ? -u01.y : u01.y;
+        const R c11x = neg ? -u11.x : u11.x, c11y = neg ? -u11.y : u11.y;
+        V2<R> o0, o1;
+        if constexpr (REAL) {
+            o0 = V2<R>{fma_(c01x, y.x, u00.x * x.x), fma_(c01x, y.y, u00.x * x.y)};
+            o1 = V2<R>{fma_(c11x, y.x, u10.x * x.x), fma_(c11x, y.y, u10.x * x.y)};
+        } else {
+            o0 = cmul(u00, x);
+            o1 = cmul(u10, x);
+            cmac(o0, V2<R>{c01x, c01y}, y);
+            cmac(o1, V2<R>{c11x, c11y}, y);
+        }
+        a[i] = o0;
+        a[i | (1 << S)] = o1;
+    }
+}
+
+// Same with RM known only at run time (interpreter).
+template <class R, int S>
+__device__ __forceinline__ void op_d1t_rt(V2<R>* a, const V2<R>* __restrict__ u, uint32_t RM, R s) {
+    const V2<R> u00 = u[0], u10 = u[2];
+    const V2<R> u01{s * u[1].x, s * u[1].y}, u11{s * u[3].x, s * u[3].y};
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (i & (1 << S)) continue;
+        const V2<R> x = a[i], y = a[i | (1 << S)];
+        const R sg = (__builtin_popcount((uint32_t)i & RM) & 1) ? R(-1) : R(1);
+        V2<R> o0 = cmul(u00, x), o1 = cmul(u10, x);
+        cmac(o0, V2<R>{sg * u01.x, sg * u01.y}, y);
+        cmac(o1, V2<R>{sg * u11.x, sg * u11.y}, y);
+        a[i] = o0;
+        a[i | (1 << S)] = o1;
+    }
+}
+
 // Thread sign of a butterfly: (-1)^(parity of the partner bits of the
 // thread's tile-local index lb and of the tile's global base).
 __device__ __forceinline__ uint32_t bf_parity(uint32_t lb, uint32_t lmask, uint64_t base, uint64_t gmask) {

@@ -1,0 +1,63 @@
+"""Full-size checks in the launch configuration bench.py times (complex64,
+default options: plan-specialised tile passes of 2^13 amplitudes, 2^4-
+amplitude segments, 512 threads).  The 33-qubit state has no independent
+FP64 reference on the host, so it is checked through a 24-qubit cut of the
+same circuit against the oracle, the norm, and the mirror circuit."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from tests.gpu_util import check_close, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def lib():
+    import paper_2008_00216_amd as m
+    return m
+
+
+def test_grid33_cut24_against_oracle():
+    m = lib()
+    c = W.grid33().cut(24)
+    s = m.StateVector(24, torch.complex64)
+    s.init("zero")
+    st = s.apply(c)
+    assert st["passes"] > 1
+    ref = oracle.simulate(c)
+    check_close(to_host(s.tensor)[0], ref, torch.complex64, "grid33 cut 24")
+
+
+def test_grid30_cut22_c128_against_oracle():
+    m = lib()
+    c = W.grid30().cut(22)
+    s = m.StateVector(22, torch.complex128)
+    s.init("zero")
+    s.apply(c)
+    check_close(to_host(s.tensor)[0], oracle.simulate(c), torch.complex128, "grid30 cut 22 c128")
+
+
+def test_grid33_norm_and_mirror():
+    m = lib()
+    c = W.grid33()
+    s = m.StateVector(33, torch.complex64)
+    s.init("zero_deferred")
+    s.apply(c)
+    nrm = float(s.norm()[0])
+    assert abs(nrm - 1.0) < 1e-5, nrm
+    # the sweep spreads the state: no amplitude keeps a large share
+    head = to_host(s.tensor[0, :1 << 16])
+    assert np.max(np.abs(head)) < 1e-3
+    s.apply(W.inverse(c))
+    psi0 = complex(s.tensor[0, 0].item())
+    nrm2 = float(s.norm()[0])
+    dist = math.sqrt(max(0.0, nrm2 - 2.0 * psi0.real + 1.0))   # || psi - |0...0> ||_2
+    assert abs(nrm2 - 1.0) < 2e-5 and dist < 1e-3, (psi0, nrm2, dist)
+    tail = to_host(s.tensor[0, 1:1 << 16])
+    assert np.max(np.abs(tail)) < 1e-4
+    del s
+    torch.cuda.empty_cache()

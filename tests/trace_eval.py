@@ -46,6 +46,25 @@ def _apply_line(f, line, n, psi, j, bit):
         x, y = psi[lo].copy(), psi[hi].copy()
         psi[lo] = x + t * y
         psi[hi] = x - t * y
+    elif f[0] == "DENSE1":
+        # DENSE1 1 q u00 u01 u10 u11 [| partners]: (x, y) <- (u00 x + s u01 y, u10 x + s u11 y)
+        q = int(f[2])
+        rest = f[3:]
+        partners = []
+        if "|" in rest:
+            partners = [int(x) for x in rest[rest.index("|") + 1:]]
+            rest = rest[:rest.index("|")]
+        v = np.array([float(x) for x in rest])
+        u = v[0::2] + 1j * v[1::2]
+        lo = j[bit[q] == 0]
+        hi = lo | (1 << q)
+        par = np.zeros(lo.size, np.int64)
+        for p in partners:
+            par ^= (lo >> p) & 1
+        sg = np.where(par == 1, -1.0, 1.0)
+        x, y = psi[lo].copy(), psi[hi].copy()
+        psi[lo] = u[0] * x + sg * u[1] * y
+        psi[hi] = u[2] * x + sg * u[3] * y
     elif f[0] == "FORM":
         e = np.full(1 << n, int(f[1]), np.int64)
         for tok in f[2:]:
