@@ -68,6 +68,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-adjoint", action="store_true")
     p.add_argument("--no-batch", action="store_true")
+    p.add_argument("--ksweep", action="store_true", help="30-qubit dense-width sweep instead of the benchmark")
     p.add_argument("--calib-copy-gib", type=float, default=0.0,
                    help="run a device copy of this size first (counter calibration)")
     p.add_argument("--structured", type=int, default=1)
@@ -222,6 +223,39 @@ def batch_leg(sv, W, torch, np, count=512):
     }
 
 
+def ksweep(sv, W, torch, steps=2):
+    """5x6 grid, 30 qubits, 20 cycles, complex64: the butterfly mode against
+    dense blocks of at most k qubits (k = 1..6).  One JSON line per mode."""
+    circ = W.grid30()
+    cabi = sv.CircuitABI(circ)
+    modes = [("butterflies", dict(structured=1))] + [(f"dense k<={k}", dict(structured=0, max_fuse_k=k))
+                                                   for k in range(1, 7)]
+    rows = []
+    for name, kw in modes:
+        s = sv.StateVector(circ.n, torch.complex64, opts=sv.make_opts(timing=1, **kw))
+        s.init("zero_deferred")
+        st = s.apply(cabi)
+        torch.cuda.synchronize()
+        s.timing()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.init("zero_deferred")
+            st = s.apply(cabi)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        tile_ms, launches, tile_bytes = s.timing()
+        row = {"mode": name, "ms_per_sweep": ms, "gates_per_s": len(circ.gates) / (ms / 1e3),
+               "passes": st["passes"], "dense_ops": st["dense_ops"],
+               "hbm_frac_sweep": st["hbm_bytes"] / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+               "tile_avg_ms": tile_ms / max(1, launches),
+               "alu_frac_tile": st["alu_ops"] * steps / (tile_ms / 1e3) / 1e12 / VALU_PEAK_TOPS if tile_ms else None}
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+        del s
+        torch.cuda.empty_cache()
+    return rows
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -235,6 +269,9 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.ksweep:
+        ksweep(sv, W, torch)
+        return
     if args.calib_copy_gib > 0:
         nb = int(args.calib_copy_gib * (1 << 30))
         a = torch.empty(nb // 4, dtype=torch.float32, device="cuda")

@@ -106,7 +106,8 @@ typedef struct {
 } sv_pauli_sum;
 
 typedef struct {
-    int32_t max_fuse_k;    /* widest fused dense block, 1..6 (default 4) */
+    int32_t max_fuse_k;    /* structured = 0: gates are fused into dense blocks of at most this many
+                              qubits, 1..6 (default 4); blocks of 5-6 qubits run as plain kernels */
     int32_t tile_bits;     /* local qubits per tile pass, 0 = default */
     int32_t low_bits;      /* contiguous low bits per tile segment, 0 = default */
     int32_t plain;         /* 1 = one kernel per gate, no reordering or fusion */

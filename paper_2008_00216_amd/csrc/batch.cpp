@@ -167,6 +167,7 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
                         bo.batch = 1;
                         bo.structured = !opts || opts->structured;
                         bo.fuse = true;
+                        bo.fuse_k = opts ? opts->max_fuse_k : 4;
                         bo.product_init = false;
                         H[i].irf = build_ir(it.circuit, it.params, bo, nullptr, it.circuit->n_qubits);
                         H[i].pf = get_batch_plan(it.circuit, H[i].irf, dtype, false);

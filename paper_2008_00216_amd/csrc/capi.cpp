@@ -166,6 +166,7 @@ sv_status get_plan(sv_ctx_s* c, const sv_circuit* circ, const double* params, bo
     bo.batch = c->batch;
     bo.structured = c->opts.structured != 0 && !use_plain(c);
     bo.fuse = !use_plain(c);
+    bo.fuse_k = use_plain(c) ? 0 : c->opts.max_fuse_k;
     bo.backward = two;
     bo.product_init = !two && !use_plain(c) && c->known_zero && c->opts.product_init != 0;
     try {
@@ -671,6 +672,7 @@ sv_status sv_plan_info(const sv_circuit* circ, sv_dtype dtype, int32_t adjoint, 
     bo.batch = 1;
     bo.structured = c.opts.structured != 0 && !use_plain(&c);
     bo.fuse = !use_plain(&c);
+    bo.fuse_k = use_plain(&c) ? 0 : c.opts.max_fuse_k;
     bo.backward = adjoint != 0;
     bo.product_init = !adjoint && !use_plain(&c) && c.opts.product_init != 0;
     auto t0 = std::chrono::steady_clock::now();
@@ -714,6 +716,7 @@ sv_status sv_plan_trace(const sv_circuit* circ, const double* params, sv_dtype d
     bo.batch = 1;
     bo.structured = c.opts.structured != 0;
     bo.fuse = true;
+    bo.fuse_k = c.opts.max_fuse_k;
     bo.backward = adjoint != 0;
     bo.product_init = false;
     std::string tr;

@@ -53,6 +53,7 @@ struct BuildOpts {
     bool fuse = true;            // fuse one-qubit chains
     bool backward = false;       // adjoint sweep: inverse gates in reverse + gradient pseudo-gates
     bool product_init = false;   // fold leading one-qubit gates (state is |0..0>)
+    int fuse_k = 0;              // dense mode: fuse gates into blocks of <= fuse_k qubits (0/1 = off)
 };
 
 struct ProductInit {
@@ -74,6 +75,9 @@ std::vector<IRGate> build_ir(const sv_circuit* c, const double* params, const Bu
 
 // True when the gate's matrix is real for every parameter value.
 bool real_gate(const IRGate& g);
+
+// Dense blocks of at most kmax qubits from an IR gate list.
+std::vector<IRGate> fuse_blocks(std::vector<IRGate>&& in, int kmax, int n);
 
 // Structural hash of a circuit for the plan cache.
 uint64_t circuit_hash(const sv_circuit* c, uint64_t seed);

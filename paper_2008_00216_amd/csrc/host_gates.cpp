@@ -536,7 +536,160 @@ std::vector<IRGate> build_ir(const sv_circuit* c, const double* params, const Bu
     res.reserve(out.size());
     for (size_t i = 0; i < out.size(); ++i)
         if (alive[i]) res.push_back(std::move(out[i]));
+    if (o.fuse_k >= 2 && !o.structured) return fuse_blocks(std::move(res), o.fuse_k, n);
     return res;
+}
+
+// Full 2^k x 2^k matrix of an IR gate for state b (any kind).
+static std::vector<cd> full_matrix(const IRGate& g, int b) {
+    const int d = 1 << g.k;
+    std::vector<cd> u((size_t)d * d, 0.0);
+    if (g.kind == K_DIAG8) {
+        const double c = std::sqrt(0.5);
+        const cd tab[8] = {cd(1, 0), cd(c, c), cd(0, 1), cd(-c, c), cd(-1, 0), cd(-c, -c), cd(0, -1), cd(c, -c)};
+        for (int l = 0; l < d; ++l) {
+            int e = 0;
+            if (l & 1) e += g.alpha[0];
+            if (g.k > 1 && (l & 2)) e += g.alpha[1];
+            if (g.k > 1 && (l & 3) == 3) e += g.beta;
+            u[(size_t)l * d + l] = tab[e & 7];
+        }
+        return u;
+    }
+    const cd* m = g.m.at(b);
+    if (g.m.diag) {
+        for (int l = 0; l < d; ++l) u[(size_t)l * d + l] = m[l];
+    } else {
+        std::copy(m, m + (size_t)d * d, u.begin());
+    }
+    return u;
+}
+
+// Dense blocks of at most kmax qubits (Sec. 4.2 contrasts this with its own
+// clustering; used for the dense mode and its width sweep).  Open blocks have
+// disjoint qubit sets, so they commute; a gate joins the blocks it touches
+// when their union stays within kmax qubits, otherwise those blocks are
+// closed (emitted) and the gate starts a new one.  Products are formed in
+// FP64 and rounded once when the plan's matrix pool is filled.  Gradient
+// pseudo-gates and wider gates close the blocks on their qubits.
+std::vector<IRGate> fuse_blocks(std::vector<IRGate>&& in, int kmax, int n) {
+    (void)n;
+    struct Blk {
+        std::vector<int> gates;   // member indices into `in`, in order
+        uint64_t qm = 0;
+    };
+    std::vector<IRGate> out;
+    out.reserve(in.size());
+    std::vector<Blk> open;
+    auto emit = [&](const Blk& B) {
+        if (B.gates.size() == 1) {
+            out.push_back(in[B.gates[0]]);
+            return;
+        }
+        IRGate f;
+        int qs[6], k = 0;
+        for (int q = 0; q < 64; ++q) if ((B.qm >> q) & 1) qs[k++] = q;
+        f.k = k;
+        for (int t = 0; t < k; ++t) f.q[t] = qs[t];
+        f.src = in[B.gates[0]].src;
+        int nb = 1;
+        bool diag = true, real = true;
+        for (int gi : B.gates) {
+            const IRGate& g = in[gi];
+            if (g.kind == K_DENSE) diag = false;
+            if (!real_gate(g)) real = false;
+            if (g.kind != K_DIAG8) nb = std::max(nb, g.m.nb);
+        }
+        const int D = 1 << k;
+        f.m.d = D;
+        f.m.nb = nb;
+        f.m.diag = diag;
+        f.m.v.assign((size_t)nb * (diag ? D : (size_t)D * D), 0.0);
+        std::vector<cd> U((size_t)D * D), col((size_t)D), tmp;
+        for (int b = 0; b < nb; ++b) {
+            std::fill(U.begin(), U.end(), cd(0.0));
+            for (int i = 0; i < D; ++i) U[(size_t)i * D + i] = 1.0;
+            for (int gi : B.gates) {
+                const IRGate& g = in[gi];
+                const int kg = g.k, dg = 1 << kg;
+                const std::vector<cd> G = full_matrix(g, g.kind == K_DIAG8 || g.m.nb == 1 ? 0 : b);
+                int pos[6];
+                for (int t = 0; t < kg; ++t)
+                    for (int s2 = 0; s2 < k; ++s2) if (qs[s2] == g.q[t]) pos[t] = s2;
+                uint32_t gmask = 0;
+                for (int t = 0; t < kg; ++t) gmask |= 1u << pos[t];
+                tmp.assign((size_t)dg, 0.0);
+                for (int c = 0; c < D; ++c) {          // U <- G_emb U, column by column
+                    for (int r = 0; r < D; ++r) col[r] = U[(size_t)r * D + c];
+                    for (int base = 0; base < D; ++base) {
+                        if (base & gmask) continue;
+                        for (int l = 0; l < dg; ++l) {
+                            cd acc = 0.0;
+                            for (int l2 = 0; l2 < dg; ++l2) {
+                                int idx = base;
+                                for (int t = 0; t < kg; ++t) if ((l2 >> t) & 1) idx |= 1 << pos[t];
+                                acc += G[(size_t)l * dg + l2] * col[idx];
+                            }
+                            tmp[l] = acc;
+                        }
+                        for (int l = 0; l < dg; ++l) {
+                            int idx = base;
+                            for (int t = 0; t < kg; ++t) if ((l >> t) & 1) idx |= 1 << pos[t];
+                            U[(size_t)idx * D + c] = tmp[l];
+                        }
+                    }
+                }
+            }
+            cd* dst = f.m.at(b);
+            if (diag) for (int i = 0; i < D; ++i) dst[i] = U[(size_t)i * D + i];
+            else std::copy(U.begin(), U.end(), dst);
+        }
+        f.kind = diag ? K_DIAGG : K_DENSE;
+        f.real = real;
+        f.param = -1;
+        f.gen = 0;
+        f.perm = PK_NONE;
+        out.push_back(f);
+    };
+    auto close_touching = [&](uint64_t qm) {
+        std::vector<Blk> keep;
+        for (Blk& B : open) {
+            if (B.qm & qm) emit(B);
+            else keep.push_back(std::move(B));
+        }
+        open.swap(keep);
+    };
+    for (size_t i = 0; i < in.size(); ++i) {
+        const IRGate& g = in[i];
+        const uint64_t qm = g.qmask();
+        if (g.grad || g.k > kmax || g.skind) {
+            close_touching(qm);
+            out.push_back(g);
+            continue;
+        }
+        uint64_t un = qm;
+        for (const Blk& B : open) if (B.qm & qm) un |= B.qm;
+        if (__builtin_popcountll(un) <= kmax) {
+            Blk nbk;
+            nbk.qm = un;
+            std::vector<Blk> keep;
+            for (Blk& B : open) {
+                if (B.qm & qm) nbk.gates.insert(nbk.gates.end(), B.gates.begin(), B.gates.end());
+                else keep.push_back(std::move(B));
+            }
+            nbk.gates.push_back((int)i);
+            keep.push_back(std::move(nbk));
+            open.swap(keep);
+        } else {
+            close_touching(qm);
+            Blk nbk;
+            nbk.qm = qm;
+            nbk.gates.push_back((int)i);
+            open.push_back(std::move(nbk));
+        }
+    }
+    for (const Blk& B : open) emit(B);
+    return out;
 }
 
 }  // namespace svmi

@@ -388,6 +388,10 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
     const int L = std::min(cfg.L, T);
     const uint64_t all = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
     const uint64_t low = (1ull << L) - 1ull;
+    // a gate whose qubits above the L low bits outnumber the tile's high bits
+    // can never be local: it runs as a plain step
+    for (size_t i = 0; i < ir.size(); ++i)
+        if (inf[i].cls == C_LOCAL && !ir[i].grad && popc(inf[i].qm & ~low) > T - L) inf[i].cls = C_BIG;
     std::vector<int> rem(ir.size());
     for (size_t i = 0; i < ir.size(); ++i) rem[i] = (int)i;
     uint64_t grad_base = 0;

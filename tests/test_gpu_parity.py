@@ -187,3 +187,22 @@ def test_mirror_returns_to_zero():
     s.apply(mirror)
     got = to_host(s.tensor)[0]
     assert abs(got[0] - 1) < 1e-5 and np.max(np.abs(got[1:])) < 1e-5
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+@pytest.mark.parametrize("k", [2, 3, 4, 5, 6])
+def test_dense_block_fusion(dtype, k):
+    """Dense mode: gates fused into blocks of <= k qubits (FP64 products),
+    k <= 4 inside tile passes, 5-6 as plain kernels."""
+    m = lib()
+    n = 12
+    c = W.random_circuit(n, 200, seed=300 + k, mat_k=(2,))
+    p = W.uniform_params(1, c.n_params, 310 + k)
+    psi0 = round_c64(W.random_state(n, 320 + k))
+    t = to_dev(psi0, dtype)
+    for jit in ((-1, 1) if k == 4 else (-1,)):
+        t.copy_(to_dev(psi0, dtype))
+        s = m.StateVector(n, dtype, tensor=t, opts=m.make_opts(structured=0, max_fuse_k=k, jit=jit))
+        s.apply(c, p)
+        ref = oracle.simulate(c, p[0], psi0=psi0)
+        check_close(to_host(t)[0], ref, dtype, f"dense k={k} jit={jit}")

@@ -82,3 +82,29 @@ def test_adjoint_plan_is_the_inverse_sweep_with_shift_rule_gradients():
     ref = oracle.grad_param_shift(c, p, h, psi0)
     got = np.array([grads[i] for i in range(c.n_params)])
     np.testing.assert_allclose(got, ref, atol=1e-11)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+def test_dense_block_fusion(k):
+    m = lib()
+    c = W.random_circuit(9, 150, seed=20 + k, mat_k=(2,))
+    p = W.uniform_params(1, c.n_params, 70 + k)[0]
+    tr = _check(m, c, p, tile_bits=8, low_bits=3, psi0=W.random_state(9, k), structured=0, max_fuse_k=k)
+    widths = [int(l.split()[1]) for l in tr.splitlines() if l.startswith(("DENSE ", "DIAG "))]
+    assert max(widths) <= max(k, 2)
+    if k >= 3:
+        assert max(widths) >= 3
+
+
+def test_dense_block_fusion_grid_adjoint():
+    m = lib()
+    c = W.random_circuit(8, 90, seed=33, ops=("H", "SQRTX", "T", "CZ", "RY", "RZ", "CNOT"), param_frac=1.0)
+    p = W.uniform_params(1, c.n_params, 34)[0]
+    h = W.pauli_sum([(1.0, {0: "Z", 1: "Z"}), (0.5, {2: "X"})])
+    tr = m.plan_trace(c, p, adjoint=True, opts=m.make_opts(tile_bits=6, low_bits=3, structured=0, max_fuse_k=3))
+    psi0 = W.random_state(8, 4)
+    fwd = oracle.simulate(c, p, psi0=psi0)
+    (back, _), grads = evaluate(tr, 8, fwd, apply_pauli_sum(fwd, 8, h))
+    assert np.max(np.abs(back - psi0)) < 1e-12
+    ref = oracle.grad_param_shift(c, p, h, psi0)
+    np.testing.assert_allclose([grads[i] for i in range(c.n_params)], ref, atol=1e-11)
