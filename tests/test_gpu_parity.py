@@ -206,3 +206,34 @@ def test_dense_block_fusion(dtype, k):
         s.apply(c, p)
         ref = oracle.simulate(c, p[0], psi0=psi0)
         check_close(to_host(t)[0], ref, dtype, f"dense k={k} jit={jit}")
+
+
+@pytest.mark.parametrize("k", [5, 6])
+@pytest.mark.parametrize("n", [12, 17])
+def test_mfma_dense_blocks(k, n):
+    """5- and 6-qubit blocks on the matrix cores (complex64): explicit
+    matrices on spread targets, and per-state fused blocks of parametric
+    gates for a batch of two states."""
+    m = lib()
+    rng = np.random.default_rng(900 + 10 * k + n)
+    gates = []
+    for rep in range(3):
+        qs = tuple(int(x) for x in rng.permutation(n)[:k])
+        z = rng.standard_normal((1 << k, 1 << k)) + 1j * rng.standard_normal((1 << k, 1 << k))
+        qm, r = np.linalg.qr(z)
+        gates.append(W.Gate("MAT", qs, mat=(qm * (np.diag(r) / np.abs(np.diag(r)))).astype(np.complex128)))
+        gates.append(W.Gate("H", (int(rng.integers(0, n)),)))
+    c = W.Circuit(n, gates, 0)
+    psi0 = round_c64(W.random_state(n, 7))
+    got, _ = run(c, psi0, torch.complex64)
+    check_close(got[0], oracle.simulate(c, psi0=psi0), torch.complex64, f"MAT k={k} n={n}")
+    # per-state matrices: dense blocks fused from RY/RZ/CZ with two parameter sets
+    c2 = W.random_circuit(n, 60, seed=950 + k, ops=("RY", "RZ", "CZ", "H"), param_frac=1.0)
+    p = W.uniform_params(2, c2.n_params, 960 + k)
+    psi = np.stack([round_c64(W.random_state(n, 11 + b)) for b in range(2)])
+    t = to_dev(psi, torch.complex64)
+    s = m.StateVector(n, torch.complex64, batch=2, tensor=t, opts=m.make_opts(structured=0, max_fuse_k=k))
+    s.apply(c2, p)
+    out = to_host(t)
+    for b in range(2):
+        check_close(out[b], oracle.simulate(c2, p[b], psi0=psi[b]), torch.complex64, f"fused k={k} state {b}")
