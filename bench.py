@@ -75,6 +75,7 @@ def parse():
     p.add_argument("--tile-bits", type=int, default=0)
     p.add_argument("--low-bits", type=int, default=0)
     p.add_argument("--threads", type=int, default=0)
+    p.add_argument("--jit", type=int, default=0, help="plan-specialised kernels: 0 auto, 1 always, -1 never")
     return p.parse_args()
 
 
@@ -169,9 +170,11 @@ def batch_leg(sv, W, torch, np, count=512):
     """512 circuits, n ~ U{10..22}, 20..60 layers (RY + a random gate per qubit
     + CZ), observable sum Z_i: energies and adjoint gradients of all of them
     in one persistent launch, against the same work one circuit at a time."""
-    circs = W.batch_circuits(count, 10, 22, 20, 60, seed0=4000)
-    params = [W.uniform_params(1, c.n_params, 4000 + i)[0] for i, c in enumerate(circs)]
-    obs = [W.z_sum(c.n) for c in circs]
+    circs_py = W.batch_circuits(count, 10, 22, 20, 60, seed0=4000)
+    params = [W.uniform_params(1, c.n_params, 4000 + i)[0] for i, c in enumerate(circs_py)]
+    # marshalled once, as a caller reusing its circuits would
+    circs = [sv.CircuitABI(c) for c in circs_py]
+    obs = [sv.PauliABI(W.z_sum(c.n)) for c in circs_py]
     states = [torch.empty(1 << c.n, dtype=torch.complex64, device="cuda") for c in circs]
     lams = [torch.empty_like(t) for t in states]
     progress(f"batch: {count} circuits generated")
@@ -207,7 +210,7 @@ def batch_leg(sv, W, torch, np, count=512):
     t_one = (time.perf_counter() - t0) * count / len(sample)
     err_e = max(abs(e[i] - e_one[i][0]) for i in sample)
     err_g = max(float(np.max(np.abs(g[i] - e_one[i][1]))) for i in sample)
-    gates = sum(len(c.gates) for c in circs)
+    gates = sum(len(c.gates) for c in circs_py)
     return {
         "workload": f"{count} circuits, n 10..22, 20..60 layers, c64, forward + adjoint of sum Z",
         "gates": gates,
@@ -220,6 +223,7 @@ def batch_leg(sv, W, torch, np, count=512):
         "max_abs_diff_energy_vs_one_at_a_time": err_e,
         "max_abs_diff_grad_vs_one_at_a_time": err_g,
         "launches": st["launches"],
+        "host_prep_ms": st["plan_ms"],
     }
 
 
@@ -287,7 +291,7 @@ def main():
     circ = W.grid_circuit(3, cols, args.cycles, seed=1002)
     n = circ.n
     opts = sv.make_opts(timing=1, structured=args.structured, tile_bits=args.tile_bits,
-                        low_bits=args.low_bits, threads=args.threads)
+                        low_bits=args.low_bits, threads=args.threads, jit=args.jit)
     s = sv.StateVector(n, torch.complex64, opts=opts)
     cabi = sv.CircuitABI(circ)
     st = None
@@ -320,7 +324,7 @@ def main():
     hbm_frac = achieved_gbs / HBM_PEAK_GBS
     alu_frac = achieved_tops / VALU_PEAK_TOPS
     default_workload = (args.qubits == 33 and args.cycles == 40 and args.structured == 1 and
-                        args.tile_bits == 0 and args.low_bits == 0 and args.threads == 0)
+                        args.tile_bits == 0 and args.low_bits == 0 and args.threads == 0 and args.jit == 0)
     traffic = recorded_traffic(default_workload)
     roofline_hbm = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(hbm_frac, 4), "traffic": traffic}

@@ -45,6 +45,13 @@ class SvGate(ctypes.Structure):
                 ("param", ctypes.c_int32), ("mat", ctypes.c_int32), ("theta", ctypes.c_double)]
 
 
+# numpy view of sv_gate (same layout as SvGate: 48 bytes, theta at offset 40)
+_GATE_DTYPE = np.dtype({"names": ["op", "nq", "q", "param", "mat", "theta"],
+                        "formats": [np.int32, np.int32, (np.int32, 6), np.int32, np.int32, np.float64],
+                        "offsets": [0, 4, 8, 32, 36, 40], "itemsize": 48})
+assert ctypes.sizeof(SvGate) == _GATE_DTYPE.itemsize
+
+
 class SvCircuit(ctypes.Structure):
     _fields_ = [("n_qubits", ctypes.c_int32), ("n_gates", ctypes.c_int32),
                 ("gates", ctypes.POINTER(SvGate)), ("n_mat_doubles", ctypes.c_int64),
@@ -146,25 +153,32 @@ class CircuitABI:
         gates = list(circ.gates)
         self.n = int(circ.n)
         self.n_params = int(circ.n_params)
-        arr = (SvGate * max(1, len(gates)))()
+        ng = max(1, len(gates))
+        rec = np.zeros(ng, _GATE_DTYPE)
         mats = []
         moff = 0
-        for i, g in enumerate(gates):
-            if g.op not in OPS:
-                raise KeyError(f"unknown gate {g.op}")
-            a = arr[i]
-            a.op = OPS[g.op]
-            a.nq = len(g.qubits)
-            for t, q in enumerate(g.qubits):
-                a.q[t] = int(q)
-            a.param = int(g.param)
-            a.theta = float(g.theta)
-            a.mat = -1
-            if g.op == "MAT":
-                m = np.ascontiguousarray(g.mat, np.complex128).view(np.float64).ravel()
-                a.mat = moff
-                mats.append(m)
-                moff += m.size
+        if gates:
+            try:
+                rec["op"][:len(gates)] = [OPS[g.op] for g in gates]
+            except KeyError as e:
+                raise KeyError(f"unknown gate {e.args[0]}") from None
+            rec["nq"][:len(gates)] = [len(g.qubits) for g in gates]
+            q = rec["q"]
+            for t in range(6):
+                sel = [i for i, g in enumerate(gates) if len(g.qubits) > t]
+                if sel:
+                    q[sel, t] = [gates[i].qubits[t] for i in sel]
+            rec["param"][:len(gates)] = [g.param for g in gates]
+            rec["theta"][:len(gates)] = [g.theta for g in gates]
+            rec["mat"][:len(gates)] = -1
+            for i, g in enumerate(gates):
+                if g.op == "MAT":
+                    m = np.ascontiguousarray(g.mat, np.complex128).view(np.float64).ravel()
+                    rec["mat"][i] = moff
+                    mats.append(m)
+                    moff += m.size
+        self._rec = rec
+        arr = ctypes.cast(rec.ctypes.data, ctypes.POINTER(SvGate))
         self._gates = arr
         self._mats = np.concatenate(mats) if mats else np.zeros(1, np.float64)
         self.c = SvCircuit(self.n, len(gates), arr, int(moff),

@@ -194,7 +194,6 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
                     if (s.type != ST_TILE)  // wide (k > 4) gates: run item by item
                         return run_batch_loop(count, items, dtype, stream, flags, energies, grads, opts, stats, err);
     }
-    const double plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 
     // ---- device layout
     const size_t ab = dtype == SV_C64 ? 8 : 16;
@@ -212,7 +211,7 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
     std::vector<std::vector<uint32_t>> gg0((size_t)count), gph((size_t)count);
     std::vector<std::vector<double>> gc((size_t)count);
     std::vector<uint32_t> hT((size_t)count);
-    size_t lds = 0;
+    size_t lds = 0, lds_bwd = 0;
     for (int i = 0; i < count; ++i) {
         const EncodedPlan& F = H[i].pf->ep;
         Off& f = off[i];
@@ -234,7 +233,7 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
             f.b_etab = take(B.etab.size() * sizeof(uint16_t));
             f.b_pool = take(H[i].poolb.size());
             f.gpart = take(B.gpart_size * sizeof(double));
-            for (const DPass& P : B.passes) lds = std::max(lds, tile_lds_bytes(dtype, true, P.T, P.nform, P.ngrad, 256));
+            for (const DPass& P : B.passes) lds_bwd = std::max(lds_bwd, tile_lds_bytes(dtype, true, P.T, P.nform, P.ngrad, 256));
         }
         // observable, grouped by x mask
         const sv_pauli_sum* h = items[i].observable;
@@ -317,33 +316,47 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
         qitems[best].push_back(i);
         qload[best] += cost(i);
     }
-    std::vector<BRec> recs;
-    BatchArgs BA{};
+    // Two persistent launches on the stream: stages before the backward sweep
+    // (init, forward passes, lambda / energy), then the backward passes, each
+    // with the interpreter it needs (the backward one carries psi and lambda).
+    std::vector<BRec> recs[2];
+    BatchArgs BA[2]{};
     std::vector<std::vector<int32_t>> recid((size_t)count);
-    for (uint32_t q = 0; q < kQueues; ++q) {
-        BA.qrec0[q] = (uint32_t)recs.size();
-        std::vector<int> its = qitems[q];
-        std::sort(its.begin(), its.end());
-        uint64_t w = 0;
-        size_t maxl = 0;
-        for (int i : its) maxl = std::max(maxl, stages[i].size());
-        for (size_t lvl = 0; lvl < maxl; ++lvl)
+    for (int ph = 0; ph < 2; ++ph) {
+        for (auto& v : recid) v.clear();
+        for (uint32_t q = 0; q < kQueues; ++q) {
+            BA[ph].qrec0[q] = (uint32_t)recs[ph].size();
+            std::vector<int> its = qitems[q];
+            std::sort(its.begin(), its.end());
+            std::vector<std::vector<BRec>> st((size_t)count);
+            size_t maxl = 0;
             for (int i : its) {
-                if (lvl >= stages[i].size()) continue;
-                BRec r = stages[i][lvl];
-                r.first_w = w;
-                r.dep = lvl ? recid[i][lvl - 1] : -1;
-                w += r.ntiles;
-                recid[i].push_back((int32_t)recs.size());
-                recs.push_back(r);
+                for (const BRec& r : stages[i])
+                    if ((r.kind == BK_BWD) == (ph == 1)) st[i].push_back(r);
+                maxl = std::max(maxl, st[i].size());
             }
-        BA.qtotal[q] = w;
-        if (w >= (1ull << 31)) { err = "batch too large for one launch"; return SV_EUNSUPPORTED; }
+            uint64_t w = 0;
+            for (size_t lvl = 0; lvl < maxl; ++lvl)
+                for (int i : its) {
+                    if (lvl >= st[i].size()) continue;
+                    BRec r = st[i][lvl];
+                    r.first_w = w;
+                    r.dep = lvl ? recid[i][lvl - 1] : -1;
+                    w += r.ntiles;
+                    recid[i].push_back((int32_t)recs[ph].size());
+                    recs[ph].push_back(r);
+                }
+            BA[ph].qtotal[q] = w;
+            if (w >= (1ull << 31)) { err = "batch too large for one launch"; return SV_EUNSUPPORTED; }
+        }
+        BA[ph].qrec0[kQueues] = (uint32_t)recs[ph].size();
     }
-    BA.qrec0[kQueues] = (uint32_t)recs.size();
     const size_t o_items = take((size_t)count * sizeof(BItem));
-    const size_t o_recs = take(recs.size() * sizeof(BRec));
-    const size_t o_cnt = take((kQueues + recs.size() + 1) * sizeof(uint32_t));
+    size_t o_recs[2], o_cnt[2];
+    for (int ph = 0; ph < 2; ++ph) {
+        o_recs[ph] = take(std::max<size_t>(1, recs[ph].size()) * sizeof(BRec));
+        o_cnt[ph] = take((kQueues + recs[ph].size() + 1) * sizeof(uint32_t));
+    }
     // reduction tasks: energies then gradient slots
     struct Task { const double* src; uint64_t ntile; uint32_t nslot; uint32_t pad; double* dst; };
     std::vector<Task> tasks;
@@ -424,40 +437,45 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
     }
     if (tasks.size() > (size_t)count * 64 + 16) { err = "too many reduction tasks"; return SV_EUNSUPPORTED; }
     put(o_items, bi.data(), bi.size() * sizeof(BItem));
-    put(o_recs, recs.data(), recs.size() * sizeof(BRec));
+    for (int ph = 0; ph < 2; ++ph) put(o_recs[ph], recs[ph].data(), recs[ph].size() * sizeof(BRec));
     put(o_tasks, tasks.data(), tasks.size() * sizeof(Task));
     he = hipMemcpyAsync(dm.p, h.data(), total, hipMemcpyHostToDevice, stream);
     if (he != hipSuccess) { err = std::string("hipMemcpyAsync: ") + hipGetErrorString(he); return SV_EDEVICE; }
-    BA.items = reinterpret_cast<const BItem*>(D + o_items);
-    BA.recs = reinterpret_cast<const BRec*>(D + o_recs);
-    BA.head = reinterpret_cast<uint32_t*>(D + o_cnt);
-    BA.done = BA.head + kQueues;
-    BA.err = BA.done + recs.size();
-    {
-        int dev0 = 0, khz = 0;
-        (void)hipGetDevice(&dev0);
-        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev0) != hipSuccess || khz <= 0) khz = 100000;
-        BA.wait_ticks = (uint64_t)khz * 2000ull;   // 2 s per dependency wait
+    int dev0 = 0, khz = 0, ncu = 0;
+    (void)hipGetDevice(&dev0);
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev0) != hipSuccess || khz <= 0) khz = 100000;
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev0);
+    // host work up to the launch: IR, plans (cached by structure), pools, layout, upload
+    const double plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (int ph = 0; ph < 2; ++ph) {
+        if (recs[ph].empty()) continue;
+        BatchArgs& A = BA[ph];
+        A.items = reinterpret_cast<const BItem*>(D + o_items);
+        A.recs = reinterpret_cast<const BRec*>(D + o_recs[ph]);
+        A.head = reinterpret_cast<uint32_t*>(D + o_cnt[ph]);
+        A.done = A.head + kQueues;
+        A.err = A.done + recs[ph].size();
+        A.wait_ticks = (uint64_t)khz * 2000ull;   // 2 s per dependency wait
+        const size_t lds_ph = ph ? lds_bwd : lds;
+        int bpc = 0;
+        he = batch_occupancy(dtype, ph == 1, lds_ph, &bpc);
+        if (he != hipSuccess || bpc < 1) { err = std::string("occupancy query failed: ") + hipGetErrorString(he); return SV_EDEVICE; }
+        uint32_t nblocks = (uint32_t)(bpc * std::max(ncu, 1));
+        nblocks = std::max<uint32_t>(kQueues, nblocks / kQueues * kQueues);
+        he = launch_batch(dtype, ph == 1, A, nblocks, lds_ph, stream);
+        if (he != hipSuccess) { err = std::string("persistent launch: ") + hipGetErrorString(he); return SV_EDEVICE; }
     }
-    int bpc = 0;
-    he = batch_occupancy(dtype, lds, &bpc);
-    if (he != hipSuccess || bpc < 1) { err = std::string("occupancy query failed: ") + hipGetErrorString(he); return SV_EDEVICE; }
-    int dev = 0, ncu = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    uint32_t nblocks = (uint32_t)(bpc * std::max(ncu, 1));
-    nblocks = std::max<uint32_t>(kQueues, nblocks / kQueues * kQueues);
-    he = launch_batch(dtype, BA, nblocks, lds, stream);
-    if (he != hipSuccess) { err = std::string("persistent launch: ") + hipGetErrorString(he); return SV_EDEVICE; }
     he = launch_multi_sum(reinterpret_cast<const void*>(D + o_tasks), (uint32_t)tasks.size(), stream);
     if (he != hipSuccess) { err = std::string("reduction launch: ") + hipGetErrorString(he); return SV_EDEVICE; }
     std::vector<double> out(nout, 0.0);
-    uint32_t errflag = 0;
+    uint32_t errflag[2] = {0, 0};
     he = hipMemcpyAsync(out.data(), D + o_out, nout * sizeof(double), hipMemcpyDeviceToHost, stream);
-    if (he == hipSuccess) he = hipMemcpyAsync(&errflag, BA.err, 4, hipMemcpyDeviceToHost, stream);
+    for (int ph = 0; ph < 2; ++ph)
+        if (he == hipSuccess && !recs[ph].empty())
+            he = hipMemcpyAsync(&errflag[ph], BA[ph].err, 4, hipMemcpyDeviceToHost, stream);
     if (he == hipSuccess) he = hipStreamSynchronize(stream);
     if (he != hipSuccess) { err = std::string("batch: ") + hipGetErrorString(he); return SV_EDEVICE; }
-    if (errflag) { err = "persistent batch: a dependency wait exceeded its time budget"; return SV_EDEVICE; }
+    if (errflag[0] || errflag[1]) { err = "persistent batch: a dependency wait exceeded its time budget"; return SV_EDEVICE; }
     size_t goff = 0;
     for (int i = 0; i < count; ++i) {
         if (energies) energies[i] = out[i];
@@ -476,7 +494,7 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
             stats->gates_in += items[i].circuit->n_gates;
             stats->passes += (int32_t)H[i].pf->ep.passes.size() + (grad ? (int32_t)H[i].pb->ep.passes.size() : 0);
         }
-        stats->launches = 2;
+        stats->launches = (recs[0].empty() ? 0 : 1) + (recs[1].empty() ? 0 : 1) + 1;
         stats->plan_ms = plan_ms;
         double bytes = 0.0;
         for (int i = 0; i < count; ++i)

@@ -51,7 +51,8 @@ struct BatchArgs {
     uint64_t wait_ticks;           // budget of one dependency wait, device wall-clock ticks
 };
 
-hipError_t launch_batch(int dtype, const BatchArgs& a, uint32_t nblocks, size_t lds, hipStream_t s);
-hipError_t batch_occupancy(int dtype, size_t lds, int* blocks_per_cu);
+// bwd = false: init / forward / lambda / energy stages; true: backward stages.
+hipError_t launch_batch(int dtype, bool bwd, const BatchArgs& a, uint32_t nblocks, size_t lds, hipStream_t s);
+hipError_t batch_occupancy(int dtype, bool bwd, size_t lds, int* blocks_per_cu);
 
 }  // namespace svmi

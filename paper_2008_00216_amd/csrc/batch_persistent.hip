@@ -7,7 +7,10 @@
 // tiles; stage s of an item may start only when all tiles of stage s-1 of the
 // same item are done.
 //
-// The host lays the (item, stage) records out in 8 queues (one per XCD,
+// The batch runs as two such launches: the stages up to lambda / the energy,
+// then the backward passes (which carry psi and lambda through the
+// interpreter and need more registers).  The host lays the (item, stage)
+// records of a launch out in 8 queues (one per XCD,
 // workgroup w serves queue w % 8) in level order, so every dependency of a
 // record precedes it in its queue.  The grid holds only resident
 // workgroups; a workgroup pops a tile index with an atomic, finds its record,
@@ -107,8 +110,16 @@ __device__ __forceinline__ T* uptr(T* p) {
     return reinterpret_cast<T*>(rfl64(reinterpret_cast<uint64_t>(p)));
 }
 
-template <class R>
-__global__ __launch_bounds__(kBNT) void k_batch(BatchArgs B) {
+// Register budgets (waves per SIMD) of the variants: two waves for complex64
+// (the backward interpreter carries psi and lambda), one for complex128.
+template <class R, bool BWD>
+struct BatchWaves {
+    static constexpr int value = sizeof(R) == 4 ? 2 : 1;
+};
+
+template <class R, bool BWD>
+__global__ __launch_bounds__(kBNT) __attribute__((amdgpu_waves_per_eu(BatchWaves<R, BWD>::value)))
+void k_batch(BatchArgs B) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_ctl[4];          // popped slot, record (-1: queue empty), skip
     __shared__ double s_red[kBNT / 64];
@@ -171,16 +182,15 @@ __global__ __launch_bounds__(kBNT) void k_batch(BatchArgs B) {
         const uint32_t kind = rfl(rc.kind);
         if (!skip) {
             const BItem& it = B.items[rfl(rc.item)];
-            if (kind == BK_INIT) {
+            if (!BWD && kind == BK_INIT) {
                 init_tile<R>(it, tile, rfl(rc.T));
-            } else if (kind == BK_HPSI || kind == BK_ENERGY) {
+            } else if (!BWD && (kind == BK_HPSI || kind == BK_ENERGY)) {
                 hpsi_tile<R>(it, tile, rfl(rc.T), kind == BK_HPSI, s_red);
             } else {
-                const bool two = kind == BK_BWD;
                 // the plan pointers are uniform: keep them in scalar registers so the
                 // interpreter's loop bounds stay scalar, as in the single-circuit kernel
                 TileArgs A{};
-                const BPlan& pl = two ? it.bwd : it.fwd;
+                const BPlan& pl = BWD ? it.bwd : it.fwd;
                 A.state = uptr<void>(it.state);
                 A.lam = uptr<void>(it.lam);
                 A.pass = uptr<const DPass>(pl.passes) + rfl(rc.pass);
@@ -193,11 +203,10 @@ __global__ __launch_bounds__(kBNT) void k_batch(BatchArgs B) {
                 A.pool_bstride = 0;
                 A.state_bstride = 0;
                 A.phase_tab = A.pool;
-                A.gpart = two ? uptr<double>(it.gpart) + A.pass->gpart_off : nullptr;
+                A.gpart = BWD ? uptr<double>(it.gpart) + A.pass->gpart_off : nullptr;
                 A.ntile_log2 = rfl(it.n) - rfl(rc.T);
                 A.nthreads = kBNT;
-                if (two) tile_interp<R, kBNT, true>(A, smem, tile);
-                else tile_interp<R, kBNT, false>(A, smem, tile);
+                tile_interp<R, kBNT, BWD>(A, smem, tile);
             }
         }
         // publish this tile's global writes; wave 0 counts it with its next pop
@@ -209,16 +218,25 @@ __global__ __launch_bounds__(kBNT) void k_batch(BatchArgs B) {
 
 }  // namespace
 
-hipError_t launch_batch(int dtype, const BatchArgs& a, uint32_t nblocks, size_t lds, hipStream_t s) {
-    if (dtype == 1)
-        hipLaunchKernelGGL(k_batch<float>, dim3(nblocks), dim3(kBNT), lds, s, a);
-    else
-        hipLaunchKernelGGL(k_batch<double>, dim3(nblocks), dim3(kBNT), lds, s, a);
+template <class R, bool BWD>
+static const void* batch_fn() {
+    return reinterpret_cast<const void*>(&k_batch<R, BWD>);
+}
+
+hipError_t launch_batch(int dtype, bool bwd, const BatchArgs& a, uint32_t nblocks, size_t lds, hipStream_t s) {
+    if (dtype == 1) {
+        if (bwd) hipLaunchKernelGGL((k_batch<float, true>), dim3(nblocks), dim3(kBNT), lds, s, a);
+        else hipLaunchKernelGGL((k_batch<float, false>), dim3(nblocks), dim3(kBNT), lds, s, a);
+    } else {
+        if (bwd) hipLaunchKernelGGL((k_batch<double, true>), dim3(nblocks), dim3(kBNT), lds, s, a);
+        else hipLaunchKernelGGL((k_batch<double, false>), dim3(nblocks), dim3(kBNT), lds, s, a);
+    }
     return hipGetLastError();
 }
 
-hipError_t batch_occupancy(int dtype, size_t lds, int* blocks_per_cu) {
-    const void* f = dtype == 1 ? (const void*)&k_batch<float> : (const void*)&k_batch<double>;
+hipError_t batch_occupancy(int dtype, bool bwd, size_t lds, int* blocks_per_cu) {
+    const void* f = dtype == 1 ? (bwd ? batch_fn<float, true>() : batch_fn<float, false>())
+                               : (bwd ? batch_fn<double, true>() : batch_fn<double, false>());
     // 160 KiB of LDS per workgroup minus the kernel's static shared variables
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
     if (e != hipSuccess) return e;

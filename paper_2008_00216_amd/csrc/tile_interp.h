@@ -55,24 +55,36 @@ __device__ __forceinline__ void diag_dispatch(V2<R>* a, uint32_t mask, const V2<
     }
 }
 
+#define SVMI_BF_CASE(S, M) \
+    case (S) * 8 + (M): op_bf_rm<R, S, M>(a, RM, s, c); break;
+
 template <class R>
-__device__ __forceinline__ void bf_dispatch(V2<R>* a, uint32_t slot, uint32_t M, uint32_t RM, R s, const V2<R>* ptab) {
-    switch (slot) {
-        case 0: op_bf_rt<R, 0>(a, M, RM, s, ptab); break;
-        case 1: op_bf_rt<R, 1>(a, M, RM, s, ptab); break;
-        case 2: op_bf_rt<R, 2>(a, M, RM, s, ptab); break;
-        case 3: op_bf_rt<R, 3>(a, M, RM, s, ptab); break;
+__device__ __forceinline__ void bf_dispatch(V2<R>* a, uint32_t slot, uint32_t M, uint32_t RM, R s, R c) {
+    switch (slot * 8 + M) {
+        SVMI_BF_CASE(0, 0) SVMI_BF_CASE(0, 1) SVMI_BF_CASE(0, 2) SVMI_BF_CASE(0, 3)
+        SVMI_BF_CASE(0, 4) SVMI_BF_CASE(0, 5) SVMI_BF_CASE(0, 6) SVMI_BF_CASE(0, 7)
+        SVMI_BF_CASE(1, 0) SVMI_BF_CASE(1, 1) SVMI_BF_CASE(1, 2) SVMI_BF_CASE(1, 3)
+        SVMI_BF_CASE(1, 4) SVMI_BF_CASE(1, 5) SVMI_BF_CASE(1, 6) SVMI_BF_CASE(1, 7)
+        SVMI_BF_CASE(2, 0) SVMI_BF_CASE(2, 1) SVMI_BF_CASE(2, 2) SVMI_BF_CASE(2, 3)
+        SVMI_BF_CASE(2, 4) SVMI_BF_CASE(2, 5) SVMI_BF_CASE(2, 6) SVMI_BF_CASE(2, 7)
+        SVMI_BF_CASE(3, 0) SVMI_BF_CASE(3, 1) SVMI_BF_CASE(3, 2) SVMI_BF_CASE(3, 3)
+        SVMI_BF_CASE(3, 4) SVMI_BF_CASE(3, 5) SVMI_BF_CASE(3, 6) SVMI_BF_CASE(3, 7)
         default: break;
     }
 }
+#undef SVMI_BF_CASE
 
 template <class R>
-__device__ __forceinline__ void d1t_dispatch(V2<R>* a, uint32_t slot, const V2<R>* u, uint32_t RM, R s) {
-    switch (slot) {
-        case 0: op_d1t_rt<R, 0>(a, u, RM, s); break;
-        case 1: op_d1t_rt<R, 1>(a, u, RM, s); break;
-        case 2: op_d1t_rt<R, 2>(a, u, RM, s); break;
-        case 3: op_d1t_rt<R, 3>(a, u, RM, s); break;
+__device__ __forceinline__ void d1t_dispatch(V2<R>* a, uint32_t slot, bool real, const V2<R>* u, uint32_t RM, R s) {
+    switch (slot * 2 + (real ? 1u : 0u)) {
+        case 0: op_d1t_rm<R, 0, false>(a, u, RM, s); break;
+        case 1: op_d1t_rm<R, 0, true>(a, u, RM, s); break;
+        case 2: op_d1t_rm<R, 1, false>(a, u, RM, s); break;
+        case 3: op_d1t_rm<R, 1, true>(a, u, RM, s); break;
+        case 4: op_d1t_rm<R, 2, false>(a, u, RM, s); break;
+        case 5: op_d1t_rm<R, 2, true>(a, u, RM, s); break;
+        case 6: op_d1t_rm<R, 3, false>(a, u, RM, s); break;
+        case 7: op_d1t_rm<R, 3, true>(a, u, RM, s); break;
         default: break;
     }
 }
@@ -139,8 +151,13 @@ __device__ __forceinline__ void tile_interp(const TileArgs& A, unsigned char* sm
             V a[16];
             V l[16];
             F.load_group(sb, soff, a, l, act);
+            // op descriptors are fetched one op ahead so that their load
+            // overlaps the arithmetic of the current op
+            DOp nxt{0u, 0u, 0u, 0u};
+            if (nop) nxt = A.ops[op0];
             for (uint32_t o = op0; o < op0 + nop; ++o) {
-                const DOp op = A.ops[o];
+                const DOp op = nxt;
+                if (o + 1 < op0 + nop) nxt = A.ops[o + 1];
                 const uint32_t type = rfl(op.type), mask = rfl(op.mask), arg = rfl(op.arg);
                 switch (type) {
                     case OP_DENSE:
@@ -155,8 +172,9 @@ __device__ __forceinline__ void tile_interp(const TileArgs& A, unsigned char* sm
                         const uint32_t kk = rfl(op.k);
                         const uint64_t gm = arg == kNoPair ? 0ull : A.pairs[arg].m[0];
                         const R sg = bf_parity(lb, mask, F.base, gm) ? R(-1) : R(1);
-                        bf_dispatch<R>(a, (kk >> 4) & 3u, kk & 7u, kk >> 8, sg, F.ptab);
-                        if constexpr (TWO) bf_dispatch<R>(l, (kk >> 4) & 3u, kk & 7u, kk >> 8, sg, F.ptab);
+                        const R cw = F.ptab[1].x;
+                        bf_dispatch<R>(a, (kk >> 4) & 3u, kk & 7u, kk >> 8, sg, cw);
+                        if constexpr (TWO) bf_dispatch<R>(l, (kk >> 4) & 3u, kk & 7u, kk >> 8, sg, cw);
                         break;
                     }
                     case OP_D1T: {
@@ -164,8 +182,9 @@ __device__ __forceinline__ void tile_interp(const TileArgs& A, unsigned char* sm
                         const uint32_t pk = kk >> 7;
                         const uint64_t gm = pk == 0 ? 0ull : A.pairs[pk - 1].m[0];
                         const R sg = bf_parity(lb, mask, F.base, gm) ? R(-1) : R(1);
-                        d1t_dispatch<R>(a, kk & 3u, F.pool + arg, (kk >> 2) & 15u, sg);
-                        if constexpr (TWO) d1t_dispatch<R>(l, kk & 3u, F.pool + arg, (kk >> 2) & 15u, sg);
+                        const bool real = ((kk >> 6) & 1u) != 0;
+                        d1t_dispatch<R>(a, kk & 3u, real, F.pool + arg, (kk >> 2) & 15u, sg);
+                        if constexpr (TWO) d1t_dispatch<R>(l, kk & 3u, real, F.pool + arg, (kk >> 2) & 15u, sg);
                         break;
                     }
                     case OP_SCALE: {

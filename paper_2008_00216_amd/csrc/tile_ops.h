@@ -88,21 +88,35 @@ __device__ __forceinline__ void op_bf(V2<R>* a, R s, R c) {
     }
 }
 
-// Same with M and RM known only at run time (interpreter): one complex
-// multiply by the twiddle w^M k from the phase table per pair.
-template <class R, int S>
-__device__ __forceinline__ void op_bf_rt(V2<R>* a, uint32_t M, uint32_t RM, R s, const V2<R>* ptab) {
-    const V2<R> w = ptab[M & 7u];
-    const V2<R> t0{s * w.x, s * w.y};
+// Interpreter form of op_bf: M is a template argument (the interpreter
+// dispatches on it), the register partner mask RM is known at run time.
+template <class R, int S, int M>
+__device__ __forceinline__ void op_bf_rm(V2<R>* a, uint32_t RM, R s, R c) {
+    constexpr int j = (M >> 1) & 3;
+    constexpr bool odd = (M & 1) != 0;
+    const R kk = odd ? s * c : s;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         if (i & (1 << S)) continue;
         const V2<R> x = a[i], y = a[i | (1 << S)];
-        const bool neg = (__builtin_popcount((uint32_t)i & RM) & 1) != 0;
-        const V2<R> t = neg ? V2<R>{-t0.x, -t0.y} : t0;
-        const V2<R> ty = cmul(t, y);
-        a[i] = V2<R>{x.x + ty.x, x.y + ty.y};
-        a[i | (1 << S)] = V2<R>{x.x - ty.x, x.y - ty.y};
+        R z0, z1;
+        if constexpr (odd) {
+            z0 = y.x - y.y;
+            z1 = y.x + y.y;
+        } else {
+            z0 = y.x;
+            z1 = y.y;
+        }
+        R p0, p1;
+        bool n0, n1;
+        if constexpr (j == 0) { p0 = z0; p1 = z1; n0 = false; n1 = false; }
+        else if constexpr (j == 1) { p0 = z1; p1 = z0; n0 = true; n1 = false; }
+        else if constexpr (j == 2) { p0 = z0; p1 = z1; n0 = true; n1 = true; }
+        else { p0 = z1; p1 = z0; n0 = false; n1 = true; }
+        const R g = (__builtin_popcount((uint32_t)i & RM) & 1) ? -kk : kk;
+        const R g0 = n0 ? -g : g, g1 = n1 ? -g : g;
+        a[i] = V2<R>{fma_(g0, p0, x.x), fma_(g1, p1, x.y)};
+        a[i | (1 << S)] = V2<R>{fma_(-g0, p0, x.x), fma_(-g1, p1, x.y)};
     }
 }
 
@@ -140,19 +154,27 @@ __device__ __forceinline__ void op_d1t(V2<R>* a, const V2<R>* __restrict__ u, R 
     }
 }
 
-// Same with RM known only at run time (interpreter).
-template <class R, int S>
-__device__ __forceinline__ void op_d1t_rt(V2<R>* a, const V2<R>* __restrict__ u, uint32_t RM, R s) {
+// Interpreter form of op_d1t: the register partner mask RM at run time.
+template <class R, int S, bool REAL>
+__device__ __forceinline__ void op_d1t_rm(V2<R>* a, const V2<R>* __restrict__ u, uint32_t RM, R s) {
     const V2<R> u00 = u[0], u10 = u[2];
     const V2<R> u01{s * u[1].x, s * u[1].y}, u11{s * u[3].x, s * u[3].y};
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         if (i & (1 << S)) continue;
-        const V2<R> x = a[i], y = a[i | (1 << S)];
-        const R sg = (__builtin_popcount((uint32_t)i & RM) & 1) ? R(-1) : R(1);
-        V2<R> o0 = cmul(u00, x), o1 = cmul(u10, x);
-        cmac(o0, V2<R>{sg * u01.x, sg * u01.y}, y);
-        cmac(o1, V2<R>{sg * u11.x, sg * u11.y}, y);
+        const V2<R> x = a[i], y0 = a[i | (1 << S)];
+        const bool neg = (__builtin_popcount((uint32_t)i & RM) & 1) != 0;
+        const V2<R> y = neg ? V2<R>{-y0.x, -y0.y} : y0;
+        V2<R> o0, o1;
+        if constexpr (REAL) {
+            o0 = V2<R>{fma_(u01.x, y.x, u00.x * x.x), fma_(u01.x, y.y, u00.x * x.y)};
+            o1 = V2<R>{fma_(u11.x, y.x, u10.x * x.x), fma_(u11.x, y.y, u10.x * x.y)};
+        } else {
+            o0 = cmul(u00, x);
+            o1 = cmul(u10, x);
+            cmac(o0, u01, y);
+            cmac(o1, u11, y);
+        }
         a[i] = o0;
         a[i | (1 << S)] = o1;
     }
