@@ -458,6 +458,17 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
         }
         std::vector<int> ex;
         scan(rem, inf, S, all, &ex);
+        // at most kMaxGradPerPass gradient reductions per pass (their per-wave
+        // partials live in LDS); a prefix of the executable list in circuit
+        // order is closed under dependencies, so the rest waits for a later pass
+        {
+            int ng = 0;
+            for (size_t e = 0; e < ex.size(); ++e)
+                if (ir[ex[e]].grad && ++ng > kMaxGradPerPass) {
+                    ex.resize(e);
+                    break;
+                }
+        }
         if (ex.empty()) {
             // the frontier is a gate wider than a register phase: plain kernel
             const int id = rem[0];
