@@ -38,19 +38,23 @@ def kernel_sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(workload_is_default: bool):
+def recorded_traffic(workload_is_default: bool, geometry):
     """HBM bytes per tile-pass launch from the committed FETCH_SIZE/WRITE_SIZE
     summary (calibrated against a device copy), or None when the kernel
-    sources changed since the counters were taken or the workload differs."""
+    sources changed since the counters were taken, or the workload or tile
+    geometry differs."""
     if not workload_is_default or not os.path.exists(PROFILE):
         return None
     vals = {}
     with open(PROFILE) as f:
         for line in f:
-            if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_sources_sha256_16"):
+            if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_sources_sha256_16",
+                                                      "tile_geometry"):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
     if vals.get("kernel_sources_sha256_16") != kernel_sources_hash():
+        return None
+    if vals.get("tile_geometry") != " ".join(str(int(x)) for x in geometry):
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])
@@ -76,17 +80,18 @@ def parse():
     p.add_argument("--low-bits", type=int, default=0)
     p.add_argument("--threads", type=int, default=0)
     p.add_argument("--jit", type=int, default=0, help="plan-specialised kernels: 0 auto, 1 always, -1 never")
+    p.add_argument("--no-tune", action="store_true", help="skip the tile-geometry autotuner")
     return p.parse_args()
 
 
-def cpu_baseline(circ, budget_s=20.0):
+def cpu_baseline(circ, budget_s=25.0):
     """The FP64 oracle on the host cores, on a cut of the same circuit: the
     first `cut` qubits (gates entirely inside them).  Reported as amplitude
     updates/s and as the equivalent gates/s at the full width."""
     import numpy as np
     import oracle
     nthreads = oracle.max_threads()
-    cut = 24
+    cut = 26
     sub = circ.cut(cut)
     # time a prefix of the cut circuit, bounded by budget_s
     psi = np.zeros(1 << cut, np.complex128)
@@ -295,6 +300,13 @@ def main():
     s = sv.StateVector(n, torch.complex64, opts=opts)
     cabi = sv.CircuitABI(circ)
     st = None
+    tuned = None
+    if not args.no_tune and args.tile_bits == 0 and args.low_bits == 0 and args.threads == 0:
+        t0 = time.perf_counter()
+        chosen, best_ms = s.tune(cabi)
+        tuned = {"tile_bits": chosen["tile_bits"], "low_bits": chosen["low_bits"], "threads": chosen["threads"],
+                 "tune_s": time.perf_counter() - t0, "best_sweep_ms": best_ms}
+        progress(f"tuned: {tuned}")
     for _ in range(args.warmup):
         s.init("zero_deferred")
         st = s.apply(cabi)
@@ -323,9 +335,10 @@ def main():
     achieved_tops = ops_tile * args.steps / (tile_ms / 1e3) / 1e12
     hbm_frac = achieved_gbs / HBM_PEAK_GBS
     alu_frac = achieved_tops / VALU_PEAK_TOPS
-    default_workload = (args.qubits == 33 and args.cycles == 40 and args.structured == 1 and
-                        args.tile_bits == 0 and args.low_bits == 0 and args.threads == 0 and args.jit == 0)
-    traffic = recorded_traffic(default_workload)
+    geometry = (tuned["tile_bits"], tuned["low_bits"], tuned["threads"]) if tuned else (
+        args.tile_bits, args.low_bits, args.threads)
+    default_workload = (args.qubits == 33 and args.cycles == 40 and args.structured == 1 and args.jit == 0)
+    traffic = recorded_traffic(default_workload, geometry)
     roofline_hbm = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(hbm_frac, 4), "traffic": traffic}
     roofline_alu = {"bound": "alu", "achieved": round(achieved_tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
@@ -358,6 +371,7 @@ def main():
         "roofline_hbm": roofline_hbm,
         "roofline_alu": roofline_alu,
         "norm_error": max(abs(x - 1.0) for x in norms),
+        "tuned_geometry": tuned,
     }
     del s
     torch.cuda.empty_cache()

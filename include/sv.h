@@ -222,6 +222,18 @@ sv_status sv_apply_batch(int32_t count, const sv_batch_item* items, sv_dtype dty
  * Synchronises the stream and resets the counters. */
 sv_status sv_timing(sv_ctx ctx, double* tile_ms, int64_t* tile_launches, double* tile_bytes);
 
+/* Tile-geometry autotuner (the block-size choice of Sec. 5.1, made by
+ * measurement): applies `circuit` once per candidate geometry -- 2^T-amplitude
+ * tiles for T in {12, 13} (c64) or {11, 12} (c128), 2^L-amplitude contiguous
+ * segments for L in {4, 5} -- to the context's state, times the second of two
+ * sweeps with HIP events, and keeps the fastest in the context's options
+ * (tile_bits, low_bits, threads).  The state's content is destroyed:
+ * initialise it afterwards.  Results are remembered per (width, dtype, batch,
+ * circuit structure, options) in the process and in a text file
+ * ($SVMI_TUNE_CACHE, default /tmp/svmi-tune.txt); a remembered result is
+ * applied without running (best_ms = -1).  chosen, best_ms may be NULL. */
+sv_status sv_tune(sv_ctx ctx, const sv_circuit* circuit, const double* params, sv_opts* chosen, double* best_ms);
+
 /* Plan a circuit on the host only (no device work) and report its shape in
  * *stats (passes, phases, dense/diagonal ops, plan time, algorithmic bytes
  * and flops for one state).  `adjoint` = 1 plans the backward sweep.

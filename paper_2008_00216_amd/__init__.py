@@ -109,16 +109,17 @@ _lib.sv_sync.argtypes = [_vp]
 _lib.sv_timing.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_int64), _dp]
 _lib.sv_plan_info.argtypes = [ctypes.POINTER(SvCircuit), ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(SvOpts),
                               ctypes.POINTER(SvStats)]
+_lib.sv_tune.argtypes = [_vp, ctypes.POINTER(SvCircuit), _dp, ctypes.POINTER(SvOpts), _dp]
 _lib.sv_plan_trace.argtypes = [ctypes.POINTER(SvCircuit), _dp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(SvOpts),
                                ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
 for _f in ("sv_create", "sv_destroy", "sv_set_stream", "sv_set_opts", "sv_init", "sv_apply_circuit",
            "sv_expect", "sv_norm", "sv_adjoint_grad", "sv_apply_batch", "sv_sync", "sv_timing", "sv_plan_info",
-           "sv_plan_trace"):
+           "sv_plan_trace", "sv_tune"):
     getattr(_lib, _f).restype = ctypes.c_int32
 
 EXPORTED = ("sv_opts_default", "sv_create", "sv_destroy", "sv_set_stream", "sv_set_opts", "sv_init",
             "sv_apply_circuit", "sv_expect", "sv_norm", "sv_adjoint_grad", "sv_apply_batch", "sv_sync",
-            "sv_timing", "sv_plan_info", "sv_plan_trace", "sv_last_error", "sv_version")
+            "sv_timing", "sv_plan_info", "sv_plan_trace", "sv_tune", "sv_last_error", "sv_version")
 
 
 class SvError(RuntimeError):
@@ -299,6 +300,18 @@ class StateVector:
                                     g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(st)))
         self.last_stats = st.as_dict()
         return e, g[:, :c.n_params]
+
+    def tune(self, circ, params=None):
+        """Pick the fastest tile geometry for circ (sv_tune; destroys the state).
+        Returns (chosen options, best ms or -1 when remembered)."""
+        self._stream()
+        c = _as_circuit(circ)
+        _, pp = _params_ptr(params, self.batch, c.n_params)
+        o = SvOpts()
+        ms = ctypes.c_double()
+        _check(_lib.sv_tune(self._h, ctypes.byref(c.c), pp, ctypes.byref(o), ctypes.byref(ms)))
+        self.opts = o
+        return {k: getattr(o, k) for k, _ in o._fields_ if k != "reserved"}, ms.value
 
     def sync(self):
         _check(_lib.sv_sync(self._h))

@@ -3,6 +3,9 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cstdlib>
+#include <fstream>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -537,6 +540,104 @@ sv_status sv_apply_circuit(sv_ctx c, const sv_circuit* circ, const double* param
         for (int64_t i = 0; i < (int64_t)c->batch * circ->n_params; ++i)
             if (!std::isfinite(params[i])) return fail(SV_EINVAL, "non-finite parameter");
     return apply_internal(c, circ, params, stats);
+}
+
+// ---- tile-geometry autotuner
+namespace {
+std::mutex g_tune_mu;
+std::unordered_map<uint64_t, std::array<int32_t, 3>> g_tune;   // key -> (tile_bits, low_bits, threads)
+
+std::string tune_cache_file() {
+    const char* d = std::getenv("SVMI_TUNE_CACHE");
+    return d && *d ? std::string(d) : std::string("/tmp/svmi-tune.txt");
+}
+}  // namespace
+
+sv_status sv_tune(sv_ctx c, const sv_circuit* circ, const double* params, sv_opts* chosen, double* best_ms) {
+    if (!c) return fail(SV_EINVAL, "ctx is NULL");
+    std::string v = validate_circuit(circ, c->n);
+    if (!v.empty()) return fail(SV_EINVAL, v);
+    if (use_plain(c)) {
+        if (chosen) *chosen = c->opts;
+        if (best_ms) *best_ms = 0.0;
+        return SV_OK;
+    }
+    const sv_opts base = c->opts;
+    uint64_t key = circuit_hash(circ, 0x5a17ull ^ ((uint64_t)c->dtype << 3) ^ ((uint64_t)c->batch << 8) ^
+                                          ((uint64_t)c->n << 40) ^ ((uint64_t)base.structured << 50) ^
+                                          ((uint64_t)(base.jit + 2) << 52) ^ ((uint64_t)base.max_fuse_k << 56));
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (g_tune.empty()) {   // results of earlier processes
+            std::ifstream f(tune_cache_file());
+            unsigned long long k;
+            int32_t t, l, nt;
+            while (f >> k >> t >> l >> nt) g_tune[k] = {t, l, nt};
+        }
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            c->opts.tile_bits = it->second[0];
+            c->opts.low_bits = it->second[1];
+            c->opts.threads = it->second[2];
+            if (chosen) *chosen = c->opts;
+            if (best_ms) *best_ms = -1.0;
+            return SV_OK;
+        }
+    }
+    // candidates around the defaults: 2^T-amplitude tiles that fit two
+    // workgroups per CU, segments of 2^L contiguous amplitudes
+    const bool c64 = c->dtype == SV_C64;
+    std::vector<std::array<int32_t, 3>> cand;
+    const int t_hi = c64 ? 13 : 12;
+    for (int T = t_hi - 1; T <= t_hi; ++T)
+        for (int L = 4; L <= 5; ++L) cand.push_back({T, L, (c64 && T == 13) ? 512 : 256});
+    {   // defined values for the timing sweeps
+        sv_status is = sv_init(c, SV_INIT_UNIFORM, 0);
+        if (is != SV_OK) return is;
+    }
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    double best = 1e300;
+    std::array<int32_t, 3> pick = {base.tile_bits, base.low_bits, base.threads};
+    sv_status st = SV_OK;
+    for (const auto& cd : cand) {
+        c->opts = base;
+        c->opts.tile_bits = cd[0];
+        c->opts.low_bits = cd[1];
+        c->opts.threads = cd[2];
+        c->opts.timing = 0;
+        c->known_zero = false;
+        c->zero_pending = false;
+        st = apply_internal(c, circ, params, nullptr);   // plans and compiles
+        if (st != SV_OK) break;
+        if (hipEventRecord(e0, c->stream) != hipSuccess) { st = fail(SV_EDEVICE, "event record failed"); break; }
+        st = apply_internal(c, circ, params, nullptr);
+        if (st != SV_OK) break;
+        if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            st = fail(SV_EDEVICE, "event failed");
+            break;
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) { best = ms; pick = cd; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->opts = base;
+    if (st != SV_OK) return st;
+    c->opts.tile_bits = pick[0];
+    c->opts.low_bits = pick[1];
+    c->opts.threads = pick[2];
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = pick;
+        std::ofstream f(tune_cache_file(), std::ios::app);
+        if (f) f << (unsigned long long)key << " " << pick[0] << " " << pick[1] << " " << pick[2] << "\n";
+    }
+    if (chosen) *chosen = c->opts;
+    if (best_ms) *best_ms = best;
+    return SV_OK;
 }
 
 sv_status sv_norm(sv_ctx c, double* out) {

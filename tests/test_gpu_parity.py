@@ -237,3 +237,19 @@ def test_mfma_dense_blocks(k, n):
     out = to_host(t)
     for b in range(2):
         check_close(out[b], oracle.simulate(c2, p[b], psi0=psi[b]), torch.complex64, f"fused k={k} state {b}")
+
+
+def test_tune_then_apply(tmp_path, monkeypatch):
+    """sv_tune picks one of its candidate geometries, remembers it, and the
+    tuned context still matches the oracle."""
+    monkeypatch.setenv("SVMI_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    m = lib()
+    c = W.grid_circuit(3, 6, 10, seed=21)
+    s = m.StateVector(c.n, torch.complex64)
+    chosen, ms = s.tune(c)
+    assert chosen["tile_bits"] in (12, 13) and chosen["low_bits"] in (4, 5) and ms > 0
+    again, ms2 = s.tune(c)
+    assert ms2 == -1.0 and again["tile_bits"] == chosen["tile_bits"]
+    s.init("zero")
+    s.apply(c)
+    check_close(to_host(s.tensor)[0], oracle.simulate(c), torch.complex64, f"tuned {chosen}")
