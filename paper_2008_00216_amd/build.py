@@ -15,9 +15,11 @@ ARCH = os.environ.get("SVMI_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 # Packed FP32 instructions are disabled for all device code; common-code
-# sinking is disabled so per-slot register kernels keep static indexing.
+# sinking is disabled so per-slot register kernels keep static indexing;
+# wave-uniform branches (the interpreter's op dispatch) are left
+# unstructured, which removes most register copies at their joins.
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-mllvm", "-simplifycfg-sink-common=false"]
+          "-mllvm", "-simplifycfg-sink-common=false", "-mllvm", "-structurizecfg-skip-uniform-regions=true"]
 
 
 def _compile(src):

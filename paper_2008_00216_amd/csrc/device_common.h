@@ -68,12 +68,16 @@ __host__ __device__ constexpr int ext4(int mask, int i) {
 // XOR-linear LDS swizzle (amplitude units).  It only flips low index bits
 // as a function of higher bits, so swz(a ^ b) == swz(a) ^ swz(b); the c64
 // variant keeps bit 0 so that the two amplitudes of a 16-byte chunk stay
-// adjacent.
+// adjacent.  For c64, bits 1..4 (the bank within a 128-byte row) are mixed
+// with bits 4..8: a register phase inserts its four slot bits among the
+// thread-index bits, and mixing in the bits just above the bank bits spreads
+// the 16-lane groups of its ds_read_b64 / ds_write_b64 over all 32 banks for
+// almost every choice of slot positions.
 template <class R>
 __host__ __device__ inline constexpr uint32_t swz(uint32_t l);
 template <>
 __host__ __device__ inline constexpr uint32_t swz<float>(uint32_t l) {
-    return l ^ ((((l >> 6) ^ (l >> 11)) & 31u) << 1);
+    return l ^ ((((l >> 4) ^ (l >> 5)) & 15u) << 1);
 }
 template <>
 __host__ __device__ inline constexpr uint32_t swz<double>(uint32_t l) {
@@ -81,6 +85,30 @@ __host__ __device__ inline constexpr uint32_t swz<double>(uint32_t l) {
 }
 
 __device__ __forceinline__ uint32_t rfl(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// 1/sqrt(2) = cos(pi/4), the state dtype's rounding of its double value
+template <class R>
+constexpr R kSqrtHalf = R(0.70710678118654752440);
+
+// Plan data (op lists, matrix pools, pair masks) is written before a launch
+// and only read by kernels.  Reading it through a constant-address-space
+// pointer lets wave-uniform reads become scalar loads into SGPRs instead of
+// vector loads into every lane.
+template <class T>
+using cptr_t = const __attribute__((address_space(4))) T*;
+template <class T>
+__device__ __forceinline__ cptr_t<T> cptr(const T* p) {
+    return (cptr_t<T>)p;
+}
+// Element-wise loads that accept generic and constant-space pointers alike.
+template <class R>
+__device__ __forceinline__ V2<R> ldv(const V2<R>* p) {
+    return *p;
+}
+template <class R>
+__device__ __forceinline__ V2<R> ldv(cptr_t<V2<R>> p) {
+    return V2<R>{p->x, p->y};
+}
 
 // Flip the sign of both parts of an amplitude when bit 31 of `m` is set (exact).
 __device__ __forceinline__ void sign_flip_mask(V2<float>& a, uint32_t m) {

@@ -95,12 +95,16 @@ struct PlanCfg {
 
 // Pool recipe: what goes into each pool slot (computed per call).
 struct Recipe {
-    enum Type { DENSE = 0, DIAG = 1, SCALE = 2, VALUE = 3, PHASETAB = 4 } type = DENSE;
+    enum Type { DENSE = 0, DIAG = 1, SCALE = 2, VALUE = 3, PHASETAB = 4, BFTAB = 5 } type = DENSE;
     int gate = -1;               // IR gate
     int perm[6] = {0, 1, 2, 3, 4, 5};  // slot order: new local bit t <- gate local bit perm[t]
     int k = 0;
     double scale = 1.0;          // SCALE
     int twiddle = 0;             // DENSE k = 1: multiply column 1 by e^{i pi twiddle/4}
+    bool inplace = false;        // DENSE k = 1: also store the in-place form (r, d, flag, sign table)
+    int slot = 0;                // DENSE k = 1 in-place / BFTAB: register slot of the qubit
+    uint32_t rm = 0;             // partner register slots
+    int bf_m = 0;                // BFTAB: twiddle exponent M
     cd value{1.0, 0.0};          // VALUE
     uint64_t off = 0;            // pool offset (complex elements)
     uint64_t size = 0;

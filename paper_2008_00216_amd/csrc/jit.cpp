@@ -93,8 +93,9 @@ std::string pass_source(const EncodedPlan& ep, int pi, int dtype, bool two, int 
                     if (two) o << "      op_diag<R, " << op.mask << ">(l, F.pool + " << op.arg << ");\n";
                     break;
                 case OP_BF: {
-                    const uint32_t M = op.k & 7u, S = (op.k >> 4) & 3u, RM = op.k >> 8;
-                    const uint64_t gm = op.arg == kNoPair ? 0ull : ep.pairs[op.arg].m[0];
+                    const uint32_t M = op.k & 7u, S = (op.k >> 4) & 3u, RM = (op.k >> 8) & 15u;
+                    const bool uni = (op.k & kBfUniform) != 0;
+                    const uint64_t gm = (uni || op.arg == kNoPair) ? 0ull : ep.pairs[op.arg].m[0];
                     const bool rt = op.mask != 0 || gm != 0;
                     o << "      { ";
                     if (rt)

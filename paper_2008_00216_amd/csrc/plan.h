@@ -43,10 +43,16 @@ enum OpType : uint32_t {
 // only in slot S (y has the bit set),
 //     x <- x + t y,   y <- x - t y,   t = w^M (-1)^(parity of the index bits in
 // the partner set),  w = e^{i pi/4}.
-// Encoding: k = M | S << 4 | RM << 8 (RM: partner register slots); mask =
-// partner tile-local positions outside the registers; arg = index of a DPair
-// whose m[0] holds the partner nonlocal qubits, or kNoPair.
+// Encoding: k = M | S << 4 | RM << 8 | U << 12 (RM: partner register
+// slots); mask = partner tile-local positions outside the registers; arg =
+// index of a DPair whose m[0] holds the partner nonlocal qubits, or kNoPair.
+// U = 1 (no partner outside the registers, mask = 0): arg is instead the pool
+// offset of a sign table of 8 entries, one per register pair in increasing
+// index order: entry p = (g_p, -2 g_p), g_p = the real factor of the
+// twiddle (1 for even M, cos(pi/4) for odd M) with the sign of the pair's
+// register partner parity.
 constexpr uint32_t kNoPair = 0xffffffffu;
+constexpr uint32_t kBfUniform = 1u << 12;
 
 // OP_D1T on slot S: (x, y) <- (u00 x + s u01 y, u10 x + s u11 y) with u the
 // 2x2 matrix at pool offset `arg` (the pending 8th-root phase of the qubit is
@@ -54,6 +60,11 @@ constexpr uint32_t kNoPair = 0xffffffffu;
 // partner bits).  Encoding: k = S | RM << 2 | REAL << 6 | (pair + 1) << 7
 // (REAL: u is real; pair: DPair index of the partner nonlocal qubits, 0 =
 // none); mask = partner tile-local positions outside the registers.
+// The pool entry continues with an in-place form of u = [[a, b], [c, e]]:
+// arg+4 = r = c / a, arg+5 = d = e - r b, arg+6 = flag (.x != 0 when
+// |a| >= |c| and the form is valid), and for REAL, arg+7..arg+14 = per
+// register pair p (increasing index order) the signed (b_p, d_p) of the
+// pair's register partner parity.
 enum GradGen : uint32_t { GEN_X = 1, GEN_Y = 2, GEN_Z = 3, GEN_P11 = 4 };
 
 struct DOp {

@@ -298,12 +298,12 @@ void slot_perm(const IRGate& g, const int* slot_of_q, Recipe& rc, uint32_t& mask
 uint64_t add_recipe(EncodedPlan& out, Recipe rc, const std::vector<IRGate>& ir) {
     if (rc.type == Recipe::DENSE) {
         const int d = 1 << rc.k;
-        rc.size = (uint64_t)d * d;
+        rc.size = (uint64_t)d * d + (rc.inplace ? 11u : 0u);
         rc.varies = ir[rc.gate].m.nb > 1;
     } else if (rc.type == Recipe::DIAG) {
         rc.size = (uint64_t)1 << rc.k;
         rc.varies = ir[rc.gate].m.nb > 1;
-    } else if (rc.type == Recipe::PHASETAB) {
+    } else if (rc.type == Recipe::PHASETAB || rc.type == Recipe::BFTAB) {
         rc.size = 8;
     } else {
         rc.size = 1;
@@ -642,6 +642,16 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
                     pending.alpha[q] = g.bf_post & 7;
                     pending.konst = (pending.konst + g.bf_g) & 7;
                     DOp op{(uint32_t)OP_BF, (uint32_t)(M | (slot_of_q[0] << 4) | (t.RM << 8)), t.lmask, t.pair};
+                    if (t.lmask == 0 && t.pair == kNoPair) {
+                        // signs from register partners only: a per-pair sign table
+                        Recipe rb;
+                        rb.type = Recipe::BFTAB;
+                        rb.slot = slot_of_q[0];
+                        rb.rm = t.RM;
+                        rb.bf_m = M;
+                        op.k |= kBfUniform;
+                        op.arg = (uint32_t)add_recipe(out, rb, ir);
+                    }
                     out.ops.push_back(op);
                     if (tr) *tr += "BF " + std::to_string(q) + " " + std::to_string(M) + t.partners + "\n";
                     scale_p += 1;
@@ -661,6 +671,9 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
                     rc.gate = id;
                     rc.k = 1;
                     rc.twiddle = t.m;
+                    rc.inplace = true;
+                    rc.slot = slot_of_q[0];
+                    rc.rm = t.RM;
                     const uint64_t off = add_recipe(out, rc, ir);
                     const uint32_t pk = t.pair == kNoPair ? 0u : t.pair + 1u;
                     DOp op{(uint32_t)OP_D1T, (uint32_t)(slot_of_q[0] | (t.RM << 2) | ((real ? 1u : 0u) << 6) | (pk << 7)),
@@ -910,6 +923,11 @@ void plan_plain(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
 }
 
 namespace {
+// Register index of the q-th pair (bit `slot` clear) in increasing order.
+int pair_index(int slot, int q) {
+    return (q & ((1 << slot) - 1)) | ((q >> slot) << (slot + 1));
+}
+
 template <class R>
 void fill_pool_t(const EncodedPlan& p, const std::vector<IRGate>& ir, int batch, std::vector<unsigned char>& bytes) {
     const int nb = p.pool_varies ? batch : 1;
@@ -955,6 +973,46 @@ void fill_pool_t(const EncodedPlan& p, const std::vector<IRGate>& ir, int batch,
                             dst[2 * (r * d + col)] = (R)v.real();
                             dst[2 * (r * d + col) + 1] = (R)v.imag();
                         }
+                    if (rc.inplace) {
+                        // u = [[a, b], [c, e]] (twiddle included) as
+                        // o0 = a x + b y, o1 = (c / a) o0 + (e - (c / a) b) y,
+                        // usable when |a| >= |c| (then |c / a| <= 1)
+                        cd u[4];
+                        for (int e = 0; e < 4; ++e) {
+                            u[e] = m[e];
+                            if (rc.twiddle && (e & 1)) u[e] *= tab[rc.twiddle & 7];
+                        }
+                        cd rr(0.0, 0.0), dd(0.0, 0.0);
+                        const bool ok = std::abs(u[0]) >= std::abs(u[2]) && std::abs(u[0]) > 0.0;
+                        if (ok) {
+                            rr = u[2] / u[0];
+                            dd = u[3] - rr * u[1];
+                        }
+                        dst[8] = (R)rr.real();
+                        dst[9] = (R)rr.imag();
+                        dst[10] = (R)dd.real();
+                        dst[11] = (R)dd.imag();
+                        dst[12] = ok ? R(1) : R(0);
+                        dst[13] = 0;
+                        // real matrices: signed (b, d) per register pair
+                        for (int q = 0; q < 8; ++q) {
+                            const int i = pair_index(rc.slot, q);
+                            const bool neg = (__builtin_popcount((unsigned)i & rc.rm) & 1) != 0;
+                            dst[14 + 2 * q] = (R)(neg ? -u[1].real() : u[1].real());
+                            dst[15 + 2 * q] = (R)(neg ? -dd.real() : dd.real());
+                        }
+                    }
+                    break;
+                }
+                case Recipe::BFTAB: {
+                    const double g = (rc.bf_m & 1) ? c : 1.0;
+                    for (int q = 0; q < 8; ++q) {
+                        const int i = pair_index(rc.slot, q);
+                        const bool neg = (__builtin_popcount((unsigned)i & rc.rm) & 1) != 0;
+                        const R gq = (R)(neg ? -g : g);
+                        dst[2 * q] = gq;
+                        dst[2 * q + 1] = R(-2) * gq;
+                    }
                     break;
                 }
                 case Recipe::DIAG: {

@@ -32,7 +32,8 @@ __device__ __forceinline__ uint32_t ins0(uint32_t x, uint32_t p) {
 
 // Global offset of tile-local index l (low L bits contiguous, then the high
 // positions hpos[0..H)).
-__device__ __forceinline__ uint64_t map_local(uint32_t l, uint32_t L, uint32_t H, const uint32_t* hpos) {
+template <class HP>
+__device__ __forceinline__ uint64_t map_local(uint32_t l, uint32_t L, uint32_t H, HP hpos) {
     uint64_t o = l & ((1u << L) - 1u);
     const uint32_t hi = l >> L;
     for (uint32_t t = 0; t < H; ++t) o |= (uint64_t)((hi >> t) & 1u) << hpos[t];
@@ -55,14 +56,16 @@ struct TileFrame {
     double* red;
 
     // Carve LDS, gather the tile, evaluate the per-tile form parts.
+    template <class HP>
     __device__ __forceinline__ void begin(const TileArgs& A, unsigned char* smem, uint32_t L, uint32_t H,
-                                          uint32_t Tn, const uint32_t* hpos, uint32_t nform, uint32_t form0,
+                                          uint32_t Tn, HP hpos, uint32_t nform, uint32_t form0,
                                           uint32_t ngrad_) {
         begin_at(A, smem, L, H, Tn, hpos, nform, form0, ngrad_, blockIdx.x);
     }
     // blk = state * 2^ntile_log2 + tile
+    template <class HP>
     __device__ __forceinline__ void begin_at(const TileArgs& A, unsigned char* smem, uint32_t L, uint32_t H,
-                                             uint32_t Tn, const uint32_t* hpos, uint32_t nform, uint32_t form0,
+                                             uint32_t Tn, HP hpos, uint32_t nform, uint32_t form0,
                                              uint32_t ngrad_, uint64_t blk) {
         tid = threadIdx.x;
         T = Tn;
@@ -183,7 +186,8 @@ struct TileFrame {
     }
 
     // Gradient partials of this tile and the scatter back to HBM.
-    __device__ __forceinline__ void end(const TileArgs& A, uint32_t L, uint32_t H, const uint32_t* hpos) {
+    template <class HP>
+    __device__ __forceinline__ void end(const TileArgs& A, uint32_t L, uint32_t H, HP hpos) {
         if constexpr (TWO) {
             if (ngrad) {
                 const uint64_t ntile = 1ull << A.ntile_log2;

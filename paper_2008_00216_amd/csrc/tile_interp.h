@@ -12,7 +12,7 @@ namespace svmi {
 namespace {
 
 template <class R>
-__device__ __forceinline__ void dense_dispatch(V2<R>* a, uint32_t mask, const V2<R>* __restrict__ u) {
+__device__ __forceinline__ void dense_dispatch(V2<R>* a, uint32_t mask, cptr_t<V2<R>> u) {
     switch (mask) {
         case 1: op_dense<R, 1>(a, u); break;
         case 2: op_dense<R, 2>(a, u); break;
@@ -34,7 +34,7 @@ __device__ __forceinline__ void dense_dispatch(V2<R>* a, uint32_t mask, const V2
 }
 
 template <class R>
-__device__ __forceinline__ void diag_dispatch(V2<R>* a, uint32_t mask, const V2<R>* __restrict__ d) {
+__device__ __forceinline__ void diag_dispatch(V2<R>* a, uint32_t mask, cptr_t<V2<R>> d) {
     switch (mask) {
         case 1: op_diag<R, 1>(a, d); break;
         case 2: op_diag<R, 2>(a, d); break;
@@ -74,8 +74,27 @@ __device__ __forceinline__ void bf_dispatch(V2<R>* a, uint32_t slot, uint32_t M,
 }
 #undef SVMI_BF_CASE
 
+#define SVMI_BFT_CASE(S, M) \
+    case (S) * 8 + (M): op_bf_t<R, S, M>(a, t); break;
+
 template <class R>
-__device__ __forceinline__ void d1t_dispatch(V2<R>* a, uint32_t slot, bool real, const V2<R>* u, uint32_t RM, R s) {
+__device__ __forceinline__ void bf_dispatch_t(V2<R>* a, uint32_t slot, uint32_t M, cptr_t<V2<R>> t) {
+    switch (slot * 8 + M) {
+        SVMI_BFT_CASE(0, 0) SVMI_BFT_CASE(0, 1) SVMI_BFT_CASE(0, 2) SVMI_BFT_CASE(0, 3)
+        SVMI_BFT_CASE(0, 4) SVMI_BFT_CASE(0, 5) SVMI_BFT_CASE(0, 6) SVMI_BFT_CASE(0, 7)
+        SVMI_BFT_CASE(1, 0) SVMI_BFT_CASE(1, 1) SVMI_BFT_CASE(1, 2) SVMI_BFT_CASE(1, 3)
+        SVMI_BFT_CASE(1, 4) SVMI_BFT_CASE(1, 5) SVMI_BFT_CASE(1, 6) SVMI_BFT_CASE(1, 7)
+        SVMI_BFT_CASE(2, 0) SVMI_BFT_CASE(2, 1) SVMI_BFT_CASE(2, 2) SVMI_BFT_CASE(2, 3)
+        SVMI_BFT_CASE(2, 4) SVMI_BFT_CASE(2, 5) SVMI_BFT_CASE(2, 6) SVMI_BFT_CASE(2, 7)
+        SVMI_BFT_CASE(3, 0) SVMI_BFT_CASE(3, 1) SVMI_BFT_CASE(3, 2) SVMI_BFT_CASE(3, 3)
+        SVMI_BFT_CASE(3, 4) SVMI_BFT_CASE(3, 5) SVMI_BFT_CASE(3, 6) SVMI_BFT_CASE(3, 7)
+        default: break;
+    }
+}
+#undef SVMI_BFT_CASE
+
+template <class R>
+__device__ __forceinline__ void d1t_dispatch(V2<R>* a, uint32_t slot, bool real, cptr_t<V2<R>> u, uint32_t RM, R s) {
     switch (slot * 2 + (real ? 1u : 0u)) {
         case 0: op_d1t_rm<R, 0, false>(a, u, RM, s); break;
         case 1: op_d1t_rm<R, 0, true>(a, u, RM, s); break;
@@ -85,6 +104,28 @@ __device__ __forceinline__ void d1t_dispatch(V2<R>* a, uint32_t slot, bool real,
         case 5: op_d1t_rm<R, 2, true>(a, u, RM, s); break;
         case 6: op_d1t_rm<R, 3, false>(a, u, RM, s); break;
         case 7: op_d1t_rm<R, 3, true>(a, u, RM, s); break;
+        default: break;
+    }
+}
+
+template <class R>
+__device__ __forceinline__ void d1t_dispatch_t(V2<R>* a, uint32_t slot, cptr_t<V2<R>> u) {
+    switch (slot) {
+        case 0: op_d1t_t<R, 0>(a, u); break;
+        case 1: op_d1t_t<R, 1>(a, u); break;
+        case 2: op_d1t_t<R, 2>(a, u); break;
+        case 3: op_d1t_t<R, 3>(a, u); break;
+        default: break;
+    }
+}
+
+template <class R>
+__device__ __forceinline__ void d1t_dispatch_u(V2<R>* a, uint32_t slot, cptr_t<V2<R>> u, uint32_t pm) {
+    switch (slot) {
+        case 0: op_d1t_u<R, 0, false>(a, u, pm); break;
+        case 1: op_d1t_u<R, 1, false>(a, u, pm); break;
+        case 2: op_d1t_u<R, 2, false>(a, u, pm); break;
+        case 3: op_d1t_u<R, 3, false>(a, u, pm); break;
         default: break;
     }
 }
@@ -119,30 +160,40 @@ __device__ __forceinline__ double grad_dispatch(const V2<R>* p, const V2<R>* l, 
     }
 }
 
+__device__ __forceinline__ DOp ld_op(cptr_t<DOp> p) {
+    return DOp{p->type, p->k, p->mask, p->arg};
+}
+
 }  // namespace
 
 // Interpreter body of one tile of one pass (blk = state * tiles + tile).
 template <class R, int NT, bool TWO>
 __device__ __forceinline__ void tile_interp(const TileArgs& A, unsigned char* smem, uint64_t blk) {
     using V = V2<R>;
-    const DPass* __restrict__ P = A.pass;
+    const cptr_t<DPass> P = cptr(A.pass);
+    const cptr_t<uint32_t> hpos = cptr(A.pass->hpos);
     // pass fields are block-uniform; readfirstlane keeps every loop that
     // contains a barrier on a scalar exit condition
     const uint32_t L = rfl(P->L), H = rfl(P->H);
     TileFrame<R, NT, TWO> F;
-    F.begin_at(A, smem, L, H, rfl(P->T), P->hpos, rfl(P->nform), rfl(P->form0), rfl(P->ngrad), blk);
+    F.begin_at(A, smem, L, H, rfl(P->T), hpos, rfl(P->nform), rfl(P->form0), rfl(P->ngrad), blk);
     const uint32_t tid = F.tid;
     const uint32_t ngroups = F.NA >> kRegBits;
     const uint32_t iters = (ngroups + NT - 1) / NT;
     const uint32_t nphase = rfl(P->nphase);
+    // phase records, op descriptors, pair masks and matrices are wave-uniform
+    // and read through scalar loads
+    const cptr_t<DPhase> phs = cptr(A.phases) + rfl(P->phase0);
+    const cptr_t<DOp> ops = cptr(A.ops);
+    const cptr_t<DPair> prs = cptr(A.pairs);
+    const cptr_t<V> pool = cptr(F.pool);
     for (uint32_t ph = 0; ph < nphase; ++ph) {
-        const DPhase* __restrict__ Ph = A.phases + rfl(P->phase0) + ph;
-        const uint32_t rpos = Ph->rpos;
+        const uint32_t rpos = phs[ph].rpos;
         const uint32_t r0 = rpos & 255u, r1 = (rpos >> 8) & 255u, r2 = (rpos >> 16) & 255u, r3 = rpos >> 24;
         uint32_t soff[16];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) soff[i] = Ph->soff[i];
-        const uint32_t op0 = Ph->op0, nop = Ph->nop;
+        for (int i = 0; i < 16; ++i) soff[i] = phs[ph].soff[i];
+        const uint32_t op0 = phs[ph].op0, nop = phs[ph].nop;
         for (uint32_t it = 0; it < iters; ++it) {
             const uint32_t gg = it * NT + tid;
             const bool act = gg < ngroups;
@@ -154,48 +205,66 @@ __device__ __forceinline__ void tile_interp(const TileArgs& A, unsigned char* sm
             // op descriptors are fetched one op ahead so that their load
             // overlaps the arithmetic of the current op
             DOp nxt{0u, 0u, 0u, 0u};
-            if (nop) nxt = A.ops[op0];
+            if (nop) nxt = ld_op(ops + op0);
             for (uint32_t o = op0; o < op0 + nop; ++o) {
                 const DOp op = nxt;
-                if (o + 1 < op0 + nop) nxt = A.ops[o + 1];
+                if (o + 1 < op0 + nop) nxt = ld_op(ops + o + 1);
                 const uint32_t type = rfl(op.type), mask = rfl(op.mask), arg = rfl(op.arg);
                 switch (type) {
                     case OP_DENSE:
-                        dense_dispatch<R>(a, mask, F.pool + arg);
-                        if constexpr (TWO) dense_dispatch<R>(l, mask, F.pool + arg);
+                        dense_dispatch<R>(a, mask, pool + arg);
+                        if constexpr (TWO) dense_dispatch<R>(l, mask, pool + arg);
                         break;
                     case OP_DIAGR:
-                        diag_dispatch<R>(a, mask, F.pool + arg);
-                        if constexpr (TWO) diag_dispatch<R>(l, mask, F.pool + arg);
+                        diag_dispatch<R>(a, mask, pool + arg);
+                        if constexpr (TWO) diag_dispatch<R>(l, mask, pool + arg);
                         break;
                     case OP_BF: {
                         const uint32_t kk = rfl(op.k);
-                        const uint64_t gm = arg == kNoPair ? 0ull : A.pairs[arg].m[0];
+                        if (kk & kBfUniform) {
+                            // every lane has the same twiddles: sign table at arg
+                            bf_dispatch_t<R>(a, (kk >> 4) & 3u, kk & 7u, pool + arg);
+                            if constexpr (TWO) bf_dispatch_t<R>(l, (kk >> 4) & 3u, kk & 7u, pool + arg);
+                            break;
+                        }
+                        const uint64_t gm = arg == kNoPair ? 0ull : prs[arg].m[0];
                         const R sg = bf_parity(lb, mask, F.base, gm) ? R(-1) : R(1);
-                        const R cw = F.ptab[1].x;
-                        bf_dispatch<R>(a, (kk >> 4) & 3u, kk & 7u, kk >> 8, sg, cw);
-                        if constexpr (TWO) bf_dispatch<R>(l, (kk >> 4) & 3u, kk & 7u, kk >> 8, sg, cw);
+                        const R cw = kSqrtHalf<R>;
+                        bf_dispatch<R>(a, (kk >> 4) & 3u, kk & 7u, (kk >> 8) & 15u, sg, cw);
+                        if constexpr (TWO) bf_dispatch<R>(l, (kk >> 4) & 3u, kk & 7u, (kk >> 8) & 15u, sg, cw);
                         break;
                     }
                     case OP_D1T: {
                         const uint32_t kk = rfl(op.k);
                         const uint32_t pk = kk >> 7;
-                        const uint64_t gm = pk == 0 ? 0ull : A.pairs[pk - 1].m[0];
+                        if (mask == 0u && pk == 0u && uflag(pool[arg + 6].x)) {
+                            // same input signs in every lane, in-place form stored
+                            if ((kk >> 6) & 1u) {
+                                d1t_dispatch_t<R>(a, kk & 3u, pool + arg);
+                                if constexpr (TWO) d1t_dispatch_t<R>(l, kk & 3u, pool + arg);
+                            } else {
+                                const uint32_t pm = rm_pattern((kk >> 2) & 15u);
+                                d1t_dispatch_u<R>(a, kk & 3u, pool + arg, pm);
+                                if constexpr (TWO) d1t_dispatch_u<R>(l, kk & 3u, pool + arg, pm);
+                            }
+                            break;
+                        }
+                        const uint64_t gm = pk == 0 ? 0ull : prs[pk - 1].m[0];
                         const R sg = bf_parity(lb, mask, F.base, gm) ? R(-1) : R(1);
                         const bool real = ((kk >> 6) & 1u) != 0;
-                        d1t_dispatch<R>(a, kk & 3u, real, F.pool + arg, (kk >> 2) & 15u, sg);
-                        if constexpr (TWO) d1t_dispatch<R>(l, kk & 3u, real, F.pool + arg, (kk >> 2) & 15u, sg);
+                        d1t_dispatch<R>(a, kk & 3u, real, pool + arg, (kk >> 2) & 15u, sg);
+                        if constexpr (TWO) d1t_dispatch<R>(l, kk & 3u, real, pool + arg, (kk >> 2) & 15u, sg);
                         break;
                     }
                     case OP_SCALE: {
-                        const R s = F.pool[arg].x;
+                        const R s = pool[arg].x;
                         op_scale<R>(a, s);
                         if constexpr (TWO) op_scale<R>(l, s);
                         break;
                     }
                     case OP_PHASE8:
                     case OP_SIGN: {
-                        const DForm* __restrict__ Fm = A.forms + arg;
+                        const cptr_t<DForm> Fm = cptr(A.forms) + arg;
                         const uint32_t et = act ? (uint32_t)A.etab[Fm->etab + gg] : 0u;
                         uint32_t e0, d[4];
                         form_thread(F.fl + 4 * Fm->slot, et, lb, r0, r1, r2, r3, e0, d);
@@ -218,7 +287,7 @@ __device__ __forceinline__ void tile_interp(const TileArgs& A, unsigned char* sm
         }
         __syncthreads();
     }
-    F.end(A, L, H, P->hpos);
+    F.end(A, L, H, hpos);
 }
 
 }  // namespace svmi

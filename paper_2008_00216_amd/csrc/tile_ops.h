@@ -11,8 +11,8 @@ namespace svmi {
 // Dense 2^k x 2^k block on the slots of MASK (k = popcount(MASK) <= 4); the
 // matrix is row-major with local index bit t = the t-th lowest slot of MASK.
 // Each matrix element is loaded once and applied to every index set.
-template <class R, int MASK>
-__device__ __forceinline__ void op_dense(V2<R>* a, const V2<R>* __restrict__ u) {
+template <class R, int MASK, class U>
+__device__ __forceinline__ void op_dense(V2<R>* a, U u) {
     constexpr int K = __builtin_popcount(MASK);
     constexpr int D = 1 << K;
     V2<R> out[16];
@@ -22,7 +22,7 @@ __device__ __forceinline__ void op_dense(V2<R>* a, const V2<R>* __restrict__ u) 
     for (int o = 0; o < D; ++o) {
 #pragma unroll
         for (int c = 0; c < D; ++c) {
-            const V2<R> m = u[o * D + c];
+            const V2<R> m = ldv(u + o * D + c);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 if (r & MASK) continue;
@@ -35,10 +35,10 @@ __device__ __forceinline__ void op_dense(V2<R>* a, const V2<R>* __restrict__ u) 
 }
 
 // Diagonal on the slots of MASK: a[i] *= d[ext(MASK, i)].
-template <class R, int MASK>
-__device__ __forceinline__ void op_diag(V2<R>* a, const V2<R>* __restrict__ d) {
+template <class R, int MASK, class U>
+__device__ __forceinline__ void op_diag(V2<R>* a, U d) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) a[i] = cmul(d[ext4(MASK, i)], a[i]);
+    for (int i = 0; i < 16; ++i) a[i] = cmul(ldv(d + ext4(MASK, i)), a[i]);
 }
 
 // Twiddled butterfly on slot S (OP_BF): for each pair (x, y), y the member
@@ -120,6 +120,67 @@ __device__ __forceinline__ void op_bf_rm(V2<R>* a, uint32_t RM, R s, R c) {
     }
 }
 
+// v with its sign flipped when the wave-uniform bit f is set, computed on
+// the scalar unit so that the result is an SGPR operand.
+__device__ __forceinline__ float uneg(float v, uint32_t f) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v) ^ (int)(f << 31)));
+}
+__device__ __forceinline__ double uneg(double v, uint32_t f) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32) ^ (int)(f << 31));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sign pattern of a register partner mask: bit i = parity of (i & RM).
+__device__ __forceinline__ uint32_t rm_pattern(uint32_t RM) {
+    return ((RM & 1u) ? 0xAAAAu : 0u) ^ ((RM & 2u) ? 0xCCCCu : 0u) ^ ((RM & 4u) ? 0xF0F0u : 0u) ^
+           ((RM & 8u) ? 0xFF00u : 0u);
+}
+
+// Register pair number of index i (bit S clear): i with bit S removed.
+template <int S>
+__device__ constexpr int pair_no(int i) {
+    return (i & ((1 << S) - 1)) | ((i >> (S + 1)) << S);
+}
+
+// Interpreter form of op_bf when no partner lies outside the registers
+// (OP_BF with kBfUniform): the signed twiddle factors of the 8 pairs come
+// from the pool table t (entry p = (g_p, -2 g_p)) as scalar operands.  The
+// outputs overwrite the inputs: x' = x + t y first, then y' = x' - 2 t y, so
+// x and y end their lives at their last use and the op needs no register
+// copies (y' is rounded from x' rather than from x).
+template <class R, int S, int M, class U>
+__device__ __forceinline__ void op_bf_t(V2<R>* a, U t) {
+    constexpr int j = (M >> 1) & 3;
+    constexpr bool odd = (M & 1) != 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (i & (1 << S)) continue;
+        const V2<R> x = a[i], y = a[i | (1 << S)];
+        R z0, z1;
+        if constexpr (odd) {
+            z0 = y.x - y.y;
+            z1 = y.x + y.y;
+        } else {
+            z0 = y.x;
+            z1 = y.y;
+        }
+        R p0, p1;
+        bool n0, n1;
+        if constexpr (j == 0) { p0 = z0; p1 = z1; n0 = false; n1 = false; }
+        else if constexpr (j == 1) { p0 = z1; p1 = z0; n0 = true; n1 = false; }
+        else if constexpr (j == 2) { p0 = z0; p1 = z1; n0 = true; n1 = true; }
+        else { p0 = z1; p1 = z0; n0 = false; n1 = true; }
+        const V2<R> gh = ldv(t + pair_no<S>(i));
+        const R g0 = n0 ? -gh.x : gh.x, g1 = n1 ? -gh.x : gh.x;
+        const R h0 = n0 ? -gh.y : gh.y, h1 = n1 ? -gh.y : gh.y;
+        const R x0 = fma_(g0, p0, x.x), x1 = fma_(g1, p1, x.y);
+        a[i] = V2<R>{x0, x1};
+        a[i | (1 << S)] = V2<R>{fma_(h0, p0, x0), fma_(h1, p1, x1)};
+    }
+}
+
 // One-qubit matrix u (row-major 2x2 at u, the qubit's pending phase already
 // in its second column) on slot S with the input sign of y
 // s * (-1)^(parity of the register slots RM in the pair index) (OP_D1T).
@@ -155,9 +216,9 @@ __device__ __forceinline__ void op_d1t(V2<R>* a, const V2<R>* __restrict__ u, R 
 }
 
 // Interpreter form of op_d1t: the register partner mask RM at run time.
-template <class R, int S, bool REAL>
-__device__ __forceinline__ void op_d1t_rm(V2<R>* a, const V2<R>* __restrict__ u, uint32_t RM, R s) {
-    const V2<R> u00 = u[0], u10 = u[2];
+template <class R, int S, bool REAL, class U>
+__device__ __forceinline__ void op_d1t_rm(V2<R>* a, U u, uint32_t RM, R s) {
+    const V2<R> u00 = ldv(u), u10 = ldv(u + 2);
     const V2<R> u01{s * u[1].x, s * u[1].y}, u11{s * u[3].x, s * u[3].y};
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
@@ -179,6 +240,57 @@ __device__ __forceinline__ void op_d1t_rm(V2<R>* a, const V2<R>* __restrict__ u,
         a[i | (1 << S)] = o1;
     }
 }
+
+// Real one-qubit matrix in the in-place form with the signed (b_p, d_p) of
+// each register pair read from the pool (entries 7..14) as scalar operands.
+template <class R, int S, class U>
+__device__ __forceinline__ void op_d1t_t(V2<R>* a, U u) {
+    const R u00 = u[0].x, r = u[4].x;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (i & (1 << S)) continue;
+        const V2<R> x = a[i], y = a[i | (1 << S)];
+        const V2<R> be = ldv(u + 7 + pair_no<S>(i));
+        const V2<R> o0{fma_(be.x, y.x, u00 * x.x), fma_(be.x, y.y, u00 * x.y)};
+        a[i] = o0;
+        a[i | (1 << S)] = V2<R>{fma_(r, o0.x, be.y * y.x), fma_(r, o0.y, be.y * y.y)};
+    }
+}
+
+// Interpreter form of op_d1t when every lane has the same input signs, with
+// the outputs written over the inputs: u = [[a, b], [c, e]] is applied as
+// o0 = a x + b' y, then o1 = r o0 + d' y with r = c / a and d = e - r b
+// (u[4], u[5]; b' and d' carry the pair's partner sign), so that x and y end
+// their lives at their last use and the op needs no register copies.  The
+// planner stores this form only when |a| >= |c|.
+template <class R, int S, bool REAL, class U>
+__device__ __forceinline__ void op_d1t_u(V2<R>* a, U u, uint32_t pm) {
+    const V2<R> u00 = ldv(u), u01 = ldv(u + 1), r = ldv(u + 4), d = ldv(u + 5);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (i & (1 << S)) continue;
+        const V2<R> x = a[i], y = a[i | (1 << S)];
+        const uint32_t neg = (pm >> i) & 1u;
+        V2<R> o0, o1;
+        if constexpr (REAL) {
+            const R b = uneg(u01.x, neg), e = uneg(d.x, neg);
+            o0 = V2<R>{fma_(b, y.x, u00.x * x.x), fma_(b, y.y, u00.x * x.y)};
+            o1 = V2<R>{fma_(r.x, o0.x, e * y.x), fma_(r.x, o0.y, e * y.y)};
+        } else {
+            const V2<R> b{uneg(u01.x, neg), uneg(u01.y, neg)}, e{uneg(d.x, neg), uneg(d.y, neg)};
+            o0 = cmul(u00, x);
+            cmac(o0, b, y);
+            o1 = cmul(e, y);
+            cmac(o1, r, o0);
+        }
+        a[i] = o0;
+        a[i | (1 << S)] = o1;
+    }
+}
+
+// True when a pool flag entry is set (its bits are not all zero).
+__device__ __forceinline__ bool uflag(float v) { return __float_as_uint(v) != 0u; }
+__device__ __forceinline__ bool uflag(double v) { return __double_as_longlong(v) != 0ll; }
 
 // Thread sign of a butterfly: (-1)^(parity of the partner bits of the
 // thread's tile-local index lb and of the tile's global base).
