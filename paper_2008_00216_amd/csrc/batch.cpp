@@ -79,6 +79,12 @@ struct PlanKeyed {
 std::mutex g_plan_mu;
 std::unordered_map<uint64_t, std::shared_ptr<PlanKeyed>> g_plans;
 
+// Pinned staging for the plan upload, grow-only and shared by batch calls;
+// a call holds g_stage_mu from packing until its stream has synchronised.
+std::mutex g_stage_mu;
+void* g_stage = nullptr;
+size_t g_stage_bytes = 0;
+
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 PlanCfg batch_cfg(int dtype, bool two, int n) {
@@ -207,6 +213,10 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
     std::vector<Off> off((size_t)count);
     size_t o = 0;
     auto take = [&](size_t bytes) { const size_t r = o; o = align_up(o + std::max<size_t>(bytes, 1), 256); return r; };
+    // scratch the kernels write before they read it (gradient and energy
+    // partials, reduced outputs): placed after the uploaded part, never copied
+    size_t so = 0;
+    auto take_scratch = [&](size_t bytes) { const size_t r = so; so = align_up(so + std::max<size_t>(bytes, 1), 256); return r; };
     std::vector<std::vector<uint64_t>> gx((size_t)count), gz((size_t)count);
     std::vector<std::vector<uint32_t>> gg0((size_t)count), gph((size_t)count);
     std::vector<std::vector<double>> gc((size_t)count);
@@ -232,7 +242,7 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
             f.b_pair = take(B.pairs.size() * sizeof(DPair));
             f.b_etab = take(B.etab.size() * sizeof(uint16_t));
             f.b_pool = take(H[i].poolb.size());
-            f.gpart = take(B.gpart_size * sizeof(double));
+            f.gpart = take_scratch(B.gpart_size * sizeof(double));
             for (const DPass& P : B.passes) lds_bwd = std::max(lds_bwd, tile_lds_bytes(dtype, true, P.T, P.nform, P.ngrad, 256));
         }
         // observable, grouped by x mask
@@ -273,7 +283,7 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
         f.pph = take(gph[i].size() * 4);
         const int n = items[i].circuit->n_qubits;
         hT[i] = (uint32_t)std::min(n, 12);
-        f.epart = take(((size_t)1 << (n - hT[i])) * sizeof(double));
+        f.epart = take_scratch(((size_t)1 << (n - hT[i])) * sizeof(double));
     }
     // records: stages per item
     std::vector<std::vector<BRec>> stages((size_t)count);
@@ -366,18 +376,38 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
         gslot0[i] = nout;
         if (grad) nout += (size_t)H[i].pb->ep.ngrad_total;
     }
-    const size_t o_out = take(nout * sizeof(double));
+    const size_t o_out = take_scratch(nout * sizeof(double));
     const size_t o_tasks = take(((size_t)count * 64 + 16) * sizeof(Task));
-    const size_t total = o;
+    const size_t upload = o;
+    const size_t total = upload + so;
 
     DevMem dm;
     hipError_t he = hipMalloc(&dm.p, total);
     if (he != hipSuccess) { err = std::string("hipMalloc: ") + hipGetErrorString(he); return SV_ENOMEM; }
     unsigned char* D = reinterpret_cast<unsigned char*>(dm.p);
-    std::vector<unsigned char> h(total, 0);
-    auto put = [&](size_t at, const void* src, size_t n) { if (n) std::memcpy(h.data() + at, src, n); };
+    unsigned char* S = D + upload;   // scratch part
+    std::unique_lock<std::mutex> stage_lock(g_stage_mu);
+    // every exit below waits for the stream, so the staging buffer is never
+    // handed to the next call while an upload from it is in flight
+    struct SyncOnExit {
+        hipStream_t s;
+        ~SyncOnExit() { (void)hipStreamSynchronize(s); }
+    } sync_on_exit{stream};
+    if (g_stage_bytes < upload) {
+        if (g_stage) (void)hipHostFree(g_stage);
+        g_stage = nullptr;
+        g_stage_bytes = 0;
+        const size_t want = align_up(upload + upload / 4, (size_t)1 << 20);
+        if (hipHostMalloc(&g_stage, want, hipHostMallocDefault) == hipSuccess) g_stage_bytes = want;
+        else g_stage = nullptr;
+    }
+    std::vector<unsigned char> hv;
+    if (!g_stage) hv.assign(upload, 0);   // pinned memory unavailable: pageable upload
+    unsigned char* hp = g_stage ? reinterpret_cast<unsigned char*>(g_stage) : hv.data();
+    for (int ph = 0; ph < 2; ++ph) std::memset(hp + o_cnt[ph], 0, (kQueues + recs[ph].size() + 1) * sizeof(uint32_t));
+    auto put = [&](size_t at, const void* src, size_t n) { if (n) std::memcpy(hp + at, src, n); };
     std::vector<BItem> bi((size_t)count);
-    for (int i = 0; i < count; ++i) {
+    auto pack_item = [&](int i) {
         const Off& f = off[i];
         const EncodedPlan& F = H[i].pf->ep;
         put(f.f_pass, F.passes.data(), F.passes.size() * sizeof(DPass));
@@ -408,7 +438,7 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
                           reinterpret_cast<const DOp*>(D + f.b_op), reinterpret_cast<const DForm*>(D + f.b_form),
                           reinterpret_cast<const DPair*>(D + f.b_pair), reinterpret_cast<const uint16_t*>(D + f.b_etab),
                           D + f.b_pool};
-            b.gpart = reinterpret_cast<double*>(D + f.gpart);
+            b.gpart = reinterpret_cast<double*>(S + f.gpart);
         }
         put(f.px, gx[i].data(), gx[i].size() * 8);
         put(f.pg0, gg0[i].data(), gg0[i].size() * 4);
@@ -421,9 +451,24 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
         b.pd.c = reinterpret_cast<const double*>(D + f.pc);
         b.pd.ph = reinterpret_cast<const uint32_t*>(D + f.pph);
         b.pd.ngroup = f.ngroup;
-        b.epart = reinterpret_cast<double*>(D + f.epart);
+        b.epart = reinterpret_cast<double*>(S + f.epart);
+    };
+    {
+        // pack the items in parallel (disjoint ranges of the staging buffer)
+        std::atomic<int> next{0};
+        unsigned hw = std::thread::hardware_concurrency();
+        const int nthr = (int)std::max(1u, std::min<unsigned>(hw ? hw : 4, 16u));
+        std::vector<std::thread> th;
+        for (int t = 0; t < std::min(nthr, (int)count); ++t)
+            th.emplace_back([&] {
+                for (int i = next++; i < count; i = next++) pack_item(i);
+            });
+        for (auto& t : th) t.join();
+    }
+    for (int i = 0; i < count; ++i) {
+        const BItem& b = bi[i];
         const int n = items[i].circuit->n_qubits;
-        double* outp = reinterpret_cast<double*>(D + o_out);
+        double* outp = reinterpret_cast<double*>(S + o_out);
         if (energies) tasks.push_back(Task{b.epart, 1ull << (n - hT[i]), 1u, 0u, outp + i});
         if (grad) {
             const EncodedPlan& B = H[i].pb->ep;
@@ -439,7 +484,7 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
     put(o_items, bi.data(), bi.size() * sizeof(BItem));
     for (int ph = 0; ph < 2; ++ph) put(o_recs[ph], recs[ph].data(), recs[ph].size() * sizeof(BRec));
     put(o_tasks, tasks.data(), tasks.size() * sizeof(Task));
-    he = hipMemcpyAsync(dm.p, h.data(), total, hipMemcpyHostToDevice, stream);
+    he = hipMemcpyAsync(dm.p, hp, upload, hipMemcpyHostToDevice, stream);
     if (he != hipSuccess) { err = std::string("hipMemcpyAsync: ") + hipGetErrorString(he); return SV_EDEVICE; }
     int dev0 = 0, khz = 0, ncu = 0;
     (void)hipGetDevice(&dev0);
@@ -469,7 +514,7 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
     if (he != hipSuccess) { err = std::string("reduction launch: ") + hipGetErrorString(he); return SV_EDEVICE; }
     std::vector<double> out(nout, 0.0);
     uint32_t errflag[2] = {0, 0};
-    he = hipMemcpyAsync(out.data(), D + o_out, nout * sizeof(double), hipMemcpyDeviceToHost, stream);
+    he = hipMemcpyAsync(out.data(), S + o_out, nout * sizeof(double), hipMemcpyDeviceToHost, stream);
     for (int ph = 0; ph < 2; ++ph)
         if (he == hipSuccess && !recs[ph].empty())
             he = hipMemcpyAsync(&errflag[ph], BA[ph].err, 4, hipMemcpyDeviceToHost, stream);
