@@ -86,6 +86,34 @@ __host__ __device__ inline constexpr uint32_t swz<double>(uint32_t l) {
 
 __device__ __forceinline__ uint32_t rfl(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// One DPP move of both halves of a double (every lane active; the patterns
+// used here read lanes of the same row only).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane_f64(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes of a wave (all lanes active), in every lane: each
+// row of 16 lanes is summed with DPP (swaps within quads, then rotations by 4
+// and 8 lanes), and the four row sums are read with readlane.  No LDS round
+// trips, unlike a shuffle tree.
+__device__ __forceinline__ double wave_sum64(double v) {
+    v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_f64<0x124>(v);   // row_ror:4
+    v += dpp_f64<0x128>(v);   // row_ror:8
+    return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
+}
+
 // 1/sqrt(2) = cos(pi/4), the state dtype's rounding of its double value
 template <class R>
 constexpr R kSqrtHalf = R(0.70710678118654752440);

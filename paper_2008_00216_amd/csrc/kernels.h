@@ -67,8 +67,9 @@ hipError_t launch_reduce(int dtype, int kind, const void* a, const void* b, uint
 // lambda = H psi (FP64 accumulation, rounded once).
 hipError_t launch_hpsi(int dtype, const void* psi, void* lam, uint64_t bstride, int batch, int n,
                        const PauliDev& pd, hipStream_t s);
-// out[b * out_stride + j] = sum_t part[(b * ntile + t) * nslot + j], t ascending
-hipError_t launch_grad_reduce(const double* part, int batch, uint64_t ntile, uint32_t nslot,
+// out[b * out_stride + j] = sum_t part[(b * ntile + t) * nslot + j] in a
+// fixed order (chunks of tiles, then the chunk sums); part is overwritten.
+hipError_t launch_grad_reduce(double* part, int batch, uint64_t ntile, uint32_t nslot,
                               double* out, uint64_t out_stride, hipStream_t s);
 
 // Tasks {const double* src; uint64 ntile; uint32 nslot; uint32 pad; double* dst}:

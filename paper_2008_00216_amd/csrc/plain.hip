@@ -160,15 +160,41 @@ __global__ __launch_bounds__(kBlock) void k_init_product(V2<R>* state, uint64_t 
     }
 }
 
+// Gradient partials part[b][tile][slot] are summed over tiles in two steps
+// with a fixed order.  Step 1: block (slot chunk of 64, tile chunk c) sums
+// tiles [c*tc, (c+1)*tc) with its 4 waves taking every 4th tile, and writes
+// the chunk sum over the chunk's first row (read only by this block).
+__global__ __launch_bounds__(kBlock) void k_grad_chunk(double* __restrict__ part, uint64_t ntile, uint32_t nslot,
+                                                       uint64_t tc) {
+    __shared__ double sh[kBlock / 64][64];
+    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    const uint32_t j = blockIdx.x * 64u + lane;
+    const uint64_t t0 = (uint64_t)blockIdx.y * tc;
+    const uint64_t t1 = t0 + tc < ntile ? t0 + tc : ntile;
+    double* p = part + (uint64_t)blockIdx.z * ntile * nslot;
+    double s = 0.0;
+    if (j < nslot)
+        for (uint64_t t = t0 + w; t < t1; t += kBlock / 64) s += p[t * nslot + j];
+    sh[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && j < nslot) {
+        double r = 0.0;
+#pragma unroll
+        for (int u = 0; u < kBlock / 64; ++u) r += sh[u][lane];
+        p[t0 * nslot + j] = r;
+    }
+}
+
+// Step 2: out[b][slot] = sum over the chunk rows, chunk order.
 __global__ __launch_bounds__(kBlock) void k_grad_reduce(const double* __restrict__ part, uint64_t ntile,
-                                                        uint32_t nslot, double* __restrict__ out,
+                                                        uint32_t nslot, uint64_t tc, double* __restrict__ out,
                                                         uint64_t out_stride) {
     const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
     const uint32_t b = blockIdx.y;
     if (j >= nslot) return;
     const double* p = part + (uint64_t)b * ntile * nslot + j;
     double s = 0.0;
-    for (uint64_t t = 0; t < ntile; ++t) s += p[t * nslot];
+    for (uint64_t t = 0; t < ntile; t += tc) s += p[t * nslot];
     out[(uint64_t)b * out_stride + j] = s;
 }
 
@@ -301,10 +327,18 @@ hipError_t launch_multi_sum(const void* tasks, uint32_t ntask, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_grad_reduce(const double* part, int batch, uint64_t ntile, uint32_t nslot, double* out,
+hipError_t launch_grad_reduce(double* part, int batch, uint64_t ntile, uint32_t nslot, double* out,
                               uint64_t out_stride, hipStream_t s) {
-    const dim3 g((nslot + kBlock - 1) / kBlock, (uint32_t)batch);
-    hipLaunchKernelGGL(k_grad_reduce, g, dim3(kBlock), 0, s, part, ntile, nslot, out, out_stride);
+    if (nslot == 0 || ntile == 0) return hipSuccess;
+    const uint64_t nchunk = ntile < 64 ? ntile : 64;
+    const uint64_t tc = (ntile + nchunk - 1) / nchunk;
+    const uint64_t nc = (ntile + tc - 1) / tc;
+    const dim3 g1((nslot + 63) / 64, (uint32_t)nc, (uint32_t)batch);
+    hipLaunchKernelGGL(k_grad_chunk, g1, dim3(kBlock), 0, s, part, ntile, nslot, tc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 g2((nslot + kBlock - 1) / kBlock, (uint32_t)batch);
+    hipLaunchKernelGGL(k_grad_reduce, g2, dim3(kBlock), 0, s, part, ntile, nslot, tc, out, out_stride);
     return hipGetLastError();
 }
 

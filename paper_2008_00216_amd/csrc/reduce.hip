@@ -127,14 +127,16 @@ __global__ __launch_bounds__(kRB) void k_reduce(int kind, const V2<R>* __restric
     if (threadIdx.x == 0) partials[(uint64_t)b * gridDim.x + blockIdx.x] = s;
 }
 
-__global__ void k_final(const double* __restrict__ partials, uint32_t nb, double* __restrict__ out,
-                        uint64_t out_stride) {
+// Sum of the block partials of one state: strided per thread, then the
+// fixed block tree.
+__global__ __launch_bounds__(kRB) void k_final(const double* __restrict__ partials, uint32_t nb,
+                                               double* __restrict__ out, uint64_t out_stride) {
+    __shared__ double sh[kRB / 64];
     const uint32_t b = blockIdx.x;
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (uint32_t i = 0; i < nb; ++i) s += partials[(uint64_t)b * nb + i];
-        out[(uint64_t)b * out_stride] = s;
-    }
+    double acc = 0.0;
+    for (uint32_t i = threadIdx.x; i < nb; i += kRB) acc += partials[(uint64_t)b * nb + i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[(uint64_t)b * out_stride] = s;
 }
 
 template <class R>
@@ -184,7 +186,7 @@ hipError_t launch_reduce(int dtype, int kind, const void* a, const void* b, uint
                            reinterpret_cast<const V2<double>*>(b), bstride, N, p, gen, gmask, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_final, dim3((uint32_t)batch), dim3(64), 0, s, partials, nb, out, out_stride);
+    hipLaunchKernelGGL(k_final, dim3((uint32_t)batch), dim3(kRB), 0, s, partials, nb, out, out_stride);
     return hipGetLastError();
 }
 

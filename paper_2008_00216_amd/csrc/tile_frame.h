@@ -179,11 +179,7 @@ struct TileFrame {
         v = wave_sum_(v);
         if ((tid & 63u) == 0) red[slot * NW + (tid >> 6)] += v;
     }
-    __device__ __forceinline__ static double wave_sum_(double v) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        return v;
-    }
+    __device__ __forceinline__ static double wave_sum_(double v) { return wave_sum64(v); }
 
     // Gradient partials of this tile and the scatter back to HBM.
     template <class HP>

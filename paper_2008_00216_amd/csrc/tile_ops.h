@@ -397,10 +397,5 @@ __device__ __forceinline__ double op_grad11(const V2<R>* p, const V2<R>* l) {
     return acc;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
 
 }  // namespace svmi
