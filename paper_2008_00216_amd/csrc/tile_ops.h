@@ -357,45 +357,48 @@ __device__ __forceinline__ void op_phase8(V2<R>* a, V2<R>* l, uint32_t e0, const
 }
 
 // ---- adjoint gradient terms -----------------------------------------------
-__device__ __forceinline__ double imcj(double ux, double uy, double vx, double vy) {
-    return ux * vy - uy * vx;  // Im(conj(u) v)
-}
-__device__ __forceinline__ double recj(double ux, double uy, double vx, double vy) {
-    return ux * vx + uy * vy;  // Re(conj(u) v)
-}
-
-// Im <lambda|G|psi> over the 16 register amplitudes (FP64), G = X, Y or Z on
-// slot S.
+// Im <lambda|G|psi> over the 16 register amplitudes, G = X, Y or Z on slot
+// S.  The thread's products are accumulated with fused multiply-adds in the
+// state's precision (two chains) and returned as a double; the sum of these
+// partials over the 2^n / 16 register groups of the state is taken in FP64.
 template <class R, int S, uint32_t GEN>
 __device__ __forceinline__ double op_grad1(const V2<R>* p, const V2<R>* l) {
-    double acc = 0.0;
+    R acc[2] = {R(0), R(0)};
+    int c = 0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         if (i & (1 << S)) continue;
         const int j = i | (1 << S);
-        const double p0x = p[i].x, p0y = p[i].y, p1x = p[j].x, p1y = p[j].y;
-        const double l0x = l[i].x, l0y = l[i].y, l1x = l[j].x, l1y = l[j].y;
+        const V2<R> p0 = p[i], p1 = p[j], l0 = l[i], l1 = l[j];
+        R& a = acc[c++ & 1];
         if constexpr (GEN == GEN_X) {
-            acc += imcj(l0x, l0y, p1x, p1y) + imcj(l1x, l1y, p0x, p0y);
+            // Im(conj(l0) p1) + Im(conj(l1) p0)
+            a = fma_(l0.x, p1.y, a); a = fma_(-l0.y, p1.x, a);
+            a = fma_(l1.x, p0.y, a); a = fma_(-l1.y, p0.x, a);
         } else if constexpr (GEN == GEN_Y) {
-            // (Y psi)_0 = -i psi_1, (Y psi)_1 = i psi_0
-            acc += -recj(l0x, l0y, p1x, p1y) + recj(l1x, l1y, p0x, p0y);
+            // (Y psi)_0 = -i psi_1, (Y psi)_1 = i psi_0: Re(conj(l1) p0) - Re(conj(l0) p1)
+            a = fma_(l1.x, p0.x, a); a = fma_(l1.y, p0.y, a);
+            a = fma_(-l0.x, p1.x, a); a = fma_(-l0.y, p1.y, a);
         } else {
-            acc += imcj(l0x, l0y, p0x, p0y) - imcj(l1x, l1y, p1x, p1y);
+            // Im(conj(l0) p0) - Im(conj(l1) p1)
+            a = fma_(l0.x, p0.y, a); a = fma_(-l0.y, p0.x, a);
+            a = fma_(-l1.x, p1.y, a); a = fma_(l1.y, p1.x, a);
         }
     }
-    return acc;
+    return (double)acc[0] + (double)acc[1];
 }
 
 // Generator -2 |11><11| on the two slots of MASK (controlled phase).
 template <class R, int MASK>
 __device__ __forceinline__ double op_grad11(const V2<R>* p, const V2<R>* l) {
-    double acc = 0.0;
+    R acc = R(0);
 #pragma unroll
     for (int i = 0; i < 16; ++i)
-        if ((i & MASK) == MASK) acc += -2.0 * imcj(l[i].x, l[i].y, p[i].x, p[i].y);
-    return acc;
+        if ((i & MASK) == MASK) {
+            acc = fma_(l[i].x, p[i].y, acc);
+            acc = fma_(-l[i].y, p[i].x, acc);
+        }
+    return -2.0 * (double)acc;
 }
-
 
 }  // namespace svmi
