@@ -316,9 +316,13 @@ uint64_t add_recipe(EncodedPlan& out, Recipe rc, const std::vector<IRGate>& ir) 
     return rc.off;
 }
 
-// Butterflies between two applications of the accumulated 1/sqrt(2) factors
-// (a growth of 2^60 at most: amplitudes stay far from the FP32 range limits).
+// Butterflies between two applications of the accumulated 1/sqrt(2) factors:
+// amplitudes grow by 2^60 at most in a forward sweep, and by 2^30 in an
+// adjoint sweep, where the gradient terms multiply a psi and a lambda
+// amplitude in the state's precision (FP32 for c64).  The factor is applied
+// as soon as the count is reached, inside a pass if need be.
 constexpr int kScaleEvery = 120;
+constexpr int kScaleEveryAdjoint = 60;
 
 double op_cost(const IRGate& g) {
     if (g.kind == K_DIAG8) return 0.0;
@@ -401,9 +405,10 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
     // twiddle, so most of them are never applied as separate ops.
     Form pending;
     // Each butterfly grows the state by sqrt(2); the factor 2^(-scale_p/2) is
-    // applied once every few passes (FP32 keeps the growth exactly) and
-    // before the state is handed back.
+    // applied when scale_p reaches its limit (FP32 keeps the growth exactly)
+    // and before the state is handed back.
     int scale_p = 0;
+    const int scale_every = cfg.two ? kScaleEveryAdjoint : kScaleEvery;
 
     while (!rem.empty()) {
         // ---- choose the local set S (|S| = T, low bits always local)
@@ -584,6 +589,21 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
                 out.alu_ops += (so ? 1.0 : 4.0) * (double)(1ull << n) * (cfg.two ? 2 : 1);
                 pending.clear();
             };
+            auto emit_scale = [&]() {
+                Recipe rc;
+                rc.type = Recipe::SCALE;
+                rc.scale = std::ldexp(1.0, -(scale_p / 2)) * ((scale_p & 1) ? std::sqrt(0.5) : 1.0);
+                const uint64_t off = add_recipe(out, rc, ir);
+                DOp op{(uint32_t)OP_SCALE, 0u, 0u, (uint32_t)off};
+                out.ops.push_back(op);
+                if (tr) {
+                    char b[64];
+                    std::snprintf(b, sizeof(b), "SCALE %.17g\n", rc.scale);
+                    *tr += b;
+                }
+                scale_p = 0;
+                out.alu_ops += 2.0 * (double)(1ull << n) * (cfg.two ? 2 : 1);
+            };
             for (int id : pex) {
                 const IRGate& g = ir[id];
                 if (inf[id].cls == C_FREE) {
@@ -637,6 +657,7 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
                 };
                 if (g.skind == OP_BF) {
                     const int q = g.q[0];
+                    if (scale_p >= scale_every) emit_scale();
                     Tw t = take_twiddle(q);
                     const int M = (t.m + g.bf_pre) & 7;
                     pending.alpha[q] = g.bf_post & 7;
@@ -744,21 +765,7 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
             }
             if (prem.empty()) {
                 if (flush_at_end) flush(true);
-                if (scale_p && (flush_at_end || scale_p >= kScaleEvery)) {
-                    Recipe rc;
-                    rc.type = Recipe::SCALE;
-                    rc.scale = std::ldexp(1.0, -(scale_p / 2)) * ((scale_p & 1) ? std::sqrt(0.5) : 1.0);
-                    const uint64_t off = add_recipe(out, rc, ir);
-                    DOp op{(uint32_t)OP_SCALE, 0u, 0u, (uint32_t)off};
-                    out.ops.push_back(op);
-                    if (tr) {
-                        char b[64];
-                        std::snprintf(b, sizeof(b), "SCALE %.17g\n", rc.scale);
-                        *tr += b;
-                    }
-                    scale_p = 0;
-                    out.alu_ops += 2.0 * (double)(1ull << n) * (cfg.two ? 2 : 1);
-                }
+                if (scale_p && (flush_at_end || scale_p >= scale_every)) emit_scale();
             }
             Ph.nop = (uint32_t)(out.ops.size() - Ph.op0);
             out.phases.push_back(Ph);

@@ -88,3 +88,24 @@ def test_autograd_function():
     for b in range(2):
         g_ref = oracle.grad_param_shift(c, th.detach().numpy()[b], h)
         np.testing.assert_allclose(th.grad.numpy()[b], g_ref, atol=1e-10)
+
+
+@pytest.mark.parametrize("jit", [-1, 1])
+def test_long_single_pass_adjoint(jit):
+    """Hundreds of butterflies inside one tile pass: the accumulated
+    1/sqrt(2) factors must be applied within the pass so that psi, lambda
+    and their products stay in the FP32 range (they overflowed to inf/NaN
+    when the factor was only applied at pass ends)."""
+    m = lib()
+    n = 11
+    c = W.layered_param_circuit(n, 40, 7011)
+    p = W.uniform_params(1, c.n_params, 7012)
+    h = W.z_sum(n)
+    s = m.StateVector(n, torch.complex64, opts=m.make_opts(jit=jit))
+    s.init("zero")
+    e, g = s.adjoint_grad(c, p, h)
+    assert np.all(np.isfinite(g)) and np.isfinite(e[0])
+    ref = oracle.grad_param_shift(c, p[0], h)
+    sel = list(range(0, c.n_params, 23))
+    np.testing.assert_allclose(g[0][sel], ref[sel], atol=2e-4)
+    assert abs(e[0] - oracle.expect(oracle.simulate(c, p[0]), h)) < 2e-4

@@ -62,3 +62,20 @@ def test_batch_adjoint_gradients(dtype):
         s.init("zero")
         e1, g1 = s.adjoint_grad(c, params[i][None, :], obs[i])
         np.testing.assert_allclose(g1[0], g[i], atol=tol)
+
+
+def test_batch_long_circuits_gradients():
+    """Long circuits (30-40 layers, one or two tile passes each) in one
+    persistent launch: gradients finite and equal to the shift rule."""
+    m = lib()
+    circs = W.batch_circuits(4, n_lo=10, n_hi=13, l_lo=30, l_hi=40, seed0=7100)
+    params = [W.uniform_params(1, c.n_params, 7200 + i)[0] for i, c in enumerate(circs)]
+    obs = [W.z_sum(c.n) for c in circs]
+    states = [torch.empty(1 << c.n, dtype=torch.complex64, device="cuda") for c in circs]
+    lams = [torch.empty_like(t) for t in states]
+    e, g, _ = m.apply_batch(circs, params, states, obs, lambdas=lams, grad=True, init_zero=True)
+    for i, c in enumerate(circs):
+        assert np.all(np.isfinite(g[i])), i
+        ref = oracle.grad_param_shift(c, params[i], obs[i])
+        sel = list(range(0, c.n_params, 29))
+        np.testing.assert_allclose(g[i][sel], ref[sel], atol=2e-4)

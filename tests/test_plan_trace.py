@@ -108,3 +108,40 @@ def test_dense_block_fusion_grid_adjoint():
     assert np.max(np.abs(back - psi0)) < 1e-12
     ref = oracle.grad_param_shift(c, p, h, psi0)
     np.testing.assert_allclose([grads[i] for i in range(c.n_params)], ref, atol=1e-11)
+
+
+def _max_scale_exponent(tr):
+    """Largest number of unscaled butterflies at any point of a trace."""
+    run = worst = 0
+    for line in tr.splitlines():
+        if line.startswith("BF "):
+            run += 1
+            worst = max(worst, run)
+        elif line.startswith("SCALE"):
+            run = 0
+    return worst
+
+
+def test_scale_factor_applied_inside_long_passes():
+    """A whole circuit in one tile pass with hundreds of butterflies: the
+    1/sqrt(2) factors are applied whenever 120 (forward) or 60 (adjoint)
+    have accumulated, not only at pass ends, and the plan stays exact."""
+    m = lib()
+    c = W.layered_param_circuit(10, 40, 4021)
+    p = W.uniform_params(1, c.n_params, 4022)[0]
+    opts = m.make_opts(tile_bits=10, low_bits=4)
+    tr = m.plan_trace(c, p, opts=opts)
+    assert tr.count("PASS") == 1 and tr.count("BF ") > 240
+    assert _max_scale_exponent(tr) <= 120
+    got, _ = evaluate(tr, c.n, W.basis_state(c.n, 0))
+    assert np.max(np.abs(got - oracle.simulate(c, p))) < 1e-12
+    tra = m.plan_trace(c, p, adjoint=True, opts=opts)
+    assert _max_scale_exponent(tra) <= 60
+    h = W.z_sum(c.n)
+    psi0 = W.random_state(c.n, 5)
+    fwd = oracle.simulate(c, p, psi0=psi0)
+    (back, _), grads = evaluate(tra, c.n, fwd, apply_pauli_sum(fwd, c.n, h))
+    assert np.max(np.abs(back - psi0)) < 1e-11
+    sel = list(range(0, c.n_params, 37))
+    ref = oracle.grad_param_shift(c, p, h, psi0)
+    np.testing.assert_allclose([grads[i] for i in sel], ref[sel], atol=1e-10)
