@@ -135,6 +135,7 @@ def adjoint_leg(sv, W, torch, np):
         e, g = s.adjoint_grad(c, th, h, scratch)
     torch.cuda.synchronize()
     t_adj = (time.time() - t0) / reps
+    adj_ops = s.last_stats["alu_ops"]   # forward + backward sweeps, all 64 sets
     # finite differences with the plain per-gate kernels on the same GPU
     sp = sv.StateVector(n, torch.complex64, batch=B, opts=sv.make_opts(plain=1))
     hstep = 1e-3
@@ -158,6 +159,9 @@ def adjoint_leg(sv, W, torch, np):
     return {
         "workload": "ansatz20q-10layers-400params-batch64-c64",
         "adjoint_s": t_adj,
+        "roofline_alu": {"bound": "alu", "achieved": round(adj_ops / t_adj / 1e12, 2), "peak": round(VALU_PEAK_TOPS, 2),
+                         "unit": "TOP/s", "frac": round(adj_ops / t_adj / 1e12 / VALU_PEAK_TOPS, 4),
+                         "note": "algorithmic vector instructions of the forward and backward sweeps / whole call"},
         "grad_vectors_per_s": B / t_adj,
         "param_grads_per_s": B * c.n_params / t_adj,
         "fd_plain_s_extrapolated": t_fd_full,
@@ -220,6 +224,10 @@ def batch_leg(sv, W, torch, np, count=512):
         "workload": f"{count} circuits, n 10..22, 20..60 layers, c64, forward + adjoint of sum Z",
         "gates": gates,
         "batch_s": t_batch,
+        "roofline_alu": {"bound": "alu", "achieved": round(st["alu_ops"] / t_batch / 1e12, 2),
+                         "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
+                         "frac": round(st["alu_ops"] / t_batch / 1e12 / VALU_PEAK_TOPS, 4),
+                         "note": "algorithmic vector instructions of all forward and backward passes / whole call"},
         "circuits_per_s": count / t_batch,
         "gates_per_s": gates / t_batch,
         "one_at_a_time_s_extrapolated": t_one,

@@ -134,7 +134,9 @@ typedef struct {
     double hbm_bytes;       /* algorithmic HBM bytes moved by the sweep */
     double flops;           /* algorithmic floating-point operations (an FMA counts 2) */
     double alu_ops;         /* algorithmic vector arithmetic instructions per lane of the
-                               tile passes (an FMA counts 1): the ALU-side roofline */
+                               tile passes (an FMA counts 1): the ALU-side roofline.
+                               sv_adjoint_grad counts the forward and backward sweeps
+                               (gradient terms included), sv_apply_batch all items */
 } sv_stats;
 
 typedef struct sv_ctx_s* sv_ctx;

@@ -538,6 +538,7 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
         for (int i = 0; i < count; ++i) {
             stats->gates_in += items[i].circuit->n_gates;
             stats->passes += (int32_t)H[i].pf->ep.passes.size() + (grad ? (int32_t)H[i].pb->ep.passes.size() : 0);
+            stats->alu_ops += H[i].pf->ep.alu_ops + (grad ? H[i].pb->ep.alu_ops : 0.0);
         }
         stats->launches = (recs[0].empty() ? 0 : 1) + (recs[1].empty() ? 0 : 1) + 1;
         stats->plan_ms = plan_ms;

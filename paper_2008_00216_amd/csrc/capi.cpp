@@ -727,7 +727,10 @@ sv_status sv_adjoint_grad(sv_ctx c, const sv_circuit* circ, const double* params
             for (int s = 0; s < ns; ++s) g[cp->ep.grad_param[s]] += cp->ep.grad_scale[s] * row[s];
         }
     }
-    if (stats) stats->plan_ms += plan_ms;
+    if (stats) {
+        stats->plan_ms += plan_ms;
+        stats->alu_ops += cp->ep.alu_ops * c->batch;   // backward sweep
+    }
     return SV_OK;
 }
 

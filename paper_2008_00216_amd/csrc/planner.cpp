@@ -729,6 +729,8 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
                     // psi and lambda both carry sqrt(2)^scale_p at this point of the pass
                     out.grad_scale.push_back(std::ldexp(1.0, -scale_p));
                     ++ngrad;
+                    // 4 multiply-adds per register pair (a psi and a lambda amplitude each)
+                    out.alu_ops += 2.0 * (double)(1ull << n);
                     continue;
                 }
                 Recipe rc;
