@@ -72,6 +72,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-adjoint", action="store_true")
     p.add_argument("--no-batch", action="store_true")
+    p.add_argument("--no-sample", action="store_true")
     p.add_argument("--ksweep", action="store_true", help="30-qubit dense-width sweep instead of the benchmark")
     p.add_argument("--calib-copy-gib", type=float, default=0.0,
                    help="run a device copy of this size first (counter calibration)")
@@ -240,6 +241,28 @@ def batch_leg(sv, W, torch, np, count=512):
     }
 
 
+def sample_leg(s, W, np, n, shots=1 << 20, reps=3):
+    """Measurement sampling from the final state of the sweep: `shots`
+    bit strings per call, inverse-CDF over FP64 chunk masses.  The state is
+    read once in full (chunk masses) plus once more per distinct chunk that
+    receives a sample (in-chunk prefix), so the HBM figure counts both."""
+    u = W.sample_uniforms(shots, seed=16)
+    s.sample(u)                                     # warm-up: buffers
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        got = s.sample(u)
+    dt = (time.perf_counter() - t0) / reps
+    amp = s.amplitudes(got[:8192])[0]
+    xeb = float(np.mean(np.abs(amp) ** 2) * float(1 << n) - 1.0)
+    chunk_bits = min(n, 12)
+    distinct = int(np.unique(got >> np.uint64(chunk_bits)).size)
+    state_bytes = float(1 << n) * 8
+    read = state_bytes + distinct * float(1 << chunk_bits) * 8
+    return {"shots": shots, "ms_per_call": dt * 1e3, "samples_per_s": shots / dt,
+            "distinct_chunks": distinct, "hbm_bytes_algorithmic": read,
+            "GBps_whole_call": read / dt / 1e9, "linear_xeb_8192": xeb}
+
+
 def ksweep(sv, W, torch, steps=2):
     """5x6 grid, 30 qubits, 20 cycles, complex64: the butterfly mode against
     dense blocks of at most k qubits (k = 1..6).  One JSON line per mode."""
@@ -381,9 +404,12 @@ def main():
         "norm_error": max(abs(x - 1.0) for x in norms),
         "tuned_geometry": tuned,
     }
+    progress(f"sweep: {ms_per_step:.1f} ms per step")
+    if not args.no_sample:
+        out["sample"] = sample_leg(s, W, np, n)
+        progress(f"sampling: {out['sample']['ms_per_call']:.1f} ms per call")
     del s
     torch.cuda.empty_cache()
-    progress(f"sweep: {ms_per_step:.1f} ms per step")
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(sv, W, torch, np)
         progress("adjoint leg done")

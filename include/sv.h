@@ -185,6 +185,26 @@ sv_status sv_expect(sv_ctx ctx, const sv_pauli_sum* obs, double* out);
 /* out[b] = ||psi_b||^2 in FP64 (norm check of Sec. 4.1).  Synchronises. */
 sv_status sv_norm(sv_ctx ctx, double* out);
 
+/* Measurement of every qubit in the computational basis (Sec. 2: the state
+ * vector gives the probability |psi_j|^2 of every output bit string j), by
+ * inverse-CDF sampling with the caller's random numbers:
+ *   uniforms  host, batch * count values in [0, 1) (row b = state b)
+ *   out       host, batch * count indices: out[b * count + k] is the
+ *             smallest j with sum_{i <= j} |psi_b[i]|^2 > u * ||psi_b||^2,
+ *             u = uniforms[b * count + k].
+ * The prefix sums are FP64: chunk masses of 4096 consecutive amplitudes on
+ * the device, their prefix on the host, the prefix inside a chunk on the
+ * device.  A target that rounding puts at the very end of a chunk maps to
+ * the chunk's last amplitude of nonzero probability.  Synchronises.
+ * Errors: SV_EINVAL for NULL pointers, uniforms outside [0, 1) or a state
+ * of zero or non-finite norm. */
+sv_status sv_sample(sv_ctx ctx, int64_t count, const double* uniforms, uint64_t* out);
+
+/* Amplitude readout: out[2 * (b * count + k)] and out[2 * (b * count + k) + 1]
+ * are the real and imaginary parts of psi_b[indices[k]] (host arrays; indices
+ * must be < 2^n).  Synchronises. */
+sv_status sv_amplitudes(sv_ctx ctx, int64_t count, const uint64_t* indices, double* out);
+
 /* Adjoint gradient of E_b = <psi_b|H|psi_b> with psi_b = U(theta_b) psi_b^in,
  * where psi_b^in is the current state.  Runs the forward sweep, forms
  * lambda = H psi in d_scratch (caller-owned, >= state_bytes), then sweeps

@@ -17,6 +17,7 @@ Functions:
   energy        expect(simulate(...))
   grad_param_shift  exact gradient for exp(-i theta P/2) gates (two-term shift)
   grad_fd       central finite differences
+  sample        measurement of all qubits by inverse-CDF sampling
 
 Parity status: every function here is pinned by tests under tests/ (brute
 force operator products, closed forms, printed matrices and identities of the
@@ -205,3 +206,23 @@ def apply_op_list(psi: np.ndarray, n: int, ops: List, nthreads: int = 0) -> np.n
     for qs, u in ops:
         apply_matrix(psi, n, qs, u, nthreads)
     return psi
+
+
+def sample(psi: np.ndarray, uniforms: np.ndarray) -> np.ndarray:
+    """Outcomes of measuring every qubit (Sec. 2: outcome j has probability
+    |alpha_j|^2; Sec. 3 notes that measurements follow from the amplitudes
+    once all are known), one per random number u in [0, 1): the smallest j
+    whose cumulative probability, sum_{i <= j} |alpha_i|^2, exceeds
+    u * ||psi||^2.  FP64 throughout; a u whose target rounds to the total maps
+    to the last outcome of nonzero probability."""
+    p = np.abs(np.asarray(psi, dtype=np.complex128)) ** 2
+    cdf = np.cumsum(p)
+    u = np.asarray(uniforms, dtype=np.float64)
+    if np.any(u < 0.0) or np.any(u >= 1.0):
+        raise ValueError("uniforms must lie in [0, 1)")
+    total = cdf[-1]
+    if not total > 0.0:
+        raise ValueError("state has zero norm")
+    j = np.searchsorted(cdf, u * total, side="right")
+    last = int(np.flatnonzero(p > 0.0)[-1])
+    return np.minimum(j, last).astype(np.uint64)

@@ -101,6 +101,8 @@ _lib.sv_init.argtypes = [_vp, ctypes.c_int32, ctypes.c_uint64]
 _lib.sv_apply_circuit.argtypes = [_vp, ctypes.POINTER(SvCircuit), _dp, ctypes.POINTER(SvStats)]
 _lib.sv_expect.argtypes = [_vp, ctypes.POINTER(SvPauliSum), _dp]
 _lib.sv_norm.argtypes = [_vp, _dp]
+_lib.sv_sample.argtypes = [_vp, ctypes.c_int64, _dp, ctypes.POINTER(ctypes.c_uint64)]
+_lib.sv_amplitudes.argtypes = [_vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64), _dp]
 _lib.sv_adjoint_grad.argtypes = [_vp, ctypes.POINTER(SvCircuit), _dp, ctypes.POINTER(SvPauliSum), _vp,
                                  ctypes.c_size_t, _dp, _dp, ctypes.POINTER(SvStats)]
 _lib.sv_apply_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(SvBatchItem), ctypes.c_int32, _vp, ctypes.c_int32,
@@ -113,12 +115,12 @@ _lib.sv_tune.argtypes = [_vp, ctypes.POINTER(SvCircuit), _dp, ctypes.POINTER(SvO
 _lib.sv_plan_trace.argtypes = [ctypes.POINTER(SvCircuit), _dp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(SvOpts),
                                ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
 for _f in ("sv_create", "sv_destroy", "sv_set_stream", "sv_set_opts", "sv_init", "sv_apply_circuit",
-           "sv_expect", "sv_norm", "sv_adjoint_grad", "sv_apply_batch", "sv_sync", "sv_timing", "sv_plan_info",
+           "sv_expect", "sv_norm", "sv_sample", "sv_amplitudes", "sv_adjoint_grad", "sv_apply_batch", "sv_sync", "sv_timing", "sv_plan_info",
            "sv_plan_trace", "sv_tune"):
     getattr(_lib, _f).restype = ctypes.c_int32
 
 EXPORTED = ("sv_opts_default", "sv_create", "sv_destroy", "sv_set_stream", "sv_set_opts", "sv_init",
-            "sv_apply_circuit", "sv_expect", "sv_norm", "sv_adjoint_grad", "sv_apply_batch", "sv_sync",
+            "sv_apply_circuit", "sv_expect", "sv_norm", "sv_sample", "sv_amplitudes", "sv_adjoint_grad", "sv_apply_batch", "sv_sync",
             "sv_timing", "sv_plan_info", "sv_plan_trace", "sv_tune", "sv_last_error", "sv_version")
 
 
@@ -282,6 +284,33 @@ class StateVector:
         out = np.zeros(self.batch, np.float64)
         _check(_lib.sv_norm(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out
+
+    def sample(self, uniforms) -> np.ndarray:
+        """Bit strings measured from every state, one per random number in
+        [0, 1): uniforms of shape (count,) for one state or (batch, count);
+        returns uint64 indices of the same shape (bit q = qubit q)."""
+        self._stream()
+        u = np.ascontiguousarray(uniforms, dtype=np.float64)
+        shape = u.shape
+        if u.ndim == 1:
+            if self.batch != 1:
+                raise ValueError("uniforms must have shape (batch, count) for a batched context")
+            u = u.reshape(1, -1)
+        if u.ndim != 2 or u.shape[0] != self.batch:
+            raise ValueError("uniforms must have shape (count,) or (batch, count)")
+        out = np.zeros(u.shape, np.uint64)
+        _check(_lib.sv_sample(self._h, u.shape[1], u.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+        return out.reshape(shape)
+
+    def amplitudes(self, indices) -> np.ndarray:
+        """Complex128 amplitudes psi_b[indices] of shape (batch, len(indices))."""
+        self._stream()
+        idx = np.ascontiguousarray(indices, dtype=np.uint64).reshape(-1)
+        out = np.zeros((self.batch, idx.size, 2), np.float64)
+        _check(_lib.sv_amplitudes(self._h, idx.size, idx.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out[..., 0] + 1j * out[..., 1]
 
     def adjoint_grad(self, circ, params, pauli, scratch: Optional[torch.Tensor] = None):
         """Returns (energy[batch], grad[batch, n_params]); see sv_adjoint_grad."""

@@ -4,6 +4,8 @@
 //
 // Every reduction uses a fixed grid and a fixed tree, so results are
 // bit-reproducible run to run.
+#include <algorithm>
+
 #include "device_common.h"
 #include "kernels.h"
 
@@ -166,7 +168,136 @@ __global__ __launch_bounds__(kRB) void k_hpsi(const V2<R>* __restrict__ psi, V2<
     }
 }
 
+// ---- measurement sampling ---------------------------------------------------
+// Sum of |psi_j|^2 over each chunk of 2^kChunkBits consecutive amplitudes
+// (FP64, fixed block tree).
+constexpr int kChunkBits = 12;
+
+template <class R>
+__global__ __launch_bounds__(kRB) void k_chunk_sums(const V2<R>* __restrict__ a, uint64_t bstride, uint32_t cbits,
+                                                    double* __restrict__ sums, uint64_t nchunk) {
+    __shared__ double sh[kRB / 64];
+    const uint32_t b = blockIdx.y;
+    const V2<R>* pa = a + (uint64_t)b * bstride + ((uint64_t)blockIdx.x << cbits);
+    double acc = 0.0;
+    for (uint32_t i = threadIdx.x; i < (1u << cbits); i += kRB) {
+        const V2<R> v = pa[i];
+        acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) sums[(uint64_t)b * nchunk + blockIdx.x] = s;
+}
+
+// One block per chunk that holds samples: the chunk's inclusive prefix sums
+// of |psi_j|^2 in LDS (FP64), then for every sample of the chunk the first
+// index whose prefix exceeds the sample's residual target.
+template <class R>
+__global__ __launch_bounds__(kRB) void k_chunk_find(const V2<R>* __restrict__ a, uint64_t bstride, uint32_t cbits,
+                                                    const SampleTask* __restrict__ tasks,
+                                                    const double* __restrict__ target, uint64_t* __restrict__ out) {
+    __shared__ double pre[1 << kChunkBits];
+    __shared__ double part[kRB];
+    const SampleTask t = tasks[blockIdx.x];
+    const uint32_t C = 1u << cbits, per = (C + kRB - 1) / kRB;
+    const V2<R>* pa = a + (uint64_t)t.state * bstride + (t.chunk << cbits);
+    // each thread: a contiguous run of `per` amplitudes, prefix within the run
+    double acc = 0.0;
+    for (uint32_t k = 0; k < per; ++k) {
+        const uint32_t i = threadIdx.x * per + k;
+        if (i >= C) break;
+        const V2<R> v = pa[i];
+        acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+        pre[i] = acc;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double run = 0.0;
+        for (uint32_t w = 0; w < kRB; ++w) {
+            const double v = part[w];
+            part[w] = run;   // exclusive prefix of the runs
+            run += v;
+        }
+    }
+    __syncthreads();
+    for (uint32_t k = 0; k < per; ++k) {
+        const uint32_t i = threadIdx.x * per + k;
+        if (i >= C) break;
+        pre[i] += part[threadIdx.x];
+    }
+    __syncthreads();
+    for (uint64_t s = t.s0 + threadIdx.x; s < t.s1; s += kRB) {
+        const double r = target[s];
+        // first i with pre[i] > r; a residual at or past the chunk's total
+        // (rounding) takes the last amplitude with nonzero probability
+        uint32_t lo = 0, hi = C;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (pre[mid] > r) hi = mid; else lo = mid + 1;
+        }
+        if (lo >= C) {
+            lo = C - 1;
+            while (lo > 0 && pre[lo] == pre[lo - 1]) --lo;
+        }
+        out[t.out0 + (s - t.s0)] = (t.chunk << cbits) + lo;
+    }
+}
+
+template <class R>
+__global__ __launch_bounds__(kRB) void k_gather(const V2<R>* __restrict__ a, uint64_t bstride, int batch,
+                                                const uint64_t* __restrict__ idx, uint64_t count,
+                                                double* __restrict__ out) {
+    const uint64_t k = (uint64_t)blockIdx.x * kRB + threadIdx.x;
+    const uint32_t b = blockIdx.y;
+    if (k >= count) return;
+    const V2<R> v = a[(uint64_t)b * bstride + idx[k]];
+    out[2 * ((uint64_t)b * count + k)] = (double)v.x;
+    out[2 * ((uint64_t)b * count + k) + 1] = (double)v.y;
+}
+
 }  // namespace
+
+uint32_t sample_chunk_bits(int n) { return (uint32_t)std::min(n, kChunkBits); }
+
+hipError_t launch_chunk_sums(int dtype, const void* a, uint64_t bstride, int batch, int n, double* sums,
+                             hipStream_t s) {
+    const uint32_t cb = sample_chunk_bits(n);
+    const uint64_t nchunk = 1ull << (n - (int)cb);
+    const dim3 g((uint32_t)nchunk, (uint32_t)batch);
+    if (dtype == 1)
+        hipLaunchKernelGGL(k_chunk_sums<float>, g, dim3(kRB), 0, s, reinterpret_cast<const V2<float>*>(a), bstride,
+                           cb, sums, nchunk);
+    else
+        hipLaunchKernelGGL(k_chunk_sums<double>, g, dim3(kRB), 0, s, reinterpret_cast<const V2<double>*>(a),
+                           bstride, cb, sums, nchunk);
+    return hipGetLastError();
+}
+
+hipError_t launch_chunk_find(int dtype, const void* a, uint64_t bstride, int n, const SampleTask* tasks,
+                             uint32_t ntask, const double* target, uint64_t* out, hipStream_t s) {
+    if (ntask == 0) return hipSuccess;
+    const uint32_t cb = sample_chunk_bits(n);
+    if (dtype == 1)
+        hipLaunchKernelGGL(k_chunk_find<float>, dim3(ntask), dim3(kRB), 0, s, reinterpret_cast<const V2<float>*>(a),
+                           bstride, cb, tasks, target, out);
+    else
+        hipLaunchKernelGGL(k_chunk_find<double>, dim3(ntask), dim3(kRB), 0, s,
+                           reinterpret_cast<const V2<double>*>(a), bstride, cb, tasks, target, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(int dtype, const void* a, uint64_t bstride, int batch, const uint64_t* idx, uint64_t count,
+                         double* out, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    const dim3 g((uint32_t)((count + kRB - 1) / kRB), (uint32_t)batch);
+    if (dtype == 1)
+        hipLaunchKernelGGL(k_gather<float>, g, dim3(kRB), 0, s, reinterpret_cast<const V2<float>*>(a), bstride,
+                           batch, idx, count, out);
+    else
+        hipLaunchKernelGGL(k_gather<double>, g, dim3(kRB), 0, s, reinterpret_cast<const V2<double>*>(a), bstride,
+                           batch, idx, count, out);
+    return hipGetLastError();
+}
 
 size_t reduce_partials_size(int n, int batch) { return (size_t)nblk_for(n) * (size_t)batch; }
 

@@ -345,3 +345,56 @@ def test_generators_deterministic():
     c = W.ansatz_circuit()
     assert len(c.gates) == 590 and c.n_params == 400
     assert len(W.ansatz_observable()) == 39
+
+
+# ------------------------------------------------------- measurement sampling
+
+def test_sample_example_circuit_is_deterministic_on_basis_inputs():
+    # Sec. 2 example: H on one qubit, CNOT, H again equals CZ, so a basis input
+    # is measured as itself with certainty
+    u = np.concatenate([[0.0], W.sample_uniforms(200, seed=7)])
+    for x in range(4):
+        c = W.Circuit(2, [W.Gate("H", (0,)), W.Gate("CNOT", (1, 0)), W.Gate("H", (0,))])
+        psi = oracle.simulate(c, psi0=W.basis_state(2, x))
+        assert np.all(oracle.sample(psi, u) == x)
+
+
+def test_sample_uniform_state_closed_form():
+    # after a Hadamard layer every outcome has probability 2^-n: the outcome
+    # of u is floor(u 2^n); random numbers at the middle of each cell keep the
+    # comparison away from rounding at the cell edges
+    for n in (1, 5, 9):
+        psi = oracle.simulate(W.Circuit(n, [W.Gate("H", (q,)) for q in range(n)]))
+        k = np.arange(1 << n)
+        assert np.array_equal(oracle.sample(psi, (k + 0.5) / (1 << n)), k)
+
+
+def test_sample_ghz_halves():
+    n = 6
+    g = [W.Gate("H", (0,))] + [W.Gate("CNOT", (i, i + 1)) for i in range(n - 1)]
+    psi = oracle.simulate(W.Circuit(n, g))
+    u = W.sample_uniforms(500, seed=8)
+    got = oracle.sample(psi, u)
+    assert np.array_equal(got, np.where(u < 0.5, 0, (1 << n) - 1))
+
+
+def test_sample_stratified_frequencies_equal_probabilities():
+    # a grid of M random numbers gives each outcome j a share of the grid
+    # within 1/M of |alpha_j|^2 (outcome j owns an interval of that length)
+    n, M = 4, 1 << 16
+    psi = W.random_state(n, seed=9)
+    got = oracle.sample(psi, (np.arange(M) + 0.5) / M)
+    freq = np.bincount(got.astype(np.int64), minlength=1 << n) / M
+    assert np.max(np.abs(freq - np.abs(psi) ** 2)) <= 1.0 / M + 1e-15
+    assert np.all(np.diff(got.astype(np.int64)) >= 0)
+
+
+def test_sample_zero_probability_outcomes_never_drawn():
+    # only qubit 0 is in superposition: outcomes 0 and 1, also for u just
+    # below 1; scaling the state does not change the outcomes
+    psi = oracle.simulate(W.Circuit(3, [W.Gate("H", (0,))]))
+    u = np.array([0.0, 0.25, 0.5 - 1e-12, 0.5 + 1e-12, np.nextafter(1.0, 0.0)])
+    assert list(oracle.sample(psi, u)) == [0, 0, 0, 1, 1]
+    assert list(oracle.sample(3.0 * psi, u)) == [0, 0, 0, 1, 1]
+    with pytest.raises(ValueError):
+        oracle.sample(psi, np.array([1.0]))

@@ -313,3 +313,10 @@ def basis_state(n: int, index: int) -> np.ndarray:
     v = np.zeros(1 << n, np.complex128)
     v[index] = 1.0
     return v
+
+
+def sample_uniforms(count: int, seed: int, batch: int = 0) -> np.ndarray:
+    """Random numbers in [0, 1) that drive measurement sampling (float64).
+    batch > 0 gives shape [batch, count]."""
+    rng = np.random.default_rng(seed)
+    return rng.random((batch, count) if batch else (count,))
