@@ -243,9 +243,10 @@ def batch_leg(sv, W, torch, np, count=512):
 
 def sample_leg(s, W, np, n, shots=1 << 20, reps=3):
     """Measurement sampling from the final state of the sweep: `shots`
-    bit strings per call, inverse-CDF over FP64 chunk masses.  The state is
-    read once in full (chunk masses) plus once more per distinct chunk that
-    receives a sample (in-chunk prefix), so the HBM figure counts both."""
+    bit strings per call.  The call reads the state once to build a 64-ary
+    FP64 tree of probability masses (writing 1/64 of the state's amplitude
+    count in nodes), then every sample reads 64 nodes per tree level and 64
+    amplitudes at the bottom; the HBM figure counts those bytes."""
     u = W.sample_uniforms(shots, seed=16)
     s.sample(u)                                     # warm-up: buffers
     t0 = time.perf_counter()
@@ -254,13 +255,14 @@ def sample_leg(s, W, np, n, shots=1 << 20, reps=3):
     dt = (time.perf_counter() - t0) / reps
     amp = s.amplitudes(got[:8192])[0]
     xeb = float(np.mean(np.abs(amp) ** 2) * float(1 << n) - 1.0)
-    chunk_bits = min(n, 12)
-    distinct = int(np.unique(got >> np.uint64(chunk_bits)).size)
+    levels = (n + 5) // 6
     state_bytes = float(1 << n) * 8
-    read = state_bytes + distinct * float(1 << chunk_bits) * 8
+    tree_bytes = sum(float(1 << max(0, n - 6 * k)) * 8 for k in range(1, levels + 1))
+    per_sample = 64 * 8 + sum(min(64, 1 << max(0, n - 6 * k)) * 8 for k in range(1, levels)) + 16
+    moved = state_bytes + tree_bytes + shots * per_sample
     return {"shots": shots, "ms_per_call": dt * 1e3, "samples_per_s": shots / dt,
-            "distinct_chunks": distinct, "hbm_bytes_algorithmic": read,
-            "GBps_whole_call": read / dt / 1e9, "linear_xeb_8192": xeb}
+            "hbm_bytes_algorithmic": moved, "GBps_whole_call": moved / dt / 1e9,
+            "hbm_frac_whole_call": moved / dt / 1e9 / HBM_PEAK_GBS, "linear_xeb_8192": xeb}
 
 
 def ksweep(sv, W, torch, steps=2):

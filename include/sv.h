@@ -192,10 +192,13 @@ sv_status sv_norm(sv_ctx ctx, double* out);
  *   out       host, batch * count indices: out[b * count + k] is the
  *             smallest j with sum_{i <= j} |psi_b[i]|^2 > u * ||psi_b||^2,
  *             u = uniforms[b * count + k].
- * The prefix sums are FP64: chunk masses of 4096 consecutive amplitudes on
- * the device, their prefix on the host, the prefix inside a chunk on the
- * device.  A target that rounding puts at the very end of a chunk maps to
- * the chunk's last amplitude of nonzero probability.  Synchronises.
+ * The prefix sums are FP64 and taken over a 64-ary tree of probability
+ * masses (node = sum of 64 children) built on the device in one pass over
+ * the state; every sample then descends the tree on the device.  A target
+ * that rounding puts at or past the end of a subtree maps to its last
+ * amplitude of nonzero probability.  Device memory: about 1/64 of the state
+ * in FP64 tree nodes plus 16 bytes per sample, kept by the context.
+ * Synchronises.
  * Errors: SV_EINVAL for NULL pointers, uniforms outside [0, 1) or a state
  * of zero or non-finite norm. */
 sv_status sv_sample(sv_ctx ctx, int64_t count, const double* uniforms, uint64_t* out);

@@ -112,7 +112,7 @@ struct sv_ctx_s {
     bool zero_pending = false;   // |0..0> requested but not yet written
     std::unordered_map<uint64_t, std::unique_ptr<CachedPlan>> cache;
     DevBuf pool, red_part, red_out, pauli, gpart, gout, pinit;
-    DevBuf smp_sums, smp_target, smp_tasks, smp_out;   // sampling and amplitude readout
+    DevBuf smp_tree, smp_u, smp_out;   // sampling and amplitude readout
     std::vector<unsigned char> pool_host;
     std::vector<double> host_out;
     // tile-pass timing (opts.timing)
@@ -689,64 +689,23 @@ sv_status sv_sample(sv_ctx c, int64_t count, const double* uniforms, uint64_t* o
         sv_status ms = materialise(c);
         if (ms != SV_OK) return ms;
     }
-    const uint32_t cb = sample_chunk_bits(c->n);
-    const uint64_t nchunk = 1ull << (c->n - (int)cb);
-    const uint64_t bstride = 1ull << c->n;
-    // 1. FP64 mass of every chunk of 2^cb consecutive amplitudes
-    HIPCHK(c->smp_sums.ensure((size_t)c->batch * nchunk * sizeof(double)));
-    HIPCHK(launch_chunk_sums(c->dtype, c->state, bstride, c->batch, c->n, reinterpret_cast<double*>(c->smp_sums.p),
-                             c->stream));
-    std::vector<double> sums((size_t)c->batch * nchunk);
-    HIPCHK(hipMemcpyAsync(sums.data(), c->smp_sums.p, sums.size() * sizeof(double), hipMemcpyDeviceToHost,
-                          c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    // 2. chunk of every sample from the chunk prefix sums; samples grouped by
-    //    (state, chunk) with their residual target inside the chunk
-    struct Smp { uint32_t b; uint64_t chunk; double r; size_t k; };
-    std::vector<Smp> smp(total);
-    std::vector<double> pre(nchunk + 1);
-    for (int b = 0; b < c->batch; ++b) {
-        const double* sb = sums.data() + (size_t)b * nchunk;
-        pre[0] = 0.0;
-        for (uint64_t i = 0; i < nchunk; ++i) pre[i + 1] = pre[i] + sb[i];
-        const double tot = pre[nchunk];
-        if (!(tot > 0.0) || !std::isfinite(tot)) return fail(SV_EINVAL, "state has zero or non-finite norm");
-        uint64_t last = nchunk - 1;
-        while (last > 0 && !(sb[last] > 0.0)) --last;
-        for (int64_t k = 0; k < count; ++k) {
-            const size_t idx = (size_t)b * count + k;
-            const double tgt = uniforms[idx] * tot;
-            uint64_t ch = (uint64_t)(std::upper_bound(pre.begin(), pre.end(), tgt) - pre.begin()) - 1;
-            if (ch > last) ch = last;
-            smp[idx] = Smp{(uint32_t)b, ch, tgt - pre[ch], idx};
-        }
-    }
-    std::sort(smp.begin(), smp.end(), [](const Smp& x, const Smp& y) {
-        return x.b != y.b ? x.b < y.b : (x.chunk != y.chunk ? x.chunk < y.chunk : x.k < y.k);
-    });
-    std::vector<double> tgt(total);
-    std::vector<SampleTask> tasks;
-    for (size_t s0 = 0; s0 < total;) {
-        size_t s1 = s0;
-        while (s1 < total && smp[s1].b == smp[s0].b && smp[s1].chunk == smp[s0].chunk) ++s1;
-        tasks.push_back(SampleTask{smp[s0].chunk, s0, s1, s0, smp[s0].b, 0u});
-        s0 = s1;
-    }
-    for (size_t s = 0; s < total; ++s) tgt[s] = smp[s].r;
-    // 3. the index inside each chunk, on the device
-    HIPCHK(c->smp_target.ensure(total * sizeof(double)));
-    HIPCHK(c->smp_tasks.ensure(tasks.size() * sizeof(SampleTask)));
+    const uint64_t tree = sample_tree_doubles(c->n, c->batch);
+    HIPCHK(c->smp_tree.ensure(tree * sizeof(double)));
+    HIPCHK(c->smp_u.ensure(total * sizeof(double)));
     HIPCHK(c->smp_out.ensure(total * sizeof(uint64_t)));
-    HIPCHK(hipMemcpyAsync(c->smp_target.p, tgt.data(), total * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipMemcpyAsync(c->smp_tasks.p, tasks.data(), tasks.size() * sizeof(SampleTask), hipMemcpyHostToDevice,
+    HIPCHK(hipMemcpyAsync(c->smp_u.p, uniforms, total * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    double* d_tree = reinterpret_cast<double*>(c->smp_tree.p);
+    HIPCHK(launch_sample(c->dtype, c->state, 1ull << c->n, c->batch, c->n, d_tree,
+                         reinterpret_cast<const double*>(c->smp_u.p), (uint64_t)count,
+                         reinterpret_cast<uint64_t*>(c->smp_out.p), c->stream));
+    // the root of every state's tree (the last level) holds its total mass
+    std::vector<double> root(c->batch);
+    HIPCHK(hipMemcpyAsync(root.data(), d_tree + tree - c->batch, c->batch * sizeof(double), hipMemcpyDeviceToHost,
                           c->stream));
-    HIPCHK(launch_chunk_find(c->dtype, c->state, bstride, c->n, reinterpret_cast<const SampleTask*>(c->smp_tasks.p),
-                             (uint32_t)tasks.size(), reinterpret_cast<const double*>(c->smp_target.p),
-                             reinterpret_cast<uint64_t*>(c->smp_out.p), c->stream));
-    std::vector<uint64_t> got(total);
-    HIPCHK(hipMemcpyAsync(got.data(), c->smp_out.p, total * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(out, c->smp_out.p, total * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    for (size_t s = 0; s < total; ++s) out[smp[s].k] = got[s];
+    for (int b = 0; b < c->batch; ++b)
+        if (!(root[b] > 0.0) || !std::isfinite(root[b])) return fail(SV_EINVAL, "state has zero or non-finite norm");
     return SV_OK;
 }
 
@@ -761,13 +720,13 @@ sv_status sv_amplitudes(sv_ctx c, int64_t count, const uint64_t* indices, double
         sv_status ms = materialise(c);
         if (ms != SV_OK) return ms;
     }
-    HIPCHK(c->smp_tasks.ensure((size_t)count * sizeof(uint64_t)));
-    HIPCHK(c->smp_target.ensure((size_t)count * c->batch * 2 * sizeof(double)));
-    HIPCHK(hipMemcpyAsync(c->smp_tasks.p, indices, (size_t)count * sizeof(uint64_t), hipMemcpyHostToDevice,
+    HIPCHK(c->smp_u.ensure((size_t)count * sizeof(uint64_t)));
+    HIPCHK(c->smp_out.ensure((size_t)count * c->batch * 2 * sizeof(double)));
+    HIPCHK(hipMemcpyAsync(c->smp_u.p, indices, (size_t)count * sizeof(uint64_t), hipMemcpyHostToDevice,
                           c->stream));
-    HIPCHK(launch_gather(c->dtype, c->state, 1ull << c->n, c->batch, reinterpret_cast<const uint64_t*>(c->smp_tasks.p),
-                         (uint64_t)count, reinterpret_cast<double*>(c->smp_target.p), c->stream));
-    HIPCHK(hipMemcpyAsync(out, c->smp_target.p, (size_t)count * c->batch * 2 * sizeof(double), hipMemcpyDeviceToHost,
+    HIPCHK(launch_gather(c->dtype, c->state, 1ull << c->n, c->batch, reinterpret_cast<const uint64_t*>(c->smp_u.p),
+                         (uint64_t)count, reinterpret_cast<double*>(c->smp_out.p), c->stream));
+    HIPCHK(hipMemcpyAsync(out, c->smp_out.p, (size_t)count * c->batch * 2 * sizeof(double), hipMemcpyDeviceToHost,
                           c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return SV_OK;

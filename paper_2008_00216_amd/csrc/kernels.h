@@ -64,24 +64,15 @@ struct PauliDev {
 hipError_t launch_reduce(int dtype, int kind, const void* a, const void* b, uint64_t bstride,
                          int batch, int n, const PauliDev* pd, int gen, uint64_t gmask,
                          double* partials, double* out, uint64_t out_stride, hipStream_t s);
-// Measurement sampling.  Amplitudes are grouped in chunks of
-// 2^sample_chunk_bits(n) consecutive indices.
-struct SampleTask {
-    uint64_t chunk;   // chunk index within the state
-    uint64_t s0, s1;  // samples [s0, s1) of the target array fall in this chunk
-    uint64_t out0;    // output position of sample s0
-    uint32_t state;   // batch element
-    uint32_t pad;
-};
-uint32_t sample_chunk_bits(int n);
-// sums[b * nchunk + c] = sum of |psi_b|^2 over chunk c (FP64, fixed order).
-hipError_t launch_chunk_sums(int dtype, const void* a, uint64_t bstride, int batch, int n, double* sums,
-                             hipStream_t s);
-// out[t.out0 + k] = chunk base + first index whose in-chunk prefix of |psi|^2
-// exceeds target[t.s0 + k] (a residual within the chunk).
-hipError_t launch_chunk_find(int dtype, const void* a, uint64_t bstride, int n, const SampleTask* tasks,
-                             uint32_t ntask, const double* target, uint64_t* out, hipStream_t s);
-// out[2 * (b * count + k) + {0, 1}] = psi_b[idx[k]] in FP64.
+// Measurement sampling by descent of a 64-ary FP64 tree of probability
+// masses.  sample_levels(n) = K tree levels above the amplitudes; the tree
+// takes sample_tree_doubles(n, batch) doubles.  out[b * count + k] = the
+// smallest j whose prefix of |psi_b|^2 (tree order) exceeds
+// uniforms[b * count + k] * (total mass of psi_b).
+int sample_levels(int n);
+uint64_t sample_tree_doubles(int n, int batch);
+hipError_t launch_sample(int dtype, const void* a, uint64_t bstride, int batch, int n, double* tree,
+                         const double* uniforms, uint64_t count, uint64_t* out, hipStream_t s);
 hipError_t launch_gather(int dtype, const void* a, uint64_t bstride, int batch, const uint64_t* idx, uint64_t count,
                          double* out, hipStream_t s);
 

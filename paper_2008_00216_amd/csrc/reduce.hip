@@ -169,78 +169,130 @@ __global__ __launch_bounds__(kRB) void k_hpsi(const V2<R>* __restrict__ psi, V2<
 }
 
 // ---- measurement sampling ---------------------------------------------------
-// Sum of |psi_j|^2 over each chunk of 2^kChunkBits consecutive amplitudes
-// (FP64, fixed block tree).
-constexpr int kChunkBits = 12;
+// A 64-ary tree of FP64 probability masses over each state: level 0 is
+// |psi_j|^2 (never stored), node i of level k+1 is the sum of nodes
+// 64 i .. 64 i + 63 of level k.  One launch builds two levels; a sample
+// descends from the root with one wave, choosing at every level the first
+// child whose inclusive prefix exceeds the residual target.
 
-template <class R>
-__global__ __launch_bounds__(kRB) void k_chunk_sums(const V2<R>* __restrict__ a, uint64_t bstride, uint32_t cbits,
-                                                    double* __restrict__ sums, uint64_t nchunk) {
-    __shared__ double sh[kRB / 64];
-    const uint32_t b = blockIdx.y;
-    const V2<R>* pa = a + (uint64_t)b * bstride + ((uint64_t)blockIdx.x << cbits);
-    double acc = 0.0;
-    for (uint32_t i = threadIdx.x; i < (1u << cbits); i += kRB) {
-        const V2<R> v = pa[i];
-        acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+__device__ __forceinline__ double prob(const V2<float>& v) {
+    return (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+}
+__device__ __forceinline__ double prob(const V2<double>& v) { return v.x * v.x + v.y * v.y; }
+__device__ __forceinline__ double prob(double v) { return v; }
+
+// A block step covers 4096 consecutive nodes of level k: wave w sums groups
+// 16 w .. 16 w + 15 of 64 nodes into level k+1 (coalesced loads, lane l
+// holding node l of each group, a 64-lane sum per group), and the step's
+// 64 level-(k+1) nodes go through LDS into one level-(k+2) node and one
+// coalesced store of the level-(k+1) nodes.  Blocks stride over the steps
+// with the next step's loads issued before the current step's arithmetic.
+// cnt_in: nodes per state at level k (a power of two).
+template <class In>
+__device__ __forceinline__ void tree_load(const In* pin, uint64_t step, uint64_t cnt_in, In (&v)[16]) {
+    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    const uint64_t i0 = step * 4096 + (uint64_t)w * 1024 + lane;
+#pragma unroll
+    for (int g = 0; g < 16; ++g) {
+        const uint64_t i = i0 + (uint64_t)g * 64;
+        if (i < cnt_in) v[g] = pin[i]; else v[g] = In{};
     }
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) sums[(uint64_t)b * nchunk + blockIdx.x] = s;
 }
 
-// One block per chunk that holds samples: the chunk's inclusive prefix sums
-// of |psi_j|^2 in LDS (FP64), then for every sample of the chunk the first
-// index whose prefix exceeds the sample's residual target.
+template <class In>
+__global__ __launch_bounds__(kRB) void k_tree2(const In* __restrict__ in, uint64_t stride_in, uint64_t cnt_in,
+                                               double* __restrict__ out1, double* __restrict__ out2) {
+    __shared__ double sh[64];
+    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    const uint32_t b = blockIdx.y;
+    const uint64_t cnt1 = cnt_in > 64 ? cnt_in >> 6 : 1, cnt2 = cnt1 > 64 ? cnt1 >> 6 : 1;
+    const uint64_t nstep = (cnt_in + 4095) / 4096;
+    const In* pin = in + (uint64_t)b * stride_in;
+    uint64_t step = blockIdx.x;
+    if (step >= nstep) return;   // block-uniform
+    In v[16];
+    tree_load(pin, step, cnt_in, v);
+    for (; step < nstep; step += gridDim.x) {
+        double p[16];
+#pragma unroll
+        for (int g = 0; g < 16; ++g) p[g] = prob(v[g]);
+        const uint64_t nxt = step + gridDim.x;
+        if (nxt < nstep) tree_load(pin, nxt, cnt_in, v);
+#pragma unroll
+        for (int g = 0; g < 16; ++g) {
+            const double t = wave_sum64(p[g]);
+            if (lane == 0) sh[w * 16 + g] = t;
+        }
+        __syncthreads();
+        if (w == 0) {
+            const double t = sh[lane];
+            const uint64_t node = step * 64 + lane;
+            if (node < cnt1) out1[(uint64_t)b * cnt1 + node] = t;
+            if (out2) {
+                const double t2 = wave_sum64(node < cnt1 ? t : 0.0);
+                if (lane == 0) out2[(uint64_t)b * cnt2 + step] = t2;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave (FP64).
+__device__ __forceinline__ double wave_incl_scan(double v) {
+    const uint32_t lane = threadIdx.x & 63u;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double o = __shfl_up(v, d, 64);
+        if (lane >= (uint32_t)d) v += o;
+    }
+    return v;
+}
+
+// One wave per sample.  lvl[k] (k = 1..K) points at level k of all states
+// (state b's nodes at b * cnt(k)); level K has one node.  uniforms and out:
+// batch * count values, row b for state b.
+struct TreeLevels {
+    const double* lvl[8];
+    int K;
+};
+
 template <class R>
-__global__ __launch_bounds__(kRB) void k_chunk_find(const V2<R>* __restrict__ a, uint64_t bstride, uint32_t cbits,
-                                                    const SampleTask* __restrict__ tasks,
-                                                    const double* __restrict__ target, uint64_t* __restrict__ out) {
-    __shared__ double pre[1 << kChunkBits];
-    __shared__ double part[kRB];
-    const SampleTask t = tasks[blockIdx.x];
-    const uint32_t C = 1u << cbits, per = (C + kRB - 1) / kRB;
-    const V2<R>* pa = a + (uint64_t)t.state * bstride + (t.chunk << cbits);
-    // each thread: a contiguous run of `per` amplitudes, prefix within the run
-    double acc = 0.0;
-    for (uint32_t k = 0; k < per; ++k) {
-        const uint32_t i = threadIdx.x * per + k;
-        if (i >= C) break;
-        const V2<R> v = pa[i];
-        acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
-        pre[i] = acc;
-    }
-    part[threadIdx.x] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double run = 0.0;
-        for (uint32_t w = 0; w < kRB; ++w) {
-            const double v = part[w];
-            part[w] = run;   // exclusive prefix of the runs
-            run += v;
+__global__ __launch_bounds__(kRB) void k_descend(const V2<R>* __restrict__ a, uint64_t bstride, int n,
+                                                 TreeLevels tl, const double* __restrict__ uniforms,
+                                                 uint64_t count, uint64_t total, uint64_t* __restrict__ out) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t s = (uint64_t)blockIdx.x * (kRB / 64) + (threadIdx.x >> 6);
+    if (s >= total) return;   // wave-uniform
+    const uint64_t b = s / count;
+    double r = 0.0;
+    uint64_t j = 0;   // node index at level k + 1
+    for (int k = tl.K - 1; k >= 0; --k) {
+        const int lb = n - 6 * k;   // log2 of the node count at level k
+        const uint32_t nch = lb >= 6 ? 64u : (1u << lb);
+        const uint64_t c = j * 64 + lane;
+        double v = 0.0;
+        if (lane < nch) {
+            if (k == 0)
+                v = prob(a[b * bstride + c]);
+            else
+                v = tl.lvl[k][(b << lb) + c];
         }
-    }
-    __syncthreads();
-    for (uint32_t k = 0; k < per; ++k) {
-        const uint32_t i = threadIdx.x * per + k;
-        if (i >= C) break;
-        pre[i] += part[threadIdx.x];
-    }
-    __syncthreads();
-    for (uint64_t s = t.s0 + threadIdx.x; s < t.s1; s += kRB) {
-        const double r = target[s];
-        // first i with pre[i] > r; a residual at or past the chunk's total
-        // (rounding) takes the last amplitude with nonzero probability
-        uint32_t lo = 0, hi = C;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (pre[mid] > r) hi = mid; else lo = mid + 1;
+        const double incl = wave_incl_scan(v);
+        if (k == tl.K - 1) r = uniforms[s] * __shfl(incl, 63, 64);   // target = u * total mass
+        uint64_t m = __ballot(lane < nch && incl > r);
+        uint32_t pick;
+        if (m) {
+            pick = (uint32_t)__builtin_ctzll(m);
+        } else {
+            // r at or past the children's total (rounding): the last child
+            // with nonzero mass
+            m = __ballot(lane < nch && v > 0.0);
+            pick = m ? 63u - (uint32_t)__builtin_clzll(m) : 0u;
         }
-        if (lo >= C) {
-            lo = C - 1;
-            while (lo > 0 && pre[lo] == pre[lo - 1]) --lo;
-        }
-        out[t.out0 + (s - t.s0)] = (t.chunk << cbits) + lo;
+        r -= __shfl(incl - v, (int)pick, 64);
+        j = j * 64 + pick;
     }
+    if (lane == 0) out[s] = j;
 }
 
 template <class R>
@@ -257,32 +309,55 @@ __global__ __launch_bounds__(kRB) void k_gather(const V2<R>* __restrict__ a, uin
 
 }  // namespace
 
-uint32_t sample_chunk_bits(int n) { return (uint32_t)std::min(n, kChunkBits); }
+int sample_levels(int n) { return (n + 5) / 6; }
 
-hipError_t launch_chunk_sums(int dtype, const void* a, uint64_t bstride, int batch, int n, double* sums,
-                             hipStream_t s) {
-    const uint32_t cb = sample_chunk_bits(n);
-    const uint64_t nchunk = 1ull << (n - (int)cb);
-    const dim3 g((uint32_t)nchunk, (uint32_t)batch);
-    if (dtype == 1)
-        hipLaunchKernelGGL(k_chunk_sums<float>, g, dim3(kRB), 0, s, reinterpret_cast<const V2<float>*>(a), bstride,
-                           cb, sums, nchunk);
-    else
-        hipLaunchKernelGGL(k_chunk_sums<double>, g, dim3(kRB), 0, s, reinterpret_cast<const V2<double>*>(a),
-                           bstride, cb, sums, nchunk);
-    return hipGetLastError();
+uint64_t sample_tree_doubles(int n, int batch) {
+    uint64_t t = 0;
+    for (int k = 1; k <= sample_levels(n); ++k) t += 1ull << std::max(0, n - 6 * k);
+    return t * (uint64_t)batch;
 }
 
-hipError_t launch_chunk_find(int dtype, const void* a, uint64_t bstride, int n, const SampleTask* tasks,
-                             uint32_t ntask, const double* target, uint64_t* out, hipStream_t s) {
-    if (ntask == 0) return hipSuccess;
-    const uint32_t cb = sample_chunk_bits(n);
+hipError_t launch_sample(int dtype, const void* a, uint64_t bstride, int batch, int n, double* tree,
+                         const double* uniforms, uint64_t count, uint64_t* out, hipStream_t s) {
+    const int K = sample_levels(n);
+    if (K > 7) return hipErrorInvalidValue;
+    TreeLevels tl{};
+    tl.K = K;
+    double* lv[8] = {};
+    uint64_t off = 0;
+    for (int k = 1; k <= K; ++k) {
+        lv[k] = tree + off;
+        tl.lvl[k] = lv[k];
+        off += (uint64_t)batch << std::max(0, n - 6 * k);
+    }
+    // levels 1, 2 from the amplitudes, then two more per launch
+    for (int k = 0; k < K; k += 2) {
+        const uint64_t cnt_in = 1ull << std::max(0, n - 6 * k);
+        // 8 resident blocks per CU over the whole batch
+        const uint64_t cap = std::max<uint64_t>(1, 2048 / (uint64_t)batch);
+        const dim3 g((uint32_t)std::min<uint64_t>((cnt_in + 4095) / 4096, cap), (uint32_t)batch);
+        double* o2 = k + 2 <= K ? lv[k + 2] : nullptr;
+        if (k == 0) {
+            if (dtype == 1)
+                hipLaunchKernelGGL(k_tree2<V2<float>>, g, dim3(kRB), 0, s, reinterpret_cast<const V2<float>*>(a),
+                                   bstride, cnt_in, lv[1], o2);
+            else
+                hipLaunchKernelGGL(k_tree2<V2<double>>, g, dim3(kRB), 0, s, reinterpret_cast<const V2<double>*>(a),
+                                   bstride, cnt_in, lv[1], o2);
+        } else {
+            hipLaunchKernelGGL(k_tree2<double>, g, dim3(kRB), 0, s, lv[k], cnt_in, cnt_in, lv[k + 1], o2);
+        }
+    }
+    const uint64_t total = count * (uint64_t)batch;
+    if (total == 0) return hipGetLastError();
+    const uint32_t per = kRB / 64;
+    const dim3 gd((uint32_t)((total + per - 1) / per));
     if (dtype == 1)
-        hipLaunchKernelGGL(k_chunk_find<float>, dim3(ntask), dim3(kRB), 0, s, reinterpret_cast<const V2<float>*>(a),
-                           bstride, cb, tasks, target, out);
+        hipLaunchKernelGGL(k_descend<float>, gd, dim3(kRB), 0, s, reinterpret_cast<const V2<float>*>(a), bstride, n,
+                           tl, uniforms, count, total, out);
     else
-        hipLaunchKernelGGL(k_chunk_find<double>, dim3(ntask), dim3(kRB), 0, s,
-                           reinterpret_cast<const V2<double>*>(a), bstride, cb, tasks, target, out);
+        hipLaunchKernelGGL(k_descend<double>, gd, dim3(kRB), 0, s, reinterpret_cast<const V2<double>*>(a), bstride,
+                           n, tl, uniforms, count, total, out);
     return hipGetLastError();
 }
 
