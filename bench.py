@@ -74,6 +74,8 @@ def parse():
     p.add_argument("--no-batch", action="store_true")
     p.add_argument("--no-sample", action="store_true")
     p.add_argument("--ksweep", action="store_true", help="30-qubit dense-width sweep instead of the benchmark")
+    p.add_argument("--ablation", action="store_true",
+                   help="32-qubit ablation and gate-category profile instead of the benchmark")
     p.add_argument("--calib-copy-gib", type=float, default=0.0,
                    help="run a device copy of this size first (counter calibration)")
     p.add_argument("--structured", type=int, default=1)
@@ -265,6 +267,112 @@ def sample_leg(s, W, np, n, shots=1 << 20, reps=3):
             "hbm_frac_whole_call": moved / dt / 1e9 / HBM_PEAK_GBS, "linear_xeb_8192": xeb}
 
 
+DIAGONAL_OPS = ("CZ", "T", "TDG", "S", "SDG", "Z", "RZ", "CP", "P")
+
+
+def categorize(circ, W, local_bits=13):
+    """Split a grid circuit into the gate categories of the paper's runtime
+    profile (Sec. 6, tab:profile), each as a circuit of its own with the
+    gates in their original order:
+      initial H      the leading layer of H gates, one per qubit;
+      diagonal       CZ and T (and any other diagonal gate);
+      low one-qubit  non-diagonal one-qubit gates on qubits below
+                     `local_bits` (inside one tile of 2^local_bits amplitudes);
+      high one-qubit non-diagonal one-qubit gates on the other qubits."""
+    g = list(circ.gates)
+    k = 0
+    seen = set()
+    while k < len(g) and g[k].op == "H" and g[k].qubits[0] not in seen:
+        seen.add(g[k].qubits[0])
+        k += 1
+    cats = {"initial H": g[:k], "diagonal": [], "low one-qubit": [], "high one-qubit": [], "other": []}
+    for x in g[k:]:
+        if x.op in DIAGONAL_OPS:
+            cats["diagonal"].append(x)
+        elif len(x.qubits) == 1:
+            cats["low one-qubit" if x.qubits[0] < local_bits else "high one-qubit"].append(x)
+        else:
+            cats["other"].append(x)
+    return {name: W.Circuit(circ.n, gates, circ.n_params, f"{circ.name}:{name}")
+            for name, gates in cats.items() if gates}
+
+
+def ablation(sv, W, torch, np, steps=1):
+    """GPU counterpart of the paper's ablation and runtime profile (Sec. 6):
+    the 32-qubit 4x8 grid circuit (initial H + 26 cycles) in complex64,
+    with the optimisations switched off one at a time, and the gate
+    categories of tab:profile timed on their own in the fused and in the
+    one-kernel-per-gate modes (the initial H layer as a product-state
+    init, the other categories applied to a written |0..0>).  Each mode's final state is compared with the
+    fully optimised one at 4096 fixed amplitudes.  Prints one JSON line."""
+    circ = W.grid_circuit(4, 8, 26, seed=1004)
+    n = circ.n
+    modes = [
+        ("all optimisations", dict()),
+        ("no plan-specialised kernels (interpreter)", dict(jit=-1)),
+        ("no product-state init", dict(product_init=0)),
+        ("no butterflies or lazy phases (2x2 matrices, explicit diagonals)", dict(structured=0, max_fuse_k=1)),
+        ("no tile passes (one kernel per gate)", dict(plain=1)),
+    ]
+    probe = np.unique(np.random.default_rng(17).integers(0, 1 << n, size=4096).astype(np.uint64))
+    ref = None
+    rows = []
+    t_state = torch.empty((1, 1 << n), dtype=torch.complex64, device="cuda")
+
+    def run(kw, c, reps, whole_step=True):
+        """ms per sweep: deferred |0..0> + apply (whole_step), or apply
+        alone on a written |0..0> (a category on its own)."""
+        s = sv.StateVector(n, torch.complex64, opts=sv.make_opts(**kw), tensor=t_state)
+        cabi = sv.CircuitABI(c)
+        s.init("zero_deferred")
+        st = s.apply(cabi)                             # warm-up: plan, compile
+        torch.cuda.synchronize()
+        dt = 0.0
+        for _ in range(reps):
+            if not whole_step:
+                s.init("zero")
+                torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if whole_step:
+                s.init("zero_deferred")
+            st = s.apply(cabi)
+            torch.cuda.synchronize()
+            dt += time.perf_counter() - t0
+        return s, st, dt * 1e3 / reps
+
+    for name, kw in modes:
+        s, st, ms = run(kw, circ, steps)
+        amp = s.amplitudes(probe)[0]
+        if ref is None:
+            ref = amp
+        rms = float(np.sqrt(np.mean(np.abs(ref) ** 2)))
+        row = {"mode": name, "ms": ms, "passes": st["passes"], "launches": st["launches"],
+               "max_abs_diff_vs_all": float(np.max(np.abs(amp - ref))),
+               "max_diff_over_rms_amp": float(np.max(np.abs(amp - ref))) / rms}
+        s.close()
+        progress(f"ablation: {name}: {ms:.1f} ms")
+        cats = {}
+        if kw in (dict(), dict(plain=1)):
+            for cname, cc in categorize(circ, W).items():
+                # a category of one-qubit gates alone is a product state: it
+                # would fold into the init entirely, so only the initial H
+                # layer keeps the product-state init
+                ckw = kw if cname == "initial H" else dict(kw, product_init=0)
+                _, cst, cms = run(ckw, cc, 1, whole_step=(cname == "initial H"))
+                cats[cname] = {"gates": len(cc), "ms": cms, "passes": cst["passes"]}
+                progress(f"ablation:   {cname} ({len(cc)} gates): {cms:.1f} ms")
+            tot = sum(v["ms"] for v in cats.values())
+            for v in cats.values():
+                v["pct_of_category_sum"] = 100.0 * v["ms"] / tot
+            row["categories_alone"] = cats
+        rows.append(row)
+    base = rows[0]["ms"]
+    for r in rows:
+        r["x_slower_than_all"] = r["ms"] / base
+    out = {"ablation": {"workload": f"grid4x8-26cycles-{n}q-c64", "gates": len(circ), "modes": rows}}
+    print(json.dumps(out), flush=True)
+
+
 def ksweep(sv, W, torch, steps=2):
     """5x6 grid, 30 qubits, 20 cycles, complex64: the butterfly mode against
     dense blocks of at most k qubits (k = 1..6).  One JSON line per mode."""
@@ -313,6 +421,9 @@ def main():
     torch.cuda.set_device(0)
     if args.ksweep:
         ksweep(sv, W, torch)
+        return
+    if args.ablation:
+        ablation(sv, W, torch, np)
         return
     if args.calib_copy_gib > 0:
         nb = int(args.calib_copy_gib * (1 << 30))
