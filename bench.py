@@ -73,6 +73,7 @@ def parse():
     p.add_argument("--no-adjoint", action="store_true")
     p.add_argument("--no-batch", action="store_true")
     p.add_argument("--no-sample", action="store_true")
+    p.add_argument("--no-c128", action="store_true")
     p.add_argument("--ksweep", action="store_true", help="30-qubit dense-width sweep instead of the benchmark")
     p.add_argument("--ablation", action="store_true",
                    help="32-qubit ablation and gate-category profile instead of the benchmark")
@@ -265,6 +266,44 @@ def sample_leg(s, W, np, n, shots=1 << 20, reps=3):
     return {"shots": shots, "ms_per_call": dt * 1e3, "samples_per_s": shots / dt,
             "hbm_bytes_algorithmic": moved, "GBps_whole_call": moved / dt / 1e9,
             "hbm_frac_whole_call": moved / dt / 1e9 / HBM_PEAK_GBS, "linear_xeb_8192": xeb}
+
+
+def c128_leg(sv, W, torch, steps=2):
+    """The same kind of sweep in complex128: the 32-qubit 4x8 grid circuit
+    with 40 cycles (64 GiB state), default options, tile passes timed with
+    HIP events.  FP64 arithmetic issues at the same lane rate as FP32, and
+    every amplitude moves twice the bytes, so the passes run against the
+    HBM roofline."""
+    circ = W.grid_circuit(4, 8, 40, seed=1005)
+    n = circ.n
+    s = sv.StateVector(n, torch.complex128, opts=sv.make_opts(timing=1))
+    cabi = sv.CircuitABI(circ)
+    s.init("zero_deferred")
+    st = s.apply(cabi)                                 # warm-up: plan, compile
+    s.norm()
+    s.timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.init("zero_deferred")
+        st = s.apply(cabi)
+        nrm = float(s.norm()[0])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    tile_ms, launches, tile_bytes = s.timing()
+    per = tile_ms / max(1, launches)
+    gbs = tile_bytes / max(1, launches) / (per / 1e3) / 1e9
+    tops = st["alu_ops"] * steps / (tile_ms / 1e3) / 1e12
+    del s
+    torch.cuda.empty_cache()
+    return {"workload": f"grid4x8-40cycles-{n}q-c128", "gates": len(circ), "ms_per_step": ms,
+            "gates_per_s": len(circ) / (ms / 1e3), "passes": st["passes"],
+            "tile_kernel": {"launches": launches, "avg_ms": per, "bytes_per_launch": tile_bytes / max(1, launches)},
+            "roofline_hbm": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(gbs / HBM_PEAK_GBS, 4)},
+            "roofline_alu": {"bound": "alu", "achieved": round(tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
+                             "unit": "TOP/s", "frac": round(tops / VALU_PEAK_TOPS, 4)},
+            "norm_error": abs(nrm - 1.0)}
 
 
 DIAGONAL_OPS = ("CZ", "T", "TDG", "S", "SDG", "Z", "RZ", "CP", "P")
@@ -523,6 +562,9 @@ def main():
         progress(f"sampling: {out['sample']['ms_per_call']:.1f} ms per call")
     del s
     torch.cuda.empty_cache()
+    if not args.no_c128:
+        out["c128"] = c128_leg(sv, W, torch)
+        progress(f"c128 leg: {out['c128']['ms_per_step']:.1f} ms per step")
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(sv, W, torch, np)
         progress("adjoint leg done")

@@ -199,13 +199,16 @@ sv_status sv_norm(sv_ctx ctx, double* out);
  * amplitude of nonzero probability.  Device memory: about 1/64 of the state
  * in FP64 tree nodes plus 16 bytes per sample, kept by the context.
  * Synchronises.
- * Errors: SV_EINVAL for NULL pointers, uniforms outside [0, 1) or a state
- * of zero or non-finite norm. */
+ * Errors: SV_EINVAL for NULL pointers, uniforms outside [0, 1), more than
+ * 2^32 samples (batch * count) in one call, or a state of zero or
+ * non-finite norm (out is then unspecified). */
 sv_status sv_sample(sv_ctx ctx, int64_t count, const double* uniforms, uint64_t* out);
 
 /* Amplitude readout: out[2 * (b * count + k)] and out[2 * (b * count + k) + 1]
  * are the real and imaginary parts of psi_b[indices[k]] (host arrays; indices
- * must be < 2^n).  Synchronises. */
+ * must be < 2^n, batch * count at most 2^32).  Synchronises.
+ * Errors: SV_EINVAL for NULL pointers, an index out of range or too many
+ * values. */
 sv_status sv_amplitudes(sv_ctx ctx, int64_t count, const uint64_t* indices, double* out);
 
 /* Adjoint gradient of E_b = <psi_b|H|psi_b> with psi_b = U(theta_b) psi_b^in,

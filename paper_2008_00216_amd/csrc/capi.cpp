@@ -677,11 +677,16 @@ sv_status sv_expect(sv_ctx c, const sv_pauli_sum* h, double* out) {
     return SV_OK;
 }
 
+// Samples (or read-back amplitudes) per call, over all states: keeps the
+// one-wave-per-sample grid within 2^30 workgroups.
+constexpr int64_t kMaxSamples = 1ll << 32;
+
 sv_status sv_sample(sv_ctx c, int64_t count, const double* uniforms, uint64_t* out) {
     if (!c) return fail(SV_EINVAL, "ctx is NULL");
     if (count < 0) return fail(SV_EINVAL, "count < 0");
     if (count == 0) return SV_OK;
     if (!uniforms || !out) return fail(SV_EINVAL, "uniforms or out is NULL");
+    if (count > kMaxSamples / c->batch) return fail(SV_EINVAL, "batch * count exceeds 2^32 samples per call");
     const size_t total = (size_t)count * (size_t)c->batch;
     for (size_t k = 0; k < total; ++k)
         if (!(uniforms[k] >= 0.0 && uniforms[k] < 1.0)) return fail(SV_EINVAL, "uniforms must lie in [0, 1)");
@@ -714,6 +719,7 @@ sv_status sv_amplitudes(sv_ctx c, int64_t count, const uint64_t* indices, double
     if (count < 0) return fail(SV_EINVAL, "count < 0");
     if (count == 0) return SV_OK;
     if (!indices || !out) return fail(SV_EINVAL, "indices or out is NULL");
+    if (count > kMaxSamples / c->batch) return fail(SV_EINVAL, "batch * count exceeds 2^32 amplitudes per call");
     for (int64_t k = 0; k < count; ++k)
         if (indices[k] >= (1ull << c->n)) return fail(SV_EINVAL, "amplitude index out of range");
     {

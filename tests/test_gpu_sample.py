@@ -6,6 +6,8 @@ there the GPU outcome must equal the oracle's bit for bit.  For random states
 the two sides add the same FP64 probabilities in different orders, so an
 outcome may differ only where u * total lies within rounding of a cumulative
 probability; the test checks that every difference is of that kind."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -113,6 +115,11 @@ def test_sample_errors_and_empty():
     for bad in ([1.0], [-0.1], [np.nan]):
         with pytest.raises(m.SvError):
             s.sample(np.array(bad))
+    # more than 2^32 samples in one call is refused before any array is read
+    u1, o1 = np.zeros(1), np.zeros(1, np.uint64)
+    st = m._lib.sv_sample(s._h, 1 << 33, u1.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                          o1.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+    assert st != 0 and b"2^32" in m._lib.sv_last_error()
     s.tensor.zero_()
     with pytest.raises(m.SvError):
         s.sample(np.array([0.3]))
