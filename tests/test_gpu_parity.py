@@ -88,6 +88,38 @@ def test_random_circuits_fused(dtype, seed):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_tiny_states(dtype, n):
+    # states smaller than a register group (16 amplitudes) or a default tile:
+    # n <= 3 runs gate by gate, n = 4, 5 as one tile holding the whole state
+    c = W.random_circuit(n, 60, 100 + n, ops=ALL_OPS, mat_k=(1, 2, 3))
+    params = W.uniform_params(1, c.n_params, n)[0]
+    psi0 = round_c64(W.random_state(n, 200 + n))
+    ref = oracle.simulate(c, params, psi0)
+    for plain in (1, 0):
+        got, _ = run(c, psi0, dtype, params, plain=plain)
+        check_close(got[0], ref, dtype, f"n={n} plain={plain}")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [1, 5, 14])
+def test_empty_circuit(dtype, n):
+    m = lib()
+    c = W.Circuit(n, [])
+    psi0 = round_c64(W.random_state(n, 300 + n))
+    for plain in (1, 0):
+        got, st = run(c, psi0, dtype, plain=plain)
+        assert np.array_equal(got[0], psi0) and st["launches"] == 0
+    # a deferred |0..0> is written by the (empty) sweep
+    s = m.StateVector(n, dtype)
+    s.tensor.fill_(1.0)
+    s.init("zero_deferred")
+    s.apply(c)
+    got = to_host(s.tensor)[0]
+    assert got[0] == 1 and np.count_nonzero(got) == 1
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
 def test_wide_matrix_gates(dtype):
     n = 12
     c = W.random_circuit(n, 20, 5, ops=("H", "CZ", "T"), mat_k=(5, 6))

@@ -53,6 +53,21 @@ def test_random_mixed_gates(seed):
     _check(m, c, p, tile_bits=7, low_bits=3, psi0=psi0)
 
 
+@pytest.mark.parametrize("n", [4, 5])
+def test_states_smaller_than_a_default_tile(n):
+    # the tile shrinks to the whole state (one or two register groups)
+    m = lib()
+    c = W.random_circuit(n, 60, seed=100 + n, mat_k=(1, 2, 3))
+    p = W.uniform_params(1, c.n_params, 7)[0]
+    _check(m, c, p, psi0=W.random_state(n, 200 + n))
+
+
+def test_empty_circuit_has_an_empty_plan():
+    m = lib()
+    info = m.plan_info(W.Circuit(7, []))
+    assert info["passes"] == 0 and info["launches"] == 0 and info["gates_in"] == 0
+
+
 def test_wide_gates_force_flush_before_plain_steps():
     m = lib()
     c = W.random_circuit(8, 80, seed=9, ops=("H", "SQRTX", "SQRTY", "SQRTW", "T", "CZ", "S"), mat_k=(5, 6))
