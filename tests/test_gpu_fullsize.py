@@ -61,3 +61,24 @@ def test_grid33_norm_and_mirror():
     assert np.max(np.abs(tail)) < 1e-4
     del s
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype,n", [(torch.complex64, 34), (torch.complex128, 33)])
+def test_maximum_width_norm_and_mirror(dtype, n):
+    # the widest states the library accepts (128 GiB): a shallow grid circuit
+    # and its inverse return |0..0>
+    m = lib()
+    torch.cuda.empty_cache()
+    c = W.grid_circuit(2, 17, 3, seed=1010) if n == 34 else W.grid_circuit(3, 11, 3, seed=1011)
+    assert c.n == n
+    s = m.StateVector(n, dtype)
+    s.init("zero_deferred")
+    st = s.apply(c)
+    assert st["passes"] >= 1
+    tol = 1e-5 if dtype == torch.complex64 else 1e-12
+    assert abs(float(s.norm()[0]) - 1.0) < tol
+    s.apply(W.inverse(c))
+    a = s.amplitudes(np.array([0, 1, (1 << n) - 1], np.uint64))[0]
+    assert abs(a[0] - 1.0) < 10 * tol and abs(a[1]) < tol and abs(a[2]) < tol, a
+    del s
+    torch.cuda.empty_cache()
