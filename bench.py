@@ -109,11 +109,22 @@ def cpu_baseline(circ, budget_s=25.0):
             break
     dt = time.time() - t0
     amp_updates = done * (1 << cut) / dt
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {
         "value": amp_updates / float(1 << circ.n),
         "unit": "gates/s (33-qubit equivalent)",
         "amp_updates_per_s": amp_updates,
         "cores": nthreads,
+        "host_cpus": os.cpu_count(),
+        "cpu_model": model,
         "kind": "oracle",
         "sample": f"FP64 oracle, gate by gate, first {done} gates of the {cut}-qubit cut (qubits 0-{cut - 1}) "
                   f"of the same grid circuit, {dt:.1f} s on {nthreads} threads; value = amp-updates/s / 2^{circ.n}",
@@ -160,6 +171,25 @@ def adjoint_leg(sv, W, torch, np):
     t_fd_sample = time.time() - t0
     t_fd_full = t_fd_sample / len(sample) * c.n_params      # 2 sweeps per parameter
     err_fd = float(np.max(np.abs(g[:, sample] - fd)))
+    # parameter shift (exact for exp(-i theta P / 2) gates) with the fused
+    # sweeps on the same GPU: 2 sweeps per parameter
+    sf = sv.StateVector(n, torch.complex64, batch=B)
+    sf.init("zero"); sf.apply(c, th); sf.expect(h)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    ps = np.zeros((B, len(sample)))
+    for j, p in enumerate(sample):
+        vals = []
+        for sgn in (1, -1):
+            tt = th.copy()
+            tt[:, p] += sgn * math.pi / 2
+            sf.init("zero")
+            sf.apply(c, tt)
+            vals.append(sf.expect(h))
+        ps[:, j] = (vals[0] - vals[1]) / 2
+    t_ps_full = (time.time() - t0) / len(sample) * c.n_params
+    err_ps = float(np.max(np.abs(g[:, sample] - ps)))
+    del sf, sp
     return {
         "workload": "ansatz20q-10layers-400params-batch64-c64",
         "adjoint_s": t_adj,
@@ -172,7 +202,68 @@ def adjoint_leg(sv, W, torch, np):
         "fd_sample": f"{len(sample)} params x 2 plain sweeps x {B} sets, h={hstep}",
         "speedup_vs_fd_plain": t_fd_full / t_adj,
         "max_abs_diff_vs_fd": err_fd,
+        "param_shift_fused_s_extrapolated": t_ps_full,
+        "param_shift_sample": f"{len(sample)} params x 2 fused sweeps x {B} sets, shifts +-pi/2",
+        "speedup_vs_param_shift_fused": t_ps_full / t_adj,
+        "max_abs_diff_vs_param_shift": err_ps,
     }
+
+
+def plain_leg(sv, W, torch, reps=20):
+    """The plain method on a small state: the 12-qubit line circuit (10
+    layers, 175 gates) in complex128 from |0..0>, one kernel per gate.  At
+    64 KiB this is bound by launch latency, not HBM, so it is reported per
+    gate; the fused sweep of the same circuit is given beside it."""
+    c = W.line_circuit(12, 10, seed=1000)
+    out = {"workload": f"line12-10layers-{len(c)}gates-c128"}
+    for name, kw in (("one_kernel_per_gate", dict(plain=1)), ("fused", dict())):
+        s = sv.StateVector(c.n, torch.complex128, opts=sv.make_opts(**kw))
+        cabi = sv.CircuitABI(c)
+        s.init("zero")
+        st = s.apply(cabi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            s.init("zero")
+            st = s.apply(cabi)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out[name] = {"us_per_gate": dt / len(c) * 1e6, "ms_per_sweep": dt * 1e3, "launches": st["launches"]}
+        s.close()
+    return out
+
+
+def copy_ceiling(sv, torch, n=30, reps=5):
+    """Streaming read + write bandwidth on this GPU, the practical ceiling
+    of a pass that reads and writes the state once: sv_copy_state between
+    two 2^n-amplitude complex64 states (8 GiB at n = 30), timed with HIP
+    events on the library's stream, next to a torch device copy."""
+    a = sv.StateVector(n, torch.complex64)
+    b = sv.StateVector(n, torch.complex64)
+    a.tensor.fill_(1.0)
+    b.copy_from(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_from(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    e0.record()
+    for _ in range(reps):
+        b.tensor.copy_(a.tensor)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_torch = e0.elapsed_time(e1) / reps
+    same = bool(torch.equal(a.tensor, b.tensor))
+    nb = float(a.tensor.numel() * a.tensor.element_size())
+    del a, b
+    torch.cuda.empty_cache()
+    gbs, gbs_t = 2.0 * nb / (ms / 1e3) / 1e9, 2.0 * nb / (ms_torch / 1e3) / 1e9
+    return {"GBps": round(gbs, 1), "frac_of_spec": round(gbs / HBM_PEAK_GBS, 4), "bytes": 2 * nb,
+            "torch_copy_GBps": round(gbs_t, 1), "copy_exact": same,
+            "what": f"sv_copy_state of a 2^{n}-amplitude complex64 state (read + write), {reps} reps, HIP events"}
 
 
 def progress(msg):
@@ -562,6 +653,10 @@ def main():
         progress(f"sampling: {out['sample']['ms_per_call']:.1f} ms per call")
     del s
     torch.cuda.empty_cache()
+    out["copy_ceiling"] = copy_ceiling(sv, torch)
+    out["roofline_hbm"]["frac_of_copy_ceiling"] = round(achieved_gbs / out["copy_ceiling"]["GBps"], 4)
+    out["plain_method"] = plain_leg(sv, W, torch)
+    progress("copy ceiling and plain-method leg done")
     if not args.no_c128:
         out["c128"] = c128_leg(sv, W, torch)
         progress(f"c128 leg: {out['c128']['ms_per_step']:.1f} ms per step")

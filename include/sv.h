@@ -182,6 +182,15 @@ sv_status sv_apply_circuit(sv_ctx ctx, const sv_circuit* circuit, const double* 
  * device with a fixed reduction order.  Synchronises the stream. */
 sv_status sv_expect(sv_ctx ctx, const sv_pauli_sum* obs, double* out);
 
+/* Copies the states of src into dst (a snapshot, or a branch point for two
+ * continuations of one simulation).  Both contexts must have the same
+ * width, dtype and batch, and disjoint state buffers.  Enqueued on dst's
+ * stream; when src uses another stream, the call first waits for it.  A
+ * pending deferred |0..0> in src is passed on without a copy.  The copy
+ * streams 16-byte words with several loads in flight per thread.
+ * Errors: SV_EINVAL for NULL or mismatched contexts or overlapping buffers. */
+sv_status sv_copy_state(sv_ctx dst, sv_ctx src);
+
 /* out[b] = ||psi_b||^2 in FP64 (norm check of Sec. 4.1).  Synchronises. */
 sv_status sv_norm(sv_ctx ctx, double* out);
 

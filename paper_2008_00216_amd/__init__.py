@@ -101,6 +101,7 @@ _lib.sv_init.argtypes = [_vp, ctypes.c_int32, ctypes.c_uint64]
 _lib.sv_apply_circuit.argtypes = [_vp, ctypes.POINTER(SvCircuit), _dp, ctypes.POINTER(SvStats)]
 _lib.sv_expect.argtypes = [_vp, ctypes.POINTER(SvPauliSum), _dp]
 _lib.sv_norm.argtypes = [_vp, _dp]
+_lib.sv_copy_state.argtypes = [_vp, _vp]
 _lib.sv_sample.argtypes = [_vp, ctypes.c_int64, _dp, ctypes.POINTER(ctypes.c_uint64)]
 _lib.sv_amplitudes.argtypes = [_vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64), _dp]
 _lib.sv_adjoint_grad.argtypes = [_vp, ctypes.POINTER(SvCircuit), _dp, ctypes.POINTER(SvPauliSum), _vp,
@@ -115,13 +116,14 @@ _lib.sv_tune.argtypes = [_vp, ctypes.POINTER(SvCircuit), _dp, ctypes.POINTER(SvO
 _lib.sv_plan_trace.argtypes = [ctypes.POINTER(SvCircuit), _dp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(SvOpts),
                                ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
 for _f in ("sv_create", "sv_destroy", "sv_set_stream", "sv_set_opts", "sv_init", "sv_apply_circuit",
-           "sv_expect", "sv_norm", "sv_sample", "sv_amplitudes", "sv_adjoint_grad", "sv_apply_batch", "sv_sync", "sv_timing", "sv_plan_info",
-           "sv_plan_trace", "sv_tune"):
+           "sv_expect", "sv_norm", "sv_copy_state", "sv_sample", "sv_amplitudes", "sv_adjoint_grad",
+           "sv_apply_batch", "sv_sync", "sv_timing", "sv_plan_info", "sv_plan_trace", "sv_tune"):
     getattr(_lib, _f).restype = ctypes.c_int32
 
 EXPORTED = ("sv_opts_default", "sv_create", "sv_destroy", "sv_set_stream", "sv_set_opts", "sv_init",
-            "sv_apply_circuit", "sv_expect", "sv_norm", "sv_sample", "sv_amplitudes", "sv_adjoint_grad", "sv_apply_batch", "sv_sync",
-            "sv_timing", "sv_plan_info", "sv_plan_trace", "sv_tune", "sv_last_error", "sv_version")
+            "sv_apply_circuit", "sv_expect", "sv_norm", "sv_copy_state", "sv_sample", "sv_amplitudes",
+            "sv_adjoint_grad", "sv_apply_batch", "sv_sync", "sv_timing", "sv_plan_info", "sv_plan_trace",
+            "sv_tune", "sv_last_error", "sv_version")
 
 
 class SvError(RuntimeError):
@@ -284,6 +286,12 @@ class StateVector:
         out = np.zeros(self.batch, np.float64)
         _check(_lib.sv_norm(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out
+
+    def copy_from(self, other: "StateVector"):
+        """This context's states = other's (same width, dtype and batch)."""
+        self._stream()
+        _check(_lib.sv_copy_state(self._h, other._h))
+        return self
 
     def sample(self, uniforms) -> np.ndarray:
         """Bit strings measured from every state, one per random number in

@@ -642,6 +642,28 @@ sv_status sv_tune(sv_ctx c, const sv_circuit* circ, const double* params, sv_opt
     return SV_OK;
 }
 
+sv_status sv_copy_state(sv_ctx dst, sv_ctx src) {
+    if (!dst || !src) return fail(SV_EINVAL, "ctx is NULL");
+    if (dst->n != src->n || dst->dtype != src->dtype || dst->batch != src->batch)
+        return fail(SV_EINVAL, "contexts differ in width, dtype or batch");
+    if (dst == src || dst->state == src->state) return SV_OK;
+    const char* lo_d = static_cast<const char*>(dst->state);
+    const char* lo_s = static_cast<const char*>(src->state);
+    if (lo_d < lo_s + src->state_bytes && lo_s < lo_d + dst->state_bytes)
+        return fail(SV_EINVAL, "state buffers overlap");
+    if (src->stream != dst->stream) HIPCHK(hipStreamSynchronize(src->stream));
+    if (src->zero_pending) {
+        // |0..0> not yet written: the copy is deferred the same way
+        dst->zero_pending = true;
+        dst->known_zero = true;
+        return SV_OK;
+    }
+    HIPCHK(launch_copy(src->state, dst->state, src->state_bytes, dst->stream));
+    dst->zero_pending = false;
+    dst->known_zero = src->known_zero;
+    return SV_OK;
+}
+
 sv_status sv_norm(sv_ctx c, double* out) {
     if (!c || !out) return fail(SV_EINVAL, "ctx or out is NULL");
     {

@@ -41,6 +41,8 @@ hipError_t launch_pair_swap(int dtype, void* state, uint64_t bstride, int batch,
                             hipStream_t s);
 
 // Initialisation.  kind: 0 zero, 1 basis(index), 2 uniform(value).
+// dst[0, bytes) = src[0, bytes) (both 16-byte aligned, bytes a multiple of 16).
+hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s);
 hipError_t launch_init(int dtype, void* state, uint64_t bstride, int batch, int n, int kind,
                        uint64_t index, double value, hipStream_t s);
 // Product state psi[j] = lo[j & (2^nlo - 1)] * hi[j >> nlo] (FP64 tables).

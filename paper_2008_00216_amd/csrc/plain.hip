@@ -216,6 +216,22 @@ __global__ __launch_bounds__(kBlock) void k_multi_sum(const SumTask* __restrict_
     }
 }
 
+// Streaming copy of n 16-byte words: grid-stride, four loads in flight per
+// thread before the four stores.
+__global__ __launch_bounds__(kBlock) void k_copy16(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
+                                                   uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        u32x4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = src[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) dst[i + u * stride] = v[u];
+    }
+    for (; i < n; i += stride) dst[i] = src[i];
+}
+
 inline dim3 grid_for(uint64_t count, int batch) {
     uint64_t g = (count + kBlock - 1) / kBlock;
     if (g > kMaxBlocks) g = kMaxBlocks;
@@ -291,6 +307,18 @@ hipError_t launch_pair_swap(int dtype, void* state, uint64_t bstride, int batch,
     else
         hipLaunchKernelGGL(k_pair_swap<double>, g, dim3(kBlock), 0, s, reinterpret_cast<V2<double>*>(state),
                            bstride, fixed, one_mask, flip, mode, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    if (bytes % 16 != 0 || (reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 != 0)
+        return hipErrorInvalidValue;
+    const uint64_t n = bytes / 16;
+    uint64_t g = (n + kBlock - 1) / kBlock;
+    if (g > 65536) g = 65536;   // enough waves to stream HBM; the rest is grid-stride
+    hipLaunchKernelGGL(k_copy16, dim3((uint32_t)g), dim3(kBlock), 0, s, reinterpret_cast<const u32x4*>(src),
+                       reinterpret_cast<u32x4*>(dst), n);
     return hipGetLastError();
 }
 

@@ -36,3 +36,14 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_every_leg_main_calls_is_defined():
+    import ast
+    tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
+    main = next(n for n in tree.body if isinstance(n, ast.FunctionDef) and n.name == "main")
+    called = {c.func.id for c in ast.walk(main) if isinstance(c, ast.Call) and isinstance(c.func, ast.Name)}
+    defined = {n.name for n in tree.body if isinstance(n, ast.FunctionDef)}
+    builtins = set(dir(__builtins__)) if isinstance(__builtins__, dict) is False else set(__builtins__)
+    missing = sorted(x for x in called - defined if x not in builtins and not hasattr(__import__("builtins"), x))
+    assert not missing, missing

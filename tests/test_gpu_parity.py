@@ -120,6 +120,29 @@ def test_empty_circuit(dtype, n):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [1, 14])
+def test_copy_state(dtype, n):
+    m = lib()
+    B = 2
+    psi0 = np.stack([round_c64(W.random_state(n, 400 + b)) for b in range(B)])
+    a = m.StateVector(n, dtype, batch=B, tensor=to_dev(psi0, dtype))
+    b = m.StateVector(n, dtype, batch=B)
+    b.copy_from(a)
+    assert np.array_equal(to_host(b.tensor), psi0)
+    # a deferred |0..0> is passed on and written by the next sweep
+    a.init("zero_deferred")
+    b.tensor.fill_(3.0)
+    b.copy_from(a)
+    b.apply(W.Circuit(n, []))
+    got = to_host(b.tensor)
+    assert np.all(got[:, 0] == 1) and np.count_nonzero(got) == B
+    with pytest.raises(m.SvError):
+        b.copy_from(m.StateVector(n + 1, dtype, batch=B))
+    with pytest.raises(m.SvError):
+        b.copy_from(m.StateVector(n, dtype, batch=B + 1))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
 def test_wide_matrix_gates(dtype):
     n = 12
     c = W.random_circuit(n, 20, 5, ops=("H", "CZ", "T"), mat_k=(5, 6))
