@@ -109,6 +109,18 @@ def cpu_baseline(circ, budget_s=25.0):
             break
     dt = time.time() - t0
     amp_updates = done * (1 << cut) / dt
+    # the same gates on one thread, a shorter sample
+    psi1 = np.zeros(1 << cut, np.complex128)
+    psi1[0] = 1.0
+    t1 = time.time()
+    done1 = 0
+    for g in sub.gates:
+        oracle.apply_matrix(psi1, cut, g.qubits, oracle.gate_matrix(g, None), 1)
+        done1 += 1
+        if time.time() - t1 > budget_s / 3:
+            break
+    dt1 = time.time() - t1
+    amp_updates_1 = done1 * (1 << cut) / dt1
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -125,6 +137,8 @@ def cpu_baseline(circ, budget_s=25.0):
         "cores": nthreads,
         "host_cpus": os.cpu_count(),
         "cpu_model": model,
+        "one_core": {"value": amp_updates_1 / float(1 << circ.n), "amp_updates_per_s": amp_updates_1,
+                     "sample": f"first {done1} gates of the same cut, {dt1:.1f} s on 1 thread"},
         "kind": "oracle",
         "sample": f"FP64 oracle, gate by gate, first {done} gates of the {cut}-qubit cut (qubits 0-{cut - 1}) "
                   f"of the same grid circuit, {dt:.1f} s on {nthreads} threads; value = amp-updates/s / 2^{circ.n}",
