@@ -518,15 +518,16 @@ def ablation(sv, W, torch, np, steps=1):
 
 
 def ksweep(sv, W, torch, steps=2):
-    """5x6 grid, 30 qubits, 20 cycles, complex64: the butterfly mode against
-    dense blocks of at most k qubits (k = 1..6).  One JSON line per mode."""
+    """5x6 grid, 30 qubits, 20 cycles, complex64 and complex128: the
+    butterfly mode against dense blocks of at most k qubits (k = 1..6).  One
+    JSON line per mode."""
     circ = W.grid30()
     cabi = sv.CircuitABI(circ)
     modes = [("butterflies", dict(structured=1))] + [(f"dense k<={k}", dict(structured=0, max_fuse_k=k))
                                                    for k in range(1, 7)]
     rows = []
-    for name, kw in modes:
-        s = sv.StateVector(circ.n, torch.complex64, opts=sv.make_opts(timing=1, **kw))
+    for dtype, name, kw in [(d, nm, kw) for d in (torch.complex64, torch.complex128) for nm, kw in modes]:
+        s = sv.StateVector(circ.n, dtype, opts=sv.make_opts(timing=1, **kw))
         s.init("zero_deferred")
         st = s.apply(cabi)
         torch.cuda.synchronize()
@@ -538,7 +539,8 @@ def ksweep(sv, W, torch, steps=2):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / steps
         tile_ms, launches, tile_bytes = s.timing()
-        row = {"mode": name, "ms_per_sweep": ms, "gates_per_s": len(circ.gates) / (ms / 1e3),
+        row = {"dtype": "c64" if dtype == torch.complex64 else "c128", "mode": name, "ms_per_sweep": ms,
+               "gates_per_s": len(circ.gates) / (ms / 1e3),
                "passes": st["passes"], "dense_ops": st["dense_ops"],
                "hbm_frac_sweep": st["hbm_bytes"] / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
                "tile_avg_ms": tile_ms / max(1, launches),

@@ -18,10 +18,11 @@ hipError_t tile_pass_set_attrs(size_t max_lds);
 
 // Plain (one kernel per gate) kernels; `batch` states spaced `bstride` amplitudes.
 // Dense k-qubit gate on ascending qubits tq[0..k), matrix row-major in that order.
-// K = 5, 6 dense gates on MFMA (complex64, n >= 12); ascending targets.
+// K = 5, 6 dense gates on MFMA (complex64: n >= 12, FP32 tiles; complex128:
+// n >= 11, FP64 tiles); ascending targets.
 bool mfma_dense_supported(int dtype, int n, int k);
-hipError_t launch_dense_mfma(void* state, uint64_t bstride, int batch, int n, int k, const int* tq, const void* mat,
-                             uint64_t mat_bstride, hipStream_t s);
+hipError_t launch_dense_mfma(int dtype, void* state, uint64_t bstride, int batch, int n, int k, const int* tq,
+                             const void* mat, uint64_t mat_bstride, hipStream_t s);
 hipError_t launch_dense_plain(int dtype, void* state, uint64_t bstride, int batch, int n, int k,
                              const int* tq, const void* mat, uint64_t mat_bstride, hipStream_t s);
 // Multiply every amplitude whose index has all bits of `mask` set by the

@@ -263,7 +263,8 @@ static hipError_t dense_plain_t(void* state, uint64_t bstride, int batch, int n,
 
 hipError_t launch_dense_plain(int dtype, void* state, uint64_t bstride, int batch, int n, int k,
                               const int* tq, const void* mat, uint64_t mat_bstride, hipStream_t s) {
-    if (mfma_dense_supported(dtype, n, k)) return launch_dense_mfma(state, bstride, batch, n, k, tq, mat, mat_bstride, s);
+    if (mfma_dense_supported(dtype, n, k))
+        return launch_dense_mfma(dtype, state, bstride, batch, n, k, tq, mat, mat_bstride, s);
     return dtype == 1 ? dense_plain_t<float>(state, bstride, batch, n, k, tq, mat, mat_bstride, s)
                       : dense_plain_t<double>(state, bstride, batch, n, k, tq, mat, mat_bstride, s);
 }

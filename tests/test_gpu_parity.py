@@ -263,12 +263,14 @@ def test_dense_block_fusion(dtype, k):
         check_close(to_host(t)[0], ref, dtype, f"dense k={k} jit={jit}")
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("k", [5, 6])
-@pytest.mark.parametrize("n", [12, 17])
-def test_mfma_dense_blocks(k, n):
-    """5- and 6-qubit blocks on the matrix cores (complex64): explicit
-    matrices on spread targets, and per-state fused blocks of parametric
-    gates for a batch of two states."""
+@pytest.mark.parametrize("n", [11, 12, 17])
+def test_mfma_dense_blocks(k, n, dtype):
+    """5- and 6-qubit blocks on the matrix cores (FP32 tiles for complex64
+    from 12 qubits, FP64 tiles for complex128 from 11): explicit matrices on
+    spread targets, and per-state fused blocks of parametric gates for a
+    batch of two states."""
     m = lib()
     rng = np.random.default_rng(900 + 10 * k + n)
     gates = []
@@ -280,18 +282,19 @@ def test_mfma_dense_blocks(k, n):
         gates.append(W.Gate("H", (int(rng.integers(0, n)),)))
     c = W.Circuit(n, gates, 0)
     psi0 = round_c64(W.random_state(n, 7))
-    got, _ = run(c, psi0, torch.complex64)
-    check_close(got[0], oracle.simulate(c, psi0=psi0), torch.complex64, f"MAT k={k} n={n}")
+    got, _ = run(c, psi0, dtype)
+    check_close(got[0], oracle.simulate(c, psi0=psi0), dtype, f"MAT k={k} n={n}")
     # per-state matrices: dense blocks fused from RY/RZ/CZ with two parameter sets
     c2 = W.random_circuit(n, 60, seed=950 + k, ops=("RY", "RZ", "CZ", "H"), param_frac=1.0)
     p = W.uniform_params(2, c2.n_params, 960 + k)
     psi = np.stack([round_c64(W.random_state(n, 11 + b)) for b in range(2)])
-    t = to_dev(psi, torch.complex64)
-    s = m.StateVector(n, torch.complex64, batch=2, tensor=t, opts=m.make_opts(structured=0, max_fuse_k=k))
-    s.apply(c2, p)
+    t = to_dev(psi, dtype)
+    s = m.StateVector(n, dtype, batch=2, tensor=t, opts=m.make_opts(structured=0, max_fuse_k=k))
+    st = s.apply(c2, p)
+    assert st["dense_ops"] > 0
     out = to_host(t)
     for b in range(2):
-        check_close(out[b], oracle.simulate(c2, p[b], psi0=psi[b]), torch.complex64, f"fused k={k} state {b}")
+        check_close(out[b], oracle.simulate(c2, p[b], psi0=psi[b]), dtype, f"fused k={k} state {b}")
 
 
 def test_tune_then_apply(tmp_path, monkeypatch):
