@@ -202,9 +202,17 @@ sv_status get_plan(sv_ctx_s* c, const sv_circuit* circ, const double* params, bo
     return SV_OK;
 }
 
+// Product-state tables for the first tile pass (lo: 2^nlo complex FP64,
+// hi: 2^{n-nlo}); the pass computes its input instead of reading psi.
+struct InitTables {
+    const double* lo = nullptr;
+    const double* hi = nullptr;
+    uint32_t nlo = 0;
+};
+
 // Execute a plan on psi (and lambda when `lam` is non-null).
 sv_status run_plan(sv_ctx_s* c, CachedPlan& cp, const std::vector<IRGate>& ir, void* psi, void* lam,
-                   double* gout, uint64_t gstride) {
+                   double* gout, uint64_t gstride, const InitTables& init = InitTables{}) {
     const EncodedPlan& e = cp.ep;
     const int dt = c->dtype;
     const uint64_t bstride = 1ull << c->n;
@@ -236,11 +244,19 @@ sv_status run_plan(sv_ctx_s* c, CachedPlan& cp, const std::vector<IRGate>& ir, v
         }
     }
     uint64_t gslot = 0;
+    bool first = true;
     for (const Step& st : e.steps) {
+        const bool fused_init = first && init.lo != nullptr;
+        first = false;
         switch (st.type) {
             case ST_TILE: {
                 const DPass& P = e.passes[st.pass];
                 TileArgs a{};
+                if (fused_init) {
+                    a.init_lo = init.lo;
+                    a.init_hi = init.hi;
+                    a.init_nlo = init.nlo;
+                }
                 a.state = psi;
                 a.lam = lam;
                 a.pass = reinterpret_cast<const DPass*>(plan + cp.o_pass) + st.pass;
@@ -270,8 +286,9 @@ sv_status run_plan(sv_ctx_s* c, CachedPlan& cp, const std::vector<IRGate>& ir, v
                 if (c->opts.timing) {
                     HIPCHK(hipEventRecord(e1, c->stream));
                     c->ev.emplace_back(e0, e1);
-                    c->ev_bytes.push_back(2.0 * (double)ab * (double)c->batch * std::ldexp(1.0, c->n) *
-                                          (lam ? 2.0 : 1.0));
+                    // a pass with the product-state input only writes
+                    c->ev_bytes.push_back((fused_init ? 1.0 : 2.0) * (double)ab * (double)c->batch *
+                                          std::ldexp(1.0, c->n) * (lam ? 2.0 : 1.0));
                 }
                 if (lam && P.ngrad) {
                     HIPCHK(launch_grad_reduce(reinterpret_cast<double*>(c->gpart.p) + P.gpart_off * c->batch,
@@ -317,7 +334,7 @@ sv_status run_plan(sv_ctx_s* c, CachedPlan& cp, const std::vector<IRGate>& ir, v
 }
 
 void fill_stats(sv_stats* st, const sv_ctx_s* c, const CachedPlan& cp, const sv_circuit* circ, double plan_ms,
-                int folded, bool init_used) {
+                int folded, bool init_used, bool init_fused = false) {
     if (!st) return;
     std::memset(st, 0, sizeof(*st));
     const EncodedPlan& e = cp.ep;
@@ -326,7 +343,7 @@ void fill_stats(sv_stats* st, const sv_ctx_s* c, const CachedPlan& cp, const sv_
     st->phases = e.n_phase;
     st->dense_ops = e.n_dense;
     st->diag_ops = e.n_diag;
-    st->launches = (int)e.steps.size() + (init_used ? 1 : 0);
+    st->launches = (int)e.steps.size() + (init_used && !init_fused ? 1 : 0);
     st->folded_init = folded;
     st->plan_ms = plan_ms;
     const double N = std::ldexp(1.0, c->n) * c->batch;
@@ -338,10 +355,14 @@ void fill_stats(sv_stats* st, const sv_ctx_s* c, const CachedPlan& cp, const sv_
         else if (s.type == ST_MASKED)
             bytes += 2.0 * N * ab * std::ldexp(1.0, -__builtin_popcountll(s.mask));
     }
-    if (init_used) bytes += N * ab;
+    if (init_used && !init_fused) bytes += N * ab;     // the product state written
+    if (init_fused) bytes -= N * ab;                   // the first pass reads nothing
     st->hbm_bytes = bytes;
     st->flops = e.flops * c->batch;
     st->alu_ops = e.alu_ops * c->batch;
+    // the fused product-state input: a complex FP64 product (4 instructions)
+    // and its rounding (2) per amplitude
+    if (init_fused) st->alu_ops += 6.0 * N;
 }
 
 sv_status upload_pauli(sv_ctx_s* c, const sv_pauli_sum* h, PauliDev& pd) {
@@ -414,6 +435,8 @@ sv_status apply_internal(sv_ctx_s* c, const sv_circuit* circ, const double* para
         if (st != SV_OK) return st;
     }
     c->zero_pending = false;
+    InitTables init;
+    bool init_fused = false;
     if (pi.used) {
         const size_t nlo = pi.lo.size(), nhi = pi.hi.size();
         HIPCHK(c->pinit.ensure((nlo + nhi) * 16));
@@ -421,13 +444,22 @@ sv_status apply_internal(sv_ctx_s* c, const sv_circuit* circ, const double* para
         HIPCHK(hipMemcpyAsync(reinterpret_cast<unsigned char*>(c->pinit.p) + nlo * 16, pi.hi.data(), nhi * 16,
                               hipMemcpyHostToDevice, c->stream));
         const double* lo = reinterpret_cast<const double*>(c->pinit.p);
-        HIPCHK(launch_init_product(c->dtype, c->state, 1ull << c->n, c->batch, c->n, pi.nlo, lo, lo + 2 * nlo,
-                                   c->stream));
+        // a first step that is a tile pass computes the product state as its
+        // input; otherwise the state is written first
+        init_fused = !cp->ep.steps.empty() && cp->ep.steps.front().type == ST_TILE && pi.nlo >= 1;
+        if (init_fused) {
+            init.lo = lo;
+            init.hi = lo + 2 * nlo;
+            init.nlo = (uint32_t)pi.nlo;
+        } else {
+            HIPCHK(launch_init_product(c->dtype, c->state, 1ull << c->n, c->batch, c->n, pi.nlo, lo, lo + 2 * nlo,
+                                       c->stream));
+        }
     }
-    st = run_plan(c, *cp, ir, c->state, nullptr, nullptr, 0);
+    st = run_plan(c, *cp, ir, c->state, nullptr, nullptr, 0, init);
     if (st != SV_OK) return st;
     c->known_zero = false;
-    fill_stats(stats, c, *cp, circ, plan_ms, pi.folded, pi.used);
+    fill_stats(stats, c, *cp, circ, plan_ms, pi.folded, pi.used, init_fused);
     return SV_OK;
 }
 
@@ -882,7 +914,8 @@ sv_status sv_plan_info(const sv_circuit* circ, sv_dtype dtype, int32_t adjoint, 
         if (!jit_compile_only(cp.ep, dtype, adjoint != 0, cp.ep.cfg.nt, jerr))
             return fail(SV_EUNSUPPORTED, "run-time specialisation failed: " + jerr);
     }
-    fill_stats(stats, &c, cp, circ, 0.0, pi.folded, pi.used);
+    const bool init_fused = pi.used && !cp.ep.steps.empty() && cp.ep.steps.front().type == ST_TILE && pi.nlo >= 1;
+    fill_stats(stats, &c, cp, circ, 0.0, pi.folded, pi.used, init_fused);
     stats->plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     stats->reserved = (int32_t)plan_ms;
     return SV_OK;

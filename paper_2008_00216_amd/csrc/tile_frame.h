@@ -23,6 +23,13 @@ struct TileArgs {
     double* gpart;           // gradient partials of this pass
     uint32_t ntile_log2;     // log2(tiles per state)
     uint32_t nthreads;
+    // Product-state input (one-state passes only): when init_lo is set the
+    // tile's amplitudes are not read but computed as lo[j mod 2^init_nlo] *
+    // hi[j >> init_nlo] (complex FP64, rounded once), the state the leading
+    // one-qubit gates make from |0..0>.
+    const double* init_lo;
+    const double* init_hi;
+    uint32_t init_nlo;
 };
 
 __device__ __forceinline__ uint32_t ins0(uint32_t x, uint32_t p) {
@@ -63,6 +70,26 @@ struct TileFrame {
         begin_at(A, smem, L, H, Tn, hpos, nform, form0, ngrad_, blockIdx.x);
     }
     // blk = state * 2^ntile_log2 + tile
+    // The 16 bytes of the product-state input at global amplitude gi (one
+    // complex128 amplitude, or the complex64 pair gi, gi + 1 with gi even).
+    __device__ __forceinline__ static u32x4 product_chunk(const TileArgs& A, uint64_t gi) {
+        constexpr uint32_t APC = 16 / sizeof(V);
+        const uint64_t amask = (1ull << A.init_nlo) - 1ull;
+        union {
+            V v[APC];
+            u32x4 u;
+        } out;
+#pragma unroll
+        for (uint32_t t = 0; t < APC; ++t) {
+            const uint64_t j = gi + t;
+            const uint64_t a = j & amask, h = j >> A.init_nlo;
+            const double ar = A.init_lo[2 * a], ai = A.init_lo[2 * a + 1];
+            const double br = A.init_hi[2 * h], bi = A.init_hi[2 * h + 1];
+            out.v[t] = V{R(ar * br - ai * bi), R(ar * bi + ai * br)};
+        }
+        return out.u;
+    }
+
     template <class HP>
     __device__ __forceinline__ void begin_at(const TileArgs& A, unsigned char* smem, uint32_t L, uint32_t H,
                                              uint32_t Tn, HP hpos, uint32_t nform, uint32_t form0,
@@ -96,6 +123,7 @@ struct TileFrame {
         constexpr uint32_t APC = 16 / sizeof(V);
         const uint32_t nchunk = NA / APC;
         ot = map_local(APC * tid, L, H, hpos);
+        const bool pinit = !TWO && A.init_lo != nullptr;   // uniform over the grid
         for (uint32_t c0 = 0; c0 < nchunk; c0 += 8 * NT) {
             u32x4 va[8];
             u32x4 vb[8];
@@ -104,7 +132,8 @@ struct TileFrame {
                 const uint32_t c = c0 + j * NT + tid;
                 if (c < nchunk) {
                     const uint64_t gi = base + ot + map_local(APC * (c0 + j * NT), L, H, hpos);
-                    va[j] = *reinterpret_cast<const u32x4*>(psi + gi);
+                    if (pinit) va[j] = product_chunk(A, gi);
+                    else va[j] = *reinterpret_cast<const u32x4*>(psi + gi);
                     if constexpr (TWO) vb[j] = *reinterpret_cast<const u32x4*>(lam + gi);
                 }
             }
