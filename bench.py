@@ -556,7 +556,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(every GPU box here has a single MI355X).", file=sys.stderr)
+              "(the library runs on a single MI355X; sharding is a design note only).", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

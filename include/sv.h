@@ -24,8 +24,9 @@
  *   - Device buffers (states, adjoint scratch) belong to the caller.  The
  *     library borrows the raw device pointers, never frees them, and needs
  *     them to stay valid for the lifetime of the context.
- *   - The library owns the context, its plan cache and small device
- *     work areas (plans, reduction partials), released by sv_destroy.
+ *   - The library owns the context, its plan cache and its device work
+ *     areas (plans, reduction partials, sampling trees), released by
+ *     sv_destroy.
  *   - Host arrays passed to a call are read during the call only.
  *
  * Errors
@@ -34,7 +35,8 @@
  *     state when validation fails.
  *   - Kernels run asynchronously on the context's HIP stream.  A device
  *     fault surfaces as SV_EDEVICE from the next call that synchronises
- *     (sv_expect, sv_norm, sv_adjoint_grad, sv_sync, sv_apply_batch).
+ *     (sv_expect, sv_norm, sv_sample, sv_amplitudes, sv_adjoint_grad,
+ *     sv_sync, sv_apply_batch).
  *   - No C++ exception crosses this boundary.  A context is not thread-safe;
  *     separate contexts are independent.
  */
@@ -53,7 +55,7 @@ typedef enum {
     SV_EINVAL = 1,        /* bad argument (qubit range, sizes, alignment, op code, ...) */
     SV_ENOMEM = 2,        /* device or host allocation failed */
     SV_EDEVICE = 3,       /* HIP runtime / kernel error */
-    SV_EUNSUPPORTED = 4   /* valid request this build does not support */
+    SV_EUNSUPPORTED = 4   /* valid request the library does not support */
 } sv_status;
 
 typedef enum { SV_C64 = 1, SV_C128 = 2 } sv_dtype;

@@ -1,4 +1,5 @@
-"""Readers for the transcribed paper fixtures in this folder."""
+"""Readers for the fixtures in this folder: values transcribed from the paper,
+and oracle values written by the scripts here."""
 import os
 
 import numpy as np
@@ -37,3 +38,19 @@ def bitmasks():
             key, _cite, vals = [x.strip() for x in line.split("|")]
             out[key] = vals.split()
     return out
+
+
+def grid33_cut28():
+    """(indices, amplitudes, norm2) written by make_grid33_cut28.py."""
+    idx, amp, nrm = [], [], None
+    with open(os.path.join(HERE, "grid33_cut28_amplitudes.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            parts = line.split()
+            if parts[0] == "norm2":
+                nrm = float(parts[1])
+                continue
+            idx.append(int(parts[0]))
+            amp.append(complex(float(parts[1]), float(parts[2])))
+    return np.array(idx, np.uint64), np.array(amp, np.complex128), nrm

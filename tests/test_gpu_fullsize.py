@@ -32,6 +32,30 @@ def test_grid33_cut24_against_oracle():
     check_close(to_host(s.tensor)[0], ref, torch.complex64, "grid33 cut 24")
 
 
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_grid33_cut28_against_stored_oracle_amplitudes(dtype):
+    # the 28-qubit cut of the headline circuit in the launch configuration
+    # the benchmark uses (tuned geometry, plan-specialised passes, product-
+    # state input), against FP64 oracle amplitudes stored by
+    # tests/golden/make_grid33_cut28.py
+    from tests.golden import load as golden
+    m = lib()
+    idx, want, nrm_want = golden.grid33_cut28()
+    c = W.grid33().cut(28)
+    opts = m.make_opts(tile_bits=13, low_bits=4, threads=512) if dtype == torch.complex64 else m.make_opts()
+    s = m.StateVector(28, dtype, opts=opts)
+    s.init("zero_deferred")
+    st = s.apply(c)
+    assert st["passes"] > 1
+    got = s.amplitudes(idx)[0]
+    tol = 1e-5 if dtype == torch.complex64 else 1e-12
+    err = float(np.max(np.abs(got - want)))
+    assert err <= tol, err
+    assert abs(float(s.norm()[0]) - nrm_want) < (1e-5 if dtype == torch.complex64 else 1e-12)
+    del s
+    torch.cuda.empty_cache()
+
+
 def test_grid30_cut22_c128_against_oracle():
     m = lib()
     c = W.grid30().cut(22)

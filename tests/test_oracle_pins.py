@@ -398,3 +398,14 @@ def test_sample_zero_probability_outcomes_never_drawn():
     assert list(oracle.sample(3.0 * psi, u)) == [0, 0, 0, 1, 1]
     with pytest.raises(ValueError):
         oracle.sample(psi, np.array([1.0]))
+
+
+def test_grid33_cut28_fixture_is_a_unit_state_sample():
+    # the stored oracle amplitudes of the 28-qubit cut: the circuit is unitary
+    # (norm 1), and a uniform sample of its Porter-Thomas amplitudes has mean
+    # 2^n |alpha|^2 near 1
+    idx, amp, nrm = golden.grid33_cut28()
+    assert abs(nrm - 1.0) < 1e-12
+    assert idx.size > 2000 and np.all(np.diff(idx.astype(np.int64)) > 0)
+    x = np.abs(amp) ** 2 * float(1 << 28)
+    assert 0.85 < float(np.mean(x)) < 1.15
