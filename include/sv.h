@@ -35,8 +35,8 @@
  *     state when validation fails.
  *   - Kernels run asynchronously on the context's HIP stream.  A device
  *     fault surfaces as SV_EDEVICE from the next call that synchronises
- *     (sv_expect, sv_norm, sv_sample, sv_amplitudes, sv_adjoint_grad,
- *     sv_sync, sv_apply_batch).
+ *     (sv_expect, sv_norm, sv_apply_circuit_norm, sv_sample, sv_amplitudes,
+ *     sv_adjoint_grad, sv_sync, sv_apply_batch).
  *   - No C++ exception crosses this boundary.  A context is not thread-safe;
  *     separate contexts are independent.
  */
@@ -179,6 +179,16 @@ sv_status sv_init(sv_ctx ctx, int32_t kind, uint64_t basis_index);
  * before any kernel is launched. */
 sv_status sv_apply_circuit(sv_ctx ctx, const sv_circuit* circuit, const double* params,
                            sv_stats* stats);
+
+/* sv_apply_circuit followed by the norm check of Sec. 4.1 in the same
+ * sweep: norm2_out (host, batch doubles) receives ||psi_b||^2 in FP64.
+ * When the plan ends with a tile pass, that pass sums |psi_j|^2 of every
+ * tile as it writes it (fixed order: lanes, waves, then the tiles in two
+ * fixed-order steps), so the norm costs no extra read of the state;
+ * otherwise a separate FP64 reduction runs.  Synchronises.
+ * Errors: those of sv_apply_circuit, and SV_EINVAL for a NULL norm2_out. */
+sv_status sv_apply_circuit_norm(sv_ctx ctx, const sv_circuit* circuit, const double* params,
+                                double* norm2_out, sv_stats* stats);
 
 /* out[b] = sum_k coeff_k Re <psi_b|P_k|psi_b>, accumulated in FP64 on the
  * device with a fixed reduction order.  Synchronises the stream. */

@@ -101,6 +101,7 @@ _lib.sv_init.argtypes = [_vp, ctypes.c_int32, ctypes.c_uint64]
 _lib.sv_apply_circuit.argtypes = [_vp, ctypes.POINTER(SvCircuit), _dp, ctypes.POINTER(SvStats)]
 _lib.sv_expect.argtypes = [_vp, ctypes.POINTER(SvPauliSum), _dp]
 _lib.sv_norm.argtypes = [_vp, _dp]
+_lib.sv_apply_circuit_norm.argtypes = [_vp, ctypes.POINTER(SvCircuit), _dp, _dp, ctypes.POINTER(SvStats)]
 _lib.sv_copy_state.argtypes = [_vp, _vp]
 _lib.sv_sample.argtypes = [_vp, ctypes.c_int64, _dp, ctypes.POINTER(ctypes.c_uint64)]
 _lib.sv_amplitudes.argtypes = [_vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64), _dp]
@@ -116,14 +117,15 @@ _lib.sv_tune.argtypes = [_vp, ctypes.POINTER(SvCircuit), _dp, ctypes.POINTER(SvO
 _lib.sv_plan_trace.argtypes = [ctypes.POINTER(SvCircuit), _dp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(SvOpts),
                                ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
 for _f in ("sv_create", "sv_destroy", "sv_set_stream", "sv_set_opts", "sv_init", "sv_apply_circuit",
-           "sv_expect", "sv_norm", "sv_copy_state", "sv_sample", "sv_amplitudes", "sv_adjoint_grad",
-           "sv_apply_batch", "sv_sync", "sv_timing", "sv_plan_info", "sv_plan_trace", "sv_tune"):
+           "sv_apply_circuit_norm", "sv_expect", "sv_norm", "sv_copy_state", "sv_sample", "sv_amplitudes",
+           "sv_adjoint_grad", "sv_apply_batch", "sv_sync", "sv_timing", "sv_plan_info", "sv_plan_trace",
+           "sv_tune"):
     getattr(_lib, _f).restype = ctypes.c_int32
 
 EXPORTED = ("sv_opts_default", "sv_create", "sv_destroy", "sv_set_stream", "sv_set_opts", "sv_init",
-            "sv_apply_circuit", "sv_expect", "sv_norm", "sv_copy_state", "sv_sample", "sv_amplitudes",
-            "sv_adjoint_grad", "sv_apply_batch", "sv_sync", "sv_timing", "sv_plan_info", "sv_plan_trace",
-            "sv_tune", "sv_last_error", "sv_version")
+            "sv_apply_circuit", "sv_apply_circuit_norm", "sv_expect", "sv_norm", "sv_copy_state", "sv_sample",
+            "sv_amplitudes", "sv_adjoint_grad", "sv_apply_batch", "sv_sync", "sv_timing", "sv_plan_info",
+            "sv_plan_trace", "sv_tune", "sv_last_error", "sv_version")
 
 
 class SvError(RuntimeError):
@@ -273,6 +275,18 @@ class StateVector:
         st = SvStats()
         _check(_lib.sv_apply_circuit(self._h, ctypes.byref(c.c), pp, ctypes.byref(st)))
         return st.as_dict()
+
+    def apply_norm(self, circ, params=None):
+        """apply() and the FP64 norms ||psi_b||^2 from the same sweep:
+        returns (stats, norms)."""
+        self._stream()
+        c = _as_circuit(circ)
+        _, pp = _params_ptr(params, self.batch, c.n_params)
+        st = SvStats()
+        out = np.zeros(self.batch, np.float64)
+        _check(_lib.sv_apply_circuit_norm(self._h, ctypes.byref(c.c), pp,
+                                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(st)))
+        return st.as_dict(), out
 
     def expect(self, pauli) -> np.ndarray:
         self._stream()

@@ -113,6 +113,7 @@ struct sv_ctx_s {
     std::unordered_map<uint64_t, std::unique_ptr<CachedPlan>> cache;
     DevBuf pool, red_part, red_out, pauli, gpart, gout, pinit;
     DevBuf smp_tree, smp_u, smp_out;   // sampling and amplitude readout
+    DevBuf npart;                      // per-tile norm partials of the last pass
     std::vector<unsigned char> pool_host;
     std::vector<double> host_out;
     // tile-pass timing (opts.timing)
@@ -210,9 +211,13 @@ struct InitTables {
     uint32_t nlo = 0;
 };
 
-// Execute a plan on psi (and lambda when `lam` is non-null).
+// Execute a plan on psi (and lambda when `lam` is non-null).  With
+// norm_out (device, batch doubles) the call also leaves ||psi_b||^2 there:
+// summed by the last pass as it stores its tiles when the plan ends with a
+// tile pass, else by a separate reduction.
 sv_status run_plan(sv_ctx_s* c, CachedPlan& cp, const std::vector<IRGate>& ir, void* psi, void* lam,
-                   double* gout, uint64_t gstride, const InitTables& init = InitTables{}) {
+                   double* gout, uint64_t gstride, const InitTables& init = InitTables{},
+                   double* norm_out = nullptr) {
     const EncodedPlan& e = cp.ep;
     const int dt = c->dtype;
     const uint64_t bstride = 1ull << c->n;
@@ -244,10 +249,11 @@ sv_status run_plan(sv_ctx_s* c, CachedPlan& cp, const std::vector<IRGate>& ir, v
         }
     }
     uint64_t gslot = 0;
-    bool first = true;
-    for (const Step& st : e.steps) {
-        const bool fused_init = first && init.lo != nullptr;
-        first = false;
+    const bool norm_in_pass = norm_out && !lam && !e.steps.empty() && e.steps.back().type == ST_TILE;
+    uint64_t norm_ntile = 0;
+    for (size_t si = 0; si < e.steps.size(); ++si) {
+        const Step& st = e.steps[si];
+        const bool fused_init = si == 0 && init.lo != nullptr;
         switch (st.type) {
             case ST_TILE: {
                 const DPass& P = e.passes[st.pass];
@@ -256,6 +262,11 @@ sv_status run_plan(sv_ctx_s* c, CachedPlan& cp, const std::vector<IRGate>& ir, v
                     a.init_lo = init.lo;
                     a.init_hi = init.hi;
                     a.init_nlo = init.nlo;
+                }
+                if (norm_in_pass && si + 1 == e.steps.size()) {
+                    norm_ntile = 1ull << (c->n - P.T);
+                    HIPCHK(c->npart.ensure((size_t)c->batch * norm_ntile * sizeof(double)));
+                    a.norm_part = reinterpret_cast<double*>(c->npart.p);
                 }
                 a.state = psi;
                 a.lam = lam;
@@ -328,6 +339,16 @@ sv_status run_plan(sv_ctx_s* c, CachedPlan& cp, const std::vector<IRGate>& ir, v
             }
             default:
                 return fail(SV_EUNSUPPORTED, "unknown plan step");
+        }
+    }
+    if (norm_out) {
+        if (norm_in_pass) {
+            HIPCHK(launch_grad_reduce(reinterpret_cast<double*>(c->npart.p), c->batch, norm_ntile, 1, norm_out, 1,
+                                      c->stream));
+        } else {
+            HIPCHK(c->red_part.ensure(reduce_partials_size(c->n, c->batch) * sizeof(double)));
+            HIPCHK(launch_reduce(dt, 0, psi, nullptr, bstride, c->batch, c->n, nullptr, 0, 0,
+                                 reinterpret_cast<double*>(c->red_part.p), norm_out, 1, c->stream));
         }
     }
     return SV_OK;
@@ -423,7 +444,8 @@ sv_status materialise(sv_ctx_s* c) {
     return SV_OK;
 }
 
-sv_status apply_internal(sv_ctx_s* c, const sv_circuit* circ, const double* params, sv_stats* stats) {
+sv_status apply_internal(sv_ctx_s* c, const sv_circuit* circ, const double* params, sv_stats* stats,
+                         double* norm_out = nullptr) {
     std::vector<IRGate> ir;
     ProductInit pi;
     CachedPlan* cp = nullptr;
@@ -456,7 +478,7 @@ sv_status apply_internal(sv_ctx_s* c, const sv_circuit* circ, const double* para
                                        c->stream));
         }
     }
-    st = run_plan(c, *cp, ir, c->state, nullptr, nullptr, 0, init);
+    st = run_plan(c, *cp, ir, c->state, nullptr, nullptr, 0, init, norm_out);
     if (st != SV_OK) return st;
     c->known_zero = false;
     fill_stats(stats, c, *cp, circ, plan_ms, pi.folded, pi.used, init_fused);
@@ -574,6 +596,27 @@ sv_status sv_apply_circuit(sv_ctx c, const sv_circuit* circ, const double* param
         for (int64_t i = 0; i < (int64_t)c->batch * circ->n_params; ++i)
             if (!std::isfinite(params[i])) return fail(SV_EINVAL, "non-finite parameter");
     return apply_internal(c, circ, params, stats);
+}
+
+sv_status sv_apply_circuit_norm(sv_ctx c, const sv_circuit* circ, const double* params, double* norm2_out,
+                                sv_stats* stats) {
+    if (!c) return fail(SV_EINVAL, "ctx is NULL");
+    if (!norm2_out) return fail(SV_EINVAL, "norm2_out is NULL");
+    std::string v = validate_circuit(circ, c->n);
+    if (!v.empty()) return fail(SV_EINVAL, v);
+    bool has_param = false;
+    for (int i = 0; i < circ->n_gates; ++i) has_param |= circ->gates[i].param >= 0;
+    if (has_param && !params) return fail(SV_EINVAL, "circuit has parameterised gates but params is NULL");
+    if (params)
+        for (int64_t i = 0; i < (int64_t)c->batch * circ->n_params; ++i)
+            if (!std::isfinite(params[i])) return fail(SV_EINVAL, "non-finite parameter");
+    HIPCHK(c->red_out.ensure((size_t)c->batch * sizeof(double)));
+    double* dnorm = reinterpret_cast<double*>(c->red_out.p);
+    sv_status st = apply_internal(c, circ, params, stats, dnorm);
+    if (st != SV_OK) return st;
+    HIPCHK(hipMemcpyAsync(norm2_out, dnorm, (size_t)c->batch * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return SV_OK;
 }
 
 // ---- tile-geometry autotuner

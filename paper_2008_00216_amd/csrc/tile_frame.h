@@ -30,6 +30,9 @@ struct TileArgs {
     const double* init_lo;
     const double* init_hi;
     uint32_t init_nlo;
+    // One-state passes: when set, the pass also writes the FP64 sum of
+    // |psi_j|^2 over each tile it stores, at norm_part[state * tiles + tile].
+    double* norm_part;
 };
 
 __device__ __forceinline__ uint32_t ins0(uint32_t x, uint32_t p) {
@@ -61,6 +64,7 @@ struct TileFrame {
     V* ptab;
     uint32_t* fl;
     double* red;
+    double* nrm;   // NW per-wave norm sums (after the gradient slots)
 
     // Carve LDS, gather the tile, evaluate the per-tile form parts.
     template <class HP>
@@ -114,6 +118,7 @@ struct TileFrame {
         ptab = sA + (TWO ? 2 * NA : NA);
         fl = reinterpret_cast<uint32_t*>(ptab + 8);
         red = reinterpret_cast<double*>(fl + ((4 * nform + 1) & ~1u));
+        nrm = red + (TWO ? ngrad * NW : 0u);
 
         if (tid < 8) ptab[tid] = reinterpret_cast<const V*>(A.phase_tab)[tid];
         for (uint32_t i = tid; i < 4 * nform; i += NT) fl[i] = 0;
@@ -227,6 +232,8 @@ struct TileFrame {
         }
         constexpr uint32_t APC = 16 / sizeof(V);
         const uint32_t nchunk = NA / APC;
+        const bool nsum = !TWO && A.norm_part != nullptr;   // uniform over the grid
+        double nacc = 0.0;
         for (uint32_t c0 = 0; c0 < nchunk; c0 += 8 * NT) {
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
@@ -234,12 +241,44 @@ struct TileFrame {
                 if (c < nchunk) {
                     const uint32_t s = swz<R>(APC * c);
                     const uint64_t gi = base + ot + map_local(APC * (c0 + j * NT), L, H, hpos);
-                    *reinterpret_cast<u32x4*>(psi + gi) = *reinterpret_cast<const u32x4*>(sA + s);
+                    const u32x4 v = *reinterpret_cast<const u32x4*>(sA + s);
+                    *reinterpret_cast<u32x4*>(psi + gi) = v;
+                    if (nsum) nacc += chunk_norm2(v);
                     if constexpr (TWO)
                         *reinterpret_cast<u32x4*>(lam + gi) = *reinterpret_cast<const u32x4*>(sB + s);
                 }
             }
         }
+        if (nsum) {
+            // fixed order: chunks per thread, the wave, the waves of the tile
+            nacc = wave_sum64(nacc);
+            if ((tid & 63u) == 0) nrm[tid >> 6] = nacc;
+            __syncthreads();
+            if (tid == 0) {
+                double t = 0.0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) t += nrm[w];
+                A.norm_part[((uint64_t)b << A.ntile_log2) + g] = t;
+            }
+        }
+    }
+
+    // FP64 sum of |psi_j|^2 over the amplitudes of one 16-byte chunk.
+    __device__ __forceinline__ static double chunk_norm2(const u32x4& u) {
+        constexpr uint32_t APC = 16 / sizeof(V);
+        union {
+            u32x4 u;
+            V v[APC];
+        } c;
+        c.u = u;
+        double t = 0.0;
+#pragma unroll
+        for (uint32_t k = 0; k < APC; ++k) {
+            const double x = (double)c.v[k].x, y = (double)c.v[k].y;
+            t = __builtin_fma(x, x, t);
+            t = __builtin_fma(y, y, t);
+        }
+        return t;
     }
 };
 

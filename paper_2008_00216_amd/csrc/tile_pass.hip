@@ -32,6 +32,7 @@ size_t tile_lds_bytes(int dtype, bool two, uint32_t T, uint32_t nform, uint32_t 
     size_t bytes = (two ? 2 : 1) * ((size_t)1 << T) * amp + 8 * amp;
     bytes += 4 * (((4 * (size_t)nform + 1) & ~(size_t)1));
     if (two) bytes += 8 * (size_t)ngrad * (nt / 64);
+    bytes += 8 * (size_t)(nt / 64);   // per-wave norm sums (one-state passes that return the norm)
     return (bytes + 15) & ~(size_t)15;
 }
 

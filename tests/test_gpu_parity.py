@@ -143,6 +143,40 @@ def test_copy_state(dtype, n):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("case", ["tile_last", "plain_last", "plain_mode"])
+def test_apply_with_norm(dtype, case):
+    # the norm returned by the sweep equals the separate FP64 norm and the
+    # oracle's: summed by the last tile pass, or by a reduction when the plan
+    # ends with a per-gate step
+    m = lib()
+    n, B = 15, 2
+    c = W.grid_circuit(3, 5, 6, seed=1007)
+    if case == "plain_last":
+        # a 6-qubit matrix at the end runs as a per-gate step after the tiles
+        rng = np.random.default_rng(5)
+        z = rng.standard_normal((64, 64)) + 1j * rng.standard_normal((64, 64))
+        qm, r = np.linalg.qr(z)
+        wide = W.Gate("MAT", (0, 3, 5, 8, 11, 14), mat=qm * (np.diag(r) / np.abs(np.diag(r))))
+        c = W.Circuit(n, list(c.gates) + [wide], 0)
+    psi0 = np.stack([round_c64(W.random_state(n, 500 + b)) * (1.0 + 0.5 * b) for b in range(B)])
+    t = to_dev(psi0, dtype)
+    s = m.StateVector(n, dtype, batch=B, tensor=t, opts=m.make_opts(plain=1 if case == "plain_mode" else 0))
+    st, nrm = s.apply_norm(c)
+    assert st["passes"] >= 1
+    sep = s.norm()
+    out = to_host(t)
+    # against the oracle the complex64 state's own rounding dominates (about
+    # 1e-6 after 300 gate-by-gate FP32 updates); against the separate FP64
+    # norm of the same state only the summation order differs
+    tol = 1e-5 if dtype == torch.complex64 else 1e-12
+    for b in range(B):
+        ref = oracle.norm2(oracle.simulate(c, psi0=psi0[b]))
+        assert abs(nrm[b] - ref) < tol * ref, (b, nrm[b], ref)
+        assert abs(nrm[b] - sep[b]) < 1e-13 * ref
+        check_close(out[b], oracle.simulate(c, psi0=psi0[b]), dtype, f"{case} state {b}")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
 def test_wide_matrix_gates(dtype):
     n = 12
     c = W.random_circuit(n, 20, 5, ops=("H", "CZ", "T"), mat_k=(5, 6))
