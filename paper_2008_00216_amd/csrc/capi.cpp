@@ -113,7 +113,7 @@ struct sv_ctx_s {
     std::unordered_map<uint64_t, std::unique_ptr<CachedPlan>> cache;
     DevBuf pool, red_part, red_out, pauli, gpart, gout, pinit;
     DevBuf smp_tree, smp_u, smp_out;   // sampling and amplitude readout
-    DevBuf npart;                      // per-tile norm partials of the last pass
+    DevBuf npart;                      // FP64 partials: the last pass's norm, the adjoint energy
     std::vector<unsigned char> pool_host;
     std::vector<double> host_out;
     // tile-pass timing (opts.timing)
@@ -853,11 +853,12 @@ sv_status sv_adjoint_grad(sv_ctx c, const sv_circuit* circ, const double* params
     // forward sweep (folds leading one-qubit gates when the state is |0...0>)
     st = apply_internal(c, circ, params, stats);
     if (st != SV_OK) return st;
-    // lambda = H psi, energy = Re <psi|lambda>
-    HIPCHK(launch_hpsi(c->dtype, c->state, d_scratch, 1ull << c->n, c->batch, c->n, pd, c->stream));
-    HIPCHK(c->red_part.ensure(reduce_partials_size(c->n, c->batch) * sizeof(double)));
-    const int ntot_slots = 0;
-    (void)ntot_slots;
+    // lambda = H psi; the same kernel leaves the block partials of the
+    // energy Re <psi|lambda>
+    const uint64_t hblk = hpsi_blocks(c->n);
+    HIPCHK(c->npart.ensure((size_t)c->batch * hblk * sizeof(double)));
+    double* epart = reinterpret_cast<double*>(c->npart.p);
+    HIPCHK(launch_hpsi(c->dtype, c->state, d_scratch, 1ull << c->n, c->batch, c->n, pd, epart, c->stream));
     // backward plan
     std::vector<IRGate> ir;
     ProductInit pi;
@@ -870,8 +871,7 @@ sv_status sv_adjoint_grad(sv_ctx c, const sv_circuit* circ, const double* params
     HIPCHK(c->gout.ensure(gbytes));
     double* gdev = reinterpret_cast<double*>(c->gout.p);
     // energy goes in column ns of the (batch x (ns+1)) output block
-    HIPCHK(launch_reduce(c->dtype, 1, c->state, d_scratch, 1ull << c->n, c->batch, c->n, nullptr, 0, 0,
-                         reinterpret_cast<double*>(c->red_part.p), gdev + ns, (uint64_t)ns + 1, c->stream));
+    HIPCHK(launch_grad_reduce(epart, c->batch, hblk, 1, gdev + ns, (uint64_t)ns + 1, c->stream));
     st = run_plan(c, *cp, ir, c->state, d_scratch, gdev, (uint64_t)ns + 1);
     if (st != SV_OK) return st;
     c->host_out.resize((size_t)c->batch * (ns + 1));

@@ -79,9 +79,12 @@ hipError_t launch_sample(int dtype, const void* a, uint64_t bstride, int batch, 
 hipError_t launch_gather(int dtype, const void* a, uint64_t bstride, int batch, const uint64_t* idx, uint64_t count,
                          double* out, hipStream_t s);
 
-// lambda = H psi (FP64 accumulation, rounded once).
+// lambda = H psi (FP64 accumulation, rounded once).  With epart (batch *
+// hpsi_blocks(n) doubles) the blocks also leave their FP64 partials of
+// Re <psi|lambda>, to be summed by launch_grad_reduce with nslot = 1.
+uint64_t hpsi_blocks(int n);
 hipError_t launch_hpsi(int dtype, const void* psi, void* lam, uint64_t bstride, int batch, int n,
-                       const PauliDev& pd, hipStream_t s);
+                       const PauliDev& pd, double* epart, hipStream_t s);
 // out[b * out_stride + j] = sum_t part[(b * ntile + t) * nslot + j] in a
 // fixed order (chunks of tiles, then the chunk sums); part is overwritten.
 hipError_t launch_grad_reduce(double* part, int batch, uint64_t ntile, uint32_t nslot,

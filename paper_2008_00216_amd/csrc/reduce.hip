@@ -141,11 +141,17 @@ __global__ __launch_bounds__(kRB) void k_final(const double* __restrict__ partia
     if (threadIdx.x == 0) out[(uint64_t)b * out_stride] = s;
 }
 
+// lambda = H psi for a Pauli sum.  With epart, each block also writes its
+// FP64 partial of Re <psi|lambda> = <psi|H|psi> (lambda before rounding to
+// the state precision), at epart[state * gridDim.x + block].
 template <class R>
 __global__ __launch_bounds__(kRB) void k_hpsi(const V2<R>* __restrict__ psi, V2<R>* __restrict__ lam,
-                                              uint64_t bstride, uint64_t N, PauliDev pd) {
+                                              uint64_t bstride, uint64_t N, PauliDev pd,
+                                              double* __restrict__ epart) {
+    __shared__ double sh[kRB / 64];
     const uint32_t b = blockIdx.y;
     const V2<R>* p = psi + (uint64_t)b * bstride;
+    double e = 0.0;
     for (uint64_t j = (uint64_t)blockIdx.x * kRB + threadIdx.x; j < N; j += (uint64_t)gridDim.x * kRB) {
     double lr = 0.0, li = 0.0;
     for (uint32_t g = 0; g < pd.ngroup; ++g) {
@@ -165,6 +171,14 @@ __global__ __launch_bounds__(kRB) void k_hpsi(const V2<R>* __restrict__ psi, V2<
         }
     }
     lam[(uint64_t)b * bstride + j] = V2<R>{R(lr), R(li)};
+    if (epart) {
+        const V2<R> v0 = p[j];
+        e += (double)v0.x * lr + (double)v0.y * li;
+    }
+    }
+    if (epart) {   // uniform over the grid
+        const double t = block_sum(e, sh);
+        if (threadIdx.x == 0) epart[(uint64_t)b * gridDim.x + blockIdx.x] = t;
     }
 }
 
@@ -396,18 +410,23 @@ hipError_t launch_reduce(int dtype, int kind, const void* a, const void* b, uint
     return hipGetLastError();
 }
 
-hipError_t launch_hpsi(int dtype, const void* psi, void* lam, uint64_t bstride, int batch, int n,
-                       const PauliDev& pd, hipStream_t s) {
+uint64_t hpsi_blocks(int n) {
     const uint64_t N = 1ull << n;
     uint64_t gx = (N + kRB - 1) / kRB;
-    if (gx > (1u << 20)) gx = 1u << 20;
+    return gx > (1u << 20) ? (1u << 20) : gx;
+}
+
+hipError_t launch_hpsi(int dtype, const void* psi, void* lam, uint64_t bstride, int batch, int n,
+                       const PauliDev& pd, double* epart, hipStream_t s) {
+    const uint64_t N = 1ull << n;
+    const uint64_t gx = hpsi_blocks(n);
     const dim3 g((uint32_t)gx, (uint32_t)batch);
     if (dtype == 1)
         hipLaunchKernelGGL(k_hpsi<float>, g, dim3(kRB), 0, s, reinterpret_cast<const V2<float>*>(psi),
-                           reinterpret_cast<V2<float>*>(lam), bstride, N, pd);
+                           reinterpret_cast<V2<float>*>(lam), bstride, N, pd, epart);
     else
         hipLaunchKernelGGL(k_hpsi<double>, g, dim3(kRB), 0, s, reinterpret_cast<const V2<double>*>(psi),
-                           reinterpret_cast<V2<double>*>(lam), bstride, N, pd);
+                           reinterpret_cast<V2<double>*>(lam), bstride, N, pd, epart);
     return hipGetLastError();
 }
 
