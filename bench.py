@@ -385,15 +385,14 @@ def c128_leg(sv, W, torch, steps=2):
     s = sv.StateVector(n, torch.complex128, opts=sv.make_opts(timing=1))
     cabi = sv.CircuitABI(circ)
     s.init("zero_deferred")
-    st = s.apply(cabi)                                 # warm-up: plan, compile
-    s.norm()
+    st, _ = s.apply_norm(cabi)                         # warm-up: plan, compile
     s.timing()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         s.init("zero_deferred")
-        st = s.apply(cabi)
-        nrm = float(s.norm()[0])
+        st, nrm2 = s.apply_norm(cabi)
+        nrm = float(nrm2[0])
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     tile_ms, launches, tile_bytes = s.timing()
