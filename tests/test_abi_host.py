@@ -47,3 +47,20 @@ def test_host_only_calls_and_errors():
         m.plan_info(bad)
     assert e.value.status == 1
     assert m._lib.sv_version().decode()
+
+
+def test_null_arguments_are_rejected_without_a_device():
+    # argument validation happens before any device call, so these run on a
+    # host without a GPU
+    m = pytest.importorskip("paper_2008_00216_amd")
+    lib = m._lib
+    EINVAL = 1
+    d = ctypes.c_double()
+    u = ctypes.c_uint64()
+    assert lib.sv_sample(None, 1, ctypes.byref(d), ctypes.byref(u)) == EINVAL
+    assert b"ctx" in lib.sv_last_error()
+    assert lib.sv_amplitudes(None, 1, ctypes.byref(u), ctypes.byref(d)) == EINVAL
+    assert lib.sv_copy_state(None, None) == EINVAL
+    assert lib.sv_norm(None, ctypes.byref(d)) == EINVAL
+    assert lib.sv_apply_circuit_norm(None, None, None, ctypes.byref(d), None) == EINVAL
+    assert lib.sv_apply_circuit(None, None, None, None) == EINVAL
