@@ -251,6 +251,74 @@ __global__ __launch_bounds__(kRB) void k_tree2(const In* __restrict__ in, uint64
     }
 }
 
+// Levels 1 and 2 from complex64 amplitudes.  Each lane loads two adjacent
+// amplitudes (16 bytes), so one wave load covers groups 2k and 2k+1 (lanes
+// 0-31 and 32-63): a row sum (DPP within each 16-lane row) and two row
+// pairs give both group sums, half the reduction work of one 64-lane sum
+// per group.  Same node layout, launch shape and prefetch as k_tree2.
+__global__ __launch_bounds__(kRB) void k_tree2_c64(const V2<float>* __restrict__ in, uint64_t stride_in,
+                                                   uint64_t cnt_in, double* __restrict__ out1,
+                                                   double* __restrict__ out2) {
+    __shared__ double sh[64];
+    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    const uint32_t b = blockIdx.y;
+    const uint64_t cnt1 = cnt_in > 64 ? cnt_in >> 6 : 1, cnt2 = cnt1 > 64 ? cnt1 >> 6 : 1;
+    const uint64_t nstep = (cnt_in + 4095) / 4096;
+    const V2<float>* pin = in + (uint64_t)b * stride_in;
+    uint64_t step = blockIdx.x;
+    if (step >= nstep) return;   // block-uniform
+    auto load = [&](uint64_t st, u32x4 (&v)[8]) {
+        const uint64_t i0 = st * 4096 + (uint64_t)w * 1024 + 2u * lane;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint64_t i = i0 + (uint64_t)k * 128;   // even, so i + 1 < cnt_in when i < cnt_in
+            if (i < cnt_in) v[k] = *reinterpret_cast<const u32x4*>(pin + i);
+            else v[k] = u32x4{0u, 0u, 0u, 0u};
+        }
+    };
+    u32x4 v[8];
+    load(step, v);
+    for (; step < nstep; step += gridDim.x) {
+        double p[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const float x0 = __uint_as_float(v[k].x), y0 = __uint_as_float(v[k].y);
+            const float x1 = __uint_as_float(v[k].z), y1 = __uint_as_float(v[k].w);
+            double t = (double)x0 * (double)x0;
+            t = __builtin_fma((double)y0, (double)y0, t);
+            t = __builtin_fma((double)x1, (double)x1, t);
+            p[k] = __builtin_fma((double)y1, (double)y1, t);
+        }
+        const uint64_t nxt = step + gridDim.x;
+        if (nxt < nstep) load(nxt, v);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            double t = p[k];
+            t += dpp_f64<0xB1>(t);    // quad_perm [1,0,3,2]
+            t += dpp_f64<0x4E>(t);    // quad_perm [2,3,0,1]
+            t += dpp_f64<0x124>(t);   // row_ror:4
+            t += dpp_f64<0x128>(t);   // row_ror:8: every lane holds its row's sum
+            const double g0 = lane_f64(t, 0) + lane_f64(t, 16);
+            const double g1 = lane_f64(t, 32) + lane_f64(t, 48);
+            if (lane == 0) {
+                sh[w * 16 + 2 * k] = g0;
+                sh[w * 16 + 2 * k + 1] = g1;
+            }
+        }
+        __syncthreads();
+        if (w == 0) {
+            const double t = sh[lane];
+            const uint64_t node = step * 64 + lane;
+            if (node < cnt1) out1[(uint64_t)b * cnt1 + node] = t;
+            if (out2) {
+                const double t2 = wave_sum64(node < cnt1 ? t : 0.0);
+                if (lane == 0) out2[(uint64_t)b * cnt2 + step] = t2;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Inclusive prefix sum over the 64 lanes of a wave (FP64).
 __device__ __forceinline__ double wave_incl_scan(double v) {
     const uint32_t lane = threadIdx.x & 63u;
@@ -353,8 +421,8 @@ hipError_t launch_sample(int dtype, const void* a, uint64_t bstride, int batch, 
         double* o2 = k + 2 <= K ? lv[k + 2] : nullptr;
         if (k == 0) {
             if (dtype == 1)
-                hipLaunchKernelGGL(k_tree2<V2<float>>, g, dim3(kRB), 0, s, reinterpret_cast<const V2<float>*>(a),
-                                   bstride, cnt_in, lv[1], o2);
+                hipLaunchKernelGGL(k_tree2_c64, g, dim3(kRB), 0, s, reinterpret_cast<const V2<float>*>(a), bstride,
+                                   cnt_in, lv[1], o2);
             else
                 hipLaunchKernelGGL(k_tree2<V2<double>>, g, dim3(kRB), 0, s, reinterpret_cast<const V2<double>*>(a),
                                    bstride, cnt_in, lv[1], o2);
