@@ -79,11 +79,19 @@ struct PlanKeyed {
 std::mutex g_plan_mu;
 std::unordered_map<uint64_t, std::shared_ptr<PlanKeyed>> g_plans;
 
-// Pinned staging for the plan upload, grow-only and shared by batch calls;
-// a call holds g_stage_mu from packing until its stream has synchronised.
+// Pinned staging for the plan upload and the device work area of each
+// device (plans, pools, queues and reduction scratch), grow-only and shared
+// by batch calls; a call holds g_stage_mu from packing until its stream has
+// synchronised.  The largest work area of each device stays allocated for
+// later calls instead of being allocated and freed around every launch.
 std::mutex g_stage_mu;
 void* g_stage = nullptr;
 size_t g_stage_bytes = 0;
+struct DevArea {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+std::unordered_map<int, DevArea> g_dev;   // by device ordinal
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -112,10 +120,6 @@ std::shared_ptr<PlanKeyed> get_batch_plan(const sv_circuit* c, const std::vector
     return pk;
 }
 
-struct DevMem {
-    void* p = nullptr;
-    ~DevMem() { if (p) (void)hipFree(p); }
-};
 
 struct ItemHost {
     std::vector<IRGate> irf, irb;
@@ -381,12 +385,22 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
     const size_t upload = o;
     const size_t total = upload + so;
 
-    DevMem dm;
-    hipError_t he = hipMalloc(&dm.p, total);
-    if (he != hipSuccess) { err = std::string("hipMalloc: ") + hipGetErrorString(he); return SV_ENOMEM; }
-    unsigned char* D = reinterpret_cast<unsigned char*>(dm.p);
-    unsigned char* S = D + upload;   // scratch part
     std::unique_lock<std::mutex> stage_lock(g_stage_mu);
+    int dev = 0;
+    hipError_t he = hipGetDevice(&dev);
+    if (he != hipSuccess) { err = std::string("hipGetDevice: ") + hipGetErrorString(he); return SV_EDEVICE; }
+    DevArea& area = g_dev[dev];
+    if (area.bytes < total) {
+        // the previous call on this device has synchronised (it released the lock)
+        if (area.p) (void)hipFree(area.p);
+        area.p = nullptr;
+        area.bytes = 0;
+        he = hipMalloc(&area.p, total);
+        if (he != hipSuccess) { (void)hipGetLastError(); err = std::string("hipMalloc: ") + hipGetErrorString(he); return SV_ENOMEM; }
+        area.bytes = total;
+    }
+    unsigned char* D = reinterpret_cast<unsigned char*>(area.p);
+    unsigned char* S = D + upload;   // scratch part
     // every exit below waits for the stream, so the staging buffer is never
     // handed to the next call while an upload from it is in flight
     struct SyncOnExit {
@@ -484,7 +498,7 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
     put(o_items, bi.data(), bi.size() * sizeof(BItem));
     for (int ph = 0; ph < 2; ++ph) put(o_recs[ph], recs[ph].data(), recs[ph].size() * sizeof(BRec));
     put(o_tasks, tasks.data(), tasks.size() * sizeof(Task));
-    he = hipMemcpyAsync(dm.p, hp, upload, hipMemcpyHostToDevice, stream);
+    he = hipMemcpyAsync(area.p, hp, upload, hipMemcpyHostToDevice, stream);
     if (he != hipSuccess) { err = std::string("hipMemcpyAsync: ") + hipGetErrorString(he); return SV_EDEVICE; }
     int dev0 = 0, khz = 0, ncu = 0;
     (void)hipGetDevice(&dev0);
