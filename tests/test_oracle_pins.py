@@ -345,6 +345,10 @@ def test_generators_deterministic():
     c = W.ansatz_circuit()
     assert len(c.gates) == 590 and c.n_params == 400
     assert len(W.ansatz_observable()) == 39
+    u = W.sample_uniforms(1000, seed=3, batch=2)
+    assert u.shape == (2, 1000) and np.array_equal(u, W.sample_uniforms(1000, seed=3, batch=2))
+    assert float(u.min()) >= 0.0 and float(u.max()) < 1.0
+    assert len(W.grid_circuit(4, 8, 26, seed=1004).gates) == 1208
 
 
 # ------------------------------------------------------- measurement sampling
