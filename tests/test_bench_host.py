@@ -1,5 +1,6 @@
 """Host-side pieces of bench.py (no GPU): the gate categories of the
-runtime profile and the one-GPU guard."""
+runtime profile, the one-GPU guard and the gating of the recorded HBM
+traffic on the kernel sources and tile geometry it was counted for."""
 import subprocess
 import sys
 import os
@@ -47,3 +48,31 @@ def test_every_leg_main_calls_is_defined():
     builtins = set(dir(__builtins__)) if isinstance(__builtins__, dict) is False else set(__builtins__)
     missing = sorted(x for x in called - defined if x not in builtins and not hasattr(__import__("builtins"), x))
     assert not missing, missing
+
+
+def test_recorded_traffic_only_for_the_profiled_sources_and_geometry(tmp_path, monkeypatch):
+    prof = tmp_path / "p.md"
+    prof.write_text("traffic_bytes_per_launch: 123456789\n"
+                    "tile_geometry: 13 4 512\n"
+                    f"kernel_sources_sha256_16: {bench.kernel_sources_hash()}\n")
+    monkeypatch.setattr(bench, "PROFILE", str(prof))
+    assert bench.recorded_traffic(True, (13, 4, 512)) == 123456789.0
+    assert bench.recorded_traffic(True, (12, 4, 512)) is None     # other tile geometry
+    assert bench.recorded_traffic(False, (13, 4, 512)) is None    # other workload
+    prof.write_text(prof.read_text().replace(bench.kernel_sources_hash(), "0" * 16))
+    assert bench.recorded_traffic(True, (13, 4, 512)) is None     # sources changed since the counters
+
+
+def test_committed_traffic_summary_is_close_to_the_algorithmic_bytes():
+    # One launch reads and writes the 2^33-amplitude complex64 state, except
+    # the first pass of the 22, which only writes it.
+    vals = {}
+    for line in open(bench.PROFILE):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    traffic = float(vals["traffic_bytes_per_launch"])
+    algorithmic = (2 ** 33 * 8) * (2 * 21 + 1) / 22
+    assert abs(traffic / algorithmic - 1) < 0.01
+    assert len(vals["kernel_sources_sha256_16"]) == 16
+    assert vals["tile_geometry"].split() == ["13", "4", "512"]
