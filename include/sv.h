@@ -120,7 +120,10 @@ typedef struct {
     int32_t timing;        /* 1 = time every tile-pass launch with HIP events (sv_timing) */
     int32_t jit;           /* run-time specialised tile passes: 0 auto (batch * 2^n >= 2^24),
                               1 always, -1 never */
-    int32_t reserved[3];
+    int32_t max_work_mib;  /* cap, in MiB, on the device memory the library allocates for a context
+                              (plans, pools, reduction and sampling scratch) or a batch call's work
+                              area; 0 = no cap.  A call that would exceed it returns SV_ENOMEM */
+    int32_t reserved[2];
 } sv_opts;
 
 typedef struct {
@@ -148,14 +151,20 @@ enum { SV_INIT_ZERO = 0, SV_INIT_BASIS = 1, SV_INIT_UNIFORM = 2, SV_INIT_ZERO_DE
 /* Fill *opts with the defaults. */
 void sv_opts_default(sv_opts* opts);
 
-/* Create a context over caller-owned device memory.
+/* Create a context over caller-owned device memory holding the state of
+ * Sec. 2: n qubits described by 2^n complex amplitudes, amplitude j at
+ * element j (qubit q = bit q of j), stored in place and kept whole for the
+ * lifetime of the context (the strong simulation of Sec. 3).
  *   n_qubits   1..34 (SV_C64) or 1..33 (SV_C128)
- *   batch      number of states (>= 1) stored back to back in d_state
- *   d_state    device pointer, 16-byte (c64) / 32-byte (c128) aligned
+ *   batch      number of states (>= 1, <= 65535) stored back to back in d_state
+ *   d_state    device pointer, 16-byte aligned; borrowed, never freed
  *   state_bytes must equal batch * 2^n * bytes-per-amplitude
  *   hip_stream hipStream_t to launch on (NULL = default stream)
- *   opts       NULL = defaults
- * Errors: SV_EINVAL on bad sizes/alignment/null pointers, SV_ENOMEM. */
+ *   opts       NULL = defaults (copied)
+ * The context itself is host memory owned by the library (sv_destroy).
+ * Errors: SV_EINVAL for a NULL out or d_state, n or batch out of range, a
+ * wrong state_bytes, misalignment or out-of-range options (nothing is
+ * created); SV_ENOMEM; SV_EDEVICE when the device cannot be configured. */
 sv_status sv_create(sv_ctx* out, int32_t n_qubits, sv_dtype dtype, int32_t batch,
                     void* d_state, size_t state_bytes, void* hip_stream, const sv_opts* opts);
 sv_status sv_destroy(sv_ctx ctx);
@@ -169,14 +178,30 @@ sv_status sv_set_opts(sv_ctx ctx, const sv_opts* opts);
  * state writes it first, unless the next sweep starts with one-qubit gates
  * that are folded into a product-state initialisation (then the state is
  * written once).  Reading the buffer directly before such a call sees stale
- * data. */
+ * data, and a caller's write to it in between is ignored.  After every other
+ * kind the buffer's content is the input of the next sweep, caller writes
+ * included (no folding). */
 sv_status sv_init(sv_ctx ctx, int32_t kind, uint64_t basis_index);
 
-/* Apply a circuit to every state of the batch.  params: host FP64 array of
- * batch * n_params values (row b = state b), may be NULL when the circuit has
- * no parameterised gates.  stats may be NULL.  Gates are validated (qubit
- * range and distinctness, nq <= 6, op codes, param < n_params, matrix range)
- * before any kernel is launched. */
+/* Apply a circuit to every state of the batch, in place: psi <- U_G ... U_1
+ * psi, where each gate updates every one of the 2^{n-k} disjoint sets of
+ * 2^k amplitudes whose indices differ only in the gate's k qubits (Sec. 3,
+ * fast Schroedinger simulation).  Gates are reordered only where they
+ * commute and clustered into tile passes (Sec. 4.2, 4.5), diagonal phases
+ * are consolidated (Sec. 4.3) and the H / sqrt(X) / sqrt(Y) family runs as
+ * multiply-free butterflies (Sec. 4.4); the result differs from the gate by
+ * gate product only by rounding.
+ *   circuit  host, read during the call; n_qubits must equal the context's
+ *   params   host FP64, batch * n_params values (row b = state b); may be
+ *            NULL when no gate is parameterised
+ *   stats    host, may be NULL: passes, launches, plan time, algorithmic
+ *            bytes, flops and ALU instructions
+ * Asynchronous on the context's stream (plans are uploaded synchronously).
+ * Errors (before any kernel, state untouched): SV_EINVAL for an unknown op,
+ * nq outside 1..6 or not the op's arity, a qubit out of range or repeated,
+ * param >= n_params, a matrix offset outside mats, NULL or non-finite
+ * params; SV_ENOMEM when a work area cannot be allocated (or exceeds
+ * max_work_mib); SV_EUNSUPPORTED when planning fails. */
 sv_status sv_apply_circuit(sv_ctx ctx, const sv_circuit* circuit, const double* params,
                            sv_stats* stats);
 
@@ -190,8 +215,16 @@ sv_status sv_apply_circuit(sv_ctx ctx, const sv_circuit* circuit, const double* 
 sv_status sv_apply_circuit_norm(sv_ctx ctx, const sv_circuit* circuit, const double* params,
                                 double* norm2_out, sv_stats* stats);
 
-/* out[b] = sum_k coeff_k Re <psi_b|P_k|psi_b>, accumulated in FP64 on the
- * device with a fixed reduction order.  Synchronises the stream. */
+/* Expectation of a Pauli sum: out[b] = sum_k coeff_k Re <psi_b|P_k|psi_b>.
+ * Every amplitude product is formed and summed in FP64 on the device
+ * (the FP64 accumulation the norm check of Sec. 4.1 calls for a float
+ * state), over a fixed grid and a fixed tree, so results repeat bit for
+ * bit.  Terms that share an x mask share one read of the state.
+ *   obs  host arrays of n_terms entries; masks must lie inside the register
+ *   out  host, batch doubles
+ * Synchronises the stream.  Errors: SV_EINVAL for NULL pointers, masks
+ * outside the register or a non-finite coefficient (nothing launched);
+ * SV_ENOMEM; SV_EDEVICE from earlier asynchronous work. */
 sv_status sv_expect(sv_ctx ctx, const sv_pauli_sum* obs, double* out);
 
 /* Copies the states of src into dst (a snapshot, or a branch point for two
@@ -233,13 +266,20 @@ sv_status sv_sample(sv_ctx ctx, int64_t count, const double* uniforms, uint64_t*
 sv_status sv_amplitudes(sv_ctx ctx, int64_t count, const uint64_t* indices, double* out);
 
 /* Adjoint gradient of E_b = <psi_b|H|psi_b> with psi_b = U(theta_b) psi_b^in,
- * where psi_b^in is the current state.  Runs the forward sweep, forms
- * lambda = H psi in d_scratch (caller-owned, >= state_bytes), then sweeps
- * back through the gates, un-computing both vectors and accumulating
+ * where psi_b^in is the current state.  Not in the paper: this is the
+ * published adjoint-differentiation method for expectation values (Jones and
+ * Gacon, 2020, arXiv:2009.02823) built on the paper's sweep.  Runs the
+ * forward sweep (as sv_apply_circuit), forms lambda = H psi in d_scratch,
+ * then sweeps back through the gates, un-computing both vectors with the
+ * inverse gates instead of storing intermediate states, and accumulates
  * grad[p] = sum over gates l using p of Im <lambda_l|G_l|psi_l> (G_l the
- * generator of exp(-i theta G_l / 2)) in FP64.
- * energy_out: host, batch values; grad_out: host, batch * n_params values.
- * On return the state holds U^dagger U psi^in (psi^in up to rounding). */
+ * generator of exp(-i theta G_l / 2)) with FP64 reductions.
+ *   d_scratch   device, caller-owned, >= state_bytes, 16-byte aligned: lambda
+ *   energy_out  host, batch values
+ *   grad_out    host, batch * n_params values (row b = state b)
+ * On return the state holds U^dagger U psi^in (psi^in up to rounding).
+ * Synchronises.  Errors: those of sv_apply_circuit and sv_expect, and
+ * SV_EINVAL for a NULL or too small d_scratch or NULL outputs. */
 sv_status sv_adjoint_grad(sv_ctx ctx, const sv_circuit* circuit, const double* params,
                           const sv_pauli_sum* obs, void* d_scratch, size_t scratch_bytes,
                           double* energy_out, double* grad_out, sv_stats* stats);
@@ -255,12 +295,25 @@ typedef struct {
 
 enum { SV_BATCH_FORWARD = 1, SV_BATCH_GRAD = 2, SV_BATCH_INIT_ZERO = 4 };
 
-/* Heterogeneous batch in ONE persistent kernel launch: every item's forward
- * sweep (and, with SV_BATCH_GRAD, its adjoint gradient) is executed by a
- * grid of resident workgroups pulling (item, pass, tile) work from a device
- * queue.  energies: host, count values; grads: host, concatenation of every
- * item's n_params gradients (may be NULL without SV_BATCH_GRAD).
- * Synchronises the stream. */
+/* Heterogeneous batch: many circuits of different widths, each swept as by
+ * sv_apply_circuit (Sec. 3 with the planning of Sec. 4) and, with
+ * SV_BATCH_GRAD, differentiated as by sv_adjoint_grad (adjoint method of
+ * Jones and Gacon, arXiv:2009.02823).  Not in the paper: one persistent
+ * kernel launch per direction runs every item -- resident workgroups pull
+ * (item, pass, tile) work from per-XCD device queues, and a tile waits only
+ * for the tiles of its own item's previous pass.  Circuits of at most 12
+ * qubits are one tile (the whole state in LDS for the whole circuit).
+ *   items     host, count entries; states and lambdas device, 16-byte aligned
+ *   dtype     of every state
+ *   flags     SV_BATCH_FORWARD or SV_BATCH_GRAD, | SV_BATCH_INIT_ZERO to start
+ *             every state at |0..0> (else the buffers hold the inputs)
+ *   energies  host, count values (needs observables)
+ *   grads     host, concatenation of every item's n_params gradients (may be
+ *             NULL without SV_BATCH_GRAD)
+ *   opts      tile geometry and fusion; NULL = defaults
+ * The library keeps a grow-only device work area per device across calls.
+ * Synchronises the stream.  Errors: SV_EINVAL for a NULL or invalid item
+ * (as sv_apply_circuit), SV_ENOMEM (including max_work_mib), SV_EDEVICE. */
 sv_status sv_apply_batch(int32_t count, const sv_batch_item* items, sv_dtype dtype,
                          void* hip_stream, int32_t flags, double* energies, double* grads,
                          const sv_opts* opts, sv_stats* stats);

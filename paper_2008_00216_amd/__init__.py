@@ -67,7 +67,8 @@ class SvOpts(ctypes.Structure):
     _fields_ = [("max_fuse_k", ctypes.c_int32), ("tile_bits", ctypes.c_int32),
                 ("low_bits", ctypes.c_int32), ("plain", ctypes.c_int32), ("threads", ctypes.c_int32),
                 ("product_init", ctypes.c_int32), ("structured", ctypes.c_int32),
-                ("timing", ctypes.c_int32), ("jit", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("timing", ctypes.c_int32), ("jit", ctypes.c_int32), ("max_work_mib", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class SvStats(ctypes.Structure):
@@ -448,7 +449,12 @@ class Energy(torch.autograd.Function):
     @staticmethod
     def forward(ctx, theta, sv: StateVector, circ, pauli):
         th = theta.detach().cpu().numpy().astype(np.float64)
-        sv.init("zero")
+        if not ctx.needs_input_grad[0]:
+            # forward only: one sweep and the FP64 expectation, no adjoint
+            sv.init("zero_deferred")
+            sv.apply(circ, th)
+            return torch.from_numpy(sv.expect(pauli))
+        sv.init("zero_deferred")
         e, g = sv.adjoint_grad(circ, th, pauli)
         ctx.save_for_backward(torch.from_numpy(g))
         return torch.from_numpy(e)

@@ -106,8 +106,13 @@ PlanCfg batch_cfg(int dtype, bool two, int n) {
     return p;
 }
 
-std::shared_ptr<PlanKeyed> get_batch_plan(const sv_circuit* c, const std::vector<IRGate>& ir, int dtype, bool two) {
-    const uint64_t key = circuit_hash(c, 0x9e3779b97f4a7c15ull ^ ((uint64_t)dtype << 8) ^ ((uint64_t)two << 12));
+// Plans are cached by circuit structure, dtype, direction, the IR options
+// (structured, fusion width) and the value-dependent decisions of the IR.
+std::shared_ptr<PlanKeyed> get_batch_plan(const sv_circuit* c, const std::vector<IRGate>& ir, int dtype, bool two,
+                                          const BuildOpts& bo) {
+    const uint64_t key = circuit_hash(c, 0x9e3779b97f4a7c15ull ^ ((uint64_t)dtype << 8) ^ ((uint64_t)two << 12) ^
+                                             ((uint64_t)bo.structured << 16) ^ ((uint64_t)(uint32_t)bo.fuse_k << 20) ^
+                                             ir_signature(ir));
     {
         std::lock_guard<std::mutex> lk(g_plan_mu);
         auto it = g_plans.find(key);
@@ -180,12 +185,12 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
                         bo.fuse_k = opts ? opts->max_fuse_k : 4;
                         bo.product_init = false;
                         H[i].irf = build_ir(it.circuit, it.params, bo, nullptr, it.circuit->n_qubits);
-                        H[i].pf = get_batch_plan(it.circuit, H[i].irf, dtype, false);
+                        H[i].pf = get_batch_plan(it.circuit, H[i].irf, dtype, false, bo);
                         fill_pool(H[i].pf->ep, H[i].irf, 1, H[i].poolf);
                         if (grad) {
                             bo.backward = true;
                             H[i].irb = build_ir(it.circuit, it.params, bo, nullptr, it.circuit->n_qubits);
-                            H[i].pb = get_batch_plan(it.circuit, H[i].irb, dtype, true);
+                            H[i].pb = get_batch_plan(it.circuit, H[i].irb, dtype, true, bo);
                             fill_pool(H[i].pb->ep, H[i].irb, 1, H[i].poolb);
                         }
                     } catch (const std::exception& e) {
@@ -384,6 +389,11 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
     const size_t o_tasks = take(((size_t)count * 64 + 16) * sizeof(Task));
     const size_t upload = o;
     const size_t total = upload + so;
+    if (opts && opts->max_work_mib > 0 && total > ((size_t)opts->max_work_mib << 20)) {
+        err = "the batch work area needs " + std::to_string(total) + " bytes, above max_work_mib = " +
+              std::to_string(opts->max_work_mib) + " MiB";
+        return SV_ENOMEM;
+    }
 
     std::unique_lock<std::mutex> stage_lock(g_stage_mu);
     int dev = 0;

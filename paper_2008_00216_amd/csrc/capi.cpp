@@ -49,16 +49,33 @@ sv_status fail(sv_status st, const std::string& msg) {
         }                                                                                    \
     } while (0)
 
+// Device memory the library allocates for one context (plans, pools,
+// reduction and sampling scratch), with an optional cap (sv_opts.max_work_mib).
+struct WorkAcct {
+    size_t used = 0;
+    size_t cap = 0;      // 0 = no cap
+};
+
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
-    ~DevBuf() { if (p) (void)hipFree(p); }
+    WorkAcct* acct = nullptr;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        if (acct) acct->used -= bytes;
+        p = nullptr;
+        bytes = 0;
+    }
     hipError_t ensure(size_t need) {
         if (need <= bytes) return hipSuccess;
-        if (p) { (void)hipFree(p); p = nullptr; bytes = 0; }
+        if (acct && acct->cap && acct->used - bytes + need > acct->cap) return hipErrorOutOfMemory;
+        release();
         hipError_t e = hipMalloc(&p, need);
-        if (e == hipSuccess) bytes = need;
-        return e;
+        if (e != hipSuccess) { p = nullptr; return e; }
+        bytes = need;
+        if (acct) acct->used += need;
+        return hipSuccess;
     }
 };
 
@@ -110,10 +127,16 @@ struct sv_ctx_s {
     sv_opts opts{};
     bool known_zero = false;
     bool zero_pending = false;   // |0..0> requested but not yet written
+    WorkAcct acct;               // declared before every DevBuf: outlives them
     std::unordered_map<uint64_t, std::unique_ptr<CachedPlan>> cache;
     DevBuf pool, red_part, red_out, pauli, gpart, gout, pinit;
     DevBuf smp_tree, smp_u, smp_out;   // sampling and amplitude readout
     DevBuf npart;                      // FP64 partials: the last pass's norm, the adjoint energy
+    sv_ctx_s() {
+        for (DevBuf* b : {&pool, &red_part, &red_out, &pauli, &gpart, &gout, &pinit, &smp_tree, &smp_u, &smp_out,
+                          &npart})
+            b->acct = &acct;
+    }
     std::vector<unsigned char> pool_host;
     std::vector<double> host_out;
     // tile-pass timing (opts.timing)
@@ -180,7 +203,7 @@ sv_status get_plan(sv_ctx_s* c, const sv_circuit* circ, const double* params, bo
     } catch (const std::exception& e) {
         return fail(SV_EINVAL, std::string("IR build failed: ") + e.what());
     }
-    const uint64_t key = circuit_hash(circ, opts_key(c, two, bo.product_init));
+    const uint64_t key = circuit_hash(circ, opts_key(c, two, bo.product_init) ^ ir_signature(ir));
     auto it = c->cache.find(key);
     plan_ms = 0.0;
     if (it != c->cache.end()) {
@@ -189,6 +212,7 @@ sv_status get_plan(sv_ctx_s* c, const sv_circuit* circ, const double* params, bo
     }
     auto t0 = std::chrono::steady_clock::now();
     auto cp = std::make_unique<CachedPlan>();
+    cp->dev.acct = &c->acct;
     try {
         if (use_plain(c)) plan_plain(ir, c->n, cfg_for(c, two), cp->ep);
         else plan_fused(ir, c->n, cfg_for(c, two), cp->ep);
@@ -386,7 +410,15 @@ void fill_stats(sv_stats* st, const sv_ctx_s* c, const CachedPlan& cp, const sv_
     if (init_fused) st->alu_ops += 6.0 * N;
 }
 
-sv_status upload_pauli(sv_ctx_s* c, const sv_pauli_sum* h, PauliDev& pd) {
+// Pauli tables in the device layout: distinct x masks, the first term of
+// each x group, then per term the z mask, coefficient and i^{|x&z|} exponent.
+struct PauliPack {
+    std::vector<unsigned char> buf;
+    size_t ox = 0, og = 0, oz = 0, oc = 0, oph = 0;
+    uint32_t ng = 0;
+};
+
+sv_status pack_pauli(const sv_ctx_s* c, const sv_pauli_sum* h, PauliPack& pk) {
     if (!h || h->n_terms < 0) return fail(SV_EINVAL, "observable is NULL or has n_terms < 0");
     if (h->n_terms > 0 && (!h->coeff || !h->x_mask || !h->z_mask)) return fail(SV_EINVAL, "observable arrays are NULL");
     const uint64_t qm = c->n >= 64 ? ~0ull : ((1ull << c->n) - 1ull);
@@ -414,24 +446,42 @@ sv_status upload_pauli(sv_ctx_s* c, const sv_pauli_sum* h, PauliDev& pd) {
         }
     }
     g0.push_back((uint32_t)z.size());
-    const size_t ox = 0, og = align_up(ox + ng * 8, 64), oz = align_up(og + (ng + 1) * 4, 64),
-                 oc = align_up(oz + nt * 8, 64), oph = align_up(oc + nt * 8, 64), tot = align_up(oph + nt * 4 + 64, 64);
-    std::vector<unsigned char> buf(tot, 0);
-    std::memcpy(buf.data() + ox, xs.data(), ng * 8);
-    std::memcpy(buf.data() + og, g0.data(), (ng + 1) * 4);
-    std::memcpy(buf.data() + oz, z.data(), nt * 8);
-    std::memcpy(buf.data() + oc, cf.data(), nt * 8);
-    std::memcpy(buf.data() + oph, ph.data(), nt * 4);
-    HIPCHK(c->pauli.ensure(tot));
-    HIPCHK(hipMemcpyAsync(c->pauli.p, buf.data(), tot, hipMemcpyHostToDevice, c->stream));
+    pk.ox = 0;
+    pk.og = align_up(pk.ox + ng * 8, 64);
+    pk.oz = align_up(pk.og + (ng + 1) * 4, 64);
+    pk.oc = align_up(pk.oz + nt * 8, 64);
+    pk.oph = align_up(pk.oc + nt * 8, 64);
+    const size_t tot = align_up(pk.oph + nt * 4 + 64, 64);
+    pk.buf.assign(tot, 0);
+    std::memcpy(pk.buf.data() + pk.ox, xs.data(), ng * 8);
+    std::memcpy(pk.buf.data() + pk.og, g0.data(), (ng + 1) * 4);
+    std::memcpy(pk.buf.data() + pk.oz, z.data(), nt * 8);
+    std::memcpy(pk.buf.data() + pk.oc, cf.data(), nt * 8);
+    std::memcpy(pk.buf.data() + pk.oph, ph.data(), nt * 4);
+    pk.ng = (uint32_t)ng;
+    return SV_OK;
+}
+
+// Device view of packed tables copied to d.
+PauliDev pauli_at(const PauliPack& pk, unsigned char* d) {
+    PauliDev pd{};
+    pd.x = reinterpret_cast<const uint64_t*>(d + pk.ox);
+    pd.g0 = reinterpret_cast<const uint32_t*>(d + pk.og);
+    pd.z = reinterpret_cast<const uint64_t*>(d + pk.oz);
+    pd.c = reinterpret_cast<const double*>(d + pk.oc);
+    pd.ph = reinterpret_cast<const uint32_t*>(d + pk.oph);
+    pd.ngroup = pk.ng;
+    return pd;
+}
+
+sv_status upload_pauli(sv_ctx_s* c, const sv_pauli_sum* h, PauliDev& pd) {
+    PauliPack pk;
+    sv_status st = pack_pauli(c, h, pk);
+    if (st != SV_OK) return st;
+    HIPCHK(c->pauli.ensure(pk.buf.size()));
+    HIPCHK(hipMemcpyAsync(c->pauli.p, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    unsigned char* d = reinterpret_cast<unsigned char*>(c->pauli.p);
-    pd.x = reinterpret_cast<const uint64_t*>(d + ox);
-    pd.g0 = reinterpret_cast<const uint32_t*>(d + og);
-    pd.z = reinterpret_cast<const uint64_t*>(d + oz);
-    pd.c = reinterpret_cast<const double*>(d + oc);
-    pd.ph = reinterpret_cast<const uint32_t*>(d + oph);
-    pd.ngroup = (uint32_t)ng;
+    pd = pauli_at(pk, reinterpret_cast<unsigned char*>(c->pauli.p));
     return SV_OK;
 }
 
@@ -515,8 +565,7 @@ sv_status sv_create(sv_ctx* out, int32_t n, sv_dtype dt, int32_t batch, void* d_
     if (batch < 1 || batch > 65535) return fail(SV_EINVAL, "batch must be in [1, 65535]");
     if (!d_state) return fail(SV_EINVAL, "d_state is NULL");
     const size_t ab = amp_bytes(dt);
-    if (((uintptr_t)d_state) % (2 * ab / 1) % ab != 0 || ((uintptr_t)d_state % 16) != 0)
-        return fail(SV_EINVAL, "d_state must be 16-byte aligned");
+    if ((uintptr_t)d_state % 16 != 0) return fail(SV_EINVAL, "d_state must be 16-byte aligned");
     const size_t need = (size_t)batch * ((size_t)1 << n) * ab;
     if (state_bytes != need) {
         std::ostringstream s;
@@ -532,6 +581,8 @@ sv_status sv_create(sv_ctx* out, int32_t n, sv_dtype dt, int32_t batch, void* d_
     c->state_bytes = state_bytes;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     if (opts) c->opts = *opts; else sv_opts_default(&c->opts);
+    if (c->opts.max_work_mib < 0) { delete c; return fail(SV_EINVAL, "max_work_mib must be >= 0"); }
+    c->acct.cap = (size_t)c->opts.max_work_mib << 20;
     if (c->opts.max_fuse_k < 0 || c->opts.max_fuse_k > 6) { delete c; return fail(SV_EINVAL, "max_fuse_k must be 0..6"); }
     if (c->opts.tile_bits < 0 || c->opts.tile_bits > kMaxTileBits) { delete c; return fail(SV_EINVAL, "tile_bits must be 0..14"); }
     static std::once_flag once;
@@ -562,8 +613,10 @@ sv_status sv_set_opts(sv_ctx c, const sv_opts* o) {
     if (!c || !o) return fail(SV_EINVAL, "ctx or opts is NULL");
     if (o->max_fuse_k < 0 || o->max_fuse_k > 6) return fail(SV_EINVAL, "max_fuse_k must be 0..6");
     if (o->tile_bits < 0 || o->tile_bits > kMaxTileBits) return fail(SV_EINVAL, "tile_bits must be 0..14");
+    if (o->max_work_mib < 0) return fail(SV_EINVAL, "max_work_mib must be >= 0");
     c->opts = *o;
     c->cache.clear();
+    c->acct.cap = (size_t)o->max_work_mib << 20;
     return SV_OK;
 }
 
@@ -581,7 +634,10 @@ sv_status sv_init(sv_ctx c, int32_t kind, uint64_t basis_index) {
     c->zero_pending = false;
     HIPCHK(launch_init(c->dtype, c->state, 1ull << c->n, c->batch, c->n, kind == SV_INIT_UNIFORM ? 2 : 1,
                        kind == SV_INIT_ZERO ? 0 : basis_index, v, c->stream));
-    c->known_zero = kind == SV_INIT_ZERO;
+    // Only SV_INIT_ZERO_DEFERRED lets the next sweep fold leading gates into
+    // a product state computed without reading the buffer: after any other
+    // init the buffer is the truth, caller writes to it included.
+    c->known_zero = false;
     return SV_OK;
 }
 

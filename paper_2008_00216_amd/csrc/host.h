@@ -82,6 +82,12 @@ std::vector<IRGate> fuse_blocks(std::vector<IRGate>&& in, int kmax, int n);
 // Structural hash of a circuit for the plan cache.
 uint64_t circuit_hash(const sv_circuit* c, uint64_t seed);
 
+// Hash of the value-dependent planning decisions of an IR list (real
+// matrices, unit diagonals, gate kinds); combined with circuit_hash in every
+// plan-cache key, so that new angles or matrices never reuse a plan made for
+// values that decided differently.
+uint64_t ir_signature(const std::vector<IRGate>& ir);
+
 // ----------------------------------------------------------------- planning
 
 struct PlanCfg {

@@ -223,6 +223,39 @@ uint64_t circuit_hash(const sv_circuit* c, uint64_t seed) {
     return h;
 }
 
+// Signature of the value-dependent planning decisions of an IR list: the
+// kind, structure and flags of every gate, whether its matrix is real, and
+// for a general diagonal whether every entry but the last is 1 (the masked
+// form of the plain sweep).  Two calls whose circuits have the same structure
+// but values that change any of these decisions get different plans.
+uint64_t ir_signature(const std::vector<IRGate>& ir) {
+    uint64_t h = 0x243f6a8885a308d3ull;
+    auto mix = [&](uint64_t v) {
+        for (int i = 0; i < 8; ++i) {
+            h ^= (v >> (8 * i)) & 255u;
+            h *= 1099511628211ull;
+        }
+    };
+    mix(ir.size());
+    for (const IRGate& g : ir) {
+        bool unit = false;
+        if (g.kind == K_DIAGG) {
+            unit = true;
+            for (int b = 0; b < g.m.nb && unit; ++b)
+                for (int i = 0; i + 1 < g.m.d; ++i)
+                    if (g.m.at(b)[i] != cd(1.0, 0.0)) { unit = false; break; }
+        }
+        mix((uint64_t)g.kind | ((uint64_t)g.k << 4) | ((uint64_t)g.skind << 8) | ((uint64_t)g.perm << 16) |
+            ((uint64_t)real_gate(g) << 20) | ((uint64_t)unit << 21) | ((uint64_t)g.grad << 22) |
+            ((uint64_t)g.m.diag << 23) | ((uint64_t)(g.m.nb > 1) << 24) | ((uint64_t)(uint32_t)g.gen << 28) |
+            ((uint64_t)(uint32_t)g.param << 32));
+        mix((uint64_t)(g.alpha[0] & 7) | ((uint64_t)(g.alpha[1] & 7) << 3) | ((uint64_t)(g.beta & 7) << 6) |
+            ((uint64_t)(g.bf_pre & 7) << 9) | ((uint64_t)(g.bf_post & 7) << 12) | ((uint64_t)(g.bf_g & 7) << 15));
+        for (int t = 0; t < g.k; ++t) mix((uint64_t)g.q[t]);
+    }
+    return h;
+}
+
 namespace {
 
 int gen_of(int op) {

@@ -88,6 +88,11 @@ def test_autograd_function():
     for b in range(2):
         g_ref = oracle.grad_param_shift(c, th.detach().numpy()[b], h)
         np.testing.assert_allclose(th.grad.numpy()[b], g_ref, atol=1e-10)
+    # without a gradient request the forward runs one sweep and the expectation
+    e2 = m.Energy.apply(th.detach(), s, c, h)
+    for b in range(2):
+        assert abs(float(e2[b]) - oracle.energy(c, th.detach().numpy()[b], h)) < 1e-10
+        assert abs(float(e2[b]) - float(e[b])) < 1e-10
 
 
 @pytest.mark.parametrize("jit", [-1, 1])

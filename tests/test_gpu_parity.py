@@ -228,11 +228,26 @@ def test_grid_product_init(dtype):
     ref = oracle.simulate(c)
     m = lib()
     s = m.StateVector(c.n, dtype)
-    s.init("zero")
+    s.init("zero_deferred")
     st = s.apply(c)
     got = to_host(s.tensor)[0]
     check_close(got, ref, dtype, "grid 20q")
     assert st["folded_init"] >= c.n
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_written_zero_is_read(dtype):
+    """After a written |0..0> the buffer is the input: a caller's write
+    through the tensor is honoured (no product-state folding)."""
+    c = W.grid_circuit(2, 4, 3, seed=5)
+    m = lib()
+    s = m.StateVector(c.n, dtype)
+    s.init("zero")
+    psi0 = round_c64(W.random_state(c.n, 77))
+    s.tensor.copy_(torch.from_numpy(psi0.astype(np.complex128)).to(s.tensor.dtype).reshape(1, -1).to(s.tensor.device))
+    st = s.apply(c)
+    assert st["folded_init"] == 0
+    check_close(to_host(s.tensor)[0], oracle.simulate(c, None, psi0), dtype, "caller-written input")
 
 
 @pytest.mark.parametrize("dtype", DTYPES)

@@ -276,6 +276,35 @@ def test_norm2_compensated_is_exact():
     assert oracle.norm2(psi) == pytest.approx(exact, rel=1e-16, abs=0)
 
 
+def test_inner_compensated_is_exact():
+    # <a|b> = sum_j conj(a_j) b_j.  Per amplitude the four components share a
+    # power of two and have 12-bit integer mantissas, so p r + q s and
+    # p s - q r are exact in FP64 (with or without contraction); the
+    # exponents span 2^-70 .. 2^0, where the order of a plain sum matters.
+    # The compensated sum must equal the exactly rounded sum (math.fsum).
+    rng = np.random.default_rng(1)
+    n = 13
+    N = 1 << n
+    e = rng.integers(-35, 1, N).astype(np.float64)
+    m = rng.integers(-2048, 2049, (4, N)).astype(np.float64)
+    sc = np.exp2(e)
+    p, q, r, s = (m[i] * sc for i in range(4))
+    a = p + 1j * q
+    b = r + 1j * s
+    want_re = math.fsum((p * r + q * s).tolist())
+    want_im = math.fsum((p * s - q * r).tolist())
+    got = oracle.inner(a, b, nthreads=1)
+    assert got.real == want_re and got.imag == want_im
+    got8 = oracle.inner(a, b)
+    assert got8.real == pytest.approx(want_re, rel=1e-16, abs=0)
+    assert got8.imag == pytest.approx(want_im, rel=1e-16, abs=0)
+    # conjugate-linear in the first argument, as np.vdot
+    x = W.random_state(6, 3)
+    y = W.random_state(6, 4)
+    assert abs(oracle.inner(x, y) - np.vdot(x, y)) < 1e-15
+    assert abs(oracle.inner(1j * x, y) - (-1j) * np.vdot(x, y)) < 1e-15
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_expectation_matches_explicit_pauli(seed):
     n = 5
