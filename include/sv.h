@@ -227,6 +227,21 @@ sv_status sv_apply_circuit_norm(sv_ctx ctx, const sv_circuit* circuit, const dou
  * SV_ENOMEM; SV_EDEVICE from earlier asynchronous work. */
 sv_status sv_expect(sv_ctx ctx, const sv_pauli_sum* obs, double* out);
 
+/* sv_expect for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same result as sv_expect, bit for bit, but the
+ * library allocates nothing.  Its Pauli tables, block partials and results
+ * live in a fixed per-device work area of 4 MiB (a file-scope device array
+ * that each GPU holds until the process ends); a call needs about
+ * 24 bytes per Pauli term + 8 * batch * min(8192, 2^n / 2048) + 8 * batch
+ * bytes of it and fails with SV_EINVAL, before any device work, when that
+ * exceeds 4 MiB.  Every call on one GPU shares that area and leaves its
+ * contents behind: calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller.  Synchronises the
+ * stream.  Errors: those of sv_expect, and SV_EINVAL when the work area is
+ * too small. */
+sv_status sv_expect_noalloc(sv_ctx ctx, const sv_pauli_sum* obs, double* out);
+
 /* Copies the states of src into dst (a snapshot, or a branch point for two
  * continuations of one simulation).  Both contexts must have the same
  * width, dtype and batch, and disjoint state buffers.  Enqueued on dst's

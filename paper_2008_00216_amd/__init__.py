@@ -101,6 +101,7 @@ _lib.sv_set_opts.argtypes = [_vp, ctypes.POINTER(SvOpts)]
 _lib.sv_init.argtypes = [_vp, ctypes.c_int32, ctypes.c_uint64]
 _lib.sv_apply_circuit.argtypes = [_vp, ctypes.POINTER(SvCircuit), _dp, ctypes.POINTER(SvStats)]
 _lib.sv_expect.argtypes = [_vp, ctypes.POINTER(SvPauliSum), _dp]
+_lib.sv_expect_noalloc.argtypes = [_vp, ctypes.POINTER(SvPauliSum), _dp]
 _lib.sv_norm.argtypes = [_vp, _dp]
 _lib.sv_apply_circuit_norm.argtypes = [_vp, ctypes.POINTER(SvCircuit), _dp, _dp, ctypes.POINTER(SvStats)]
 _lib.sv_copy_state.argtypes = [_vp, _vp]
@@ -118,13 +119,13 @@ _lib.sv_tune.argtypes = [_vp, ctypes.POINTER(SvCircuit), _dp, ctypes.POINTER(SvO
 _lib.sv_plan_trace.argtypes = [ctypes.POINTER(SvCircuit), _dp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(SvOpts),
                                ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
 for _f in ("sv_create", "sv_destroy", "sv_set_stream", "sv_set_opts", "sv_init", "sv_apply_circuit",
-           "sv_apply_circuit_norm", "sv_expect", "sv_norm", "sv_copy_state", "sv_sample", "sv_amplitudes",
+           "sv_apply_circuit_norm", "sv_expect", "sv_expect_noalloc", "sv_norm", "sv_copy_state", "sv_sample", "sv_amplitudes",
            "sv_adjoint_grad", "sv_apply_batch", "sv_sync", "sv_timing", "sv_plan_info", "sv_plan_trace",
            "sv_tune"):
     getattr(_lib, _f).restype = ctypes.c_int32
 
 EXPORTED = ("sv_opts_default", "sv_create", "sv_destroy", "sv_set_stream", "sv_set_opts", "sv_init",
-            "sv_apply_circuit", "sv_apply_circuit_norm", "sv_expect", "sv_norm", "sv_copy_state", "sv_sample",
+            "sv_apply_circuit", "sv_apply_circuit_norm", "sv_expect", "sv_expect_noalloc", "sv_norm", "sv_copy_state", "sv_sample",
             "sv_amplitudes", "sv_adjoint_grad", "sv_apply_batch", "sv_sync", "sv_timing", "sv_plan_info",
             "sv_plan_trace", "sv_tune", "sv_last_error", "sv_version")
 
@@ -294,6 +295,16 @@ class StateVector:
         p = _as_pauli(pauli)
         out = np.zeros(self.batch, np.float64)
         _check(_lib.sv_expect(self._h, ctypes.byref(p.p), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def expect_noalloc(self, pauli) -> np.ndarray:
+        """expect() through sv_expect_noalloc: the library allocates nothing
+        (its work area is a fixed per-device array)."""
+        self._stream()
+        p = _as_pauli(pauli)
+        out = np.zeros(self.batch, np.float64)
+        _check(_lib.sv_expect_noalloc(self._h, ctypes.byref(p.p),
+                                      out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out
 
     def norm(self) -> np.ndarray:

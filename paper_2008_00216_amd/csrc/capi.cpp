@@ -830,6 +830,40 @@ sv_status sv_expect(sv_ctx c, const sv_pauli_sum* h, double* out) {
     return SV_OK;
 }
 
+sv_status sv_expect_noalloc(sv_ctx c, const sv_pauli_sum* h, double* out) {
+    if (!c || !out) return fail(SV_EINVAL, "ctx or out is NULL");
+    PauliPack pk;
+    sv_status st = pack_pauli(c, h, pk);
+    if (st != SV_OK) return st;
+    // fixed work area: Pauli tables, then the block partials, then the results
+    const size_t o_part = align_up(pk.buf.size(), 256);
+    const size_t n_part = reduce_partials_size(c->n, c->batch);
+    const size_t o_out = align_up(o_part + n_part * sizeof(double), 256);
+    const size_t need = o_out + (size_t)c->batch * sizeof(double);
+    if (need > kStaticScratchBytes) {
+        std::ostringstream m;
+        m << "sv_expect_noalloc needs " << need << " bytes of its fixed device work area (" << kStaticScratchBytes
+          << " bytes): use fewer states or Pauli terms, or sv_expect";
+        return fail(SV_EINVAL, m.str());
+    }
+    void* base = nullptr;
+    HIPCHK(static_scratch(&base));
+    {
+        sv_status ms = materialise(c);
+        if (ms != SV_OK) return ms;
+    }
+    unsigned char* d = reinterpret_cast<unsigned char*>(base);
+    HIPCHK(hipMemcpyAsync(d, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice, c->stream));
+    const PauliDev pd = pauli_at(pk, d);
+    double* part = reinterpret_cast<double*>(d + o_part);
+    double* res = reinterpret_cast<double*>(d + o_out);
+    HIPCHK(launch_reduce(c->dtype, 2, c->state, nullptr, 1ull << c->n, c->batch, c->n, &pd, 0, 0, part, res, 1,
+                         c->stream));
+    HIPCHK(hipMemcpyAsync(out, res, (size_t)c->batch * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return SV_OK;
+}
+
 // Samples (or read-back amplitudes) per call, over all states: keeps the
 // one-wave-per-sample grid within 2^30 workgroups.
 constexpr int64_t kMaxSamples = 1ll << 32;

@@ -8,7 +8,12 @@
 
 namespace svmi {
 
-
+// Fixed device work area of the allocation-free entry point: a file-scope
+// __device__ array of this many bytes per GPU, held until the process ends.
+// static_scratch() returns its device address on the current device (looked
+// up once per device with hipGetSymbolAddress); never pass the array's name.
+constexpr size_t kStaticScratchBytes = 4u << 20;
+hipError_t static_scratch(void** ptr);
 
 // Dynamic LDS bytes a tile pass needs.
 size_t tile_lds_bytes(int dtype, bool two, uint32_t T, uint32_t nform, uint32_t ngrad, int nt);
