@@ -18,6 +18,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from tests.golden import load as golden   # stored FP64 oracle values (text), never the oracle itself
+
 HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E, GB/s
 # Vector ALU issue peak without packed FP32: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
 # = 39.3 T lane-instructions/s (an add, a multiply or an FMA each count once).
@@ -89,61 +91,122 @@ def parse():
     return p.parse_args()
 
 
-def cpu_baseline(circ, budget_s=25.0):
-    """The FP64 oracle on the host cores, on a cut of the same circuit: the
-    first `cut` qubits (gates entirely inside them).  Reported as amplitude
-    updates/s and as the equivalent gates/s at the full width."""
-    import numpy as np
-    import oracle
-    nthreads = oracle.max_threads()
-    cut = 26
-    sub = circ.cut(cut)
-    # time a prefix of the cut circuit, bounded by budget_s
-    psi = np.zeros(1 << cut, np.complex128)
-    psi[0] = 1.0
-    t0 = time.time()
-    done = 0
-    for g in sub.gates:
-        oracle.apply_matrix(psi, cut, g.qubits, oracle.gate_matrix(g, None), nthreads)
-        done += 1
-        if time.time() - t0 > budget_s:
-            break
-    dt = time.time() - t0
-    amp_updates = done * (1 << cut) / dt
-    # the same gates on one thread, a shorter sample
-    psi1 = np.zeros(1 << cut, np.complex128)
-    psi1[0] = 1.0
-    t1 = time.time()
-    done1 = 0
-    for g in sub.gates:
-        oracle.apply_matrix(psi1, cut, g.qubits, oracle.gate_matrix(g, None), 1)
-        done1 += 1
-        if time.time() - t1 > budget_s / 3:
-            break
-    dt1 = time.time() - t1
-    amp_updates_1 = done1 * (1 << cut) / dt1
-    model = ""
+def _cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
                 if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
+                    return line.split(":", 1)[1].strip()
     except OSError:
         pass
-    return {
-        "value": amp_updates / float(1 << circ.n),
-        "unit": "gates/s (33-qubit equivalent)",
-        "amp_updates_per_s": amp_updates,
-        "cores": nthreads,
-        "host_cpus": os.cpu_count(),
-        "cpu_model": model,
-        "one_core": {"value": amp_updates_1 / float(1 << circ.n), "amp_updates_per_s": amp_updates_1,
-                     "sample": f"first {done1} gates of the same cut, {dt1:.1f} s on 1 thread"},
-        "kind": "oracle",
-        "sample": f"FP64 oracle, gate by gate, first {done} gates of the {cut}-qubit cut (qubits 0-{cut - 1}) "
-                  f"of the same grid circuit, {dt:.1f} s on {nthreads} threads; value = amp-updates/s / 2^{circ.n}",
-    }
+    return ""
+
+
+def _oracle_prefix_rate(oracle, np, circ, params, nthreads, budget_s):
+    """Apply gates of circ one by one in FP64 from |0..0> until budget_s has
+    passed (or the circuit ends): (gates done, seconds, amp-updates/s)."""
+    n = circ.n
+    psi = np.zeros(1 << n, np.complex128)
+    psi[0] = 1.0
+    t0 = time.perf_counter()
+    done = 0
+    for g in circ.gates:
+        oracle.apply_matrix(psi, n, g.qubits, oracle.gate_matrix(g, params), nthreads)
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return done, dt, done * float(1 << n) / dt
+
+
+def cpu_baseline(circ, W, np, budget_s=8.0):
+    """The FP64 oracle, gate by gate, on this host's cores (all of them and
+    one), on a bounded sample of every workload; each figure is extrapolated
+    from the timed sample to the whole workload by amplitude updates.  The
+    headline value is the 33-qubit grid's: the amp-updates/s of its 28-qubit
+    cut over 2^33."""
+    import oracle
+    nthreads = oracle.max_threads()
+    out = {"kind": "oracle", "cores": nthreads, "host_cpus": os.cpu_count(), "cpu_model": _cpu_model()}
+    cfg = {}
+
+    def sweep_entry(name, c, params=None, whole=None):
+        whole = whole if whole is not None else len(c)
+        done, dt, rate = _oracle_prefix_rate(oracle, np, c, params, nthreads, budget_s)
+        done1, dt1, rate1 = _oracle_prefix_rate(oracle, np, c, params, 1, budget_s / 3)
+        amps = float(1 << c.n)
+        cfg[name] = {"qubits": c.n, "gates": whole,
+                     "all_cores": {"gates_per_s": rate / amps, "amp_updates_per_s": rate,
+                                   "sweep_s_extrapolated": whole * amps / rate,
+                                   "sample": f"first {done} gates, {dt:.1f} s on {nthreads} threads"},
+                     "one_core": {"gates_per_s": rate1 / amps, "amp_updates_per_s": rate1,
+                                  "sweep_s_extrapolated": whole * amps / rate1,
+                                  "sample": f"first {done1} gates, {dt1:.1f} s on 1 thread"}}
+        return rate
+
+    # line, 12 qubits, 175 gates, whole circuit
+    sweep_entry("line12_10layers", W.line_circuit(12, 10, seed=1000))
+    progress("cpu baseline: line circuit done")
+    # 5x6 grid, 20 cycles: its 28-qubit cut
+    sweep_entry("grid5x6_20cycles_cut28", W.grid30().cut(28))
+    progress("cpu baseline: 30-qubit grid cut done")
+    # the headline 3x11 grid, 40 cycles: its 28-qubit cut
+    rate33 = sweep_entry("grid3x11_40cycles_cut28", circ.cut(28))
+    progress("cpu baseline: 33-qubit grid cut done")
+    # ansatz, 20 qubits: one energy; parameter shift needs 2 per parameter
+    a = W.ansatz_circuit(20, 10)
+    h = W.ansatz_observable(20)
+    th = W.uniform_params(64, a.n_params, 3003)
+    t0 = time.perf_counter()
+    oracle.energy(a, th[0], h, nthreads=nthreads)
+    t_e = time.perf_counter() - t0
+    done1, dt1, rate1 = _oracle_prefix_rate(oracle, np, a, th[0], 1, budget_s / 3)
+    t_e1 = len(a) * float(1 << 20) / rate1
+    cfg["ansatz20_400params"] = {
+        "qubits": 20, "gates": len(a), "params": a.n_params,
+        "energy_s": {"all_cores": t_e, "one_core_extrapolated": t_e1},
+        "param_shift_2_sets_s_extrapolated": {"all_cores": 2 * (2 * a.n_params + 1) * t_e,
+                                              "one_core": 2 * (2 * a.n_params + 1) * t_e1},
+        "param_shift_64_sets_s_extrapolated": {"all_cores": 64 * (2 * a.n_params + 1) * t_e},
+        "sample": f"one energy on {nthreads} threads (forward sweep + 39 Pauli terms); one core: first "
+                  f"{done1} gates in {dt1:.1f} s"}
+    progress("cpu baseline: ansatz done")
+    # batch of 512 circuits: forward of every 64th circuit, scaled by amp-updates
+    bc = W.batch_circuits(512, 10, 22, 20, 60, seed0=4000)
+    tot_upd = sum(len(c) * float(1 << c.n) for c in bc)
+    grad_upd = sum(2 * c.n_params * len(c) * float(1 << c.n) for c in bc)
+    pick = []
+    t0 = time.perf_counter()
+    upd = 0.0
+    for i in range(0, 512, 64):        # every 64th circuit, until the budget is spent
+        c = bc[i]
+        p = W.uniform_params(1, c.n_params, 4000 + i)[0]
+        oracle.energy(c, p, W.z_sum(c.n), nthreads=nthreads)
+        upd += len(c) * float(1 << c.n)
+        pick.append(i)
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    rate = upd / dt
+    cfg["batch512"] = {"circuits": 512, "gates": sum(len(c) for c in bc),
+                       "forward_s_extrapolated": tot_upd / rate,
+                       "param_shift_grads_s_extrapolated": grad_upd / rate,
+                       "amp_updates_per_s": rate,
+                       "sample": f"forward + energy of circuits {pick} ({upd:.3g} amp-updates) in {dt:.1f} s on "
+                                 f"{nthreads} threads; gradients by parameter shift = 2 sweeps per parameter"}
+    progress("cpu baseline: batch sample done")
+    out["value"] = rate33 / float(1 << circ.n)
+    out["unit"] = "gates/s (33-qubit equivalent)"
+    out["sample"] = (f"FP64 oracle, gate by gate, on the 28-qubit cut (qubits 0-27) of the 33-qubit grid circuit, "
+                     f"{budget_s:.0f} s on {nthreads} threads; value = amp-updates/s / 2^{circ.n}")
+    out["configs"] = cfg
+    return out
+
+
+def _err_vs_fp64(got, want, n):
+    import numpy as np
+    err = float(np.max(np.abs(np.asarray(got) - np.asarray(want))))
+    return {"max_abs_err_vs_fp64": err, "max_abs_err_x_2^(n/2)": err * 2.0 ** (n / 2)}
 
 
 def adjoint_leg(sv, W, torch, np):
@@ -155,13 +218,13 @@ def adjoint_leg(sv, W, torch, np):
     s = sv.StateVector(n, torch.complex64, batch=B)
     scratch = torch.empty_like(s.tensor)
     # warm up (plans)
-    s.init("zero")
+    s.init("zero_deferred")
     s.adjoint_grad(c, th, h, scratch)
     torch.cuda.synchronize()
     reps = 3
     t0 = time.time()
     for _ in range(reps):
-        s.init("zero")
+        s.init("zero_deferred")
         e, g = s.adjoint_grad(c, th, h, scratch)
     torch.cuda.synchronize()
     t_adj = (time.time() - t0) / reps
@@ -205,6 +268,11 @@ def adjoint_leg(sv, W, torch, np):
     t_ps_full = (time.time() - t0) / len(sample) * c.n_params
     err_ps = float(np.max(np.abs(g[:, sample] - ps)))
     del sf, sp
+    sel, en, gr = golden.ansatz20_gradients()
+    fp64 = {"energy_max_abs_err_vs_fp64": max(abs(e[b] - en[b]) for b in en),
+            "grad_max_abs_err_vs_fp64": max(float(np.max(np.abs(g[b][sel] - gr[b]))) for b in gr),
+            "sample": f"sets {sorted(en)}: energies and parameter-shift gradients of {len(sel)} sampled "
+                      "parameters from the FP64 oracle (tests/golden/ansatz20_gradients.txt)"}
     return {
         "workload": "ansatz20q-10layers-400params-batch64-c64",
         "adjoint_s": t_adj,
@@ -221,6 +289,7 @@ def adjoint_leg(sv, W, torch, np):
         "param_shift_sample": f"{len(sample)} params x 2 fused sweeps x {B} sets, shifts +-pi/2",
         "speedup_vs_param_shift_fused": t_ps_full / t_adj,
         "max_abs_diff_vs_param_shift": err_ps,
+        "fp64_check": fp64,
     }
 
 
@@ -243,7 +312,10 @@ def plain_leg(sv, W, torch, reps=20):
             st = s.apply(cabi)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
-        out[name] = {"us_per_gate": dt / len(c) * 1e6, "ms_per_sweep": dt * 1e3, "launches": st["launches"]}
+        idx, want, _ = golden.amplitudes("line12_amplitudes.txt")
+        got = s.amplitudes(idx)[0]
+        out[name] = {"us_per_gate": dt / len(c) * 1e6, "ms_per_sweep": dt * 1e3, "launches": st["launches"],
+                     "fp64_check": _err_vs_fp64(got, want, c.n)}
         s.close()
     return out
 
@@ -313,7 +385,7 @@ def batch_leg(sv, W, torch, np, count=512):
     for i in sample:
         c = circs[i]
         s = sv.StateVector(c.n, torch.complex64, tensor=states[i].view(1, -1))
-        s.init("zero")
+        s.init("zero_deferred")
         s.adjoint_grad(c, params[i][None, :], obs[i], lams[i].view(1, -1))
         ctxs[i] = s
     torch.cuda.synchronize()
@@ -322,7 +394,7 @@ def batch_leg(sv, W, torch, np, count=512):
     e_one = {}
     for i in sample:
         s = ctxs[i]
-        s.init("zero")
+        s.init("zero_deferred")
         ee, gg = s.adjoint_grad(circs[i], params[i][None, :], obs[i], lams[i].view(1, -1))
         e_one[i] = (ee[0], gg[0])
     torch.cuda.synchronize()
@@ -330,6 +402,13 @@ def batch_leg(sv, W, torch, np, count=512):
     err_e = max(abs(e[i] - e_one[i][0]) for i in sample)
     err_g = max(float(np.max(np.abs(g[i] - e_one[i][1]))) for i in sample)
     gates = sum(len(c.gates) for c in circs_py)
+    wide = golden.batch_wide_gradients()
+    fp64 = {"energy_max_abs_err_vs_fp64": max(abs(e[i] - d["energy"]) for i, d in wide.items()),
+            "grad_max_abs_err_vs_fp64": max(float(np.max(np.abs(g[i][d["params"]] - d["grad"])))
+                                            for i, d in wide.items() if "grad" in d),
+            "sample": f"energies of the {len(wide)} circuits of 21-22 qubits among the first 64 and parameter-"
+                      "shift gradients of 6 parameters of the two widest, FP64 oracle "
+                      "(tests/golden/batch_wide_gradients.txt)"}
     return {
         "workload": f"{count} circuits, n 10..22, 20..60 layers, c64, forward + adjoint of sum Z",
         "gates": gates,
@@ -347,7 +426,26 @@ def batch_leg(sv, W, torch, np, count=512):
         "max_abs_diff_grad_vs_one_at_a_time": err_g,
         "launches": st["launches"],
         "host_prep_ms": st["plan_ms"],
+        "fp64_check": fp64,
     }
+
+
+def headline_fp64_check(sv, torch, circ, geometry):
+    """The 33-qubit state has no FP64 reference; its 28-qubit cut (qubits
+    0-27, gates entirely inside them) runs with the same options and tile
+    geometry and is compared with FP64 oracle amplitudes
+    (tests/golden/grid33_cut28_amplitudes.txt)."""
+    cut = circ.cut(28)
+    kw = dict(zip(("tile_bits", "low_bits", "threads"), (int(x) for x in geometry)))
+    s = sv.StateVector(28, torch.complex64, opts=sv.make_opts(**kw))
+    s.init("zero_deferred")
+    _, nrm = s.apply_norm(cut)
+    idx, want, nrm_want = golden.grid33_cut28()
+    got = s.amplitudes(idx)[0]
+    del s
+    torch.cuda.empty_cache()
+    return dict(_err_vs_fp64(got, want, 28), norm_err_vs_fp64=abs(float(nrm[0]) - nrm_want),
+                sample=f"{len(idx)} amplitudes and the norm of the 28-qubit cut ({len(cut)} gates)")
 
 
 def sample_leg(s, W, np, n, shots=1 << 20, reps=3):
@@ -401,7 +499,16 @@ def c128_leg(sv, W, torch, steps=2):
     tops = st["alu_ops"] * steps / (tile_ms / 1e3) / 1e12
     del s
     torch.cuda.empty_cache()
-    return {"workload": f"grid4x8-40cycles-{n}q-c128", "gates": len(circ), "ms_per_step": ms,
+    cut = circ.cut(24)
+    sc = sv.StateVector(24, torch.complex128)
+    sc.init("zero_deferred")
+    sc.apply(cut)
+    idx, want, nrm_want = golden.amplitudes("grid4x8_cut24_amplitudes.txt")
+    fp64 = dict(_err_vs_fp64(sc.amplitudes(idx)[0], want, 24),
+                sample=f"{len(idx)} amplitudes of the 24-qubit cut ({len(cut)} gates) against the FP64 oracle "
+                       "(tests/golden/grid4x8_cut24_amplitudes.txt)")
+    del sc
+    return {"workload": f"grid4x8-40cycles-{n}q-c128", "gates": len(circ), "ms_per_step": ms, "fp64_check": fp64,
             "gates_per_s": len(circ) / (ms / 1e3), "passes": st["passes"],
             "tile_kernel": {"launches": launches, "avg_ms": per, "bytes_per_launch": tile_bytes / max(1, launches)},
             "roofline_hbm": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -634,7 +741,9 @@ def main():
                     "frac": round(hbm_frac, 4), "traffic": traffic}
     roofline_alu = {"bound": "alu", "achieved": round(achieved_tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
                     "unit": "TOP/s", "frac": round(alu_frac, 4)}
-    roofline = roofline_hbm if hbm_frac >= alu_frac else dict(roofline_alu, traffic=traffic)
+    # the metric is the HBM fraction; the ALU fraction beside it names the
+    # resource that binds the pass
+    roofline = dict(roofline_hbm, binding=("alu" if alu_frac > hbm_frac else "hbm"), alu_frac=round(alu_frac, 4))
 
     out = {
         "metric": "gates/s & %HBM peak at 33q complex64; adjoint grads/s vs plain at stated error",
@@ -665,6 +774,9 @@ def main():
         "tuned_geometry": tuned,
     }
     progress(f"sweep: {ms_per_step:.1f} ms per step")
+    if default_workload:
+        out["fp64_check"] = headline_fp64_check(sv, torch, circ, geometry)
+        progress("sweep: 28-qubit cut checked against the FP64 oracle")
     if not args.no_sample:
         out["sample"] = sample_leg(s, W, np, n)
         progress(f"sampling: {out['sample']['ms_per_call']:.1f} ms per call")
@@ -683,7 +795,7 @@ def main():
     if not args.no_batch:
         out["batch"] = batch_leg(sv, W, torch, np)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(circ)
+        out["cpu_baseline"] = cpu_baseline(circ, W, np)
         progress("cpu baseline done")
     print(json.dumps(out), flush=True)
 
