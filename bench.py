@@ -77,6 +77,8 @@ def parse():
     p.add_argument("--no-batch", action="store_true")
     p.add_argument("--no-sample", action="store_true")
     p.add_argument("--no-c128", action="store_true")
+    p.add_argument("--no-sf", action="store_true")
+    p.add_argument("--sf-only", action="store_true", help="only the Schroedinger-Feynman leg")
     p.add_argument("--ksweep", action="store_true", help="30-qubit dense-width sweep instead of the benchmark")
     p.add_argument("--ablation", action="store_true",
                    help="32-qubit ablation and gate-category profile instead of the benchmark")
@@ -518,6 +520,79 @@ def c128_leg(sv, W, torch, steps=2):
             "norm_error": abs(nrm - 1.0)}
 
 
+def sf_mask(rows, cols, n_a):
+    """Half A of a row-major grid: the first n_a qubits in column-major order
+    (column 0 top to bottom, then column 1, ...), a cut with a short boundary."""
+    order = [r * cols + c for c in range(cols) for r in range(rows)]
+    return sum(1 << q for q in order[:n_a])
+
+
+def sf_leg(sv, W, torch, np, reps=3, amplitudes=4096):
+    """Schroedinger-Feynman mode: the 34-qubit 2x17 grid circuit (20 cycles)
+    cut into two 17-qubit halves, 15 gates across the cut, 2^15 paths held in
+    memory; `amplitudes` seeded output amplitudes per call.  Checked against
+    the full 34-qubit Schroedinger sweep of the same circuit (complex64, 128
+    GiB) and, for FP64, the same construction at 22 qubits against stored
+    oracle amplitudes."""
+    c = W.grid_circuit(2, 17, 20, seed=1007)
+    mask = sf_mask(2, 17, 17)
+    idx = np.unique(np.random.default_rng(17).integers(0, 1 << c.n, amplitudes).astype(np.uint64))
+    sim = sv.SchrodingerFeynman(c, mask, torch.complex64)
+    info = sim.info
+    t0 = time.perf_counter()
+    got, st = sim.amplitudes(idx)                 # plans and compiles every half-width sweep
+    t_first = time.perf_counter() - t0
+    progress(f"sf: first call {t_first:.1f} s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        got, st = sim.amplitudes(idx)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    progress(f"sf: {t * 1e3:.1f} ms per call")
+    del sim
+    torch.cuda.empty_cache()
+    # the same amplitudes from the full-width sweep on this GPU
+    s = sv.StateVector(c.n, torch.complex64)
+    s.init("zero_deferred")
+    t0 = time.perf_counter()
+    s.apply(c)
+    full = s.amplitudes(idx)[0]
+    torch.cuda.synchronize()
+    t_full = time.perf_counter() - t0
+    s.apply(c)                                     # plans compiled: time a second sweep
+    s.init("zero_deferred")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.apply(c)
+    torch.cuda.synchronize()
+    t_full = time.perf_counter() - t0
+    del s
+    torch.cuda.empty_cache()
+    # FP64: the 22-qubit version of the same construction
+    c22 = W.grid_circuit(2, 11, 20, seed=1006)
+    i22, want, _ = golden.amplitudes("grid2x11_amplitudes.txt")
+    s22 = sv.SchrodingerFeynman(c22, sf_mask(2, 11, 11), torch.complex64)
+    got22, _ = s22.amplitudes(i22)
+    del s22
+    torch.cuda.empty_cache()
+    gbs = st["hbm_bytes"] / t / 1e9
+    return {"workload": f"grid2x17-20cycles-34q-c64, halves of 17 qubits, {info['n_cross']} cross gates, "
+                        f"{len(idx)} amplitudes",
+            "paths": info["paths"], "paths_in_memory_bits": info["n_inner"], "s_per_call": t,
+            "paths_per_s": info["paths"] / t, "amplitudes_per_s": len(idx) / t,
+            "first_call_s": t_first, "passes": st["passes"], "launches": st["launches"],
+            "roofline_hbm": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(gbs / HBM_PEAK_GBS, 4),
+                             "note": "algorithmic bytes of every half-width pass, doubling copy and path "
+                                     "contraction / whole call"},
+            "full_schroedinger_s": t_full, "speedup_vs_full_schroedinger": t_full / t,
+            "max_abs_diff_vs_full_schroedinger_c64": float(np.max(np.abs(got - full))),
+            "fp64_check": dict(_err_vs_fp64(got22, want, 22),
+                               sample=f"{len(i22)} amplitudes of the 22-qubit 2x11 grid (20 cycles) by the same "
+                                      "split against the FP64 oracle (tests/golden/grid2x11_amplitudes.txt)")}
+
+
 DIAGONAL_OPS = ("CZ", "T", "TDG", "S", "SDG", "Z", "RZ", "CP", "P")
 
 
@@ -678,6 +753,9 @@ def main():
     if args.ablation:
         ablation(sv, W, torch, np)
         return
+    if args.sf_only:
+        print(json.dumps(sf_leg(sv, W, torch, np)), flush=True)
+        return
     if args.calib_copy_gib > 0:
         nb = int(args.calib_copy_gib * (1 << 30))
         a = torch.empty(nb // 4, dtype=torch.float32, device="cuda")
@@ -794,6 +872,9 @@ def main():
         progress("adjoint leg done")
     if not args.no_batch:
         out["batch"] = batch_leg(sv, W, torch, np)
+    if not args.no_sf:
+        out["schroedinger_feynman"] = sf_leg(sv, W, torch, np)
+        progress("Schroedinger-Feynman leg done")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(circ, W, np)
         progress("cpu baseline done")

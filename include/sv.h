@@ -64,7 +64,9 @@ typedef enum { SV_C64 = 1, SV_C128 = 2 } sv_dtype;
  * X^(1/2), Y^(1/2) and T; Sec. 4.3 adds P = T^2, Z = T^4.  sqrt(Y) is the
  * principal square root (it squares to Y).  Rotations are exp(-i theta P/2),
  * SV_OP_P is diag(1, e^{i theta}), SV_OP_CP is diag(1,1,1,e^{i theta}).
- * SV_OP_MAT is an explicit 2^nq x 2^nq matrix (nq <= 6) from sv_circuit.mats. */
+ * SV_OP_MAT is an explicit 2^nq x 2^nq matrix (nq <= 6) from sv_circuit.mats;
+ * SV_OP_DIAG an explicit diagonal of 2^nq entries (a diagonal gate of
+ * Sec. 4.3 with arbitrary phases or magnitudes), also from mats. */
 typedef enum {
     SV_OP_I = 0, SV_OP_H = 1, SV_OP_X = 2, SV_OP_Y = 3, SV_OP_Z = 4,
     SV_OP_S = 5, SV_OP_SDG = 6, SV_OP_T = 7, SV_OP_TDG = 8,
@@ -72,14 +74,15 @@ typedef enum {
     SV_OP_SQRTXDG = 12, SV_OP_SQRTYDG = 13, SV_OP_SQRTWDG = 14,
     SV_OP_RX = 15, SV_OP_RY = 16, SV_OP_RZ = 17, SV_OP_P = 18,
     SV_OP_CZ = 19, SV_OP_CNOT = 20, SV_OP_SWAP = 21, SV_OP_CP = 22,
-    SV_OP_MAT = 23,
-    SV_OP_COUNT_ = 24
+    SV_OP_MAT = 23, SV_OP_DIAG = 24,
+    SV_OP_COUNT_ = 25
 } sv_op;
 
 /* One gate.  nq: number of qubits (1..6).  param: index into the parameter
  * vector for angle gates (theta used when param < 0).  mat: offset, in
- * doubles, of the gate's matrix in sv_circuit.mats (SV_OP_MAT only); the
- * matrix is row-major, interleaved complex, 2^nq x 2^nq. */
+ * doubles, of the gate's matrix in sv_circuit.mats (SV_OP_MAT: row-major,
+ * interleaved complex, 2^nq x 2^nq; SV_OP_DIAG: 2^nq interleaved complex
+ * diagonal entries). */
 typedef struct {
     int32_t op;
     int32_t nq;
@@ -380,6 +383,57 @@ sv_status sv_plan_info(const sv_circuit* circuit, sv_dtype dtype, int32_t adjoin
  * without a GPU. */
 sv_status sv_plan_trace(const sv_circuit* circuit, const double* params, sv_dtype dtype, int32_t adjoint,
                         const sv_opts* opts, char* buf, size_t cap, size_t* len);
+
+/* ---- Schroedinger-Feynman mode (Sec. 1, Sec. 6: the paper's second mode,
+ * whose Schroedinger sweeps it accelerates; built here from the path sum).
+ * The register is cut into half A (the qubits set in half_mask) and half B.
+ * Every gate across the cut (CZ, CP or CNOT; any other is SV_EUNSUPPORTED)
+ * is the sum of two products of one-half operators, |0><0| (x) I +
+ * |1><1| (x) U, so the circuit is a sum over 2^c paths (c = cross gates) of
+ * products of half-width states: psi[j] = sum_s A_s[jA] B_s[jB], where jA
+ * and jB gather the bits of j on each half in qubit order.  Both halves
+ * start at |0..0>.  Path bits are carried as extra high qubits of each
+ * half's buffer, added at their cross gates (so a gate before a cross gate
+ * is applied once for all the paths that share it); when the work area
+ * cannot hold them all, the last cross gates are enumerated one assignment
+ * at a time from a checkpoint.  The path sum of each requested amplitude is
+ * accumulated in FP64. */
+typedef struct sv_sf_s* sv_sf;
+
+typedef struct {
+    int32_t n_qubits, n_a, n_b;   /* register and half widths */
+    int32_t n_cross;              /* gates across the cut = path bits */
+    int32_t n_inner;              /* path bits held in memory for the given work size (-1: none fits) */
+    int32_t n_outer;              /* path bits enumerated one assignment at a time */
+    double paths;                 /* 2^n_cross */
+    size_t work_bytes_all_inner;  /* device work bytes to hold every path bit */
+    size_t work_bytes_min;        /* device work bytes with every path bit enumerated */
+} sv_sf_info;
+
+/* Host only: cut statistics and work sizes for `work_bytes` of device work
+ * area.  Errors: SV_EINVAL (bad circuit, dtype), SV_EUNSUPPORTED (a gate
+ * across the cut other than CZ, CP, CNOT; an empty half). */
+sv_status sv_sf_plan(const sv_circuit* circuit, uint64_t half_mask, sv_dtype dtype, size_t work_bytes,
+                     sv_sf_info* info);
+
+/* Create a Schroedinger-Feynman simulator of `circuit` (copied) over a
+ * caller-owned device work area (256-byte aligned, borrowed for the life of
+ * the object): the two half buffers and, when path bits are enumerated,
+ * their checkpoints.  Errors: those of sv_sf_plan, SV_EINVAL when the work
+ * area holds no split, SV_ENOMEM, SV_EDEVICE. */
+sv_status sv_sf_create(sv_sf* out, const sv_circuit* circuit, uint64_t half_mask, sv_dtype dtype, void* d_work,
+                       size_t work_bytes, void* hip_stream, const sv_opts* opts);
+sv_status sv_sf_destroy(sv_sf sf);
+
+/* Amplitudes psi[indices[k]] of U(params)|0..0>, k < count: out[2k], out[2k+1]
+ * (host FP64) = real and imaginary part.  params: host, n_params values (may
+ * be NULL without parameters).  The first call plans (and compiles) every
+ * half-width sweep.  stats (may be NULL): passes, launches and algorithmic
+ * bytes of the sweeps, copies and path contractions.  Synchronises.
+ * Errors: SV_EINVAL for NULL pointers, indices >= 2^n, NULL or non-finite
+ * params; SV_ENOMEM; SV_EDEVICE. */
+sv_status sv_sf_amplitudes(sv_sf sf, const double* params, int64_t count, const uint64_t* indices, double* out,
+                           sv_stats* stats);
 
 /* Wait for the context's stream and report any device error. */
 sv_status sv_sync(sv_ctx ctx);

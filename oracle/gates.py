@@ -94,6 +94,8 @@ SHIFTABLE = {"RX", "RY", "RZ", "P", "CP"}
 def matrix(op: str, theta: float = 0.0, mat: np.ndarray | None = None) -> np.ndarray:
     if op == "MAT":
         return np.asarray(mat, np.complex128)
+    if op == "DIAG":                       # explicit diagonal entries
+        return np.diag(np.asarray(mat, np.complex128).ravel())
     if op in FIXED:
         return FIXED[op]
     if op in ANGLE:

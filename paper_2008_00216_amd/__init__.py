@@ -36,7 +36,7 @@ BATCH_FORWARD, BATCH_GRAD, BATCH_INIT_ZERO = 1, 2, 4
 OPS = {
     "I": 0, "H": 1, "X": 2, "Y": 3, "Z": 4, "S": 5, "SDG": 6, "T": 7, "TDG": 8,
     "SQRTX": 9, "SQRTY": 10, "SQRTW": 11, "SQRTXDG": 12, "SQRTYDG": 13, "SQRTWDG": 14,
-    "RX": 15, "RY": 16, "RZ": 17, "P": 18, "CZ": 19, "CNOT": 20, "SWAP": 21, "CP": 22, "MAT": 23,
+    "RX": 15, "RY": 16, "RZ": 17, "P": 18, "CZ": 19, "CNOT": 20, "SWAP": 21, "CP": 22, "MAT": 23, "DIAG": 24,
 }
 
 
@@ -82,6 +82,16 @@ class SvStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class SvSfInfo(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int32), ("n_a", ctypes.c_int32), ("n_b", ctypes.c_int32),
+                ("n_cross", ctypes.c_int32), ("n_inner", ctypes.c_int32), ("n_outer", ctypes.c_int32),
+                ("paths", ctypes.c_double), ("work_bytes_all_inner", ctypes.c_size_t),
+                ("work_bytes_min", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class SvBatchItem(ctypes.Structure):
     _fields_ = [("circuit", ctypes.POINTER(SvCircuit)), ("params", ctypes.POINTER(ctypes.c_double)),
                 ("d_state", ctypes.c_void_p), ("d_lambda", ctypes.c_void_p),
@@ -111,6 +121,13 @@ _lib.sv_adjoint_grad.argtypes = [_vp, ctypes.POINTER(SvCircuit), _dp, ctypes.POI
                                  ctypes.c_size_t, _dp, _dp, ctypes.POINTER(SvStats)]
 _lib.sv_apply_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(SvBatchItem), ctypes.c_int32, _vp, ctypes.c_int32,
                                 _dp, _dp, ctypes.POINTER(SvOpts), ctypes.POINTER(SvStats)]
+_lib.sv_sf_plan.argtypes = [ctypes.POINTER(SvCircuit), ctypes.c_uint64, ctypes.c_int32, ctypes.c_size_t,
+                            ctypes.POINTER(SvSfInfo)]
+_lib.sv_sf_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(SvCircuit), ctypes.c_uint64, ctypes.c_int32, _vp,
+                              ctypes.c_size_t, _vp, ctypes.POINTER(SvOpts)]
+_lib.sv_sf_destroy.argtypes = [_vp]
+_lib.sv_sf_amplitudes.argtypes = [_vp, _dp, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64), _dp,
+                                  ctypes.POINTER(SvStats)]
 _lib.sv_sync.argtypes = [_vp]
 _lib.sv_timing.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_int64), _dp]
 _lib.sv_plan_info.argtypes = [ctypes.POINTER(SvCircuit), ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(SvOpts),
@@ -121,13 +138,14 @@ _lib.sv_plan_trace.argtypes = [ctypes.POINTER(SvCircuit), _dp, ctypes.c_int32, c
 for _f in ("sv_create", "sv_destroy", "sv_set_stream", "sv_set_opts", "sv_init", "sv_apply_circuit",
            "sv_apply_circuit_norm", "sv_expect", "sv_expect_noalloc", "sv_norm", "sv_copy_state", "sv_sample", "sv_amplitudes",
            "sv_adjoint_grad", "sv_apply_batch", "sv_sync", "sv_timing", "sv_plan_info", "sv_plan_trace",
-           "sv_tune"):
+           "sv_tune", "sv_sf_plan", "sv_sf_create", "sv_sf_destroy", "sv_sf_amplitudes"):
     getattr(_lib, _f).restype = ctypes.c_int32
 
 EXPORTED = ("sv_opts_default", "sv_create", "sv_destroy", "sv_set_stream", "sv_set_opts", "sv_init",
             "sv_apply_circuit", "sv_apply_circuit_norm", "sv_expect", "sv_expect_noalloc", "sv_norm", "sv_copy_state", "sv_sample",
             "sv_amplitudes", "sv_adjoint_grad", "sv_apply_batch", "sv_sync", "sv_timing", "sv_plan_info",
-            "sv_plan_trace", "sv_tune", "sv_last_error", "sv_version")
+            "sv_plan_trace", "sv_tune", "sv_sf_plan", "sv_sf_create", "sv_sf_destroy", "sv_sf_amplitudes",
+            "sv_last_error", "sv_version")
 
 
 class SvError(RuntimeError):
@@ -181,7 +199,7 @@ class CircuitABI:
             rec["theta"][:len(gates)] = [g.theta for g in gates]
             rec["mat"][:len(gates)] = -1
             for i, g in enumerate(gates):
-                if g.op == "MAT":
+                if g.op in ("MAT", "DIAG"):
                     m = np.ascontiguousarray(g.mat, np.complex128).view(np.float64).ravel()
                     rec["mat"][i] = moff
                     mats.append(m)
@@ -450,6 +468,59 @@ def apply_batch(circuits: Sequence, params: Sequence, states: Sequence[torch.Ten
         out.append(grads[off:off + c.n_params].copy())
         off += c.n_params
     return energies[:count], out, st.as_dict()
+
+
+def sf_plan(circ, half_mask: int, dtype=torch.complex64, work_bytes: int = 0) -> dict:
+    """Host-only statistics of a Schroedinger-Feynman split (sv_sf_plan)."""
+    c = _as_circuit(circ)
+    info = SvSfInfo()
+    _check(_lib.sv_sf_plan(ctypes.byref(c.c), int(half_mask), SV_C64 if dtype == torch.complex64 else SV_C128,
+                           int(work_bytes), ctypes.byref(info)))
+    return info.as_dict()
+
+
+class SchrodingerFeynman:
+    """Amplitudes of a circuit cut into two halves (sv_sf_*): half A holds the
+    qubits set in half_mask.  The device work area is a torch tensor owned by
+    this object (by default large enough to hold every path bit)."""
+
+    def __init__(self, circ, half_mask: int, dtype=torch.complex64, work_bytes: Optional[int] = None,
+                 opts: Optional[SvOpts] = None, device="cuda"):
+        self._c = _as_circuit(circ)
+        self.dtype = dtype
+        dt = SV_C64 if dtype == torch.complex64 else SV_C128
+        info = sf_plan(self._c, half_mask, dtype, 0)
+        if work_bytes is None:
+            work_bytes = info["work_bytes_all_inner"]
+        self.work = torch.empty(int(work_bytes), dtype=torch.uint8, device=device)
+        self.opts = opts if opts is not None else make_opts()
+        h = ctypes.c_void_p()
+        _check(_lib.sv_sf_create(ctypes.byref(h), ctypes.byref(self._c.c), int(half_mask), dt,
+                                 ctypes.c_void_p(self.work.data_ptr()), int(work_bytes), _stream_handle(),
+                                 ctypes.byref(self.opts)))
+        self._h = h
+        self.info = sf_plan(self._c, half_mask, dtype, int(work_bytes))
+
+    def amplitudes(self, indices, params=None):
+        """(complex128 amplitudes of the given indices, stats dict)."""
+        idx = np.ascontiguousarray(indices, dtype=np.uint64).reshape(-1)
+        out = np.zeros((idx.size, 2), np.float64)
+        _, pp = _params_ptr(params, 1, self._c.n_params)
+        st = SvStats()
+        _check(_lib.sv_sf_amplitudes(self._h, pp, idx.size, idx.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(st)))
+        return out[:, 0] + 1j * out[:, 1], st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.sv_sf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Energy(torch.autograd.Function):

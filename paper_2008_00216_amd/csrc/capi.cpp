@@ -227,6 +227,25 @@ sv_status get_plan(sv_ctx_s* c, const sv_circuit* circ, const double* params, bo
     return SV_OK;
 }
 
+// Plan-specialised kernels for large states, compiled on a plan's first use.
+sv_status ensure_jit(sv_ctx_s* c, CachedPlan& cp, bool two) {
+    const EncodedPlan& e = cp.ep;
+    if (cp.jit_tried || e.passes.empty()) return SV_OK;
+    cp.jit_tried = true;
+    // auto: specialise when every launch streams >= 2^24 amplitudes, where a
+    // few seconds of compilation (cached on disk) pay for themselves
+    const bool big = (uint64_t)c->batch << c->n >= (1ull << 24);
+    bool eligible = jit_enabled() && c->opts.jit >= 0 && (c->opts.jit > 0 || big);
+    for (const DPass& P : e.passes)
+        if ((1u << (P.T - kRegBits)) < (uint32_t)e.cfg.nt) eligible = false;
+    if (eligible) {
+        std::string jerr;
+        cp.jit = jit_get(e, c->dtype, two, e.cfg.nt, jerr);
+        if (!cp.jit && c->opts.jit > 0) return fail(SV_EDEVICE, "run-time specialisation failed: " + jerr);
+    }
+    return SV_OK;
+}
+
 // Product-state tables for the first tile pass (lo: 2^nlo complex FP64,
 // hi: 2^{n-nlo}); the pass computes its input instead of reading psi.
 struct InitTables {
@@ -257,20 +276,9 @@ sv_status run_plan(sv_ctx_s* c, CachedPlan& cp, const std::vector<IRGate>& ir, v
     const unsigned char* plan = reinterpret_cast<const unsigned char*>(cp.dev.p);
     void* states[2] = {psi, lam};
     const int nstates = lam ? 2 : 1;
-    // plan-specialised kernels for large states
-    if (!cp.jit_tried && !e.passes.empty()) {
-        cp.jit_tried = true;
-        // auto: specialise when every launch streams >= 2^24 amplitudes, where a
-        // few seconds of compilation (cached on disk) pay for themselves
-        const bool big = (uint64_t)c->batch << c->n >= (1ull << 24);
-        bool eligible = jit_enabled() && c->opts.jit >= 0 && (c->opts.jit > 0 || big);
-        for (const DPass& P : e.passes)
-            if ((1u << (P.T - kRegBits)) < (uint32_t)e.cfg.nt) eligible = false;
-        if (eligible) {
-            std::string jerr;
-            cp.jit = jit_get(e, dt, lam != nullptr, e.cfg.nt, jerr);
-            if (!cp.jit && c->opts.jit > 0) return fail(SV_EDEVICE, "run-time specialisation failed: " + jerr);
-        }
+    {
+        sv_status js = ensure_jit(c, cp, lam != nullptr);
+        if (js != SV_OK) return js;
     }
     uint64_t gslot = 0;
     const bool norm_in_pass = norm_out && !lam && !e.steps.empty() && e.steps.back().type == ST_TILE;
@@ -536,6 +544,28 @@ sv_status apply_internal(sv_ctx_s* c, const sv_circuit* circ, const double* para
 }
 
 }  // namespace
+
+namespace svmi {
+
+sv_status sf_fail(sv_status st, const std::string& msg) { return fail(st, msg); }
+
+// Plan (and compile, where specialised kernels apply) the forward sweep of
+// `circ` on context c without launching it, so that the plans of many
+// contexts can be prepared from several host threads before they run.
+sv_status prepare_apply(sv_ctx c, const sv_circuit* circ, const double* params) {
+    if (!c) return fail(SV_EINVAL, "ctx is NULL");
+    std::string v = validate_circuit(circ, c->n);
+    if (!v.empty()) return fail(SV_EINVAL, v);
+    std::vector<IRGate> ir;
+    ProductInit pi;
+    CachedPlan* cp = nullptr;
+    double plan_ms = 0.0;
+    sv_status st = get_plan(c, circ, params, false, ir, pi, cp, plan_ms);
+    if (st != SV_OK) return st;
+    return ensure_jit(c, *cp, false);
+}
+
+}  // namespace svmi
 
 extern "C" {
 

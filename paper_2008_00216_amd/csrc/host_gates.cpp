@@ -31,7 +31,7 @@ const double kR = std::sqrt(0.5);
 int op_arity(int op) {
     switch (op) {
         case SV_OP_CZ: case SV_OP_CNOT: case SV_OP_SWAP: case SV_OP_CP: return 2;
-        case SV_OP_MAT: return -1;
+        case SV_OP_MAT: case SV_OP_DIAG: return -1;
         default: return 1;
     }
 }
@@ -142,6 +142,12 @@ void gate_matrix(int op, double theta, const double* mat, int nq, std::vector<cd
             for (int i = 0; i < d * d; ++i) m[i] = cd(mat[2 * i], mat[2 * i + 1]);
             break;
         }
+        case SV_OP_DIAG: {
+            const int d = 1 << nq;
+            m.assign((size_t)d * d, 0.0);
+            for (int i = 0; i < d; ++i) m[(size_t)i * d + i] = cd(mat[2 * i], mat[2 * i + 1]);
+            break;
+        }
         default: m.clear(); break;
     }
 }
@@ -189,8 +195,8 @@ std::string validate_circuit(const sv_circuit* c, int n_qubits) {
                 return e.str();
             }
         }
-        if (g.op == SV_OP_MAT) {
-            const int64_t need = 2ll * (1ll << g.nq) * (1ll << g.nq);
+        if (g.op == SV_OP_MAT || g.op == SV_OP_DIAG) {
+            const int64_t need = 2ll * (1ll << g.nq) * (g.op == SV_OP_MAT ? (1ll << g.nq) : 1ll);
             if (!c->mats || g.mat < 0 || (int64_t)g.mat + need > c->n_mat_doubles) {
                 e << "gate " << i << ": matrix offset " << g.mat << " out of range";
                 return e.str();
@@ -326,7 +332,7 @@ IRGate make_ir(const sv_circuit* c, int gi, const double* params, const BuildOpt
         else r.alpha[0] = inv ? (8 - a8) & 7 : a8;
         return r;
     }
-    const bool diag = g.op == SV_OP_RZ || g.op == SV_OP_P || g.op == SV_OP_CP;
+    const bool diag = g.op == SV_OP_RZ || g.op == SV_OP_P || g.op == SV_OP_CP || g.op == SV_OP_DIAG;
     r.kind = diag ? K_DIAGG : K_DENSE;
     if (!diag && o.structured && butterfly_form(g.op, inv, r.bf_pre, r.bf_post, r.bf_g)) r.skind = OP_BF;
     r.perm = inv && g.op == SV_OP_Y ? PK_Y : perm_of(g.op);
@@ -339,7 +345,7 @@ IRGate make_ir(const sv_circuit* c, int gi, const double* params, const BuildOpt
     std::vector<cd> m;
     for (int b = 0; b < nb; ++b) {
         const double th = g.param >= 0 ? params[(size_t)b * c->n_params + g.param] : g.theta;
-        gate_matrix(g.op, th, g.op == SV_OP_MAT ? c->mats + g.mat : nullptr, g.nq, m);
+        gate_matrix(g.op, th, (g.op == SV_OP_MAT || g.op == SV_OP_DIAG) ? c->mats + g.mat : nullptr, g.nq, m);
         if (inv) conj_transpose(m, d);
         cd* dst = r.m.at(b);
         if (diag)
@@ -433,7 +439,7 @@ std::vector<IRGate> build_ir(const sv_circuit* c, const double* params, const Bu
             const sv_gate& g = c->gates[i];
             if (g.nq == 1 && leading[g.q[0]] && g.param < 0) {
                 std::vector<cd> m;
-                gate_matrix(g.op, g.theta, g.op == SV_OP_MAT ? c->mats + g.mat : nullptr, 1, m);
+                gate_matrix(g.op, g.theta, (g.op == SV_OP_MAT || g.op == SV_OP_DIAG) ? c->mats + g.mat : nullptr, 1, m);
                 std::vector<cd>& x = v[g.q[0]];
                 const cd a = m[0] * x[0] + m[1] * x[1], b = m[2] * x[0] + m[3] * x[1];
                 x = {a, b};

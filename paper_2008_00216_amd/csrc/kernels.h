@@ -15,6 +15,12 @@ namespace svmi {
 constexpr size_t kStaticScratchBytes = 4u << 20;
 hipError_t static_scratch(void** ptr);
 
+// Schroedinger-Feynman path sum: acc[k] (+)= sum_{s < npath} A[(s << nA) | jA[k]] *
+// B[(s << nB) | jB[k]] in FP64 (acc: count interleaved complex doubles).
+hipError_t launch_sf_contract(int dtype, const void* A, const void* B, int nA, int nB, uint64_t npath,
+                              const uint64_t* jA, const uint64_t* jB, uint64_t count, double* acc, int accumulate,
+                              hipStream_t s);
+
 // Dynamic LDS bytes a tile pass needs.
 size_t tile_lds_bytes(int dtype, bool two, uint32_t T, uint32_t nform, uint32_t ngrad, int nt);
 hipError_t launch_tile_pass(int dtype, bool two, int nt, const TileArgs& a, uint64_t nblocks,

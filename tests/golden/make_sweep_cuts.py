@@ -6,6 +6,9 @@ checked against:
                                 with 40 cycles, seed 1005, from |0...0>
   line12_amplitudes.txt         the 12-qubit line circuit (10 layers,
                                 seed 1000), from |0...0>
+  grid2x11_amplitudes.txt       the 22-qubit 2x11 grid circuit (20 cycles,
+                                seed 1006), from |0...0> (the width-22
+                                version of the Schroedinger-Feynman workload)
 
 each as a seeded sample of amplitudes (the first and last 16 indices plus
 2048 random ones; all 4096 for the line) and the norm.  Only the oracle
@@ -41,6 +44,9 @@ def main() -> None:
     c = W.grid_circuit(4, 8, 40, seed=1005).cut(24)
     write(os.path.join(HERE, "grid4x8_cut24_amplitudes.txt"),
           "the 24-qubit cut of the 4x8 grid circuit (40 cycles, seed 1005)", c, sample_indices(c.n))
+    g = W.grid_circuit(2, 11, 20, seed=1006)
+    write(os.path.join(HERE, "grid2x11_amplitudes.txt"), "the 2x11 grid circuit (20 cycles, seed 1006)", g,
+          sample_indices(g.n))
     line = W.line_circuit(12, 10, seed=1000)
     write(os.path.join(HERE, "line12_amplitudes.txt"), "the 12-qubit line circuit (10 layers, seed 1000)",
           line, np.arange(1 << 12))

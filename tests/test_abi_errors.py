@@ -148,3 +148,24 @@ def test_entry_points_reject_null_context():
                     ("sv_tune", (None, None, None, None, None))):
         assert getattr(lib, f)(*args) == EINVAL, f
         assert lib.sv_last_error().decode(), f
+
+
+def test_sf_plan_host_only():
+    c = W.grid_circuit(2, 17, 20, seed=1007)
+    mask = sum(1 << q for q in range(34) if q % 17 < 8 or q == 8)
+    info = m.sf_plan(c, mask, work_bytes=80 << 30)
+    # a 2 x 17 grid cut after column 8 of row 0 and column 7 of row 1: three
+    # edges cross, one of them active in each of three of every four cycles
+    assert (info["n_a"], info["n_b"], info["n_cross"]) == (17, 17, 15)
+    assert info["n_inner"] == 15 and info["n_outer"] == 0 and info["paths"] == 2.0 ** 15
+    assert info["work_bytes_all_inner"] == 2 * (1 << 32) * 8
+    small = m.sf_plan(c, mask, work_bytes=info["work_bytes_all_inner"] // 8)
+    assert small["n_inner"] + small["n_outer"] == 15 and small["n_outer"] > 0
+    # SWAP across the cut has no two-term split: unsupported
+    bad = W.Circuit(4, [W.Gate("SWAP", (0, 3))], 0)
+    with pytest.raises(m.SvError) as e:
+        m.sf_plan(bad, 0b0011)
+    assert e.value.status == 4 and "crosses the cut" in str(e.value)
+    with pytest.raises(m.SvError) as e:
+        m.sf_plan(W.grid_circuit(2, 2, 1, seed=1), 0b1111)
+    assert e.value.status == 4

@@ -78,7 +78,7 @@ def test_single_gate_plain_and_fused(dtype, op):
 @pytest.mark.parametrize("seed", range(4))
 def test_random_circuits_fused(dtype, seed):
     n = [6, 9, 14, 16][seed]
-    c = W.random_circuit(n, 150, seed, ops=ALL_OPS, mat_k=(1, 2, 3, 4))
+    c = W.random_circuit(n, 150, seed, ops=ALL_OPS, mat_k=(1, 2, 3, 4), diag_k=(1, 2, 3))
     params = W.uniform_params(1, c.n_params, seed)[0]
     psi0 = round_c64(W.random_state(n, seed + 11))
     ref = oracle.simulate(c, params, psi0)
@@ -92,7 +92,7 @@ def test_random_circuits_fused(dtype, seed):
 def test_tiny_states(dtype, n):
     # states smaller than a register group (16 amplitudes) or a default tile:
     # n <= 3 runs gate by gate, n = 4, 5 as one tile holding the whole state
-    c = W.random_circuit(n, 60, 100 + n, ops=ALL_OPS, mat_k=(1, 2, 3))
+    c = W.random_circuit(n, 60, 100 + n, ops=ALL_OPS, mat_k=(1, 2, 3), diag_k=(1, 2))
     params = W.uniform_params(1, c.n_params, n)[0]
     psi0 = round_c64(W.random_state(n, 200 + n))
     ref = oracle.simulate(c, params, psi0)

@@ -114,7 +114,7 @@ ALL_OPS = ("H", "X", "Y", "Z", "S", "SDG", "T", "TDG", "SQRTX", "SQRTY", "SQRTW"
 @pytest.mark.parametrize("seed", range(6))
 def test_oracle_matches_brute_force(seed):
     n = 3 + seed % 5
-    c = W.random_circuit(n, 40, seed, ops=ALL_OPS, mat_k=(1, 2, 3) if n >= 3 else (1, 2))
+    c = W.random_circuit(n, 40, seed, ops=ALL_OPS, mat_k=(1, 2, 3) if n >= 3 else (1, 2), diag_k=(1, 2, 3))
     params = W.uniform_params(1, c.n_params, seed + 99)[0]
     psi0 = W.random_state(n, seed + 7)
     a = oracle.simulate(c, params, psi0)

@@ -55,7 +55,8 @@ class Gate:
     qubits: Tuple[int, ...]
     param: int = -1            # index into the parameter vector, or -1
     theta: float = 0.0         # fixed angle when param < 0
-    mat: Optional[np.ndarray] = None  # explicit 2^k x 2^k complex matrix for op "MAT"
+    mat: Optional[np.ndarray] = None  # explicit 2^k x 2^k complex matrix for op "MAT",
+                                      # or the 2^k diagonal entries for op "DIAG"
 
 
 @dataclass
@@ -241,18 +242,27 @@ def random_circuit(n: int, n_gates: int, seed: int,
                    ops: Sequence[str] = ("H", "X", "Y", "Z", "S", "SDG", "T", "TDG", "SQRTX",
                                          "SQRTY", "SQRTW", "RX", "RY", "RZ", "P", "CZ", "CNOT",
                                          "SWAP", "CP"),
-                   mat_k: Sequence[int] = (), param_frac: float = 0.5) -> Circuit:
+                   mat_k: Sequence[int] = (), param_frac: float = 0.5,
+                   diag_k: Sequence[int] = ()) -> Circuit:
     """Random circuit over `ops` with random (non-adjacent, any order) qubits.
     Angle gates get a parameter slot with probability `param_frac`, otherwise
     a fixed angle.  `mat_k` lists arities of random explicit-matrix gates to
     mix in (the matrices are Haar-ish random unitaries from a QR of a complex
-    Gaussian, drawn here as input data)."""
+    Gaussian, drawn here as input data); `diag_k` arities of explicit
+    diagonal gates with random unit-modulus entries."""
     rng = np.random.default_rng(seed)
-    choices = list(ops) + [f"MAT{k}" for k in mat_k]
+    choices = list(ops) + [f"MAT{k}" for k in mat_k] + [f"DIAG{k}" for k in diag_k]
     gates: List[Gate] = []
     p = 0
     for _ in range(n_gates):
         op = choices[int(rng.integers(0, len(choices)))]
+        if op.startswith("DIAG"):
+            k = int(op[4:])
+            if k > n:
+                continue
+            qs = tuple(int(x) for x in rng.permutation(n)[:k])
+            gates.append(Gate("DIAG", qs, mat=np.exp(1j * rng.uniform(-np.pi, np.pi, 1 << k))))
+            continue
         if op.startswith("MAT"):
             k = int(op[3:])
             if k > n:
