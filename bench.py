@@ -79,6 +79,7 @@ def parse():
     p.add_argument("--no-c128", action="store_true")
     p.add_argument("--no-sf", action="store_true")
     p.add_argument("--sf-only", action="store_true", help="only the Schroedinger-Feynman leg")
+    p.add_argument("--batch-only", action="store_true", help="only the 512-circuit batch leg")
     p.add_argument("--ksweep", action="store_true", help="30-qubit dense-width sweep instead of the benchmark")
     p.add_argument("--ablation", action="store_true",
                    help="32-qubit ablation and gate-category profile instead of the benchmark")
@@ -379,8 +380,23 @@ def batch_leg(sv, W, torch, np, count=512):
     for _ in range(reps):
         e, g, st = sv.apply_batch(circs, params, states, obs, lambdas=lams, grad=True, init_zero=True)
     torch.cuda.synchronize()
+    t_default = (time.perf_counter() - t0) / reps
+    progress(f"batch: {t_default * 1e3:.1f} ms per launch with the default geometry")
+    # per-width fusion mode and tile geometry by measurement
+    t0 = time.perf_counter()
+    ntuned = sv.tune_batch(circs, params, states, obs, lambdas=lams, grad=True)
+    t_tune = time.perf_counter() - t0
+    widths = sorted({c.n for c in circs_py})
+    tuning = {int(w): sv.batch_tuning(w, grad=True) for w in widths}
+    topts = sv.make_opts(batch_tuned=1)
+    e, g, st = sv.apply_batch(circs, params, states, obs, lambdas=lams, grad=True, init_zero=True, opts=topts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        e, g, st = sv.apply_batch(circs, params, states, obs, lambdas=lams, grad=True, init_zero=True, opts=topts)
+    torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / reps
-    progress(f"batch: {t_batch * 1e3:.1f} ms per launch")
+    progress(f"batch: {t_batch * 1e3:.1f} ms per launch tuned ({ntuned} widths, {t_tune:.1f} s)")
     # one circuit at a time (per-circuit launches, same library)
     sample = list(range(0, count, 8))
     ctxs = {}
@@ -415,6 +431,9 @@ def batch_leg(sv, W, torch, np, count=512):
         "workload": f"{count} circuits, n 10..22, 20..60 layers, c64, forward + adjoint of sum Z",
         "gates": gates,
         "batch_s": t_batch,
+        "batch_s_default_geometry": t_default,
+        "tune_s": t_tune,
+        "tuning_per_width": tuning,
         "roofline_alu": {"bound": "alu", "achieved": round(st["alu_ops"] / t_batch / 1e12, 2),
                          "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
                          "frac": round(st["alu_ops"] / t_batch / 1e12 / VALU_PEAK_TOPS, 4),
@@ -755,6 +774,9 @@ def main():
         return
     if args.sf_only:
         print(json.dumps(sf_leg(sv, W, torch, np)), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps(batch_leg(sv, W, torch, np)), flush=True)
         return
     if args.calib_copy_gib > 0:
         nb = int(args.calib_copy_gib * (1 << 30))

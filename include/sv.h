@@ -126,7 +126,9 @@ typedef struct {
     int32_t max_work_mib;  /* cap, in MiB, on the device memory the library allocates for a context
                               (plans, pools, reduction and sampling scratch) or a batch call's work
                               area; 0 = no cap.  A call that would exceed it returns SV_ENOMEM */
-    int32_t reserved[2];
+    int32_t batch_tuned;   /* sv_apply_batch: 1 = items of every width that sv_tune_batch has tuned
+                              (same dtype and direction) use its fusion mode and tile geometry */
+    int32_t reserved;
 } sv_opts;
 
 typedef struct {
@@ -335,6 +337,27 @@ enum { SV_BATCH_FORWARD = 1, SV_BATCH_GRAD = 2, SV_BATCH_INIT_ZERO = 4 };
 sv_status sv_apply_batch(int32_t count, const sv_batch_item* items, sv_dtype dtype,
                          void* hip_stream, int32_t flags, double* energies, double* grads,
                          const sv_opts* opts, sv_stats* stats);
+
+/* Autotuner of the batched launch (the block-size choice of Sec. 5.1 made by
+ * measurement, and the fusion width): for every width among the items, times
+ * one persistent launch of that width's items under candidate fusion modes
+ * (butterflies with lazily applied phases; dense blocks of 2, 3 or 4
+ * qubits), then 2^T-amplitude tiles (T = 11..13) and 2^L-amplitude segments
+ * (L = 3..5) around the best, keeping a change only when it is more than
+ * 3 % faster.  The choices are remembered per (dtype, direction, width) in
+ * the process and in $SVMI_BATCH_TUNE_CACHE (default
+ * /tmp/svmi-batch-tune.txt); sv_apply_batch uses them when opts.batch_tuned
+ * is set.  flags as for sv_apply_batch (SV_BATCH_GRAD tunes the gradient
+ * direction).  The items' states (and lambdas) are overwritten: initialise
+ * them afterwards.  widths_tuned (may be NULL) receives the number of widths
+ * tuned.  Errors: those of sv_apply_batch. */
+sv_status sv_tune_batch(int32_t count, const sv_batch_item* items, sv_dtype dtype, void* hip_stream, int32_t flags,
+                        const sv_opts* opts, int32_t* widths_tuned);
+
+/* The remembered choice of sv_tune_batch for one width: out->structured,
+ * max_fuse_k, tile_bits and low_bits (0 = default).  Host only.
+ * Errors: SV_EINVAL when that width has not been tuned. */
+sv_status sv_batch_tuning(sv_dtype dtype, int32_t grad, int32_t n_qubits, sv_opts* out);
 
 /* Accumulated tile-pass kernel time since the last call (needs opts.timing):
  * total milliseconds, number of launches and the algorithmic HBM bytes of

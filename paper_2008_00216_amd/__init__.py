@@ -68,7 +68,7 @@ class SvOpts(ctypes.Structure):
                 ("low_bits", ctypes.c_int32), ("plain", ctypes.c_int32), ("threads", ctypes.c_int32),
                 ("product_init", ctypes.c_int32), ("structured", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("jit", ctypes.c_int32), ("max_work_mib", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("batch_tuned", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class SvStats(ctypes.Structure):
@@ -128,6 +128,9 @@ _lib.sv_sf_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(SvCircuit), ct
 _lib.sv_sf_destroy.argtypes = [_vp]
 _lib.sv_sf_amplitudes.argtypes = [_vp, _dp, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64), _dp,
                                   ctypes.POINTER(SvStats)]
+_lib.sv_tune_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(SvBatchItem), ctypes.c_int32, _vp, ctypes.c_int32,
+                               ctypes.POINTER(SvOpts), ctypes.POINTER(ctypes.c_int32)]
+_lib.sv_batch_tuning.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(SvOpts)]
 _lib.sv_sync.argtypes = [_vp]
 _lib.sv_timing.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_int64), _dp]
 _lib.sv_plan_info.argtypes = [ctypes.POINTER(SvCircuit), ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(SvOpts),
@@ -138,14 +141,15 @@ _lib.sv_plan_trace.argtypes = [ctypes.POINTER(SvCircuit), _dp, ctypes.c_int32, c
 for _f in ("sv_create", "sv_destroy", "sv_set_stream", "sv_set_opts", "sv_init", "sv_apply_circuit",
            "sv_apply_circuit_norm", "sv_expect", "sv_expect_noalloc", "sv_norm", "sv_copy_state", "sv_sample", "sv_amplitudes",
            "sv_adjoint_grad", "sv_apply_batch", "sv_sync", "sv_timing", "sv_plan_info", "sv_plan_trace",
-           "sv_tune", "sv_sf_plan", "sv_sf_create", "sv_sf_destroy", "sv_sf_amplitudes"):
+           "sv_tune", "sv_sf_plan", "sv_sf_create", "sv_sf_destroy", "sv_sf_amplitudes", "sv_tune_batch",
+           "sv_batch_tuning"):
     getattr(_lib, _f).restype = ctypes.c_int32
 
 EXPORTED = ("sv_opts_default", "sv_create", "sv_destroy", "sv_set_stream", "sv_set_opts", "sv_init",
             "sv_apply_circuit", "sv_apply_circuit_norm", "sv_expect", "sv_expect_noalloc", "sv_norm", "sv_copy_state", "sv_sample",
             "sv_amplitudes", "sv_adjoint_grad", "sv_apply_batch", "sv_sync", "sv_timing", "sv_plan_info",
             "sv_plan_trace", "sv_tune", "sv_sf_plan", "sv_sf_create", "sv_sf_destroy", "sv_sf_amplitudes",
-            "sv_last_error", "sv_version")
+            "sv_tune_batch", "sv_batch_tuning", "sv_last_error", "sv_version")
 
 
 class SvError(RuntimeError):
@@ -430,6 +434,49 @@ def plan_trace(circ, params=None, dtype=torch.complex64, adjoint=False, opts: Op
     buf = ctypes.create_string_buffer(n.value + 1)
     _check(_lib.sv_plan_trace(*args, buf, n.value + 1, ctypes.byref(n)))
     return buf.value.decode()
+
+
+def _batch_items(circuits, params, states, observables, lambdas):
+    count = len(circuits)
+    cabi = [_as_circuit(c) for c in circuits]
+    pabi = [_as_pauli(p) for p in observables]
+    items = (SvBatchItem * max(1, count))()
+    keep = [cabi, pabi]
+    for i in range(count):
+        pr = None
+        if cabi[i].n_params:
+            pr = np.ascontiguousarray(np.asarray(params[i], np.float64))
+            keep.append(pr)
+        items[i].circuit = ctypes.pointer(cabi[i].c)
+        items[i].params = pr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if pr is not None else None
+        items[i].d_state = states[i].data_ptr()
+        items[i].d_lambda = lambdas[i].data_ptr() if lambdas is not None else None
+        items[i].observable = ctypes.pointer(pabi[i].p)
+    return items, keep
+
+
+def tune_batch(circuits: Sequence, params: Sequence, states: Sequence[torch.Tensor], observables: Sequence,
+               lambdas: Optional[Sequence[torch.Tensor]] = None, grad: bool = False,
+               opts: Optional[SvOpts] = None) -> int:
+    """sv_tune_batch: per-width fusion mode and tile geometry by measurement
+    (overwrites the states).  Returns the number of widths tuned; apply with
+    make_opts(batch_tuned=1)."""
+    items, keep = _batch_items(circuits, params, states, observables, lambdas)
+    n = ctypes.c_int32()
+    o = opts if opts is not None else make_opts()
+    _check(_lib.sv_tune_batch(len(circuits), items, SV_C64 if states[0].dtype == torch.complex64 else SV_C128,
+                              _stream_handle(), BATCH_GRAD if grad else BATCH_FORWARD, ctypes.byref(o),
+                              ctypes.byref(n)))
+    return n.value
+
+
+def batch_tuning(n_qubits: int, dtype=torch.complex64, grad: bool = False) -> dict:
+    """The remembered sv_tune_batch choice for one width."""
+    o = SvOpts()
+    _check(_lib.sv_batch_tuning(SV_C64 if dtype == torch.complex64 else SV_C128, 1 if grad else 0, int(n_qubits),
+                                ctypes.byref(o)))
+    return {"structured": o.structured, "max_fuse_k": o.max_fuse_k, "tile_bits": o.tile_bits,
+            "low_bits": o.low_bits}
 
 
 def apply_batch(circuits: Sequence, params: Sequence, states: Sequence[torch.Tensor],

@@ -10,6 +10,8 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -95,31 +97,35 @@ std::unordered_map<int, DevArea> g_dev;   // by device ordinal
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-PlanCfg batch_cfg(int dtype, bool two, int n) {
+PlanCfg batch_cfg(int dtype, bool two, int n, const BatchGeom& g) {
     PlanCfg p;
     p.dtype = dtype;
-    const int T = dtype == SV_C64 ? 12 : (two ? 11 : 12);
+    int T = g.T > 0 ? g.T : (dtype == SV_C64 ? 12 : (two ? 11 : 12));
+    if (dtype != SV_C64 && two) T = std::min(T, 12);   // two c128 states per tile: at most 128 KiB of LDS
     p.T = std::min(T, n);
-    p.L = std::min(4, p.T - 1);   // same tile geometry as the single-circuit default
+    p.L = std::min(g.L > 0 ? g.L : 4, p.T - 1);   // default: the single-circuit tile geometry
+    if (p.T - p.L > kMaxHigh) p.L = p.T - kMaxHigh;
     p.nt = 256;
     p.two = two;
     return p;
 }
 
 // Plans are cached by circuit structure, dtype, direction, the IR options
-// (structured, fusion width) and the value-dependent decisions of the IR.
+// (structured, fusion width), the tile geometry and the value-dependent
+// decisions of the IR.
 std::shared_ptr<PlanKeyed> get_batch_plan(const sv_circuit* c, const std::vector<IRGate>& ir, int dtype, bool two,
-                                          const BuildOpts& bo) {
+                                          const BuildOpts& bo, const BatchGeom& g) {
+    const PlanCfg cfg = batch_cfg(dtype, two, c->n_qubits, g);
     const uint64_t key = circuit_hash(c, 0x9e3779b97f4a7c15ull ^ ((uint64_t)dtype << 8) ^ ((uint64_t)two << 12) ^
                                              ((uint64_t)bo.structured << 16) ^ ((uint64_t)(uint32_t)bo.fuse_k << 20) ^
-                                             ir_signature(ir));
+                                             ((uint64_t)cfg.T << 28) ^ ((uint64_t)cfg.L << 34) ^ ir_signature(ir));
     {
         std::lock_guard<std::mutex> lk(g_plan_mu);
         auto it = g_plans.find(key);
         if (it != g_plans.end()) return it->second;
     }
     auto pk = std::make_shared<PlanKeyed>();
-    plan_fused(ir, c->n_qubits, batch_cfg(dtype, two, c->n_qubits), pk->ep);
+    plan_fused(ir, c->n_qubits, cfg, pk->ep);
     std::lock_guard<std::mutex> lk(g_plan_mu);
     g_plans[key] = pk;
     return pk;
@@ -137,7 +143,7 @@ struct ItemHost {
 
 sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dtype dtype, hipStream_t stream,
                                int32_t flags, double* energies, double* grads, const sv_opts* opts,
-                               sv_stats* stats, std::string& err) {
+                               sv_stats* stats, std::string& err, const GeomTable* geoms) {
     if (count < 0) { err = "count < 0"; return SV_EINVAL; }
     if (count > 0 && !items) { err = "items is NULL"; return SV_EINVAL; }
     if (dtype != SV_C64 && dtype != SV_C128) { err = "dtype must be SV_C64 or SV_C128"; return SV_EINVAL; }
@@ -178,19 +184,27 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
                     if (i >= count) return;
                     const sv_batch_item& it = items[i];
                     try {
+                        // geometry and fusion: the tuned choice for this width, else the options
+                        BatchGeom g;
+                        g.structured = !opts || opts->structured;
+                        g.fuse_k = opts ? opts->max_fuse_k : 4;
+                        if (geoms) {
+                            auto gi = geoms->find(it.circuit->n_qubits);
+                            if (gi != geoms->end()) g = gi->second;
+                        }
                         BuildOpts bo;
                         bo.batch = 1;
-                        bo.structured = !opts || opts->structured;
+                        bo.structured = g.structured != 0;
                         bo.fuse = true;
-                        bo.fuse_k = opts ? opts->max_fuse_k : 4;
+                        bo.fuse_k = g.fuse_k;
                         bo.product_init = false;
                         H[i].irf = build_ir(it.circuit, it.params, bo, nullptr, it.circuit->n_qubits);
-                        H[i].pf = get_batch_plan(it.circuit, H[i].irf, dtype, false, bo);
+                        H[i].pf = get_batch_plan(it.circuit, H[i].irf, dtype, false, bo, g);
                         fill_pool(H[i].pf->ep, H[i].irf, 1, H[i].poolf);
                         if (grad) {
                             bo.backward = true;
                             H[i].irb = build_ir(it.circuit, it.params, bo, nullptr, it.circuit->n_qubits);
-                            H[i].pb = get_batch_plan(it.circuit, H[i].irb, dtype, true, bo);
+                            H[i].pb = get_batch_plan(it.circuit, H[i].irb, dtype, true, bo, g);
                             fill_pool(H[i].pb->ep, H[i].irb, 1, H[i].poolb);
                         }
                     } catch (const std::exception& e) {
@@ -572,6 +586,160 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
                 bytes += (double)ab * std::ldexp(1.0, items[i].circuit->n_qubits) * (r.kind == BK_BWD ? 4.0 : 2.0);
         stats->hbm_bytes = bytes;
     }
+    return SV_OK;
+}
+
+}  // namespace svmi
+
+// ---- autotuner of the batch's fusion mode and tile geometry, per width
+namespace svmi {
+
+namespace {
+
+std::mutex g_btune_mu;
+std::map<uint64_t, BatchGeom> g_btune;   // (dtype, direction, width) -> choice
+bool g_btune_loaded = false;
+
+uint64_t btune_key(int dtype, bool grad, int n) {
+    return ((uint64_t)dtype << 40) | ((uint64_t)(grad ? 1 : 0) << 32) | (uint64_t)(uint32_t)n;
+}
+
+std::string btune_file() {
+    const char* d = std::getenv("SVMI_BATCH_TUNE_CACHE");
+    return d && *d ? std::string(d) : std::string("/tmp/svmi-batch-tune.txt");
+}
+
+// caller holds g_btune_mu
+void btune_load() {
+    if (g_btune_loaded) return;
+    g_btune_loaded = true;
+    FILE* f = std::fopen(btune_file().c_str(), "r");
+    if (!f) return;
+    int dt, gr, n, s, k, T, L;
+    while (std::fscanf(f, "%d %d %d %d %d %d %d", &dt, &gr, &n, &s, &k, &T, &L) == 7) {
+        BatchGeom g;
+        g.structured = s;
+        g.fuse_k = k;
+        g.T = T;
+        g.L = L;
+        g_btune[btune_key(dt, gr != 0, n)] = g;
+    }
+    std::fclose(f);
+}
+
+}  // namespace
+
+bool batch_tuned_table(int dtype, bool grad, GeomTable& out) {
+    std::lock_guard<std::mutex> lk(g_btune_mu);
+    btune_load();
+    out.clear();
+    for (const auto& kv : g_btune)
+        if ((int)(kv.first >> 40) == dtype && (((kv.first >> 32) & 1) != 0) == grad)
+            out[(int)(kv.first & 0xffffffffu)] = kv.second;
+    return !out.empty();
+}
+
+bool batch_tuned_lookup(int dtype, bool grad, int n, BatchGeom& g) {
+    std::lock_guard<std::mutex> lk(g_btune_mu);
+    btune_load();
+    auto it = g_btune.find(btune_key(dtype, grad, n));
+    if (it == g_btune.end()) return false;
+    g = it->second;
+    return true;
+}
+
+// For every width among the items: time the persistent launch of that
+// width's items under candidate fusion modes (butterflies with lazy phases,
+// dense blocks of 2, 3 or 4 qubits), then tile sizes 2^T and segment lengths
+// 2^L around the best, one coordinate at a time, keeping a change only when
+// it saves more than 3 %.  Each candidate runs twice (plans, then timed).
+sv_status tune_batch(int32_t count, const sv_batch_item* items, sv_dtype dtype, hipStream_t stream, int32_t flags,
+                     const sv_opts* opts, int32_t* widths_tuned, std::string& err) {
+    if (count <= 0 || !items) { err = "no items"; return SV_EINVAL; }
+    const bool grad = (flags & SV_BATCH_GRAD) != 0;
+    const int32_t rflags = (grad ? SV_BATCH_GRAD : SV_BATCH_FORWARD) | SV_BATCH_INIT_ZERO;
+    std::map<int, std::vector<int>> by_w;
+    for (int32_t i = 0; i < count; ++i) {
+        if (!items[i].circuit) { err = "item " + std::to_string(i) + ": NULL circuit"; return SV_EINVAL; }
+        by_w[items[i].circuit->n_qubits].push_back(i);
+    }
+    int tuned = 0;
+    for (const auto& kv : by_w) {
+        const int w = kv.first;
+        if (w < 4) continue;                      // gate by gate: nothing to choose
+        std::vector<sv_batch_item> sub;
+        size_t np = 0;
+        for (int i : kv.second) {
+            sub.push_back(items[i]);
+            np += (size_t)std::max(0, items[i].circuit->n_params);
+        }
+        std::vector<double> e(sub.size() + 1), gr(np + 1);
+        bool obs_all = true;
+        for (const sv_batch_item& it : sub) obs_all = obs_all && it.observable;
+        sv_status st = SV_OK;
+        auto time_geom = [&](const BatchGeom& g) -> double {
+            const GeomTable t{{w, g}};
+            double best = 1e300;
+            for (int rep = 0; rep < 2 && st == SV_OK; ++rep) {
+                const auto t0 = std::chrono::steady_clock::now();
+                st = run_batch_persistent((int32_t)sub.size(), sub.data(), dtype, stream, rflags,
+                                          obs_all ? e.data() : nullptr, grad ? gr.data() : nullptr, opts, nullptr,
+                                          err, &t);
+                const double ms =
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                if (rep > 0) best = ms;
+            }
+            return best;
+        };
+        BatchGeom best;
+        best.structured = 1;
+        best.fuse_k = 4;
+        double best_ms = time_geom(best);
+        if (st != SV_OK) return st;
+        auto consider = [&](const BatchGeom& g) {
+            const double ms = time_geom(g);
+            if (st == SV_OK && ms < 0.97 * best_ms) {
+                best_ms = ms;
+                best = g;
+            }
+        };
+        for (int k = 2; k <= 4 && st == SV_OK; ++k) {
+            BatchGeom g = best;
+            g.structured = 0;
+            g.fuse_k = k;
+            consider(g);
+        }
+        if (w > 10) {
+            const int tmax = (dtype == SV_C128 && grad) ? 12 : 13;
+            const BatchGeom base = best;
+            for (int T = 11; T <= std::min(tmax, w) && st == SV_OK; ++T) {
+                BatchGeom g = base;
+                g.T = T;
+                if (T == (dtype == SV_C64 ? 12 : (grad ? 11 : 12))) continue;   // the default, timed above
+                consider(g);
+            }
+            const BatchGeom base2 = best;
+            for (int L = 3; L <= 5 && st == SV_OK; ++L) {
+                if (L == 4) continue;
+                BatchGeom g = base2;
+                g.L = L;
+                consider(g);
+            }
+        }
+        if (st != SV_OK) return st;
+        {
+            std::lock_guard<std::mutex> lk(g_btune_mu);
+            btune_load();
+            g_btune[btune_key(dtype, grad, w)] = best;
+            if (FILE* f = std::fopen(btune_file().c_str(), "a")) {
+                std::fprintf(f, "%d %d %d %d %d %d %d\n", (int)dtype, grad ? 1 : 0, w, best.structured, best.fuse_k,
+                             best.T, best.L);
+                std::fclose(f);
+            }
+        }
+        ++tuned;
+    }
+    if (widths_tuned) *widths_tuned = tuned;
     return SV_OK;
 }
 

@@ -25,7 +25,11 @@
 namespace svmi {
 sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dtype dtype, hipStream_t stream,
                                int32_t flags, double* energies, double* grads, const sv_opts* opts,
-                               sv_stats* stats, std::string& err);
+                               sv_stats* stats, std::string& err, const GeomTable* geoms);
+bool batch_tuned_table(int dtype, bool grad, GeomTable& out);
+bool batch_tuned_lookup(int dtype, bool grad, int n, BatchGeom& g);
+sv_status tune_batch(int32_t count, const sv_batch_item* items, sv_dtype dtype, hipStream_t stream, int32_t flags,
+                     const sv_opts* opts, int32_t* widths_tuned, std::string& err);
 }
 
 using namespace svmi;
@@ -1135,12 +1139,42 @@ sv_status sv_apply_batch(int32_t count, const sv_batch_item* items, sv_dtype dty
                          double* energies, double* grads, const sv_opts* opts, sv_stats* stats) {
     g_err.clear();
     std::string err;
+    GeomTable tuned;
+    const bool use_tuned = opts && opts->batch_tuned &&
+                           batch_tuned_table(dtype, (flags & SV_BATCH_GRAD) != 0, tuned);
     sv_status st = run_batch_persistent(count, items, dtype, reinterpret_cast<hipStream_t>(hip_stream), flags,
-                                        energies, grads, opts, stats, err);
+                                        energies, grads, opts, stats, err, use_tuned ? &tuned : nullptr);
     if (st != SV_OK) {
         (void)hipGetLastError();
         return fail(st, err);
     }
+    return SV_OK;
+}
+
+sv_status sv_tune_batch(int32_t count, const sv_batch_item* items, sv_dtype dtype, void* hip_stream, int32_t flags,
+                        const sv_opts* opts, int32_t* widths_tuned) {
+    g_err.clear();
+    if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "dtype must be SV_C64 or SV_C128");
+    std::string err;
+    sv_status st = tune_batch(count, items, dtype, reinterpret_cast<hipStream_t>(hip_stream), flags, opts,
+                              widths_tuned, err);
+    if (st != SV_OK) {
+        (void)hipGetLastError();
+        return fail(st, err);
+    }
+    return SV_OK;
+}
+
+sv_status sv_batch_tuning(sv_dtype dtype, int32_t grad, int32_t n_qubits, sv_opts* out) {
+    if (!out) return fail(SV_EINVAL, "out is NULL");
+    BatchGeom g;
+    if (!batch_tuned_lookup(dtype, grad != 0, n_qubits, g)) return fail(SV_EINVAL, "width not tuned");
+    sv_opts_default(out);
+    out->structured = g.structured;
+    out->max_fuse_k = g.fuse_k;
+    out->tile_bits = g.T;
+    out->low_bits = g.L;
+    out->batch_tuned = 1;
     return SV_OK;
 }
 

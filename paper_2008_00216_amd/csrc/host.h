@@ -2,6 +2,7 @@
 #pragma once
 #include <complex>
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -87,6 +88,16 @@ uint64_t circuit_hash(const sv_circuit* c, uint64_t seed);
 // plan-cache key, so that new angles or matrices never reuse a plan made for
 // values that decided differently.
 uint64_t ir_signature(const std::vector<IRGate>& ir);
+
+// Geometry and fusion of the items of one width in a heterogeneous batch
+// (T, L = 0: the defaults).
+struct BatchGeom {
+    int structured = 1;
+    int fuse_k = 4;
+    int T = 0;
+    int L = 0;
+};
+using GeomTable = std::map<int, BatchGeom>;   // width -> choice
 
 // ----------------------------------------------------------------- planning
 

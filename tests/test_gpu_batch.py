@@ -79,3 +79,30 @@ def test_batch_long_circuits_gradients():
         ref = oracle.grad_param_shift(c, params[i], obs[i])
         sel = list(range(0, c.n_params, 29))
         np.testing.assert_allclose(g[i][sel], ref[sel], atol=2e-4)
+
+
+def test_tuned_batch_matches_oracle(tmp_path, monkeypatch):
+    """sv_tune_batch picks a fusion mode and tile geometry per width by
+    timing; the batch run with those choices gives the oracle's energies and
+    gradients."""
+    import oracle
+    import paper_2008_00216_amd as m
+    monkeypatch.setenv("SVMI_BATCH_TUNE_CACHE", str(tmp_path / "bt.txt"))
+    widths = [8, 12, 13, 15, 15, 16]
+    circs = [W.layered_param_circuit(n, 6, 90 + i) for i, n in enumerate(widths)]
+    params = [W.uniform_params(1, c.n_params, 190 + i)[0] for i, c in enumerate(circs)]
+    obs = [W.z_sum(c.n) for c in circs]
+    states = [torch.zeros((1, 1 << c.n), dtype=torch.complex64, device="cuda") for c in circs]
+    lams = [torch.zeros_like(t) for t in states]
+    tuned = m.tune_batch(circs, params, states, obs, lambdas=lams, grad=True)
+    assert tuned == len(set(widths))
+    for n in set(widths):
+        g = m.batch_tuning(n, grad=True)
+        assert g["structured"] in (0, 1) and 2 <= g["max_fuse_k"] <= 4
+    e, gr, st = m.apply_batch(circs, params, states, obs, lambdas=lams, grad=True,
+                              opts=m.make_opts(batch_tuned=1))
+    for i, c in enumerate(circs):
+        assert abs(e[i] - oracle.energy(c, params[i], obs[i])) < 2e-5
+        which = list(range(0, c.n_params, 9))
+        ref = oracle.grad_param_shift(c, params[i], obs[i], which=which)
+        assert np.max(np.abs(gr[i][which] - ref)) < 2e-5, i
