@@ -218,7 +218,7 @@ void k_batch(BatchArgs B) {
                 A.gpart = BWD ? uptr<double>(it.gpart) + A.pass->gpart_off : nullptr;
                 A.ntile_log2 = rfl(it.n) - rfl(rc.T);
                 A.nthreads = kBNT;
-                tile_interp<R, kBNT, BWD>(A, smem, tile);
+                tile_interp<R, kBNT, BWD, false>(A, smem, tile);
             }
         }
         // every wave's global writes have completed before wave 0 publishes

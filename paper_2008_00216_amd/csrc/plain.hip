@@ -222,14 +222,16 @@ __global__ __launch_bounds__(kBlock) void k_copy16(const u32x4* __restrict__ src
                                                    uint64_t n) {
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    // four 16-byte words in flight per thread, non-temporal (each word is
+    // touched once)
     for (; i + 3 * stride < n; i += 4 * stride) {
         u32x4 v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = src[i + u * stride];
+        for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(src + i + u * stride);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) dst[i + u * stride] = v[u];
+        for (int u = 0; u < 4; ++u) __builtin_nontemporal_store(v[u], dst + i + u * stride);
     }
-    for (; i < n; i += stride) dst[i] = src[i];
+    for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 inline dim3 grid_for(uint64_t count, int batch) {
@@ -317,7 +319,7 @@ hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s
         return hipErrorInvalidValue;
     const uint64_t n = bytes / 16;
     uint64_t g = (n + kBlock - 1) / kBlock;
-    if (g > 65536) g = 65536;   // enough waves to stream HBM; the rest is grid-stride
+    if (g > 262144) g = 262144;   // enough waves to stream HBM; the rest is grid-stride
     hipLaunchKernelGGL(k_copy16, dim3((uint32_t)g), dim3(kBlock), 0, s, reinterpret_cast<const u32x4*>(src),
                        reinterpret_cast<u32x4*>(dst), n);
     return hipGetLastError();

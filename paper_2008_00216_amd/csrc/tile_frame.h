@@ -50,7 +50,11 @@ __device__ __forceinline__ uint64_t map_local(uint32_t l, uint32_t L, uint32_t H
     return o;
 }
 
-template <class R, int NT, bool TWO>
+// STREAM: the tile's global loads and stores carry the non-temporal hint
+// (every amplitude is read and written once per pass, so caching them only
+// evicts other lines); off in the persistent batch, whose tiles hand data to
+// later tiles of the same launch through the cache hierarchy.
+template <class R, int NT, bool TWO, bool STREAM = true>
 struct TileFrame {
     using V = V2<R>;
     static constexpr int NW = NT / 64;
@@ -65,6 +69,15 @@ struct TileFrame {
     uint32_t* fl;
     double* red;
     double* nrm;   // NW per-wave norm sums (after the gradient slots)
+
+    __device__ __forceinline__ static u32x4 gload(const u32x4* p) {
+        if constexpr (STREAM) return __builtin_nontemporal_load(p);
+        else return *p;
+    }
+    __device__ __forceinline__ static void gstore(u32x4* p, const u32x4& v) {
+        if constexpr (STREAM) __builtin_nontemporal_store(v, p);
+        else *p = v;
+    }
 
     // Carve LDS, gather the tile, evaluate the per-tile form parts.
     template <class HP>
@@ -138,8 +151,8 @@ struct TileFrame {
                 if (c < nchunk) {
                     const uint64_t gi = base + ot + map_local(APC * (c0 + j * NT), L, H, hpos);
                     if (pinit) va[j] = product_chunk(A, gi);
-                    else va[j] = *reinterpret_cast<const u32x4*>(psi + gi);
-                    if constexpr (TWO) vb[j] = *reinterpret_cast<const u32x4*>(lam + gi);
+                    else va[j] = gload(reinterpret_cast<const u32x4*>(psi + gi));
+                    if constexpr (TWO) vb[j] = gload(reinterpret_cast<const u32x4*>(lam + gi));
                 }
             }
 #pragma unroll
@@ -242,10 +255,9 @@ struct TileFrame {
                     const uint32_t s = swz<R>(APC * c);
                     const uint64_t gi = base + ot + map_local(APC * (c0 + j * NT), L, H, hpos);
                     const u32x4 v = *reinterpret_cast<const u32x4*>(sA + s);
-                    *reinterpret_cast<u32x4*>(psi + gi) = v;
+                    gstore(reinterpret_cast<u32x4*>(psi + gi), v);
                     if (nsum) nacc += chunk_norm2(v);
-                    if constexpr (TWO)
-                        *reinterpret_cast<u32x4*>(lam + gi) = *reinterpret_cast<const u32x4*>(sB + s);
+                    if constexpr (TWO) gstore(reinterpret_cast<u32x4*>(lam + gi), *reinterpret_cast<const u32x4*>(sB + s));
                 }
             }
         }

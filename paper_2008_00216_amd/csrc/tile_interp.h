@@ -167,7 +167,7 @@ __device__ __forceinline__ DOp ld_op(cptr_t<DOp> p) {
 }  // namespace
 
 // Interpreter body of one tile of one pass (blk = state * tiles + tile).
-template <class R, int NT, bool TWO>
+template <class R, int NT, bool TWO, bool STREAM = true>
 __device__ __forceinline__ void tile_interp(const TileArgs& A, unsigned char* smem, uint64_t blk) {
     using V = V2<R>;
     const cptr_t<DPass> P = cptr(A.pass);
@@ -175,7 +175,7 @@ __device__ __forceinline__ void tile_interp(const TileArgs& A, unsigned char* sm
     // pass fields are block-uniform; readfirstlane keeps every loop that
     // contains a barrier on a scalar exit condition
     const uint32_t L = rfl(P->L), H = rfl(P->H);
-    TileFrame<R, NT, TWO> F;
+    TileFrame<R, NT, TWO, STREAM> F;
     F.begin_at(A, smem, L, H, rfl(P->T), hpos, rfl(P->nform), rfl(P->form0), rfl(P->ngrad), blk);
     const uint32_t tid = F.tid;
     const uint32_t ngroups = F.NA >> kRegBits;
