@@ -658,6 +658,9 @@ def ablation(sv, W, torch, np, steps=1):
         ("no product-state init", dict(product_init=0)),
         ("no butterflies or lazy phases (2x2 matrices, explicit diagonals)", dict(structured=0, max_fuse_k=1)),
         ("no tile passes (one kernel per gate)", dict(plain=1)),
+        ("the paper's plan: kind clusters, gate pairs, Gray-code CZ, rescale passes (sqrt(W) gate by gate)",
+         dict(paper=1)),
+        ("the paper's plan with the recursive transform (a layer's low gates on LDS chunks)", dict(paper=2)),
     ]
     probe = np.unique(np.random.default_rng(17).integers(0, 1 << n, size=4096).astype(np.uint64))
     ref = None
@@ -714,7 +717,27 @@ def ablation(sv, W, torch, np, steps=1):
     base = rows[0]["ms"]
     for r in rows:
         r["x_slower_than_all"] = r["ms"] / base
-    out = {"ablation": {"workload": f"grid4x8-26cycles-{n}q-c64", "gates": len(circ), "modes": rows}}
+    # the paper's own gate set (sqrt(X), sqrt(Y), T; no sqrt(W)), where its
+    # plan needs no gate-by-gate fallback
+    fam = W.grid_circuit(4, 8, 26, seed=1004, family=("SQRTX", "SQRTY", "T"))
+    frows = []
+    fref = None
+    for name, kw in (("tile passes, all optimisations", dict()), ("the paper's plan", dict(paper=1)),
+                     ("the paper's plan with the recursive transform", dict(paper=2))):
+        s, st, ms = run(kw, fam, steps)
+        amp = s.amplitudes(probe)[0]
+        if fref is None:
+            fref = amp
+        frows.append({"mode": name, "ms": ms, "passes": st["passes"], "launches": st["launches"],
+                      "max_abs_diff_vs_tile_passes": float(np.max(np.abs(amp - fref))),
+                      "x_slower_than_tile_passes": None})
+        s.close()
+        progress(f"ablation (sqrt(X)/sqrt(Y)/T grid): {name}: {ms:.1f} ms")
+    for r in frows:
+        r["x_slower_than_tile_passes"] = r["ms"] / frows[0]["ms"]
+    out = {"ablation": {"workload": f"grid4x8-26cycles-{n}q-c64", "gates": len(circ), "modes": rows},
+           "paper_gate_set": {"workload": f"grid4x8-26cycles-{n}q-c64, family sqrt(X)/sqrt(Y)/T", "gates": len(fam),
+                              "modes": frows}}
     print(json.dumps(out), flush=True)
 
 

@@ -128,7 +128,13 @@ typedef struct {
                               area; 0 = no cap.  A call that would exceed it returns SV_ENOMEM */
     int32_t batch_tuned;   /* sv_apply_batch: 1 = items of every width that sv_tune_batch has tuned
                               (same dtype and direction) use its fusion mode and tile geometry */
-    int32_t reserved;
+    int32_t paper;         /* sv_apply_circuit: the paper's own plan instead of tile passes, for
+                              ablations: 1 = kind clusters (Sec. 4.2, 4.5) with one pass per
+                              diagonal cluster (bitmask phases, Gray-code CZ, Sec. 4.3) and per pair
+                              of one-qubit gates (multiply-free unnormalised products, scale and
+                              phase counters with rescale passes, Sec. 4.1, 4.4); 2 = the same with
+                              the recursive transform of Sec. 5.1 (a layer's low-qubit gates on
+                              LDS-staged chunks); 0 = tile passes (default) */
 } sv_opts;
 
 typedef struct {
@@ -401,7 +407,15 @@ sv_status sv_plan_info(const sv_circuit* circuit, sv_dtype dtype, int32_t adjoin
  *   SCALE s              multiply every amplitude by s
  *   GRAD p gen s q...    adjoint plans: parameter p gains s * Im<lambda|G|psi>, G = X, Y,
  *                        Z (gen 1, 2, 3) on q or -2|11><11| (gen 4) on q0 q1
- * Product-state folding of leading gates is off for the trace.  Writes at
+ * Product-state folding of leading gates is off for the trace.  With
+ * opts.paper set, the trace is the paper's plan instead, one line per kind
+ * cluster:
+ *   DIAG e8 b0 b1 b2 cz k:m... | g...   8th-root phase exponent bit-planes
+ *                        and the one-sided CZ masks m_k (partners below k),
+ *                        binary with qubit n-1 first
+ *   LAYER op m | g...    one-qubit gates of kind op on the qubits of mask m
+ *   GATES | g...         gates applied one by one
+ * where g... are the circuit's gate indices in the order applied.  Writes at
  * most cap-1 bytes plus a NUL to buf and the full length to *len.  Usable
  * without a GPU. */
 sv_status sv_plan_trace(const sv_circuit* circuit, const double* params, sv_dtype dtype, int32_t adjoint,

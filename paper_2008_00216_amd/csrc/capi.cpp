@@ -136,9 +136,10 @@ struct sv_ctx_s {
     DevBuf pool, red_part, red_out, pauli, gpart, gout, pinit;
     DevBuf smp_tree, smp_u, smp_out;   // sampling and amplitude readout
     DevBuf npart;                      // FP64 partials: the last pass's norm, the adjoint energy
+    DevBuf ppmask;                     // the paper's plan: CZ masks of its diagonal clusters
     sv_ctx_s() {
         for (DevBuf* b : {&pool, &red_part, &red_out, &pauli, &gpart, &gout, &pinit, &smp_tree, &smp_u, &smp_out,
-                          &npart})
+                          &npart, &ppmask})
             b->acct = &acct;
     }
     std::vector<unsigned char> pool_host;
@@ -506,8 +507,171 @@ sv_status materialise(sv_ctx_s* c) {
     return SV_OK;
 }
 
+// The paper's own plan (opts.paper): kind clusters, one memory pass per
+// diagonal cluster and per pair of one-qubit gates, the scale and phase of
+// the unnormalised factors kept as counters and folded back by rescale
+// passes; gates of no cluster kind run gate by gate.
+sv_status apply_paper(sv_ctx_s* c, const sv_circuit* circ, const double* params, sv_stats* stats,
+                      double* norm_out) {
+    auto t0 = std::chrono::steady_clock::now();
+    const PaperPlan pp = paper_plan(circ);
+    const int n = c->n;
+    const uint64_t bs = 1ull << n;
+    const double pass_bytes = 2.0 * (double)bs * (double)amp_bytes(c->dtype) * c->batch;
+    sv_stats acc{};
+    acc.gates_in = circ->n_gates;
+    // CZ masks of every diagonal cluster: one-sided, then symmetric
+    std::vector<uint64_t> masks;
+    std::vector<size_t> moff;
+    for (const PStep& st : pp.steps) {
+        if (st.type != PS_DIAG) continue;
+        moff.push_back(masks.size());
+        std::vector<uint64_t> sym((size_t)n, 0);
+        for (int k = 0; k < n; ++k)
+            for (int l = 0; l < k; ++l)
+                if ((st.cz[(size_t)k] >> l) & 1) { sym[(size_t)k] |= 1ull << l; sym[(size_t)l] |= 1ull << k; }
+        masks.insert(masks.end(), st.cz.begin(), st.cz.end());
+        masks.insert(masks.end(), sym.begin(), sym.end());
+    }
+    if (!masks.empty()) {
+        HIPCHK(c->ppmask.ensure(masks.size() * sizeof(uint64_t)));
+        HIPCHK(hipMemcpyAsync(c->ppmask.p, masks.data(), masks.size() * sizeof(uint64_t), hipMemcpyHostToDevice,
+                              c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    acc.plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    const uint64_t* dmask = reinterpret_cast<const uint64_t*>(c->ppmask.p);
+    size_t si = 0, di = 0;
+    // a first H layer on every qubit of a deferred |0..0> is the uniform state
+    // (the paper's footnote on the initial Hadamard layer)
+    if (c->zero_pending && !pp.steps.empty() && pp.steps[0].type == PS_LAYER && pp.steps[0].kind == SV_OP_H &&
+        (int)pp.steps[0].layer.size() == n) {
+        const double v = std::ldexp(1.0, -n / 2) * ((n & 1) ? std::sqrt(0.5) : 1.0);
+        HIPCHK(launch_init(c->dtype, c->state, bs, c->batch, n, 2, 0, v, c->stream));
+        acc.hbm_bytes += pass_bytes / 2;
+        acc.launches += 1;
+        acc.folded_init = n;
+        si = 1;
+    } else {
+        sv_status ms = materialise(c);
+        if (ms != SV_OK) return ms;
+    }
+    c->zero_pending = false;
+    c->known_zero = false;
+    int p = 0, s8 = 0;     // pending (1/sqrt(2))^p and w^s8
+    auto rescale = [&](bool final) -> sv_status {
+        if (p == 0 && (s8 & 7) == 0) return SV_OK;
+        if (!final && p <= 100) return SV_OK;
+        double re = std::ldexp(1.0, -(p / 2)) * ((p & 1) ? std::sqrt(0.5) : 1.0), im = 0.0;
+        if (final && (s8 & 7)) {
+            const double a = M_PI / 4 * (s8 & 7);
+            im = re * std::sin(a);
+            re = re * std::cos(a);
+            s8 = 0;
+        }
+        p = 0;
+        HIPCHK(launch_pp_scale(c->dtype, c->state, bs, c->batch, n, re, im, c->stream));
+        acc.passes += 1;
+        acc.launches += 1;
+        acc.hbm_bytes += pass_bytes;
+        return SV_OK;
+    };
+    const int C = std::min(n, c->dtype == SV_C64 ? 12 : 11);
+    for (size_t k = si; k < pp.steps.size(); ++k) {
+        const PStep& st = pp.steps[k];
+        if (st.type == PS_DIAG) {
+            const uint64_t* m1 = dmask + moff[di];
+            HIPCHK(launch_pp_diag(c->dtype, c->state, bs, c->batch, n, st.e8, m1, m1 + n, c->stream));
+            ++di;
+            acc.passes += 1;
+            acc.launches += 1;
+            acc.diag_ops += (int)st.gates.size();
+            acc.hbm_bytes += pass_bytes;
+            continue;
+        }
+        if (st.type == PS_LAYER) {
+            // pairs in qubit order, so that paired gates act on close qubits
+            std::vector<std::array<int, 4>> ops;   // (qa, ga, qb, gb), gb < 0: single
+            for (size_t i = 0; i < st.layer.size(); i += 2) {
+                const auto& a = st.layer[i];
+                if (i + 1 < st.layer.size()) ops.push_back({a.first, a.second, st.layer[i + 1].first, st.layer[i + 1].second});
+                else ops.push_back({a.first, a.second, -1, -1});
+                p += pg_scale_pow(a.second);
+                s8 += pg_phase8(a.second);
+                if (i + 1 < st.layer.size()) {
+                    p += pg_scale_pow(st.layer[i + 1].second) - (pg_pair_even(a.second, st.layer[i + 1].second) ? 2 : 0);
+                    s8 += pg_phase8(st.layer[i + 1].second);
+                }
+            }
+            std::vector<std::array<int, 4>> low;
+            if (c->opts.paper == 2 && C >= 2) {
+                // recursive transform: high pairs over the whole state, most
+                // significant first, then the low ones chunk by chunk
+                std::vector<std::array<int, 4>> high;
+                for (const auto& o : ops) (std::max(o[0], o[2]) >= C ? high : low).push_back(o);
+                std::reverse(high.begin(), high.end());
+                ops = high;
+            }
+            for (const auto& o : ops) {
+                HIPCHK(launch_pp_pair(c->dtype, c->state, bs, c->batch, n, o[0], o[1], o[2], o[3], c->stream));
+                acc.passes += 1;
+                acc.launches += 1;
+                acc.hbm_bytes += pass_bytes;
+            }
+            for (size_t b0 = 0; b0 < low.size(); b0 += 32) {
+                const size_t cnt = std::min<size_t>(32, low.size() - b0);
+                std::vector<int> qa(cnt), ga(cnt), qb(cnt), gb(cnt);
+                for (size_t i = 0; i < cnt; ++i) {
+                    qa[i] = low[b0 + i][0]; ga[i] = low[b0 + i][1]; qb[i] = low[b0 + i][2]; gb[i] = low[b0 + i][3];
+                }
+                HIPCHK(launch_pp_chunk(c->dtype, c->state, bs, c->batch, n, C, (int)cnt, qa.data(), ga.data(),
+                                       qb.data(), gb.data(), c->stream));
+                acc.passes += 1;
+                acc.launches += 1;
+                acc.hbm_bytes += pass_bytes;
+            }
+            acc.dense_ops += (int)st.gates.size();
+            sv_status rs = rescale(false);
+            if (rs != SV_OK) return rs;
+            continue;
+        }
+        // gates of no cluster kind, one kernel per gate
+        std::vector<sv_gate> sub;
+        for (int gi : st.gates) sub.push_back(circ->gates[gi]);
+        sv_circuit sc = *circ;
+        sc.n_gates = (int32_t)sub.size();
+        sc.gates = sub.data();
+        const int32_t plain0 = c->opts.plain;
+        c->opts.plain = 1;
+        std::vector<IRGate> ir;
+        ProductInit pi;
+        CachedPlan* cp = nullptr;
+        double pms = 0.0;
+        sv_status gs = get_plan(c, &sc, params, false, ir, pi, cp, pms);
+        if (gs == SV_OK) gs = run_plan(c, *cp, ir, c->state, nullptr, nullptr, 0);
+        c->opts.plain = plain0;
+        if (gs != SV_OK) return gs;
+        acc.passes += (int)cp->ep.steps.size();
+        acc.launches += (int)cp->ep.steps.size();
+        acc.hbm_bytes += pass_bytes * (double)cp->ep.steps.size();
+        acc.plan_ms += pms;
+    }
+    {
+        sv_status rs = rescale(true);
+        if (rs != SV_OK) return rs;
+    }
+    if (norm_out) {
+        HIPCHK(c->red_part.ensure(reduce_partials_size(n, c->batch) * sizeof(double)));
+        HIPCHK(launch_reduce(c->dtype, 0, c->state, nullptr, bs, c->batch, n, nullptr, 0, 0,
+                             reinterpret_cast<double*>(c->red_part.p), norm_out, 1, c->stream));
+    }
+    if (stats) *stats = acc;
+    return SV_OK;
+}
+
 sv_status apply_internal(sv_ctx_s* c, const sv_circuit* circ, const double* params, sv_stats* stats,
                          double* norm_out = nullptr) {
+    if (c->opts.paper) return apply_paper(c, circ, params, stats, norm_out);
     std::vector<IRGate> ir;
     ProductInit pi;
     CachedPlan* cp = nullptr;
@@ -616,6 +780,7 @@ sv_status sv_create(sv_ctx* out, int32_t n, sv_dtype dt, int32_t batch, void* d_
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     if (opts) c->opts = *opts; else sv_opts_default(&c->opts);
     if (c->opts.max_work_mib < 0) { delete c; return fail(SV_EINVAL, "max_work_mib must be >= 0"); }
+    if (c->opts.paper < 0 || c->opts.paper > 2) { delete c; return fail(SV_EINVAL, "paper must be 0, 1 or 2"); }
     c->acct.cap = (size_t)c->opts.max_work_mib << 20;
     if (c->opts.max_fuse_k < 0 || c->opts.max_fuse_k > 6) { delete c; return fail(SV_EINVAL, "max_fuse_k must be 0..6"); }
     if (c->opts.tile_bits < 0 || c->opts.tile_bits > kMaxTileBits) { delete c; return fail(SV_EINVAL, "tile_bits must be 0..14"); }
@@ -648,6 +813,7 @@ sv_status sv_set_opts(sv_ctx c, const sv_opts* o) {
     if (o->max_fuse_k < 0 || o->max_fuse_k > 6) return fail(SV_EINVAL, "max_fuse_k must be 0..6");
     if (o->tile_bits < 0 || o->tile_bits > kMaxTileBits) return fail(SV_EINVAL, "tile_bits must be 0..14");
     if (o->max_work_mib < 0) return fail(SV_EINVAL, "max_work_mib must be >= 0");
+    if (o->paper < 0 || o->paper > 2) return fail(SV_EINVAL, "paper must be 0, 1 or 2");
     c->opts = *o;
     c->cache.clear();
     c->acct.cap = (size_t)o->max_work_mib << 20;
@@ -1100,6 +1266,18 @@ sv_status sv_plan_trace(const sv_circuit* circ, const double* params, sv_dtype d
     c.dtype = dtype;
     c.batch = 1;
     if (opts) c.opts = *opts; else sv_opts_default(&c.opts);
+    if (c.opts.paper) {
+        // the paper's plan: one line per kind cluster (bitmasks in binary,
+        // qubit n-1 first) and the circuit gates it applies, in order
+        const std::string tr = paper_trace(paper_plan(circ));
+        *len = tr.size();
+        if (buf && cap) {
+            const size_t m = std::min(cap - 1, tr.size());
+            std::memcpy(buf, tr.data(), m);
+            buf[m] = '\0';
+        }
+        return SV_OK;
+    }
     if (use_plain(&c)) return fail(SV_EUNSUPPORTED, "the plain path has no fused plan to trace");
     BuildOpts bo;
     bo.batch = 1;

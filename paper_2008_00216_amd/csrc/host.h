@@ -89,6 +89,35 @@ uint64_t circuit_hash(const sv_circuit* c, uint64_t seed);
 // values that decided differently.
 uint64_t ir_signature(const std::vector<IRGate>& ir);
 
+// ----------------------------------------------- the paper's own plan (ablation)
+//
+// Kind clusters of Sec. 4.2 formed by the reordering scan of Sec. 4.5, with
+// the bitmask encodings of Sec. 4.3 (8th-root phases as exponent bit-planes,
+// CZ gates as one mask per qubit) and one-qubit layers of one gate kind.
+
+enum PaperStep { PS_DIAG = 0, PS_LAYER = 1, PS_GATES = 2 };
+
+struct PStep {
+    int type = PS_DIAG;
+    int kind = 0;                       // the clustered gate kind (sv_op of the layer; SV_OP_T for DIAG)
+    uint64_t e8[3] = {0, 0, 0};         // PS_DIAG: exponent of w per qubit, bit-planes (mod 8)
+    std::vector<uint64_t> cz;           // PS_DIAG: m_k = partners l < k of the CZ gates on qubit k
+    std::vector<std::pair<int, int>> layer;   // PS_LAYER: (qubit, PaperGate), sorted by qubit
+    std::vector<int> gates;             // circuit gates of the step in execution order
+};
+
+struct PaperPlan {
+    int n = 0;
+    std::vector<PStep> steps;
+};
+
+// Cluster a circuit by kind (Sec. 4.5 scan).  Gates other than the 8th-root
+// diagonals, CZ, H and the square-root family form single-gate PS_GATES steps
+// (consecutive ones merged).
+PaperPlan paper_plan(const sv_circuit* c);
+// Text form of a paper plan (one line per step) for host-side checks.
+std::string paper_trace(const PaperPlan& p);
+
 // Geometry and fusion of the items of one width in a heterogeneous batch
 // (T, L = 0: the defaults).
 struct BatchGeom {

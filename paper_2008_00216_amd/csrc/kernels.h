@@ -21,6 +21,22 @@ hipError_t launch_sf_contract(int dtype, const void* A, const void* B, int nA, i
                               const uint64_t* jA, const uint64_t* jB, uint64_t count, double* acc, int accumulate,
                               hipStream_t s);
 
+// The paper's own plan (ablation).  Diagonal cluster in one pass: amplitude j
+// times e^{i pi e/4}, e = popc(j&e8[0]) + 2 popc(j&e8[1]) + 4 popc(j&e8[2]) +
+// 4 (CZ parity from the one-sided masks d_m1s; d_msym the symmetric ones),
+// both device arrays of n masks.
+hipError_t launch_pp_diag(int dtype, void* state, uint64_t bstride, int batch, int n, const uint64_t* e8,
+                          const uint64_t* d_m1s, const uint64_t* d_msym, hipStream_t s);
+// Unnormalised factor ga on qubit qa and gb on qb (gb < 0: ga alone), one pass.
+hipError_t launch_pp_pair(int dtype, void* state, uint64_t bstride, int batch, int n, int qa, int ga, int qb, int gb,
+                          hipStream_t s);
+// nops (<= 32) pairs / single gates on qubits < C over chunks of 2^C contiguous amplitudes in LDS.
+hipError_t launch_pp_chunk(int dtype, void* state, uint64_t bstride, int batch, int n, int C, int nops,
+                           const int* qa, const int* ga, const int* qb, const int* gb, hipStream_t s);
+// Every amplitude times (re + i im).
+hipError_t launch_pp_scale(int dtype, void* state, uint64_t bstride, int batch, int n, double re, double im,
+                           hipStream_t s);
+
 // Dynamic LDS bytes a tile pass needs.
 size_t tile_lds_bytes(int dtype, bool two, uint32_t T, uint32_t nform, uint32_t ngrad, int nt);
 hipError_t launch_tile_pass(int dtype, bool two, int nt, const TileArgs& a, uint64_t nblocks,

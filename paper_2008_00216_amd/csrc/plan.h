@@ -28,6 +28,46 @@ constexpr int kMaxTileBits = 14;      // local qubits per tile pass
 constexpr int kMaxHigh = 12;          // high local bits per pass
 constexpr int kMaxGradPerPass = 128;  // gradient slots reduced per pass
 
+// Unnormalised one-qubit factors of the paper's multiply-free family (the
+// paper's own plan, Sec. 4.4): H = H'/sqrt(2), sqrt(X)(dg) = sqrt(X)(dg)'/2,
+// sqrt(Y)(dg) = w^(+-1) sqrt(Y)(dg)'/sqrt(2) with w = e^{i pi/4}; PG_GEN is
+// any other one-qubit matrix (applied as it is).
+enum PaperGate { PG_H = 0, PG_SX = 1, PG_SXDG = 2, PG_SY = 3, PG_SYDG = 4, PG_GEN = 5 };
+
+// Entries re + i im of the unnormalised factors:
+//   H' = [[1, 1], [1, -1]],  sqrt(X)' = [[1+i, 1-i], [1-i, 1+i]],
+//   sqrt(X)dg' = [[1-i, 1+i], [1+i, 1-i]],  sqrt(Y)' = [[1, -1], [1, 1]],
+//   sqrt(Y)dg' = [[1, 1], [-1, 1]].
+struct GInt {
+    int re, im;
+};
+constexpr GInt gmul(GInt a, GInt b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+constexpr GInt pg_fac(int g, int r, int c) {
+    return g == PG_H ? ((r & c) ? GInt{-1, 0} : GInt{1, 0})
+         : g == PG_SX ? (r == c ? GInt{1, 1} : GInt{1, -1})
+         : g == PG_SXDG ? (r == c ? GInt{1, -1} : GInt{1, 1})
+         : g == PG_SY ? ((r == 0 && c == 1) ? GInt{-1, 0} : GInt{1, 0})
+                      : ((r == 1 && c == 0) ? GInt{-1, 0} : GInt{1, 0});
+}
+// Entry (r, c) of ga' (x) gb' (ga on local bit 0, gb on local bit 1).
+constexpr GInt pg_pair(int ga, int gb, int r, int c) {
+    return gmul(pg_fac(ga, r & 1, c & 1), pg_fac(gb, r >> 1, c >> 1));
+}
+// True when every entry of ga' (x) gb' is twice a Gaussian integer (as for
+// sqrt(X)' (x) sqrt(X)'); the pair is then applied with the entries halved and
+// one factor 1/2 fewer in the scale counter.
+constexpr bool pg_pair_even(int ga, int gb) {
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+            const GInt v = pg_pair(ga, gb, r, c);
+            if ((v.re & 1) || (v.im & 1)) return false;
+        }
+    return true;
+}
+// Powers of 1/sqrt(2) factored out of one unnormalised gate, and of w.
+constexpr int pg_scale_pow(int g) { return (g == PG_SX || g == PG_SXDG) ? 2 : 1; }
+constexpr int pg_phase8(int g) { return g == PG_SY ? 1 : g == PG_SYDG ? 7 : 0; }
+
 enum OpType : uint32_t {
     OP_DENSE = 1,   // k <= 4 slots (mask in `mask`), matrix at `arg` (pool elements)
     OP_DIAGR = 2,   // diagonal on slots `mask`, 2^k entries at `arg`
