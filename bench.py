@@ -80,6 +80,9 @@ def parse():
     p.add_argument("--no-sf", action="store_true")
     p.add_argument("--sf-only", action="store_true", help="only the Schroedinger-Feynman leg")
     p.add_argument("--batch-only", action="store_true", help="only the 512-circuit batch leg")
+    p.add_argument("--dense-blocks", action="store_true",
+                   help="4 random 5-qubit and 4 random 6-qubit unitaries on a 30-qubit complex128 state, one "
+                        "kernel each (the MFMA dense-block kernel)")
     p.add_argument("--ksweep", action="store_true", help="30-qubit dense-width sweep instead of the benchmark")
     p.add_argument("--ablation", action="store_true",
                    help="32-qubit ablation and gate-category profile instead of the benchmark")
@@ -741,6 +744,41 @@ def ablation(sv, W, torch, np, steps=1):
     print(json.dumps(out), flush=True)
 
 
+def dense_blocks(sv, W, torch, np, n=30, reps=4):
+    """Explicit 5- and 6-qubit unitaries (random, from a QR of complex
+    Gaussians; seeded) on random targets of a 2^30-amplitude complex128
+    state, one kernel per gate (the MFMA dense-block kernel), `reps` of each
+    width; HIP-event time per gate."""
+    rng = np.random.default_rng(30)
+    s = sv.StateVector(n, torch.complex128, opts=sv.make_opts(plain=1))
+    s.init("uniform")
+    out = {"workload": f"{n}-qubit complex128 state, {reps} random 5-qubit and {reps} random 6-qubit unitaries"}
+    for k in (5, 6):
+        gates = []
+        for _ in range(reps):
+            z = rng.standard_normal((1 << k, 1 << k)) + 1j * rng.standard_normal((1 << k, 1 << k))
+            q, r = np.linalg.qr(z)
+            gates.append(W.Gate("MAT", tuple(int(x) for x in rng.permutation(n)[:k]),
+                                mat=(q * (np.diag(r) / np.abs(np.diag(r)))).astype(np.complex128)))
+        c = sv.CircuitABI(W.Circuit(n, gates, 0, f"dense{k}"))
+        s.apply(c)                                   # warm-up: plans
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        st = s.apply(c)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        flops = float(1 << n) * 8 * (1 << k)
+        out[f"k{k}"] = {"ms_per_gate": ms, "fp64_TFLOPs": flops / (ms / 1e3) / 1e12,
+                        "hbm_TBs": 2.0 * (1 << n) * 16 / (ms / 1e3) / 1e12}
+    nrm = float(s.norm()[0])
+    out["norm_error"] = abs(nrm - 1.0)
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
 def ksweep(sv, W, torch, steps=2):
     """5x6 grid, 30 qubits, 20 cycles, complex64 and complex128: the
     butterfly mode against dense blocks of at most k qubits (k = 1..6).  One
@@ -794,6 +832,9 @@ def main():
         return
     if args.ablation:
         ablation(sv, W, torch, np)
+        return
+    if args.dense_blocks:
+        print(json.dumps(dense_blocks(sv, W, torch, np)), flush=True)
         return
     if args.sf_only:
         print(json.dumps(sf_leg(sv, W, torch, np)), flush=True)

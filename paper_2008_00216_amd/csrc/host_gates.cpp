@@ -505,6 +505,7 @@ std::vector<IRGate> build_ir(const sv_circuit* c, const double* params, const Bu
         if (g.grad || g.k != 1) return false;
         if (o.backward && g.param >= 0) return false;
         if (g.skind) return false;
+        if (o.structured && g.perm != PK_NONE) return false;   // applied as a register permutation
         if (o.structured && g.kind == K_DIAG8) return false;
         return true;
     };

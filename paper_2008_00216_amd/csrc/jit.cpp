@@ -125,6 +125,14 @@ std::string pass_source(const EncodedPlan& ep, int pi, int dtype, bool two, int 
                     o << " }\n";
                     break;
                 }
+                case OP_PERM: {
+                    const uint32_t sa = op.mask & 3u, sb = op.k <= 2 ? sa : (op.mask >> 2) & 3u;
+                    const std::string targs = std::to_string(op.k) + ", " + std::to_string(sa) + ", " +
+                                              std::to_string(sb);
+                    o << "      op_perm<R, " << targs << ">(a);\n";
+                    if (two) o << "      op_perm<R, " << targs << ">(l);\n";
+                    break;
+                }
                 case OP_SCALE:
                     o << "      { const R s_ = F.pool[" << op.arg << "].x; op_scale<R>(a, s_);";
                     if (two) o << " op_scale<R>(l, s_);";

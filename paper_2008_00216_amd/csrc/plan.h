@@ -77,7 +77,13 @@ enum OpType : uint32_t {
     OP_SCALE = 6,   // multiply by the real scalar at pool element `arg` (.x)
     OP_BF = 11,     // twiddled butterfly, see below
     OP_D1T = 12,    // one-qubit 2x2 matrix at `arg` with a +-1 input sign, see below
+    OP_PERM = 13,   // exact permutation on register slots, see below
 };
+
+// OP_PERM: X (k = 1) or Y (k = 2) on slot a, CNOT (k = 3, control a, target
+// b) or SWAP (k = 4) of slots a and b; mask = a | b << 2.  Amplitudes move
+// between registers (renamed away in the specialised kernels); Y also
+// multiplies by +-i (a swap of real and imaginary parts and one sign).
 
 // OP_BF on register slot S: for every pair (x, y) of amplitudes that differ
 // only in slot S (y has the bit set),

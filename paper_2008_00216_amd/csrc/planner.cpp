@@ -681,6 +681,23 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
                     out.alu_ops += ((M & 1) ? 3.0 : 2.0) * (double)(1ull << n) * (cfg.two ? 2 : 1);
                     continue;
                 }
+                if (g.perm != PK_NONE && g.kind == K_DENSE && !g.grad &&
+                    g.k == ((g.perm == PK_X || g.perm == PK_Y) ? 1 : 2)) {
+                    // X, Y, CNOT, SWAP: amplitudes change registers, no
+                    // arithmetic (Y: a swap of real and imaginary parts and
+                    // a sign); pending phases on its qubits are applied first
+                    if (pending.depends(g.qmask())) flush(false);
+                    const uint32_t sa = (uint32_t)slot_of_q[0], sb = g.k > 1 ? (uint32_t)slot_of_q[1] : sa;
+                    DOp op{(uint32_t)OP_PERM, (uint32_t)g.perm, sa | (sb << 2), 0u};
+                    out.ops.push_back(op);
+                    if (tr) {
+                        *tr += "PERM " + std::to_string(g.perm) + " " + std::to_string(g.q[0]);
+                        if (g.k > 1) *tr += " " + std::to_string(g.q[1]);
+                        *tr += "\n";
+                    }
+                    out.alu_ops += (g.perm == PK_Y ? 1.0 : 0.0) * (double)(1ull << n) * (cfg.two ? 2 : 1);
+                    continue;
+                }
                 if (g.kind == K_DENSE && g.k == 1 && !g.grad) {
                     // one-qubit matrix: the pending phase of q folds into its
                     // second column, the partner signs into the kernel

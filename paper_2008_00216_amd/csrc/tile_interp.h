@@ -160,6 +160,29 @@ __device__ __forceinline__ double grad_dispatch(const V2<R>* p, const V2<R>* l, 
     }
 }
 
+#define SVMI_PERM1(K, S) \
+    case (K) * 16 + (S) * 4 + (S): op_perm<R, K, S, S>(a); break;
+#define SVMI_PERM2(K, A, B) \
+    case (K) * 16 + (A) * 4 + (B): op_perm<R, K, A, B>(a); break;
+
+template <class R>
+__device__ __forceinline__ void perm_dispatch(V2<R>* a, uint32_t kind, uint32_t mask) {
+    const uint32_t sa = mask & 3u, sb = (mask >> 2) & 3u;
+    switch (kind * 16 + sa * 4 + (kind <= 2 ? sa : sb)) {
+        SVMI_PERM1(1, 0) SVMI_PERM1(1, 1) SVMI_PERM1(1, 2) SVMI_PERM1(1, 3)
+        SVMI_PERM1(2, 0) SVMI_PERM1(2, 1) SVMI_PERM1(2, 2) SVMI_PERM1(2, 3)
+        SVMI_PERM2(3, 0, 1) SVMI_PERM2(3, 0, 2) SVMI_PERM2(3, 0, 3) SVMI_PERM2(3, 1, 0)
+        SVMI_PERM2(3, 1, 2) SVMI_PERM2(3, 1, 3) SVMI_PERM2(3, 2, 0) SVMI_PERM2(3, 2, 1)
+        SVMI_PERM2(3, 2, 3) SVMI_PERM2(3, 3, 0) SVMI_PERM2(3, 3, 1) SVMI_PERM2(3, 3, 2)
+        SVMI_PERM2(4, 0, 1) SVMI_PERM2(4, 0, 2) SVMI_PERM2(4, 0, 3) SVMI_PERM2(4, 1, 0)
+        SVMI_PERM2(4, 1, 2) SVMI_PERM2(4, 1, 3) SVMI_PERM2(4, 2, 0) SVMI_PERM2(4, 2, 1)
+        SVMI_PERM2(4, 2, 3) SVMI_PERM2(4, 3, 0) SVMI_PERM2(4, 3, 1) SVMI_PERM2(4, 3, 2)
+        default: break;
+    }
+}
+#undef SVMI_PERM1
+#undef SVMI_PERM2
+
 __device__ __forceinline__ DOp ld_op(cptr_t<DOp> p) {
     return DOp{p->type, p->k, p->mask, p->arg};
 }
@@ -256,6 +279,10 @@ __device__ __forceinline__ void tile_interp(const TileArgs& A, unsigned char* sm
                         if constexpr (TWO) d1t_dispatch<R>(l, kk & 3u, real, pool + arg, (kk >> 2) & 15u, sg);
                         break;
                     }
+                    case OP_PERM:
+                        perm_dispatch<R>(a, rfl(op.k), mask);
+                        if constexpr (TWO) perm_dispatch<R>(l, rfl(op.k), mask);
+                        break;
                     case OP_SCALE: {
                         const R s = pool[arg].x;
                         op_scale<R>(a, s);

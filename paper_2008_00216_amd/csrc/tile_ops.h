@@ -401,4 +401,40 @@ __device__ __forceinline__ double op_grad11(const V2<R>* p, const V2<R>* l) {
     return -2.0 * (double)acc;
 }
 
+// Exact permutation on register slots (OP_PERM): KIND 1 = X on slot SA,
+// 2 = Y on slot SA, 3 = CNOT (control SA, target SB), 4 = SWAP(SA, SB).
+template <class R, int KIND, int SA, int SB>
+__device__ __forceinline__ void op_perm(V2<R>* a) {
+    constexpr uint32_t ma = 1u << SA, mb = 1u << SB;
+#pragma unroll
+    for (uint32_t i = 0; i < 16; ++i) {
+        if constexpr (KIND == 1) {
+            if (!(i & ma)) {
+                const V2<R> x = a[i];
+                a[i] = a[i | ma];
+                a[i | ma] = x;
+            }
+        } else if constexpr (KIND == 2) {
+            if (!(i & ma)) {   // (x, y) <- (-i y, i x)
+                const V2<R> x = a[i], y = a[i | ma];
+                a[i] = V2<R>{y.y, -y.x};
+                a[i | ma] = V2<R>{-x.y, x.x};
+            }
+        } else if constexpr (KIND == 3) {
+            if ((i & ma) && !(i & mb)) {
+                const V2<R> x = a[i];
+                a[i] = a[i | mb];
+                a[i | mb] = x;
+            }
+        } else {
+            if ((i & ma) && !(i & mb)) {
+                const uint32_t j = i ^ ma ^ mb;
+                const V2<R> x = a[i];
+                a[i] = a[j];
+                a[j] = x;
+            }
+        }
+    }
+}
+
 }  // namespace svmi

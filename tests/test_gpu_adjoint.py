@@ -92,7 +92,7 @@ def test_autograd_function():
     e2 = m.Energy.apply(th.detach(), s, c, h)
     for b in range(2):
         assert abs(float(e2[b]) - oracle.energy(c, th.detach().numpy()[b], h)) < 1e-10
-        assert abs(float(e2[b]) - float(e[b])) < 1e-10
+        assert abs(float(e2[b]) - float(e.detach()[b])) < 1e-10
 
 
 @pytest.mark.parametrize("jit", [-1, 1])

@@ -61,3 +61,54 @@ def test_jit_adjoint():
         assert abs(e[b] - oracle.energy(c, th[b], h)) < 2e-4
         ref = oracle.grad_param_shift(c, th[b], h, which=list(range(0, c.n_params, 9)))
         np.testing.assert_allclose(g[b][::9], ref, atol=2e-4)
+
+
+@pytest.mark.parametrize("jit", [1, -1])
+def test_permutation_circuits_exact_in_tile_passes(jit):
+    """X, Y, CNOT, SWAP with Z, S, CZ: register permutations and sign flips
+    only, so the fused sweep (specialised or interpreted) equals the oracle
+    exactly (+0 and -0 compare equal)."""
+    m = lib()
+    n = 17
+    c = W.random_circuit(n, 300, 31, ops=("X", "Y", "CNOT", "SWAP", "Z", "S", "SDG", "CZ"))
+    psi0 = round_c64(W.random_state(n, 32))
+    ref = oracle.simulate(c, None, psi0)
+    for dtype in (torch.complex64, torch.complex128):
+        t = to_dev(psi0, dtype)
+        s = m.StateVector(n, dtype, tensor=t, opts=m.make_opts(jit=jit))
+        st = s.apply(c)
+        assert st["dense_ops"] == 0
+        assert np.array_equal(to_host(t)[0], ref), (jit, dtype)
+
+
+def test_permutations_in_the_batch_and_adjoint():
+    m = lib()
+    n = 12
+    gates = []
+    p = 0
+    rng = np.random.default_rng(5)
+    for layer in range(6):
+        for q in range(n):
+            gates.append(W.Gate("RY", (q,), param=p)); p += 1
+        for q in range(layer % 2, n - 1, 2):
+            gates.append(W.Gate(("CNOT", "SWAP", "CZ")[int(rng.integers(0, 3))], (q, q + 1)))
+        gates.append(W.Gate("X", (int(rng.integers(0, n)),)))
+        gates.append(W.Gate("Y", (int(rng.integers(0, n)),)))
+    c = W.Circuit(n, gates, p, "perm-ansatz")
+    h = W.ansatz_observable(n)
+    th = W.uniform_params(2, c.n_params, 3)
+    s = m.StateVector(n, torch.complex64, batch=2)
+    s.init("zero_deferred")
+    e, g = s.adjoint_grad(c, th, h)
+    circs, params, states, lams = [c, c], [th[0], th[1]], [], []
+    for b in range(2):
+        states.append(torch.zeros(1 << n, dtype=torch.complex64, device="cuda"))
+        lams.append(torch.zeros(1 << n, dtype=torch.complex64, device="cuda"))
+    eb, gb, _ = m.apply_batch(circs, params, states, [h, h], lambdas=lams, grad=True)
+    for b in range(2):
+        ref = oracle.energy(c, th[b], h)
+        assert abs(e[b] - ref) < 2e-5 and abs(eb[b] - ref) < 2e-5
+        which = list(range(0, c.n_params, 7))
+        gref = oracle.grad_param_shift(c, th[b], h, which=which)
+        np.testing.assert_allclose(g[b][which], gref, atol=2e-5)
+        np.testing.assert_allclose(gb[b][which], gref, atol=2e-5)

@@ -160,3 +160,21 @@ def test_scale_factor_applied_inside_long_passes():
     sel = list(range(0, c.n_params, 37))
     ref = oracle.grad_param_shift(c, p, h, psi0)
     np.testing.assert_allclose([grads[i] for i in sel], ref[sel], atol=1e-10)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_permutation_gates_are_register_permutations(seed):
+    """X, Y, CNOT and SWAP run as register permutations (PERM lines), never
+    as dense matrices, and the plan still equals the oracle."""
+    m = lib()
+    ops = ("H", "T", "CZ", "SQRTX", "X", "Y", "CNOT", "SWAP", "S")
+    c = W.random_circuit(9, 150, seed=300 + seed, ops=ops)
+    psi0 = W.random_state(9, 40 + seed)
+    tr = _check(m, c, None, tile_bits=7, low_bits=3, psi0=psi0)
+    lines = tr.splitlines()
+    nperm = sum(1 for g in c.gates if g.op in ("X", "Y", "CNOT", "SWAP"))
+    assert sum(1 for l in lines if l.startswith("PERM ")) == nperm
+    assert not any(l.startswith("DENSE ") for l in lines)
+    # adjoint plans too (inverse gates in reverse order)
+    tr_b = m.plan_trace(c, None, opts=m.make_opts(tile_bits=7, low_bits=3), adjoint=True)
+    assert sum(1 for l in tr_b.splitlines() if l.startswith("PERM ")) == nperm

@@ -88,6 +88,22 @@ def _apply_line(f, line, n, psi, j, bit):
             for t, qq in enumerate(qs):
                 loc |= bit[qq] << t
             psi *= z[loc]
+    elif f[0] == "PERM":
+        # PERM kind q [q2]: 1 = X, 2 = Y, 3 = CNOT (control q, target q2), 4 = SWAP
+        kind, q = int(f[1]), int(f[2])
+        src = j.copy()
+        if kind in (1, 2):
+            src = j ^ (1 << q)
+        elif kind == 3:
+            q2 = int(f[3])
+            src = np.where(bit[q] == 1, j ^ (1 << q2), j)
+        else:
+            q2 = int(f[3])
+            src = np.where(bit[q] != bit[q2], j ^ (1 << q) ^ (1 << q2), j)
+        out = psi[src]
+        if kind == 2:                   # Y: (Y psi)_j = i psi_{j^q} if bit q of j is 1, else -i
+            out = np.where(bit[q] == 1, 1j, -1j) * out
+        psi[:] = out
     elif f[0] == "SCALE":
         psi *= float(f[1])
     else:
