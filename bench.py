@@ -80,6 +80,10 @@ def parse():
     p.add_argument("--no-sf", action="store_true")
     p.add_argument("--sf-only", action="store_true", help="only the Schroedinger-Feynman leg")
     p.add_argument("--batch-only", action="store_true", help="only the 512-circuit batch leg")
+    p.add_argument("--batch-tune-file", default=None,
+                   help="with --batch-only: use the batch tuning stored in this file (SVMI_BATCH_TUNE_CACHE) "
+                        "instead of tuning and timing the default geometry")
+    p.add_argument("--c128-only", action="store_true", help="only the complex128 sweep leg")
     p.add_argument("--dense-blocks", action="store_true",
                    help="4 random 5-qubit and 4 random 6-qubit unitaries on a 30-qubit complex128 state, one "
                         "kernel each (the MFMA dense-block kernel)")
@@ -363,7 +367,7 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def batch_leg(sv, W, torch, np, count=512):
+def batch_leg(sv, W, torch, np, count=512, tune_file=None):
     """512 circuits, n ~ U{10..22}, 20..60 layers (RY + a random gate per qubit
     + CZ), observable sum Z_i: energies and adjoint gradients of all of them
     in one persistent launch, against the same work one circuit at a time."""
@@ -375,20 +379,26 @@ def batch_leg(sv, W, torch, np, count=512):
     states = [torch.empty(1 << c.n, dtype=torch.complex64, device="cuda") for c in circs]
     lams = [torch.empty_like(t) for t in states]
     progress(f"batch: {count} circuits generated")
-    e, g, st = sv.apply_batch(circs, params, states, obs, lambdas=lams, grad=True, init_zero=True)
-    torch.cuda.synchronize()
-    progress("batch: first persistent launch done (plans built)")
-    reps = 3
-    t0 = time.perf_counter()
-    for _ in range(reps):
+    if tune_file is None:
         e, g, st = sv.apply_batch(circs, params, states, obs, lambdas=lams, grad=True, init_zero=True)
-    torch.cuda.synchronize()
-    t_default = (time.perf_counter() - t0) / reps
-    progress(f"batch: {t_default * 1e3:.1f} ms per launch with the default geometry")
-    # per-width fusion mode and tile geometry by measurement
-    t0 = time.perf_counter()
-    ntuned = sv.tune_batch(circs, params, states, obs, lambdas=lams, grad=True)
-    t_tune = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        progress("batch: first persistent launch done (plans built)")
+    reps = 3
+    t_default = None
+    if tune_file is None:
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            e, g, st = sv.apply_batch(circs, params, states, obs, lambdas=lams, grad=True, init_zero=True)
+        torch.cuda.synchronize()
+        t_default = (time.perf_counter() - t0) / reps
+        progress(f"batch: {t_default * 1e3:.1f} ms per launch with the default geometry")
+        # per-width fusion mode and tile geometry by measurement
+        t0 = time.perf_counter()
+        ntuned = sv.tune_batch(circs, params, states, obs, lambdas=lams, grad=True)
+        t_tune = time.perf_counter() - t0
+    else:
+        # choices of an earlier sv_tune_batch run, read from its file
+        ntuned, t_tune = -1, 0.0
     widths = sorted({c.n for c in circs_py})
     tuning = {int(w): sv.batch_tuning(w, grad=True) for w in widths}
     topts = sv.make_opts(batch_tuned=1)
@@ -823,10 +833,22 @@ def main():
     import numpy as np
     import torch
 
+    if args.batch_tune_file:
+        os.environ["SVMI_BATCH_TUNE_CACHE"] = args.batch_tune_file
     import paper_2008_00216_amd as sv
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.calib_copy_gib > 0:
+        nb = int(args.calib_copy_gib * (1 << 30))
+        a = torch.empty(nb // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        torch.cuda.empty_cache()
     if args.ksweep:
         ksweep(sv, W, torch)
         return
@@ -840,18 +862,11 @@ def main():
         print(json.dumps(sf_leg(sv, W, torch, np)), flush=True)
         return
     if args.batch_only:
-        print(json.dumps(batch_leg(sv, W, torch, np)), flush=True)
+        print(json.dumps(batch_leg(sv, W, torch, np, tune_file=args.batch_tune_file)), flush=True)
         return
-    if args.calib_copy_gib > 0:
-        nb = int(args.calib_copy_gib * (1 << 30))
-        a = torch.empty(nb // 4, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        a.fill_(1.0)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-        torch.cuda.empty_cache()
+    if args.c128_only:
+        print(json.dumps(c128_leg(sv, W, torch)), flush=True)
+        return
 
     cols = args.qubits // 3
     circ = W.grid_circuit(3, cols, args.cycles, seed=1002)
