@@ -10,6 +10,7 @@
 // of a phase form, general diagonals (RZ, P, CP) stay diagonal, everything
 // else is a dense (non-diagonal) gate.  With `structured`, H, sqrt(X),
 // sqrt(Y) and sqrt(W) keep their factored multiply-free form (Sec. 4.4).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <sstream>
@@ -580,29 +581,10 @@ std::vector<IRGate> build_ir(const sv_circuit* c, const double* params, const Bu
     return res;
 }
 
-// Full 2^k x 2^k matrix of an IR gate for state b (any kind).
-static std::vector<cd> full_matrix(const IRGate& g, int b) {
-    const int d = 1 << g.k;
-    std::vector<cd> u((size_t)d * d, 0.0);
-    if (g.kind == K_DIAG8) {
-        const double c = std::sqrt(0.5);
-        const cd tab[8] = {cd(1, 0), cd(c, c), cd(0, 1), cd(-c, c), cd(-1, 0), cd(-c, -c), cd(0, -1), cd(c, -c)};
-        for (int l = 0; l < d; ++l) {
-            int e = 0;
-            if (l & 1) e += g.alpha[0];
-            if (g.k > 1 && (l & 2)) e += g.alpha[1];
-            if (g.k > 1 && (l & 3) == 3) e += g.beta;
-            u[(size_t)l * d + l] = tab[e & 7];
-        }
-        return u;
-    }
-    const cd* m = g.m.at(b);
-    if (g.m.diag) {
-        for (int l = 0; l < d; ++l) u[(size_t)l * d + l] = m[l];
-    } else {
-        std::copy(m, m + (size_t)d * d, u.begin());
-    }
-    return u;
+// Complex product without the library's inf/NaN recovery (all entries here
+// are finite).
+static inline cd cmul_plain(cd a, cd b) {
+    return cd(a.real() * b.real() - a.imag() * b.imag(), a.real() * b.imag() + a.imag() * b.real());
 }
 
 // Dense blocks of at most kmax qubits (Sec. 4.2 contrasts this with its own
@@ -612,18 +594,27 @@ static std::vector<cd> full_matrix(const IRGate& g, int b) {
 // closed (emitted) and the gate starts a new one.  Products are formed in
 // FP64 and rounded once when the plan's matrix pool is filled.  Gradient
 // pseudo-gates and wider gates close the blocks on their qubits.
+//
+// Block members are kept as linked lists over the input indices (merging
+// blocks concatenates lists) and the products are formed in reused buffers,
+// so a block costs one allocation, for its own matrix.
 std::vector<IRGate> fuse_blocks(std::vector<IRGate>&& in, int kmax, int n) {
     (void)n;
     struct Blk {
-        std::vector<int> gates;   // member indices into `in`, in order
-        uint64_t qm = 0;
+        uint64_t qm;
+        int head, tail, count;   // member list in circuit order (links in `nxt`)
     };
+    std::vector<int> nxt(in.size(), -1);
     std::vector<IRGate> out;
     out.reserve(in.size());
     std::vector<Blk> open;
+    open.reserve(64);
+    std::vector<cd> U, gath;
+    const double c8 = std::sqrt(0.5);
+    const cd tab8[8] = {cd(1, 0), cd(c8, c8), cd(0, 1), cd(-c8, c8), cd(-1, 0), cd(-c8, -c8), cd(0, -1), cd(c8, -c8)};
     auto emit = [&](const Blk& B) {
-        if (B.gates.size() == 1) {
-            out.push_back(in[B.gates[0]]);
+        if (B.count == 1) {
+            out.push_back(std::move(in[B.head]));
             return;
         }
         IRGate f;
@@ -631,10 +622,10 @@ std::vector<IRGate> fuse_blocks(std::vector<IRGate>&& in, int kmax, int n) {
         for (int q = 0; q < 64; ++q) if ((B.qm >> q) & 1) qs[k++] = q;
         f.k = k;
         for (int t = 0; t < k; ++t) f.q[t] = qs[t];
-        f.src = in[B.gates[0]].src;
+        f.src = in[B.head].src;
         int nb = 1;
         bool diag = true, real = true;
-        for (int gi : B.gates) {
+        for (int gi = B.head; gi >= 0; gi = nxt[gi]) {
             const IRGate& g = in[gi];
             if (g.kind == K_DENSE) diag = false;
             if (!real_gate(g)) real = false;
@@ -645,37 +636,65 @@ std::vector<IRGate> fuse_blocks(std::vector<IRGate>&& in, int kmax, int n) {
         f.m.nb = nb;
         f.m.diag = diag;
         f.m.v.assign((size_t)nb * (diag ? D : (size_t)D * D), 0.0);
-        std::vector<cd> U((size_t)D * D), col((size_t)D), tmp;
+        U.resize((size_t)D * D);
+        gath.resize((size_t)D * D);
         for (int b = 0; b < nb; ++b) {
             std::fill(U.begin(), U.end(), cd(0.0));
             for (int i = 0; i < D; ++i) U[(size_t)i * D + i] = 1.0;
-            for (int gi : B.gates) {
+            for (int gi = B.head; gi >= 0; gi = nxt[gi]) {
                 const IRGate& g = in[gi];
                 const int kg = g.k, dg = 1 << kg;
-                const std::vector<cd> G = full_matrix(g, g.kind == K_DIAG8 || g.m.nb == 1 ? 0 : b);
                 int pos[6];
                 for (int t = 0; t < kg; ++t)
                     for (int s2 = 0; s2 < k; ++s2) if (qs[s2] == g.q[t]) pos[t] = s2;
+                // block-local index of gate-local index l (bits deposited at pos)
+                int dep[64];
                 uint32_t gmask = 0;
                 for (int t = 0; t < kg; ++t) gmask |= 1u << pos[t];
-                tmp.assign((size_t)dg, 0.0);
-                for (int c = 0; c < D; ++c) {          // U <- G_emb U, column by column
-                    for (int r = 0; r < D; ++r) col[r] = U[(size_t)r * D + c];
-                    for (int base = 0; base < D; ++base) {
-                        if (base & gmask) continue;
-                        for (int l = 0; l < dg; ++l) {
-                            cd acc = 0.0;
-                            for (int l2 = 0; l2 < dg; ++l2) {
-                                int idx = base;
-                                for (int t = 0; t < kg; ++t) if ((l2 >> t) & 1) idx |= 1 << pos[t];
-                                acc += G[(size_t)l * dg + l2] * col[idx];
-                            }
-                            tmp[l] = acc;
+                for (int l = 0; l < dg; ++l) {
+                    int idx = 0;
+                    for (int t = 0; t < kg; ++t) if ((l >> t) & 1) idx |= 1 << pos[t];
+                    dep[l] = idx;
+                }
+                if (g.kind == K_DIAG8 || g.m.diag) {
+                    // U <- diag(G_emb) U: scale the rows
+                    const cd* m = g.kind == K_DIAG8 ? nullptr : g.m.at(g.m.nb == 1 ? 0 : b);
+                    for (int l = 0; l < dg; ++l) {
+                        cd v;
+                        if (!m) {
+                            int e = 0;
+                            if (l & 1) e += g.alpha[0];
+                            if (kg > 1 && (l & 2)) e += g.alpha[1];
+                            if (kg > 1 && (l & 3) == 3) e += g.beta;
+                            v = tab8[e & 7];
+                        } else {
+                            v = m[l];
                         }
-                        for (int l = 0; l < dg; ++l) {
-                            int idx = base;
-                            for (int t = 0; t < kg; ++t) if ((l >> t) & 1) idx |= 1 << pos[t];
-                            U[(size_t)idx * D + c] = tmp[l];
+                        for (int base = 0; base < D; ++base) {
+                            if (base & gmask) continue;
+                            cd* row = U.data() + (size_t)(base | dep[l]) * D;
+                            for (int c = 0; c < D; ++c) {
+                                // + 0.0 keeps the zeros positive, as a sum started from 0 does
+                                const cd r = cmul_plain(v, row[c]);
+                                row[c] = cd(r.real() + 0.0, r.imag() + 0.0);
+                            }
+                        }
+                    }
+                    continue;
+                }
+                // U <- G_emb U: rows base|dep[l] mix through G, all columns at once
+                const cd* G = g.m.at(g.m.nb == 1 ? 0 : b);
+                for (int base = 0; base < D; ++base) {
+                    if (base & gmask) continue;
+                    for (int l = 0; l < dg; ++l)
+                        std::copy_n(U.data() + (size_t)(base | dep[l]) * D, D, gath.data() + (size_t)l * D);
+                    for (int l = 0; l < dg; ++l) {
+                        cd* row = U.data() + (size_t)(base | dep[l]) * D;
+                        for (int c = 0; c < D; ++c) row[c] = 0.0;
+                        for (int l2 = 0; l2 < dg; ++l2) {
+                            const cd x = G[(size_t)l * dg + l2];
+                            const cd* src = gath.data() + (size_t)l2 * D;
+                            for (int c = 0; c < D; ++c) row[c] += cmul_plain(x, src[c]);
                         }
                     }
                 }
@@ -689,43 +708,51 @@ std::vector<IRGate> fuse_blocks(std::vector<IRGate>&& in, int kmax, int n) {
         f.param = -1;
         f.gen = 0;
         f.perm = PK_NONE;
-        out.push_back(f);
+        out.push_back(std::move(f));
     };
+    // emit the open blocks that touch qm (in order) and keep the others (in order)
     auto close_touching = [&](uint64_t qm) {
-        std::vector<Blk> keep;
-        for (Blk& B : open) {
-            if (B.qm & qm) emit(B);
-            else keep.push_back(std::move(B));
+        size_t w = 0;
+        for (size_t r = 0; r < open.size(); ++r) {
+            if (open[r].qm & qm) emit(open[r]);
+            else open[w++] = open[r];
         }
-        open.swap(keep);
+        open.resize(w);
     };
     for (size_t i = 0; i < in.size(); ++i) {
         const IRGate& g = in[i];
         const uint64_t qm = g.qmask();
         if (g.grad || g.k > kmax || g.skind) {
             close_touching(qm);
-            out.push_back(g);
+            out.push_back(std::move(in[i]));
             continue;
         }
         uint64_t un = qm;
         for (const Blk& B : open) if (B.qm & qm) un |= B.qm;
         if (__builtin_popcountll(un) <= kmax) {
-            Blk nbk;
-            nbk.qm = un;
-            std::vector<Blk> keep;
-            for (Blk& B : open) {
-                if (B.qm & qm) nbk.gates.insert(nbk.gates.end(), B.gates.begin(), B.gates.end());
-                else keep.push_back(std::move(B));
+            // merge the touching blocks (in order) and the gate into one block at the end
+            Blk nbk{un, -1, -1, 0};
+            size_t w = 0;
+            for (size_t r = 0; r < open.size(); ++r) {
+                const Blk& B = open[r];
+                if (B.qm & qm) {
+                    if (nbk.head < 0) nbk.head = B.head;
+                    else nxt[nbk.tail] = B.head;
+                    nbk.tail = B.tail;
+                    nbk.count += B.count;
+                } else {
+                    open[w++] = B;
+                }
             }
-            nbk.gates.push_back((int)i);
-            keep.push_back(std::move(nbk));
-            open.swap(keep);
+            open.resize(w);
+            if (nbk.head < 0) nbk.head = (int)i;
+            else nxt[nbk.tail] = (int)i;
+            nbk.tail = (int)i;
+            nbk.count += 1;
+            open.push_back(nbk);
         } else {
             close_touching(qm);
-            Blk nbk;
-            nbk.qm = qm;
-            nbk.gates.push_back((int)i);
-            open.push_back(std::move(nbk));
+            open.push_back(Blk{qm, (int)i, (int)i, 1});
         }
     }
     for (const Blk& B : open) emit(B);
