@@ -187,6 +187,35 @@ __device__ __forceinline__ DOp ld_op(cptr_t<DOp> p) {
     return DOp{p->type, p->k, p->mask, p->arg};
 }
 
+// Fixed registers for the amplitudes of the two states (complex64) at the head
+// of every op iteration.  Without them the compiler homes the loop-carried
+// amplitudes where the dense ops leave them, and every op that only reads
+// them (the gradient terms) pays two moves of all 64 registers per iteration.
+#define SVMI_PIN4(V0, V1, V2_, V3, x0, x1, x2, x3) \
+    "+{v" #V0 "}"(x0), "+{v" #V1 "}"(x1), "+{v" #V2_ "}"(x2), "+{v" #V3 "}"(x3)
+template <class R>
+__device__ __forceinline__ void pin_pair(V2<R>*, V2<R>*) {}
+template <>
+__device__ __forceinline__ void pin_pair<float>(V2<float>* a, V2<float>* l) {
+    asm volatile("" : SVMI_PIN4(64, 65, 66, 67, a[0].x, a[0].y, a[1].x, a[1].y),
+                      SVMI_PIN4(68, 69, 70, 71, a[2].x, a[2].y, a[3].x, a[3].y),
+                      SVMI_PIN4(72, 73, 74, 75, a[4].x, a[4].y, a[5].x, a[5].y),
+                      SVMI_PIN4(76, 77, 78, 79, a[6].x, a[6].y, a[7].x, a[7].y));
+    asm volatile("" : SVMI_PIN4(80, 81, 82, 83, a[8].x, a[8].y, a[9].x, a[9].y),
+                      SVMI_PIN4(84, 85, 86, 87, a[10].x, a[10].y, a[11].x, a[11].y),
+                      SVMI_PIN4(88, 89, 90, 91, a[12].x, a[12].y, a[13].x, a[13].y),
+                      SVMI_PIN4(92, 93, 94, 95, a[14].x, a[14].y, a[15].x, a[15].y));
+    asm volatile("" : SVMI_PIN4(96, 97, 98, 99, l[0].x, l[0].y, l[1].x, l[1].y),
+                      SVMI_PIN4(100, 101, 102, 103, l[2].x, l[2].y, l[3].x, l[3].y),
+                      SVMI_PIN4(104, 105, 106, 107, l[4].x, l[4].y, l[5].x, l[5].y),
+                      SVMI_PIN4(108, 109, 110, 111, l[6].x, l[6].y, l[7].x, l[7].y));
+    asm volatile("" : SVMI_PIN4(112, 113, 114, 115, l[8].x, l[8].y, l[9].x, l[9].y),
+                      SVMI_PIN4(116, 117, 118, 119, l[10].x, l[10].y, l[11].x, l[11].y),
+                      SVMI_PIN4(120, 121, 122, 123, l[12].x, l[12].y, l[13].x, l[13].y),
+                      SVMI_PIN4(124, 125, 126, 127, l[14].x, l[14].y, l[15].x, l[15].y));
+}
+#undef SVMI_PIN4
+
 }  // namespace
 
 // Interpreter body of one tile of one pass (blk = state * tiles + tile).
@@ -232,6 +261,7 @@ __device__ __forceinline__ void tile_interp(const TileArgs& A, unsigned char* sm
             for (uint32_t o = op0; o < op0 + nop; ++o) {
                 const DOp op = nxt;
                 if (o + 1 < op0 + nop) nxt = ld_op(ops + o + 1);
+                if constexpr (TWO) pin_pair<R>(a, l);
                 const uint32_t type = rfl(op.type), mask = rfl(op.mask), arg = rfl(op.arg);
                 switch (type) {
                     case OP_DENSE:
