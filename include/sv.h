@@ -337,9 +337,15 @@ enum { SV_BATCH_FORWARD = 1, SV_BATCH_GRAD = 2, SV_BATCH_INIT_ZERO = 4 };
  *   grads     host, concatenation of every item's n_params gradients (may be
  *             NULL without SV_BATCH_GRAD)
  *   opts      tile geometry and fusion; NULL = defaults
- * The library keeps a grow-only device work area per device across calls.
+ * The library keeps two grow-only device work areas per device across calls
+ * (one per launch) and a side stream of default priority for uploads.  The
+ * backward plans are built on the host while the forward launch runs (not
+ * with max_work_mib, where everything is planned first); stats->plan_ms is
+ * the host work before the first launch.  Batches with gates of more than 4
+ * qubits, or dense fusion beyond 4 qubits, run item by item.
  * Synchronises the stream.  Errors: SV_EINVAL for a NULL or invalid item
- * (as sv_apply_circuit), SV_ENOMEM (including max_work_mib), SV_EDEVICE. */
+ * (as sv_apply_circuit), SV_ENOMEM (including max_work_mib), SV_EDEVICE;
+ * after an error the states are unspecified. */
 sv_status sv_apply_batch(int32_t count, const sv_batch_item* items, sv_dtype dtype,
                          void* hip_stream, int32_t flags, double* energies, double* grads,
                          const sv_opts* opts, sv_stats* stats);

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -87,13 +88,21 @@ std::unordered_map<uint64_t, std::shared_ptr<PlanKeyed>> g_plans;
 // synchronised.  The largest work area of each device stays allocated for
 // later calls instead of being allocated and freed around every launch.
 std::mutex g_stage_mu;
-void* g_stage = nullptr;
-size_t g_stage_bytes = 0;
+struct Stage {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+Stage g_stage[2];   // one per launch of a call
 struct DevArea {
     void* p = nullptr;
     size_t bytes = 0;
 };
-std::unordered_map<int, DevArea> g_dev;   // by device ordinal
+struct DevState {
+    DevArea area[2];            // what the first and the second launch read
+    hipStream_t up = nullptr;   // uploads of the second area (default priority)
+    hipEvent_t ev = nullptr;
+};
+std::unordered_map<int, DevState> g_dev;   // by device ordinal
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -169,10 +178,36 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
     if (count == 0) return SV_OK;
     if (small || (opts && opts->plain)) return run_batch_loop(count, items, dtype, stream, flags, energies, grads, opts, stats, err);
 
-    auto t0 = std::chrono::steady_clock::now();
-    // ---- IR and plans (planned in parallel; plans are cached by structure)
+    const auto t0 = std::chrono::steady_clock::now();
+    auto ms_since = [](std::chrono::steady_clock::time_point t) {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t).count();
+    };
+    // geometry and fusion of an item: the tuned choice for its width, else the options
+    auto geom_of = [&](int i) {
+        BatchGeom g;
+        g.structured = !opts || opts->structured;
+        g.fuse_k = opts ? opts->max_fuse_k : 4;
+        if (geoms) {
+            auto gi = geoms->find(items[i].circuit->n_qubits);
+            if (gi != geoms->end()) g = gi->second;
+        }
+        return g;
+    };
+    // Gates wider than a register phase (input gates of more than 4 qubits,
+    // or dense blocks fused beyond 4) become plain kernels in either
+    // direction: such batches run item by item.  Decided before anything is
+    // launched, since the backward plans are only built while the forward
+    // launch runs.
+    for (int i = 0; i < count; ++i) {
+        const BatchGeom g = geom_of(i);
+        bool wide = !g.structured && g.fuse_k > 4;
+        for (int32_t k = 0; k < items[i].circuit->n_gates && !wide; ++k) wide = items[i].circuit->gates[k].nq > 4;
+        if (wide) return run_batch_loop(count, items, dtype, stream, flags, energies, grads, opts, stats, err);
+    }
+
+    // ---- IR, plans (cached by structure) and pools of one direction, in parallel
     std::vector<ItemHost> H((size_t)count);
-    {
+    auto plan_dir = [&](bool bwd) -> sv_status {
         std::atomic<int> next{0};
         unsigned hw = std::thread::hardware_concurrency();
         const int nthr = (int)std::max(1u, std::min<unsigned>(hw ? hw : 4, 16u));
@@ -184,62 +219,81 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
                     if (i >= count) return;
                     const sv_batch_item& it = items[i];
                     try {
-                        // geometry and fusion: the tuned choice for this width, else the options
-                        BatchGeom g;
-                        g.structured = !opts || opts->structured;
-                        g.fuse_k = opts ? opts->max_fuse_k : 4;
-                        if (geoms) {
-                            auto gi = geoms->find(it.circuit->n_qubits);
-                            if (gi != geoms->end()) g = gi->second;
-                        }
+                        const BatchGeom g = geom_of(i);
                         BuildOpts bo;
                         bo.batch = 1;
                         bo.structured = g.structured != 0;
                         bo.fuse = true;
                         bo.fuse_k = g.fuse_k;
                         bo.product_init = false;
-                        H[i].irf = build_ir(it.circuit, it.params, bo, nullptr, it.circuit->n_qubits);
-                        H[i].pf = get_batch_plan(it.circuit, H[i].irf, dtype, false, bo, g);
-                        fill_pool(H[i].pf->ep, H[i].irf, 1, H[i].poolf);
-                        if (grad) {
-                            bo.backward = true;
-                            H[i].irb = build_ir(it.circuit, it.params, bo, nullptr, it.circuit->n_qubits);
-                            H[i].pb = get_batch_plan(it.circuit, H[i].irb, dtype, true, bo, g);
-                            fill_pool(H[i].pb->ep, H[i].irb, 1, H[i].poolb);
-                        }
+                        bo.backward = bwd;
+                        std::vector<IRGate>& ir = bwd ? H[i].irb : H[i].irf;
+                        ir = build_ir(it.circuit, it.params, bo, nullptr, it.circuit->n_qubits);
+                        std::shared_ptr<PlanKeyed>& pk = bwd ? H[i].pb : H[i].pf;
+                        pk = get_batch_plan(it.circuit, ir, dtype, bwd, bo, g);
+                        fill_pool(pk->ep, ir, 1, bwd ? H[i].poolb : H[i].poolf);
                     } catch (const std::exception& e) {
                         H[i].err = e.what();
                     }
                 }
             });
         for (auto& t : th) t.join();
-    }
-    for (int i = 0; i < count; ++i) {
-        if (!H[i].err.empty()) { err = "item " + std::to_string(i) + ": planning failed: " + H[i].err; return SV_EUNSUPPORTED; }
-        const EncodedPlan* eps[2] = {&H[i].pf->ep, grad ? &H[i].pb->ep : nullptr};
-        for (const EncodedPlan* e : eps)
-            if (e)
-                for (const Step& s : e->steps)
-                    if (s.type != ST_TILE)  // wide (k > 4) gates: run item by item
-                        return run_batch_loop(count, items, dtype, stream, flags, energies, grads, opts, stats, err);
+        for (int i = 0; i < count; ++i) {
+            if (!H[i].err.empty()) { err = "item " + std::to_string(i) + ": planning failed: " + H[i].err; return SV_EUNSUPPORTED; }
+            const EncodedPlan& e = bwd ? H[i].pb->ep : H[i].pf->ep;
+            for (const Step& s : e.steps)
+                if (s.type != ST_TILE) {
+                    err = "item " + std::to_string(i) + ": a plan step is not a tile pass";
+                    return SV_EUNSUPPORTED;
+                }
+        }
+        return SV_OK;
+    };
+    // With a cap on the work area both directions are planned first, so that
+    // the whole area is known before anything runs; otherwise the backward
+    // plans are built while the forward launch runs.
+    const bool overlap = grad && !(opts && opts->max_work_mib > 0);
+    sv_status st = plan_dir(false);
+    if (st != SV_OK) return st;
+    if (grad && !overlap) {
+        st = plan_dir(true);
+        if (st != SV_OK) return st;
     }
 
-    // ---- device layout
     const size_t ab = dtype == SV_C64 ? 8 : 16;
+    // Two work areas: [0] what the first launch reads (forward plans,
+    // observables, its records, energy partials), [1] what the second launch
+    // and the reduction read (backward plans, records, gradient partials,
+    // reduction tasks and outputs).  Each is an uploaded part followed by
+    // scratch the kernels write before they read it.
+    struct Layout {
+        size_t up = 0, sc = 0;
+        size_t take(size_t bytes) { const size_t r = up; up = align_up(up + std::max<size_t>(bytes, 1), 256); return r; }
+        size_t take_scratch(size_t bytes) { const size_t r = sc; sc = align_up(sc + std::max<size_t>(bytes, 1), 256); return r; }
+        size_t total() const { return up + sc; }
+    };
+    struct POff {
+        size_t pass, phase, op, form, pair, etab, pool;
+    };
     struct Off {
-        size_t f_pass, f_phase, f_op, f_form, f_pair, f_etab, f_pool;
-        size_t b_pass, b_phase, b_op, b_form, b_pair, b_etab, b_pool;
+        POff f, b;
         size_t px, pg0, pz, pc, pph;
         size_t gpart, epart;
         uint32_t ngroup, nterm;
     };
     std::vector<Off> off((size_t)count);
-    size_t o = 0;
-    auto take = [&](size_t bytes) { const size_t r = o; o = align_up(o + std::max<size_t>(bytes, 1), 256); return r; };
-    // scratch the kernels write before they read it (gradient and energy
-    // partials, reduced outputs): placed after the uploaded part, never copied
-    size_t so = 0;
-    auto take_scratch = [&](size_t bytes) { const size_t r = so; so = align_up(so + std::max<size_t>(bytes, 1), 256); return r; };
+    Layout LA[2];
+    auto take_plan = [&](Layout& L, const EncodedPlan& E, const std::vector<unsigned char>& pool) {
+        POff p;
+        p.pass = L.take(E.passes.size() * sizeof(DPass));
+        p.phase = L.take(E.phases.size() * sizeof(DPhase));
+        p.op = L.take(E.ops.size() * sizeof(DOp));
+        p.form = L.take(E.forms.size() * sizeof(DForm));
+        p.pair = L.take(E.pairs.size() * sizeof(DPair));
+        p.etab = L.take(E.etab.size() * sizeof(uint16_t));
+        p.pool = L.take(pool.size());
+        return p;
+    };
     std::vector<std::vector<uint64_t>> gx((size_t)count), gz((size_t)count);
     std::vector<std::vector<uint32_t>> gg0((size_t)count), gph((size_t)count);
     std::vector<std::vector<double>> gc((size_t)count);
@@ -248,26 +302,8 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
     for (int i = 0; i < count; ++i) {
         const EncodedPlan& F = H[i].pf->ep;
         Off& f = off[i];
-        f.f_pass = take(F.passes.size() * sizeof(DPass));
-        f.f_phase = take(F.phases.size() * sizeof(DPhase));
-        f.f_op = take(F.ops.size() * sizeof(DOp));
-        f.f_form = take(F.forms.size() * sizeof(DForm));
-        f.f_pair = take(F.pairs.size() * sizeof(DPair));
-        f.f_etab = take(F.etab.size() * sizeof(uint16_t));
-        f.f_pool = take(H[i].poolf.size());
+        f.f = take_plan(LA[0], F, H[i].poolf);
         for (const DPass& P : F.passes) lds = std::max(lds, tile_lds_bytes(dtype, false, P.T, P.nform, 0, 256));
-        if (grad) {
-            const EncodedPlan& B = H[i].pb->ep;
-            f.b_pass = take(B.passes.size() * sizeof(DPass));
-            f.b_phase = take(B.phases.size() * sizeof(DPhase));
-            f.b_op = take(B.ops.size() * sizeof(DOp));
-            f.b_form = take(B.forms.size() * sizeof(DForm));
-            f.b_pair = take(B.pairs.size() * sizeof(DPair));
-            f.b_etab = take(B.etab.size() * sizeof(uint16_t));
-            f.b_pool = take(H[i].poolb.size());
-            f.gpart = take_scratch(B.gpart_size * sizeof(double));
-            for (const DPass& P : B.passes) lds_bwd = std::max(lds_bwd, tile_lds_bytes(dtype, true, P.T, P.nform, P.ngrad, 256));
-        }
         // observable, grouped by x mask
         const sv_pauli_sum* h = items[i].observable;
         if (h) {
@@ -299,75 +335,64 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
         }
         f.ngroup = (uint32_t)gx[i].size();
         f.nterm = (uint32_t)gz[i].size();
-        f.px = take(gx[i].size() * 8);
-        f.pg0 = take(gg0[i].size() * 4);
-        f.pz = take(gz[i].size() * 8);
-        f.pc = take(gc[i].size() * 8);
-        f.pph = take(gph[i].size() * 4);
+        f.px = LA[0].take(gx[i].size() * 8);
+        f.pg0 = LA[0].take(gg0[i].size() * 4);
+        f.pz = LA[0].take(gz[i].size() * 8);
+        f.pc = LA[0].take(gc[i].size() * 8);
+        f.pph = LA[0].take(gph[i].size() * 4);
         const int n = items[i].circuit->n_qubits;
         hT[i] = (uint32_t)std::min(n, 12);
-        f.epart = take_scratch(((size_t)1 << (n - hT[i])) * sizeof(double));
+        f.epart = LA[0].take_scratch(((size_t)1 << (n - hT[i])) * sizeof(double));
     }
-    // records: stages per item
-    std::vector<std::vector<BRec>> stages((size_t)count);
-    for (int i = 0; i < count; ++i) {
-        const int n = items[i].circuit->n_qubits;
-        auto add = [&](uint32_t kind, uint32_t pass, uint32_t T) {
-            BRec r{};
-            r.item = (uint32_t)i;
-            r.kind = kind;
-            r.pass = pass;
-            r.T = T;
-            r.ntiles = 1u << (n - (int)T);
-            stages[i].push_back(r);
-        };
-        if (flags & SV_BATCH_INIT_ZERO) add(BK_INIT, 0, hT[i]);
-        const EncodedPlan& F = H[i].pf->ep;
-        for (size_t p = 0; p < F.passes.size(); ++p) add(BK_FWD, (uint32_t)p, F.passes[p].T);
-        if (grad) {
-            add(BK_HPSI, 0, hT[i]);
-            const EncodedPlan& B = H[i].pb->ep;
-            for (size_t p = 0; p < B.passes.size(); ++p) add(BK_BWD, (uint32_t)p, B.passes[p].T);
-        } else if (energies) {
-            add(BK_ENERGY, 0, hT[i]);
+    // records (item, stage) of one launch, laid out in queues: largest items
+    // first onto the least-loaded queue, then level order within a queue, so
+    // that every dependency of a record precedes it in its queue
+    auto build_recs = [&](bool bwd, std::vector<BRec>& recs, BatchArgs& A) -> sv_status {
+        std::vector<std::vector<BRec>> st((size_t)count);
+        for (int i = 0; i < count; ++i) {
+            const int n = items[i].circuit->n_qubits;
+            auto add = [&](uint32_t kind, uint32_t pass, uint32_t T) {
+                BRec r{};
+                r.item = (uint32_t)i;
+                r.kind = kind;
+                r.pass = pass;
+                r.T = T;
+                r.ntiles = 1u << (n - (int)T);
+                st[i].push_back(r);
+            };
+            if (!bwd) {
+                if (flags & SV_BATCH_INIT_ZERO) add(BK_INIT, 0, hT[i]);
+                const EncodedPlan& F = H[i].pf->ep;
+                for (size_t p = 0; p < F.passes.size(); ++p) add(BK_FWD, (uint32_t)p, F.passes[p].T);
+                if (grad) add(BK_HPSI, 0, hT[i]);
+                else if (energies) add(BK_ENERGY, 0, hT[i]);
+            } else {
+                const EncodedPlan& B = H[i].pb->ep;
+                for (size_t p = 0; p < B.passes.size(); ++p) add(BK_BWD, (uint32_t)p, B.passes[p].T);
+            }
         }
-    }
-    // queues: largest items first onto the least-loaded queue
-    std::vector<int> order((size_t)count);
-    for (int i = 0; i < count; ++i) order[i] = i;
-    auto cost = [&](int i) {
-        double c = 0.0;
-        for (const BRec& r : stages[i]) c += (double)r.ntiles * std::ldexp(1.0, (int)r.T) * (r.kind == BK_BWD ? 2.0 : 1.0);
-        return c;
-    };
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
-    std::vector<std::vector<int>> qitems(kQueues);
-    double qload[kQueues] = {0};
-    for (int i : order) {
-        uint32_t best = 0;
-        for (uint32_t q = 1; q < kQueues; ++q) if (qload[q] < qload[best]) best = q;
-        qitems[best].push_back(i);
-        qload[best] += cost(i);
-    }
-    // Two persistent launches on the stream: stages before the backward sweep
-    // (init, forward passes, lambda / energy), then the backward passes, each
-    // with the interpreter it needs (the backward one carries psi and lambda).
-    std::vector<BRec> recs[2];
-    BatchArgs BA[2]{};
-    std::vector<std::vector<int32_t>> recid((size_t)count);
-    for (int ph = 0; ph < 2; ++ph) {
-        for (auto& v : recid) v.clear();
+        std::vector<int> order((size_t)count);
+        std::vector<double> cost((size_t)count, 0.0);
+        for (int i = 0; i < count; ++i) {
+            order[i] = i;
+            for (const BRec& r : st[i]) cost[i] += (double)r.ntiles * std::ldexp(1.0, (int)r.T) * (bwd ? 2.0 : 1.0);
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+        std::vector<std::vector<int>> qitems(kQueues);
+        double qload[kQueues] = {0};
+        for (int i : order) {
+            uint32_t best = 0;
+            for (uint32_t q = 1; q < kQueues; ++q) if (qload[q] < qload[best]) best = q;
+            qitems[best].push_back(i);
+            qload[best] += cost[i];
+        }
+        std::vector<std::vector<int32_t>> recid((size_t)count);
         for (uint32_t q = 0; q < kQueues; ++q) {
-            BA[ph].qrec0[q] = (uint32_t)recs[ph].size();
+            A.qrec0[q] = (uint32_t)recs.size();
             std::vector<int> its = qitems[q];
             std::sort(its.begin(), its.end());
-            std::vector<std::vector<BRec>> st((size_t)count);
             size_t maxl = 0;
-            for (int i : its) {
-                for (const BRec& r : stages[i])
-                    if ((r.kind == BK_BWD) == (ph == 1)) st[i].push_back(r);
-                maxl = std::max(maxl, st[i].size());
-            }
+            for (int i : its) maxl = std::max(maxl, st[i].size());
             uint64_t w = 0;
             for (size_t lvl = 0; lvl < maxl; ++lvl)
                 for (int i : its) {
@@ -376,166 +401,147 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
                     r.first_w = w;
                     r.dep = lvl ? recid[i][lvl - 1] : -1;
                     w += r.ntiles;
-                    recid[i].push_back((int32_t)recs[ph].size());
-                    recs[ph].push_back(r);
+                    recid[i].push_back((int32_t)recs.size());
+                    recs.push_back(r);
                 }
-            BA[ph].qtotal[q] = w;
+            A.qtotal[q] = w;
             if (w >= (1ull << 31)) { err = "batch too large for one launch"; return SV_EUNSUPPORTED; }
         }
-        BA[ph].qrec0[kQueues] = (uint32_t)recs[ph].size();
-    }
-    const size_t o_items = take((size_t)count * sizeof(BItem));
-    size_t o_recs[2], o_cnt[2];
-    for (int ph = 0; ph < 2; ++ph) {
-        o_recs[ph] = take(std::max<size_t>(1, recs[ph].size()) * sizeof(BRec));
-        o_cnt[ph] = take((kQueues + recs[ph].size() + 1) * sizeof(uint32_t));
-    }
-    // reduction tasks: energies then gradient slots
+        A.qrec0[kQueues] = (uint32_t)recs.size();
+        return SV_OK;
+    };
+    std::vector<BRec> recs[2];
+    BatchArgs BA[2]{};
+    st = build_recs(false, recs[0], BA[0]);
+    if (st != SV_OK) return st;
+    const size_t o_items0 = LA[0].take((size_t)count * sizeof(BItem));
+    const size_t o_recs0 = LA[0].take(std::max<size_t>(1, recs[0].size()) * sizeof(BRec));
+    const size_t o_cnt0 = LA[0].take((kQueues + recs[0].size() + 1) * sizeof(uint32_t));
+
+    // the second area: backward plans, records, partials, reduction tasks, outputs
     struct Task { const double* src; uint64_t ntile; uint32_t nslot; uint32_t pad; double* dst; };
-    std::vector<Task> tasks;
-    size_t nout = (size_t)count;
     std::vector<size_t> gslot0((size_t)count, 0);
-    for (int i = 0; i < count; ++i) {
-        gslot0[i] = nout;
-        if (grad) nout += (size_t)H[i].pb->ep.ngrad_total;
+    size_t nout = 0, o_items1 = 0, o_recs1 = 0, o_cnt1 = 0, o_out = 0, o_tasks = 0;
+    auto layout_second = [&]() -> sv_status {
+        if (grad) {
+            for (int i = 0; i < count; ++i) {
+                const EncodedPlan& B = H[i].pb->ep;
+                off[i].b = take_plan(LA[1], B, H[i].poolb);
+                off[i].gpart = LA[1].take_scratch(B.gpart_size * sizeof(double));
+                for (const DPass& P : B.passes) lds_bwd = std::max(lds_bwd, tile_lds_bytes(dtype, true, P.T, P.nform, P.ngrad, 256));
+            }
+            const sv_status s2 = build_recs(true, recs[1], BA[1]);
+            if (s2 != SV_OK) return s2;
+        }
+        o_items1 = LA[1].take((size_t)count * sizeof(BItem));
+        o_recs1 = LA[1].take(std::max<size_t>(1, recs[1].size()) * sizeof(BRec));
+        o_cnt1 = LA[1].take((kQueues + recs[1].size() + 1) * sizeof(uint32_t));
+        nout = (size_t)count;
+        for (int i = 0; i < count; ++i) {
+            gslot0[i] = nout;
+            if (grad) nout += (size_t)H[i].pb->ep.ngrad_total;
+        }
+        o_out = LA[1].take_scratch(nout * sizeof(double));
+        o_tasks = LA[1].take(((size_t)count * 64 + 16) * sizeof(Task));
+        return SV_OK;
+    };
+    if (!overlap) {
+        st = layout_second();
+        if (st != SV_OK) return st;
     }
-    const size_t o_out = take_scratch(nout * sizeof(double));
-    const size_t o_tasks = take(((size_t)count * 64 + 16) * sizeof(Task));
-    const size_t upload = o;
-    const size_t total = upload + so;
-    if (opts && opts->max_work_mib > 0 && total > ((size_t)opts->max_work_mib << 20)) {
-        err = "the batch work area needs " + std::to_string(total) + " bytes, above max_work_mib = " +
-              std::to_string(opts->max_work_mib) + " MiB";
-        return SV_ENOMEM;
+    if (opts && opts->max_work_mib > 0) {
+        const size_t total = LA[0].total() + LA[1].total();
+        if (total > ((size_t)opts->max_work_mib << 20)) {
+            err = "the batch work area needs " + std::to_string(total) + " bytes, above max_work_mib = " +
+                  std::to_string(opts->max_work_mib) + " MiB";
+            return SV_ENOMEM;
+        }
     }
 
     std::unique_lock<std::mutex> stage_lock(g_stage_mu);
     int dev = 0;
     hipError_t he = hipGetDevice(&dev);
     if (he != hipSuccess) { err = std::string("hipGetDevice: ") + hipGetErrorString(he); return SV_EDEVICE; }
-    DevArea& area = g_dev[dev];
-    if (area.bytes < total) {
-        // the previous call on this device has synchronised (it released the lock)
-        if (area.p) (void)hipFree(area.p);
-        area.p = nullptr;
-        area.bytes = 0;
-        he = hipMalloc(&area.p, total);
-        if (he != hipSuccess) { (void)hipGetLastError(); err = std::string("hipMalloc: ") + hipGetErrorString(he); return SV_ENOMEM; }
-        area.bytes = total;
-    }
-    unsigned char* D = reinterpret_cast<unsigned char*>(area.p);
-    unsigned char* S = D + upload;   // scratch part
-    // every exit below waits for the stream, so the staging buffer is never
-    // handed to the next call while an upload from it is in flight
+    DevState& ds = g_dev[dev];
+    // every exit below waits for the stream (and the upload stream), so the
+    // staging buffers and work areas are never handed to the next call while
+    // a copy or kernel that uses them is in flight
     struct SyncOnExit {
         hipStream_t s;
-        ~SyncOnExit() { (void)hipStreamSynchronize(s); }
-    } sync_on_exit{stream};
-    if (g_stage_bytes < upload) {
-        if (g_stage) (void)hipHostFree(g_stage);
-        g_stage = nullptr;
-        g_stage_bytes = 0;
-        const size_t want = align_up(upload + upload / 4, (size_t)1 << 20);
-        if (hipHostMalloc(&g_stage, want, hipHostMallocDefault) == hipSuccess) g_stage_bytes = want;
-        else g_stage = nullptr;
-    }
-    std::vector<unsigned char> hv;
-    if (!g_stage) hv.assign(upload, 0);   // pinned memory unavailable: pageable upload
-    unsigned char* hp = g_stage ? reinterpret_cast<unsigned char*>(g_stage) : hv.data();
-    for (int ph = 0; ph < 2; ++ph) std::memset(hp + o_cnt[ph], 0, (kQueues + recs[ph].size() + 1) * sizeof(uint32_t));
-    auto put = [&](size_t at, const void* src, size_t n) { if (n) std::memcpy(hp + at, src, n); };
-    std::vector<BItem> bi((size_t)count);
-    auto pack_item = [&](int i) {
-        const Off& f = off[i];
-        const EncodedPlan& F = H[i].pf->ep;
-        put(f.f_pass, F.passes.data(), F.passes.size() * sizeof(DPass));
-        put(f.f_phase, F.phases.data(), F.phases.size() * sizeof(DPhase));
-        put(f.f_op, F.ops.data(), F.ops.size() * sizeof(DOp));
-        put(f.f_form, F.forms.data(), F.forms.size() * sizeof(DForm));
-        put(f.f_pair, F.pairs.data(), F.pairs.size() * sizeof(DPair));
-        put(f.f_etab, F.etab.data(), F.etab.size() * sizeof(uint16_t));
-        put(f.f_pool, H[i].poolf.data(), H[i].poolf.size());
-        BItem& b = bi[i];
-        b.state = items[i].d_state;
-        b.lam = items[i].d_lambda;
-        b.n = (uint32_t)items[i].circuit->n_qubits;
-        b.fwd = BPlan{reinterpret_cast<const DPass*>(D + f.f_pass), reinterpret_cast<const DPhase*>(D + f.f_phase),
-                      reinterpret_cast<const DOp*>(D + f.f_op), reinterpret_cast<const DForm*>(D + f.f_form),
-                      reinterpret_cast<const DPair*>(D + f.f_pair), reinterpret_cast<const uint16_t*>(D + f.f_etab),
-                      D + f.f_pool};
-        if (grad) {
-            const EncodedPlan& B = H[i].pb->ep;
-            put(f.b_pass, B.passes.data(), B.passes.size() * sizeof(DPass));
-            put(f.b_phase, B.phases.data(), B.phases.size() * sizeof(DPhase));
-            put(f.b_op, B.ops.data(), B.ops.size() * sizeof(DOp));
-            put(f.b_form, B.forms.data(), B.forms.size() * sizeof(DForm));
-            put(f.b_pair, B.pairs.data(), B.pairs.size() * sizeof(DPair));
-            put(f.b_etab, B.etab.data(), B.etab.size() * sizeof(uint16_t));
-            put(f.b_pool, H[i].poolb.data(), H[i].poolb.size());
-            b.bwd = BPlan{reinterpret_cast<const DPass*>(D + f.b_pass), reinterpret_cast<const DPhase*>(D + f.b_phase),
-                          reinterpret_cast<const DOp*>(D + f.b_op), reinterpret_cast<const DForm*>(D + f.b_form),
-                          reinterpret_cast<const DPair*>(D + f.b_pair), reinterpret_cast<const uint16_t*>(D + f.b_etab),
-                          D + f.b_pool};
-            b.gpart = reinterpret_cast<double*>(S + f.gpart);
+        DevState* d;
+        ~SyncOnExit() {
+            (void)hipStreamSynchronize(s);
+            if (d->up) (void)hipStreamSynchronize(d->up);
         }
-        put(f.px, gx[i].data(), gx[i].size() * 8);
-        put(f.pg0, gg0[i].data(), gg0[i].size() * 4);
-        put(f.pz, gz[i].data(), gz[i].size() * 8);
-        put(f.pc, gc[i].data(), gc[i].size() * 8);
-        put(f.pph, gph[i].data(), gph[i].size() * 4);
-        b.pd.x = reinterpret_cast<const uint64_t*>(D + f.px);
-        b.pd.g0 = reinterpret_cast<const uint32_t*>(D + f.pg0);
-        b.pd.z = reinterpret_cast<const uint64_t*>(D + f.pz);
-        b.pd.c = reinterpret_cast<const double*>(D + f.pc);
-        b.pd.ph = reinterpret_cast<const uint32_t*>(D + f.pph);
-        b.pd.ngroup = f.ngroup;
-        b.epart = reinterpret_cast<double*>(S + f.epart);
+    } sync_on_exit{stream, &ds};
+    // grow-only device area `a` and pinned staging `a` of this device
+    auto reserve = [&](int a) -> unsigned char* {
+        DevArea& area = ds.area[a];
+        const size_t total = LA[a].total();
+        if (area.bytes < total) {
+            // the previous call on this device has synchronised (it released the lock)
+            if (area.p) (void)hipFree(area.p);
+            area.p = nullptr;
+            area.bytes = 0;
+            he = hipMalloc(&area.p, total);
+            if (he != hipSuccess) { (void)hipGetLastError(); err = std::string("hipMalloc: ") + hipGetErrorString(he); return nullptr; }
+            area.bytes = total;
+        }
+        Stage& sg = g_stage[a];
+        if (sg.bytes < LA[a].up) {
+            if (sg.p) (void)hipHostFree(sg.p);
+            sg.p = nullptr;
+            sg.bytes = 0;
+            const size_t want = align_up(LA[a].up + LA[a].up / 4, (size_t)1 << 20);
+            if (hipHostMalloc(&sg.p, want, hipHostMallocDefault) == hipSuccess) sg.bytes = want;
+            else sg.p = nullptr;   // pinned memory unavailable: pageable upload
+        }
+        return reinterpret_cast<unsigned char*>(area.p);
     };
-    {
-        // pack the items in parallel (disjoint ranges of the staging buffer)
+    std::vector<unsigned char> hv[2];
+    auto staging = [&](int a) {
+        if (g_stage[a].p) return reinterpret_cast<unsigned char*>(g_stage[a].p);
+        hv[a].assign(LA[a].up, 0);
+        return hv[a].data();
+    };
+    // pack items in parallel (disjoint ranges of a staging buffer)
+    auto parallel_items = [&](const std::function<void(int)>& fn) {
         std::atomic<int> next{0};
         unsigned hw = std::thread::hardware_concurrency();
         const int nthr = (int)std::max(1u, std::min<unsigned>(hw ? hw : 4, 16u));
         std::vector<std::thread> th;
         for (int t = 0; t < std::min(nthr, (int)count); ++t)
             th.emplace_back([&] {
-                for (int i = next++; i < count; i = next++) pack_item(i);
+                for (int i = next++; i < count; i = next++) fn(i);
             });
         for (auto& t : th) t.join();
-    }
-    for (int i = 0; i < count; ++i) {
-        const BItem& b = bi[i];
-        const int n = items[i].circuit->n_qubits;
-        double* outp = reinterpret_cast<double*>(S + o_out);
-        if (energies) tasks.push_back(Task{b.epart, 1ull << (n - hT[i]), 1u, 0u, outp + i});
-        if (grad) {
-            const EncodedPlan& B = H[i].pb->ep;
-            size_t slot = gslot0[i];
-            for (const DPass& P : B.passes) {
-                if (!P.ngrad) continue;
-                tasks.push_back(Task{b.gpart + P.gpart_off, 1ull << (n - P.T), P.ngrad, 0u, outp + slot});
-                slot += P.ngrad;
-            }
-        }
-    }
-    if (tasks.size() > (size_t)count * 64 + 16) { err = "too many reduction tasks"; return SV_EUNSUPPORTED; }
-    put(o_items, bi.data(), bi.size() * sizeof(BItem));
-    for (int ph = 0; ph < 2; ++ph) put(o_recs[ph], recs[ph].data(), recs[ph].size() * sizeof(BRec));
-    put(o_tasks, tasks.data(), tasks.size() * sizeof(Task));
-    he = hipMemcpyAsync(area.p, hp, upload, hipMemcpyHostToDevice, stream);
-    if (he != hipSuccess) { err = std::string("hipMemcpyAsync: ") + hipGetErrorString(he); return SV_EDEVICE; }
+    };
+    auto plan_ptrs = [](unsigned char* D, const POff& p) {
+        return BPlan{reinterpret_cast<const DPass*>(D + p.pass), reinterpret_cast<const DPhase*>(D + p.phase),
+                     reinterpret_cast<const DOp*>(D + p.op), reinterpret_cast<const DForm*>(D + p.form),
+                     reinterpret_cast<const DPair*>(D + p.pair), reinterpret_cast<const uint16_t*>(D + p.etab),
+                     D + p.pool};
+    };
+    auto put_plan = [](unsigned char* hp, const POff& p, const EncodedPlan& E, const std::vector<unsigned char>& pool) {
+        auto put = [&](size_t at, const void* src, size_t n) { if (n) std::memcpy(hp + at, src, n); };
+        put(p.pass, E.passes.data(), E.passes.size() * sizeof(DPass));
+        put(p.phase, E.phases.data(), E.phases.size() * sizeof(DPhase));
+        put(p.op, E.ops.data(), E.ops.size() * sizeof(DOp));
+        put(p.form, E.forms.data(), E.forms.size() * sizeof(DForm));
+        put(p.pair, E.pairs.data(), E.pairs.size() * sizeof(DPair));
+        put(p.etab, E.etab.data(), E.etab.size() * sizeof(uint16_t));
+        put(p.pool, pool.data(), pool.size());
+    };
     int dev0 = 0, khz = 0, ncu = 0;
     (void)hipGetDevice(&dev0);
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev0) != hipSuccess || khz <= 0) khz = 100000;
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev0);
-    // host work up to the launch: IR, plans (cached by structure), pools, layout, upload
-    const double plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    for (int ph = 0; ph < 2; ++ph) {
-        if (recs[ph].empty()) continue;
+    auto launch = [&](int ph, unsigned char* D, size_t o_items, size_t o_recs, size_t o_cnt) -> sv_status {
+        if (recs[ph].empty()) return SV_OK;
         BatchArgs& A = BA[ph];
         A.items = reinterpret_cast<const BItem*>(D + o_items);
-        A.recs = reinterpret_cast<const BRec*>(D + o_recs[ph]);
-        A.head = reinterpret_cast<uint32_t*>(D + o_cnt[ph]);
+        A.recs = reinterpret_cast<const BRec*>(D + o_recs);
+        A.head = reinterpret_cast<uint32_t*>(D + o_cnt);
         A.done = A.head + kQueues;
         A.err = A.done + recs[ph].size();
         A.wait_ticks = (uint64_t)khz * 2000ull;   // 2 s per dependency wait
@@ -547,12 +553,115 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
         nblocks = std::max<uint32_t>(kQueues, nblocks / kQueues * kQueues);
         he = launch_batch(dtype, ph == 1, A, nblocks, lds_ph, stream);
         if (he != hipSuccess) { err = std::string("persistent launch: ") + hipGetErrorString(he); return SV_EDEVICE; }
+        return SV_OK;
+    };
+
+    // ---- first launch: init, forward passes, lambda / energies
+    unsigned char* D0 = reserve(0);
+    if (!D0) return SV_ENOMEM;
+    unsigned char* S0 = D0 + LA[0].up;   // scratch part
+    {
+        unsigned char* hp = staging(0);
+        std::memset(hp + o_cnt0, 0, (kQueues + recs[0].size() + 1) * sizeof(uint32_t));
+        std::vector<BItem> bi((size_t)count);
+        parallel_items([&](int i) {
+            const Off& f = off[i];
+            put_plan(hp, f.f, H[i].pf->ep, H[i].poolf);
+            auto put = [&](size_t at, const void* src, size_t n) { if (n) std::memcpy(hp + at, src, n); };
+            put(f.px, gx[i].data(), gx[i].size() * 8);
+            put(f.pg0, gg0[i].data(), gg0[i].size() * 4);
+            put(f.pz, gz[i].data(), gz[i].size() * 8);
+            put(f.pc, gc[i].data(), gc[i].size() * 8);
+            put(f.pph, gph[i].data(), gph[i].size() * 4);
+            BItem& b = bi[i];
+            b = BItem{};
+            b.state = items[i].d_state;
+            b.lam = items[i].d_lambda;
+            b.n = (uint32_t)items[i].circuit->n_qubits;
+            b.fwd = plan_ptrs(D0, f.f);
+            b.pd.x = reinterpret_cast<const uint64_t*>(D0 + f.px);
+            b.pd.g0 = reinterpret_cast<const uint32_t*>(D0 + f.pg0);
+            b.pd.z = reinterpret_cast<const uint64_t*>(D0 + f.pz);
+            b.pd.c = reinterpret_cast<const double*>(D0 + f.pc);
+            b.pd.ph = reinterpret_cast<const uint32_t*>(D0 + f.pph);
+            b.pd.ngroup = f.ngroup;
+            b.epart = reinterpret_cast<double*>(S0 + f.epart);
+        });
+        std::memcpy(hp + o_items0, bi.data(), bi.size() * sizeof(BItem));
+        if (!recs[0].empty()) std::memcpy(hp + o_recs0, recs[0].data(), recs[0].size() * sizeof(BRec));
+        he = hipMemcpyAsync(D0, hp, LA[0].up, hipMemcpyHostToDevice, stream);
+        if (he != hipSuccess) { err = std::string("hipMemcpyAsync: ") + hipGetErrorString(he); return SV_EDEVICE; }
     }
-    he = launch_multi_sum(reinterpret_cast<const void*>(D + o_tasks), (uint32_t)tasks.size(), stream);
+    const double prep_ms = ms_since(t0);   // host work before the first launch
+    st = launch(0, D0, o_items0, o_recs0, o_cnt0);
+    if (st != SV_OK) return st;
+
+    // ---- backward plans and the second area, built while the first launch runs
+    if (overlap) {
+        st = plan_dir(true);
+        if (st == SV_OK) st = layout_second();
+        if (st != SV_OK) return st;
+    }
+    unsigned char* D1 = reserve(1);
+    if (!D1) return SV_ENOMEM;
+    unsigned char* S1 = D1 + LA[1].up;
+    std::vector<Task> tasks;
+    {
+        unsigned char* hp = staging(1);
+        std::memset(hp + o_cnt1, 0, (kQueues + recs[1].size() + 1) * sizeof(uint32_t));
+        std::vector<BItem> bi((size_t)count);
+        parallel_items([&](int i) {
+            BItem& b = bi[i];
+            b = BItem{};
+            b.state = items[i].d_state;
+            b.lam = items[i].d_lambda;
+            b.n = (uint32_t)items[i].circuit->n_qubits;
+            if (grad) {
+                put_plan(hp, off[i].b, H[i].pb->ep, H[i].poolb);
+                b.bwd = plan_ptrs(D1, off[i].b);
+                b.gpart = reinterpret_cast<double*>(S1 + off[i].gpart);
+            }
+        });
+        // reduction tasks: energies (partials in the first area), then gradient slots
+        double* outp = reinterpret_cast<double*>(S1 + o_out);
+        for (int i = 0; i < count; ++i) {
+            const int n = items[i].circuit->n_qubits;
+            if (energies)
+                tasks.push_back(Task{reinterpret_cast<double*>(S0 + off[i].epart), 1ull << (n - hT[i]), 1u, 0u, outp + i});
+            if (grad) {
+                const EncodedPlan& B = H[i].pb->ep;
+                size_t slot = gslot0[i];
+                for (const DPass& P : B.passes) {
+                    if (!P.ngrad) continue;
+                    tasks.push_back(Task{bi[i].gpart + P.gpart_off, 1ull << (n - P.T), P.ngrad, 0u, outp + slot});
+                    slot += P.ngrad;
+                }
+            }
+        }
+        if (tasks.size() > (size_t)count * 64 + 16) { err = "too many reduction tasks"; return SV_EUNSUPPORTED; }
+        std::memcpy(hp + o_items1, bi.data(), bi.size() * sizeof(BItem));
+        if (!recs[1].empty()) std::memcpy(hp + o_recs1, recs[1].data(), recs[1].size() * sizeof(BRec));
+        std::memcpy(hp + o_tasks, tasks.data(), tasks.size() * sizeof(Task));
+        // upload on a side stream so the copy overlaps the first launch; the
+        // stream waits for it before the second launch
+        if (!ds.up) {
+            he = hipStreamCreateWithFlags(&ds.up, hipStreamNonBlocking);
+            if (he == hipSuccess) he = hipEventCreateWithFlags(&ds.ev, hipEventDisableTiming);
+            if (he != hipSuccess) { err = std::string("upload stream: ") + hipGetErrorString(he); return SV_EDEVICE; }
+        }
+        he = hipMemcpyAsync(D1, hp, LA[1].up, hipMemcpyHostToDevice, ds.up);
+        if (he == hipSuccess) he = hipEventRecord(ds.ev, ds.up);
+        if (he == hipSuccess) he = hipStreamWaitEvent(stream, ds.ev, 0);
+        if (he != hipSuccess) { err = std::string("upload: ") + hipGetErrorString(he); return SV_EDEVICE; }
+    }
+    const double plan_ms = prep_ms;
+    st = launch(1, D1, o_items1, o_recs1, o_cnt1);
+    if (st != SV_OK) return st;
+    he = launch_multi_sum(reinterpret_cast<const void*>(D1 + o_tasks), (uint32_t)tasks.size(), stream);
     if (he != hipSuccess) { err = std::string("reduction launch: ") + hipGetErrorString(he); return SV_EDEVICE; }
     std::vector<double> out(nout, 0.0);
     uint32_t errflag[2] = {0, 0};
-    he = hipMemcpyAsync(out.data(), S + o_out, nout * sizeof(double), hipMemcpyDeviceToHost, stream);
+    he = hipMemcpyAsync(out.data(), S1 + o_out, nout * sizeof(double), hipMemcpyDeviceToHost, stream);
     for (int ph = 0; ph < 2; ++ph)
         if (he == hipSuccess && !recs[ph].empty())
             he = hipMemcpyAsync(&errflag[ph], BA[ph].err, 4, hipMemcpyDeviceToHost, stream);
@@ -581,9 +690,9 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
         stats->launches = (recs[0].empty() ? 0 : 1) + (recs[1].empty() ? 0 : 1) + 1;
         stats->plan_ms = plan_ms;
         double bytes = 0.0;
-        for (int i = 0; i < count; ++i)
-            for (const BRec& r : stages[i])
-                bytes += (double)ab * std::ldexp(1.0, items[i].circuit->n_qubits) * (r.kind == BK_BWD ? 4.0 : 2.0);
+        for (int ph = 0; ph < 2; ++ph)
+            for (const BRec& r : recs[ph])
+                bytes += (double)ab * std::ldexp(1.0, items[r.item].circuit->n_qubits) * (r.kind == BK_BWD ? 4.0 : 2.0);
         stats->hbm_bytes = bytes;
     }
     return SV_OK;
