@@ -148,6 +148,19 @@ struct ItemHost {
     std::string err;
 };
 
+// fn(i) for every item, on up to 16 host threads
+void for_items(int count, const std::function<void(int)>& fn) {
+    std::atomic<int> next{0};
+    unsigned hw = std::thread::hardware_concurrency();
+    const int nthr = (int)std::max(1u, std::min<unsigned>(hw ? hw : 4, 16u));
+    std::vector<std::thread> th;
+    for (int t = 0; t < std::min(nthr, count); ++t)
+        th.emplace_back([&] {
+            for (int i = next++; i < count; i = next++) fn(i);
+        });
+    for (auto& t : th) t.join();
+}
+
 }  // namespace
 
 sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dtype dtype, hipStream_t stream,
@@ -159,11 +172,16 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
     const bool grad = (flags & SV_BATCH_GRAD) != 0;
     if (grad && (!energies || !grads)) { err = "energies and grads are required"; return SV_EINVAL; }
     bool small = false;
+    // circuit validation (every gate of every item) in parallel; the errors
+    // are reported in item order, each after that item's NULL checks
+    std::vector<std::string> verr((size_t)std::max(count, 0));
+    for_items(count, [&](int i) {
+        if (items[i].circuit) verr[i] = validate_circuit(items[i].circuit, items[i].circuit->n_qubits);
+    });
     for (int32_t i = 0; i < count; ++i) {
         const sv_batch_item& it = items[i];
         if (!it.circuit || !it.d_state) { err = "item " + std::to_string(i) + ": NULL circuit or state"; return SV_EINVAL; }
-        std::string v = validate_circuit(it.circuit, it.circuit->n_qubits);
-        if (!v.empty()) { err = "item " + std::to_string(i) + ": " + v; return SV_EINVAL; }
+        if (!verr[i].empty()) { err = "item " + std::to_string(i) + ": " + verr[i]; return SV_EINVAL; }
         const int nmax = dtype == SV_C64 ? 34 : 33;
         if (it.circuit->n_qubits < 1 || it.circuit->n_qubits > nmax) { err = "item " + std::to_string(i) + ": bad width"; return SV_EINVAL; }
         if ((uintptr_t)it.d_state % 16) { err = "item " + std::to_string(i) + ": state not 16-byte aligned"; return SV_EINVAL; }
@@ -208,36 +226,26 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
     // ---- IR, plans (cached by structure) and pools of one direction, in parallel
     std::vector<ItemHost> H((size_t)count);
     auto plan_dir = [&](bool bwd) -> sv_status {
-        std::atomic<int> next{0};
-        unsigned hw = std::thread::hardware_concurrency();
-        const int nthr = (int)std::max(1u, std::min<unsigned>(hw ? hw : 4, 16u));
-        std::vector<std::thread> th;
-        for (int t = 0; t < std::min(nthr, (int)count); ++t)
-            th.emplace_back([&] {
-                for (;;) {
-                    const int i = next++;
-                    if (i >= count) return;
-                    const sv_batch_item& it = items[i];
-                    try {
-                        const BatchGeom g = geom_of(i);
-                        BuildOpts bo;
-                        bo.batch = 1;
-                        bo.structured = g.structured != 0;
-                        bo.fuse = true;
-                        bo.fuse_k = g.fuse_k;
-                        bo.product_init = false;
-                        bo.backward = bwd;
-                        std::vector<IRGate>& ir = bwd ? H[i].irb : H[i].irf;
-                        ir = build_ir(it.circuit, it.params, bo, nullptr, it.circuit->n_qubits);
-                        std::shared_ptr<PlanKeyed>& pk = bwd ? H[i].pb : H[i].pf;
-                        pk = get_batch_plan(it.circuit, ir, dtype, bwd, bo, g);
-                        fill_pool(pk->ep, ir, 1, bwd ? H[i].poolb : H[i].poolf);
-                    } catch (const std::exception& e) {
-                        H[i].err = e.what();
-                    }
-                }
-            });
-        for (auto& t : th) t.join();
+        for_items(count, [&](int i) {
+            const sv_batch_item& it = items[i];
+            try {
+                const BatchGeom g = geom_of(i);
+                BuildOpts bo;
+                bo.batch = 1;
+                bo.structured = g.structured != 0;
+                bo.fuse = true;
+                bo.fuse_k = g.fuse_k;
+                bo.product_init = false;
+                bo.backward = bwd;
+                std::vector<IRGate>& ir = bwd ? H[i].irb : H[i].irf;
+                ir = build_ir(it.circuit, it.params, bo, nullptr, it.circuit->n_qubits);
+                std::shared_ptr<PlanKeyed>& pk = bwd ? H[i].pb : H[i].pf;
+                pk = get_batch_plan(it.circuit, ir, dtype, bwd, bo, g);
+                fill_pool(pk->ep, ir, 1, bwd ? H[i].poolb : H[i].poolf);
+            } catch (const std::exception& e) {
+                H[i].err = e.what();
+            }
+        });
         for (int i = 0; i < count; ++i) {
             if (!H[i].err.empty()) { err = "item " + std::to_string(i) + ": planning failed: " + H[i].err; return SV_EUNSUPPORTED; }
             const EncodedPlan& e = bwd ? H[i].pb->ep : H[i].pf->ep;
@@ -504,18 +512,6 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
         hv[a].assign(LA[a].up, 0);
         return hv[a].data();
     };
-    // pack items in parallel (disjoint ranges of a staging buffer)
-    auto parallel_items = [&](const std::function<void(int)>& fn) {
-        std::atomic<int> next{0};
-        unsigned hw = std::thread::hardware_concurrency();
-        const int nthr = (int)std::max(1u, std::min<unsigned>(hw ? hw : 4, 16u));
-        std::vector<std::thread> th;
-        for (int t = 0; t < std::min(nthr, (int)count); ++t)
-            th.emplace_back([&] {
-                for (int i = next++; i < count; i = next++) fn(i);
-            });
-        for (auto& t : th) t.join();
-    };
     auto plan_ptrs = [](unsigned char* D, const POff& p) {
         return BPlan{reinterpret_cast<const DPass*>(D + p.pass), reinterpret_cast<const DPhase*>(D + p.phase),
                      reinterpret_cast<const DOp*>(D + p.op), reinterpret_cast<const DForm*>(D + p.form),
@@ -564,7 +560,7 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
         unsigned char* hp = staging(0);
         std::memset(hp + o_cnt0, 0, (kQueues + recs[0].size() + 1) * sizeof(uint32_t));
         std::vector<BItem> bi((size_t)count);
-        parallel_items([&](int i) {
+        for_items(count, [&](int i) {   // disjoint ranges of the staging buffer
             const Off& f = off[i];
             put_plan(hp, f.f, H[i].pf->ep, H[i].poolf);
             auto put = [&](size_t at, const void* src, size_t n) { if (n) std::memcpy(hp + at, src, n); };
@@ -610,7 +606,7 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
         unsigned char* hp = staging(1);
         std::memset(hp + o_cnt1, 0, (kQueues + recs[1].size() + 1) * sizeof(uint32_t));
         std::vector<BItem> bi((size_t)count);
-        parallel_items([&](int i) {
+        for_items(count, [&](int i) {   // disjoint ranges of the staging buffer
             BItem& b = bi[i];
             b = BItem{};
             b.state = items[i].d_state;
