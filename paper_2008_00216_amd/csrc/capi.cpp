@@ -241,8 +241,9 @@ sv_status ensure_jit(sv_ctx_s* c, CachedPlan& cp, bool two) {
     // few seconds of compilation (cached on disk) pay for themselves
     const bool big = (uint64_t)c->batch << c->n >= (1ull << 24);
     bool eligible = jit_enabled() && c->opts.jit >= 0 && (c->opts.jit > 0 || big);
+    // passes with fewer register groups than threads need whole idle waves
     for (const DPass& P : e.passes)
-        if ((1u << (P.T - kRegBits)) < (uint32_t)e.cfg.nt) eligible = false;
+        if ((1u << (P.T - kRegBits)) < (uint32_t)e.cfg.nt && ((1u << (P.T - kRegBits)) % 64u) != 0) eligible = false;
     if (eligible) {
         std::string jerr;
         cp.jit = jit_get(e, c->dtype, two, e.cfg.nt, jerr);

@@ -66,7 +66,10 @@ std::string pass_source(const EncodedPlan& ep, int pi, int dtype, bool two, int 
     o << "  F.begin(A, smem, L, H, T, HP, " << P.nform << "u, " << P.form0 << "u, " << P.ngrad << "u);\n";
     o << "  const uint32_t tid = F.tid;\n  const R cw = F.ptab[1].x;\n  (void)cw;\n";
     const uint32_t ngroups = 1u << (P.T - kRegBits);
-    const uint32_t iters = ngroups / nt;
+    // fewer register groups than threads (whole waves, 64 | ngroups): the
+    // waves past the last group skip the phases and only help move the tile
+    const bool part = ngroups < (uint32_t)nt;
+    const uint32_t iters = part ? 1u : ngroups / nt;
     for (uint32_t ph = 0; ph < P.nphase; ++ph) {
         const DPhase& Ph = ep.phases[P.phase0 + ph];
         const uint32_t r[4] = {Ph.rpos & 255u, (Ph.rpos >> 8) & 255u, (Ph.rpos >> 16) & 255u, Ph.rpos >> 24};
@@ -76,6 +79,7 @@ std::string pass_source(const EncodedPlan& ep, int pi, int dtype, bool two, int 
         o << "    constexpr uint32_t soff[16] = {";
         for (int i = 0; i < 16; ++i) o << Ph.soff[i] << (i < 15 ? "," : "");
         o << "};\n";
+        if (part) o << "    if (tid < " << ngroups << "u)\n";
         o << "    for (uint32_t it = 0; it < " << iters << "u; ++it) {\n";
         o << "      const uint32_t gg = it * " << nt << "u + tid;\n";
         o << "      const uint32_t lb = ins0(ins0(ins0(ins0(gg, r0), r1), r2), r3);\n";

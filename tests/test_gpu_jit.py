@@ -33,6 +33,25 @@ def test_jit_grid_matches_oracle_and_interpreter(dtype):
     assert np.max(np.abs(outs[0] - outs[1])) < (2e-6 if dtype == torch.complex64 else 1e-13)
 
 
+@pytest.mark.parametrize("dtype,T", [(torch.complex64, 12), (torch.complex128, 12), (torch.complex128, 11)])
+def test_jit_idle_waves(dtype, T):
+    """512-thread workgroups on tiles with fewer register groups than threads:
+    the waves past the last group only move the tile (2^12 amplitudes: 256
+    groups, 4 of 8 waves idle in the phases; 2^11: 6 of 8)."""
+    m = lib()
+    c = W.grid_circuit(3, 6, 14, seed=21)        # 18 qubits
+    ref = oracle.simulate(c)
+    outs = []
+    for jit in (1, -1):
+        s = m.StateVector(c.n, dtype, opts=m.make_opts(jit=jit, tile_bits=T, threads=512))
+        s.init("zero")
+        s.apply(c)
+        got = to_host(s.tensor)[0]
+        check_close(got, ref, dtype, f"jit={jit} T={T}")
+        outs.append(got)
+    assert np.max(np.abs(outs[0] - outs[1])) < (2e-6 if dtype == torch.complex64 else 1e-13)
+
+
 def test_jit_random_circuit_all_ops():
     m = lib()
     n = 17
