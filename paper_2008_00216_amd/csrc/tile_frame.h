@@ -142,11 +142,14 @@ struct TileFrame {
         const uint32_t nchunk = NA / APC;
         ot = map_local(APC * tid, L, H, hpos);
         const bool pinit = !TWO && A.init_lo != nullptr;   // uniform over the grid
-        for (uint32_t c0 = 0; c0 < nchunk; c0 += 8 * NT) {
-            u32x4 va[8];
-            u32x4 vb[8];
+        // 16-byte chunks in flight per thread before the first wait: all 16 of
+        // a complex128 tile's share (one state), else 8
+        constexpr int KB = (sizeof(V) == 16 && !TWO) ? 16 : 8;
+        for (uint32_t c0 = 0; c0 < nchunk; c0 += KB * NT) {
+            u32x4 va[KB];
+            u32x4 vb[TWO ? KB : 1];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
+            for (int j = 0; j < KB; ++j) {
                 const uint32_t c = c0 + j * NT + tid;
                 if (c < nchunk) {
                     const uint64_t gi = base + ot + map_local(APC * (c0 + j * NT), L, H, hpos);
@@ -156,7 +159,7 @@ struct TileFrame {
                 }
             }
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
+            for (int j = 0; j < KB; ++j) {
                 const uint32_t c = c0 + j * NT + tid;
                 if (c < nchunk) {
                     const uint32_t s = swz<R>(APC * c);
