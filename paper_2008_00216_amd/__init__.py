@@ -486,7 +486,7 @@ def apply_batch(circuits: Sequence, params: Sequence, states: Sequence[torch.Ten
     count = len(circuits)
     cabi = [_as_circuit(c) for c in circuits]
     pabi = [_as_pauli(p) for p in observables]
-    dtype = states[0].dtype
+    dtype = states[0].dtype if count else torch.complex64
     items = (SvBatchItem * max(1, count))()
     keep = []
     for i in range(count):

@@ -64,6 +64,31 @@ def test_batch_adjoint_gradients(dtype):
         np.testing.assert_allclose(g1[0], g[i], atol=tol)
 
 
+def test_batch_planned_up_front_matches_overlapped():
+    """With max_work_mib set, both directions are planned before the first
+    launch; otherwise the backward plans are built while the forward launch
+    runs.  Both give the same energies, gradients and states, bit for bit,
+    and an empty batch is a no-op."""
+    m = lib()
+    circs = small_batch(24, 910)
+    params = [W.uniform_params(1, c.n_params, 920 + i)[0] for i, c in enumerate(circs)]
+    obs = [W.z_sum(c.n) for c in circs]
+    out = []
+    for o in (None, m.make_opts(max_work_mib=1 << 16)):
+        states = [torch.empty(1 << c.n, dtype=torch.complex64, device="cuda") for c in circs]
+        lams = [torch.empty_like(t) for t in states]
+        e, g, st = m.apply_batch(circs, params, states, obs, lambdas=lams, grad=True, init_zero=True, opts=o)
+        assert st["launches"] == 3
+        out.append((e, g, [to_host(t) for t in states]))
+    (e0, g0, s0), (e1, g1, s1) = out
+    assert np.array_equal(e0, e1)
+    for i in range(len(circs)):
+        assert np.array_equal(g0[i], g1[i])
+        assert np.array_equal(s0[i], s1[i])
+    e, g, st = m.apply_batch([], [], [], [], grad=False, init_zero=True)
+    assert len(e) == 0
+
+
 def test_batch_long_circuits_gradients():
     """Long circuits (30-40 layers, one or two tile passes each) in one
     persistent launch: gradients finite and equal to the shift rule."""
