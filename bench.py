@@ -410,6 +410,23 @@ def batch_leg(sv, W, torch, np, count=512, tune_file=None):
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / reps
     progress(f"batch: {t_batch * 1e3:.1f} ms per launch tuned ({ntuned} widths, {t_tune:.1f} s)")
+    # a stream of batches: the host validates, plans and uploads batch k + 1
+    # while the GPU runs batch k (sv_apply_batch_async / sv_batch_finish)
+    reps_pipe = 6
+    prev = None
+    pipe_equal = True
+    t0 = time.perf_counter()
+    for _ in range(reps_pipe):
+        job = sv.apply_batch_async(circs, params, states, obs, lambdas=lams, grad=True, init_zero=True, opts=topts)
+        if prev is not None:
+            ep, gp, _ = prev.finish()
+            pipe_equal = pipe_equal and bool(np.array_equal(ep, e)) and all(np.array_equal(a, b) for a, b in zip(gp, g))
+        prev = job
+    ep, gp, _ = prev.finish()
+    torch.cuda.synchronize()
+    t_pipe = (time.perf_counter() - t0) / reps_pipe
+    pipe_equal = pipe_equal and bool(np.array_equal(ep, e)) and all(np.array_equal(a, b) for a, b in zip(gp, g))
+    progress(f"batch: {t_pipe * 1e3:.1f} ms per batch in a stream of {reps_pipe} (asynchronous calls)")
     # one circuit at a time (per-circuit launches, same library)
     sample = list(range(0, count, 8))
     ctxs = {}
@@ -451,6 +468,13 @@ def batch_leg(sv, W, torch, np, count=512, tune_file=None):
                          "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
                          "frac": round(st["alu_ops"] / t_batch / 1e12 / VALU_PEAK_TOPS, 4),
                          "note": "algorithmic vector instructions of all forward and backward passes / whole call"},
+        "batch_s_stream": t_pipe,
+        "stream": f"{reps_pipe} batches through sv_apply_batch_async / sv_batch_finish, one in flight while the "
+                  "host prepares the next; results equal to the synchronous call: " + str(pipe_equal),
+        "roofline_alu_stream": {"bound": "alu", "achieved": round(st["alu_ops"] / t_pipe / 1e12, 2),
+                                "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
+                                "frac": round(st["alu_ops"] / t_pipe / 1e12 / VALU_PEAK_TOPS, 4),
+                                "note": "algorithmic vector instructions of all passes / time per batch in the stream"},
         "circuits_per_s": count / t_batch,
         "gates_per_s": gates / t_batch,
         "one_at_a_time_s_extrapolated": t_one,

@@ -319,7 +319,7 @@ typedef struct {
     const sv_pauli_sum* observable;
 } sv_batch_item;
 
-enum { SV_BATCH_FORWARD = 1, SV_BATCH_GRAD = 2, SV_BATCH_INIT_ZERO = 4 };
+enum { SV_BATCH_FORWARD = 1, SV_BATCH_GRAD = 2, SV_BATCH_INIT_ZERO = 4, SV_BATCH_ENERGY = 8 };
 
 /* Heterogeneous batch: many circuits of different widths, each swept as by
  * sv_apply_circuit (Sec. 3 with the planning of Sec. 4) and, with
@@ -349,6 +349,35 @@ enum { SV_BATCH_FORWARD = 1, SV_BATCH_GRAD = 2, SV_BATCH_INIT_ZERO = 4 };
 sv_status sv_apply_batch(int32_t count, const sv_batch_item* items, sv_dtype dtype,
                          void* hip_stream, int32_t flags, double* energies, double* grads,
                          const sv_opts* opts, sv_stats* stats);
+
+typedef struct sv_batch_job_s* sv_batch_job;
+
+/* sv_apply_batch in two halves, so that a caller can prepare its next batch
+ * while the GPU runs the current one (not in the paper).  sv_apply_batch_async
+ * validates, plans, uploads and queues every launch of the batch on the
+ * stream, then returns without waiting; *job receives a handle.  The items,
+ * circuits, parameters and observables may be released on return; the
+ * device states and lambdas must stay until the job is finished.  Energies
+ * are computed with SV_BATCH_GRAD, or in a forward batch with
+ * SV_BATCH_ENERGY (every item then needs an observable).  Two jobs may be in
+ * flight per device (each holds one of the device's two work-area slots); a
+ * third call, asynchronous or not, fails with SV_EINVAL until one is
+ * finished.  Work queued on the same stream runs in order, so consecutive
+ * jobs on the same states are safe.  Errors: those of sv_apply_batch, found
+ * before anything is queued; a failed call returns no job. */
+sv_status sv_apply_batch_async(int32_t count, const sv_batch_item* items, sv_dtype dtype,
+                               void* hip_stream, int32_t flags, const sv_opts* opts, sv_batch_job* job);
+
+/* Waits for a job of sv_apply_batch_async, writes its results and releases
+ * it (the handle is invalid afterwards, also on error).
+ *   energies  host, count values (NULL if the job computed none)
+ *   grads     host, the items' n_params gradients concatenated (NULL without
+ *             SV_BATCH_GRAD)
+ *   stats     may be NULL; plan_ms is the host work before the first launch
+ * Errors: SV_EINVAL for a NULL job or missing outputs (the job is still
+ * waited for and released), SV_EDEVICE for a device error or a dependency
+ * wait that exceeded its time budget. */
+sv_status sv_batch_finish(sv_batch_job job, double* energies, double* grads, sv_stats* stats);
 
 /* Autotuner of the batched launch (the block-size choice of Sec. 5.1 made by
  * measurement, and the fusion width): for every width among the items, times

@@ -31,7 +31,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 SV_OK, SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_EUNSUPPORTED = 0, 1, 2, 3, 4
 SV_C64, SV_C128 = 1, 2
 INIT_ZERO, INIT_BASIS, INIT_UNIFORM, INIT_ZERO_DEFERRED = 0, 1, 2, 3
-BATCH_FORWARD, BATCH_GRAD, BATCH_INIT_ZERO = 1, 2, 4
+BATCH_FORWARD, BATCH_GRAD, BATCH_INIT_ZERO, BATCH_ENERGY = 1, 2, 4, 8
 
 OPS = {
     "I": 0, "H": 1, "X": 2, "Y": 3, "Z": 4, "S": 5, "SDG": 6, "T": 7, "TDG": 8,
@@ -131,6 +131,9 @@ _lib.sv_sf_amplitudes.argtypes = [_vp, _dp, ctypes.c_int64, ctypes.POINTER(ctype
 _lib.sv_tune_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(SvBatchItem), ctypes.c_int32, _vp, ctypes.c_int32,
                                ctypes.POINTER(SvOpts), ctypes.POINTER(ctypes.c_int32)]
 _lib.sv_batch_tuning.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(SvOpts)]
+_lib.sv_apply_batch_async.argtypes = [ctypes.c_int32, ctypes.POINTER(SvBatchItem), ctypes.c_int32, _vp,
+                                      ctypes.c_int32, ctypes.POINTER(SvOpts), ctypes.POINTER(_vp)]
+_lib.sv_batch_finish.argtypes = [_vp, _dp, _dp, ctypes.POINTER(SvStats)]
 _lib.sv_sync.argtypes = [_vp]
 _lib.sv_timing.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_int64), _dp]
 _lib.sv_plan_info.argtypes = [ctypes.POINTER(SvCircuit), ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(SvOpts),
@@ -142,14 +145,15 @@ for _f in ("sv_create", "sv_destroy", "sv_set_stream", "sv_set_opts", "sv_init",
            "sv_apply_circuit_norm", "sv_expect", "sv_expect_noalloc", "sv_norm", "sv_copy_state", "sv_sample", "sv_amplitudes",
            "sv_adjoint_grad", "sv_apply_batch", "sv_sync", "sv_timing", "sv_plan_info", "sv_plan_trace",
            "sv_tune", "sv_sf_plan", "sv_sf_create", "sv_sf_destroy", "sv_sf_amplitudes", "sv_tune_batch",
-           "sv_batch_tuning"):
+           "sv_batch_tuning", "sv_apply_batch_async", "sv_batch_finish"):
     getattr(_lib, _f).restype = ctypes.c_int32
 
 EXPORTED = ("sv_opts_default", "sv_create", "sv_destroy", "sv_set_stream", "sv_set_opts", "sv_init",
             "sv_apply_circuit", "sv_apply_circuit_norm", "sv_expect", "sv_expect_noalloc", "sv_norm", "sv_copy_state", "sv_sample",
             "sv_amplitudes", "sv_adjoint_grad", "sv_apply_batch", "sv_sync", "sv_timing", "sv_plan_info",
             "sv_plan_trace", "sv_tune", "sv_sf_plan", "sv_sf_create", "sv_sf_destroy", "sv_sf_amplitudes",
-            "sv_tune_batch", "sv_batch_tuning", "sv_last_error", "sv_version")
+            "sv_tune_batch", "sv_batch_tuning", "sv_apply_batch_async", "sv_batch_finish", "sv_last_error",
+            "sv_version")
 
 
 class SvError(RuntimeError):
@@ -515,6 +519,65 @@ def apply_batch(circuits: Sequence, params: Sequence, states: Sequence[torch.Ten
         out.append(grads[off:off + c.n_params].copy())
         off += c.n_params
     return energies[:count], out, st.as_dict()
+
+
+class BatchJob:
+    """A batch queued by apply_batch_async; finish() waits and returns
+    (energies, grads list, stats) like apply_batch."""
+
+    def __init__(self, handle, count, nparams, grad, energies, keep):
+        self._h = handle
+        self._count = count
+        self._nparams = nparams
+        self._grad = grad
+        self._energies = energies
+        self._keep = keep      # device buffers the job still uses
+
+    def finish(self):
+        if self._h is None:
+            raise RuntimeError("batch job already finished")
+        h, self._h = self._h, None
+        energies = np.zeros(max(1, self._count), np.float64)
+        grads = np.zeros(max(1, sum(self._nparams)), np.float64)
+        st = SvStats()
+        _check(_lib.sv_batch_finish(h, energies.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+                                    if self._energies else None,
+                                    grads.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if self._grad else None,
+                                    ctypes.byref(st)))
+        self._keep = None
+        out, off = [], 0
+        for n in self._nparams:
+            out.append(grads[off:off + n].copy())
+            off += n
+        return energies[:self._count], out, st.as_dict()
+
+    def __del__(self):
+        # a job that is dropped unfinished is still waited for, so its slot is freed
+        if getattr(self, "_h", None) is not None:
+            try:
+                self.finish()
+            except Exception:
+                pass
+
+
+def apply_batch_async(circuits: Sequence, params: Sequence, states: Sequence[torch.Tensor],
+                      observables: Sequence, lambdas: Optional[Sequence[torch.Tensor]] = None,
+                      grad: bool = False, init_zero: bool = True, energies: bool = True,
+                      opts: Optional[SvOpts] = None) -> BatchJob:
+    """sv_apply_batch_async: queue the batch and return at once; the host can
+    prepare the next batch while this one runs.  BatchJob.finish() gives the
+    results.  At most two jobs may be unfinished per device."""
+    count = len(circuits)
+    items, keep = _batch_items(circuits, params, states, observables, lambdas)
+    cabi = keep[0]
+    flags = (BATCH_GRAD if grad else BATCH_FORWARD) | (BATCH_INIT_ZERO if init_zero else 0) | \
+            (BATCH_ENERGY if (energies and not grad) else 0)
+    h = _vp()
+    o = opts if opts is not None else make_opts()
+    _check(_lib.sv_apply_batch_async(count, items, SV_C64 if (not count or states[0].dtype == torch.complex64)
+                                     else SV_C128, _stream_handle(), flags, ctypes.byref(o), ctypes.byref(h)))
+    return BatchJob(h, count, [c.n_params for c in cabi], grad, energies or grad,
+                    (list(states), list(lambdas) if lambdas is not None else None))
 
 
 def sf_plan(circ, half_mask: int, dtype=torch.complex64, work_bytes: int = 0) -> dict:

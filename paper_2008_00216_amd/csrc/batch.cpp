@@ -92,14 +92,24 @@ struct Stage {
     void* p = nullptr;
     size_t bytes = 0;
 };
-Stage g_stage[2];   // one per launch of a call
 struct DevArea {
     void* p = nullptr;
     size_t bytes = 0;
 };
+// The resources of one call: the device work areas the first and the second
+// launch read, their pinned staging, and pinned space for the results.  A
+// device has two slots, so one call can be prepared and launched while the
+// previous one runs (sv_apply_batch_async).
+struct Slot {
+    DevArea area[2];
+    Stage stage[2];
+    Stage res;                  // outputs and the two wait-error flags
+    hipEvent_t done = nullptr;  // recorded after the copy of the results
+    bool busy = false;          // held by a job until it is finished
+};
 struct DevState {
-    DevArea area[2];            // what the first and the second launch read
-    hipStream_t up = nullptr;   // uploads of the second area (default priority)
+    Slot slot[2];
+    hipStream_t up = nullptr;   // uploads of the second areas (default priority)
     hipEvent_t ev = nullptr;
 };
 std::unordered_map<int, DevState> g_dev;   // by device ordinal
@@ -163,14 +173,37 @@ void for_items(int count, const std::function<void(int)>& fn) {
 
 }  // namespace
 
-sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dtype dtype, hipStream_t stream,
-                               int32_t flags, double* energies, double* grads, const sv_opts* opts,
-                               sv_stats* stats, std::string& err, const GeomTable* geoms) {
+// A launched batch call, finished by batch_finish: where its results land
+// and what turns them into energies and gradients.
+struct BatchJob {
+    bool immediate = false;      // ran item by item: results already in e, g
+    std::vector<double> e, g;
+    int dev = 0, slot = -1;
+    hipStream_t stream = nullptr;
+    int count = 0;
+    bool grad = false, want_e = false;
+    size_t nout = 0;
+    const double* out = nullptr; // pinned (or job-owned) copy of the reduced outputs
+    const uint32_t* errflag = nullptr;
+    std::vector<double> outv;    // used when pinned memory is unavailable
+    std::vector<unsigned char> hv[2];   // pageable staging when pinned memory is unavailable
+    std::vector<int> nparams;
+    std::vector<std::shared_ptr<PlanKeyed>> pb;
+    std::vector<size_t> gslot0;
+    sv_stats stats{};
+};
+
+sv_status batch_launch(int32_t count, const sv_batch_item* items, sv_dtype dtype, hipStream_t stream, int32_t flags,
+                       bool want_e, const sv_opts* opts, std::string& err, const GeomTable* geoms, BatchJob& job) {
     if (count < 0) { err = "count < 0"; return SV_EINVAL; }
     if (count > 0 && !items) { err = "items is NULL"; return SV_EINVAL; }
     if (dtype != SV_C64 && dtype != SV_C128) { err = "dtype must be SV_C64 or SV_C128"; return SV_EINVAL; }
     const bool grad = (flags & SV_BATCH_GRAD) != 0;
-    if (grad && (!energies || !grads)) { err = "energies and grads are required"; return SV_EINVAL; }
+    if (grad) want_e = true;
+    job.count = count;
+    job.grad = grad;
+    job.want_e = want_e;
+    job.stream = stream;
     bool small = false;
     // circuit validation (every gate of every item) in parallel; the errors
     // are reported in item order, each after that item's NULL checks
@@ -189,12 +222,25 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
             err = "item " + std::to_string(i) + ": gradients need d_lambda and an observable";
             return SV_EINVAL;
         }
-        if (energies && !it.observable) { err = "item " + std::to_string(i) + ": energies need an observable"; return SV_EINVAL; }
+        if (want_e && !it.observable) { err = "item " + std::to_string(i) + ": energies need an observable"; return SV_EINVAL; }
         if (it.circuit->n_params > 0 && !it.params) { err = "item " + std::to_string(i) + ": params is NULL"; return SV_EINVAL; }
         if (it.circuit->n_qubits < 4) small = true;
     }
-    if (count == 0) return SV_OK;
-    if (small || (opts && opts->plain)) return run_batch_loop(count, items, dtype, stream, flags, energies, grads, opts, stats, err);
+    // item by item, synchronously: the job holds the results
+    auto immediate = [&]() -> sv_status {
+        job.immediate = true;
+        size_t np = 0;
+        for (int i = 0; i < count; ++i) np += (size_t)items[i].circuit->n_params;
+        job.e.assign((size_t)count, 0.0);
+        job.g.assign(np, 0.0);
+        return run_batch_loop(count, items, dtype, stream, flags, want_e ? job.e.data() : nullptr, job.g.data(),
+                              opts, &job.stats, err);
+    };
+    if (count == 0) {
+        job.immediate = true;
+        return SV_OK;
+    }
+    if (small || (opts && opts->plain)) return immediate();
 
     const auto t0 = std::chrono::steady_clock::now();
     auto ms_since = [](std::chrono::steady_clock::time_point t) {
@@ -220,7 +266,7 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
         const BatchGeom g = geom_of(i);
         bool wide = !g.structured && g.fuse_k > 4;
         for (int32_t k = 0; k < items[i].circuit->n_gates && !wide; ++k) wide = items[i].circuit->gates[k].nq > 4;
-        if (wide) return run_batch_loop(count, items, dtype, stream, flags, energies, grads, opts, stats, err);
+        if (wide) return immediate();
     }
 
     // ---- IR, plans (cached by structure) and pools of one direction, in parallel
@@ -373,7 +419,7 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
                 const EncodedPlan& F = H[i].pf->ep;
                 for (size_t p = 0; p < F.passes.size(); ++p) add(BK_FWD, (uint32_t)p, F.passes[p].T);
                 if (grad) add(BK_HPSI, 0, hT[i]);
-                else if (energies) add(BK_ENERGY, 0, hT[i]);
+                else if (want_e) add(BK_ENERGY, 0, hT[i]);
             } else {
                 const EncodedPlan& B = H[i].pb->ep;
                 for (size_t p = 0; p < B.passes.size(); ++p) add(BK_BWD, (uint32_t)p, B.passes[p].T);
@@ -471,23 +517,37 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
     hipError_t he = hipGetDevice(&dev);
     if (he != hipSuccess) { err = std::string("hipGetDevice: ") + hipGetErrorString(he); return SV_EDEVICE; }
     DevState& ds = g_dev[dev];
-    // every exit below waits for the stream (and the upload stream), so the
+    const int si = !ds.slot[0].busy ? 0 : (!ds.slot[1].busy ? 1 : -1);
+    if (si < 0) {
+        err = "two batch jobs are in flight on this device: finish one first (sv_batch_finish)";
+        return SV_EINVAL;
+    }
+    Slot& sl = ds.slot[si];
+    sl.busy = true;
+    job.dev = dev;
+    job.slot = si;
+    // every error exit below waits for the streams and frees the slot, so its
     // staging buffers and work areas are never handed to the next call while
-    // a copy or kernel that uses them is in flight
-    struct SyncOnExit {
+    // a copy or kernel that uses them is in flight; a launched job keeps the
+    // slot until batch_finish
+    struct Guard {
         hipStream_t s;
         DevState* d;
-        ~SyncOnExit() {
+        Slot* sl;
+        bool keep = false;
+        ~Guard() {
+            if (keep) return;
             (void)hipStreamSynchronize(s);
             if (d->up) (void)hipStreamSynchronize(d->up);
+            sl->busy = false;
         }
-    } sync_on_exit{stream, &ds};
-    // grow-only device area `a` and pinned staging `a` of this device
+    } guard{stream, &ds, &sl};
+    // grow-only device area `a` and pinned staging `a` of the slot
     auto reserve = [&](int a) -> unsigned char* {
-        DevArea& area = ds.area[a];
+        DevArea& area = sl.area[a];
         const size_t total = LA[a].total();
         if (area.bytes < total) {
-            // the previous call on this device has synchronised (it released the lock)
+            // the slot's previous job has finished (its stream has synchronised)
             if (area.p) (void)hipFree(area.p);
             area.p = nullptr;
             area.bytes = 0;
@@ -495,7 +555,7 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
             if (he != hipSuccess) { (void)hipGetLastError(); err = std::string("hipMalloc: ") + hipGetErrorString(he); return nullptr; }
             area.bytes = total;
         }
-        Stage& sg = g_stage[a];
+        Stage& sg = sl.stage[a];
         if (sg.bytes < LA[a].up) {
             if (sg.p) (void)hipHostFree(sg.p);
             sg.p = nullptr;
@@ -506,11 +566,10 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
         }
         return reinterpret_cast<unsigned char*>(area.p);
     };
-    std::vector<unsigned char> hv[2];
     auto staging = [&](int a) {
-        if (g_stage[a].p) return reinterpret_cast<unsigned char*>(g_stage[a].p);
-        hv[a].assign(LA[a].up, 0);
-        return hv[a].data();
+        if (sl.stage[a].p) return reinterpret_cast<unsigned char*>(sl.stage[a].p);
+        job.hv[a].assign(LA[a].up, 0);
+        return job.hv[a].data();
     };
     auto plan_ptrs = [](unsigned char* D, const POff& p) {
         return BPlan{reinterpret_cast<const DPass*>(D + p.pass), reinterpret_cast<const DPhase*>(D + p.phase),
@@ -622,7 +681,7 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
         double* outp = reinterpret_cast<double*>(S1 + o_out);
         for (int i = 0; i < count; ++i) {
             const int n = items[i].circuit->n_qubits;
-            if (energies)
+            if (want_e)
                 tasks.push_back(Task{reinterpret_cast<double*>(S0 + off[i].epart), 1ull << (n - hT[i]), 1u, 0u, outp + i});
             if (grad) {
                 const EncodedPlan& B = H[i].pb->ep;
@@ -650,48 +709,153 @@ sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dty
         if (he == hipSuccess) he = hipStreamWaitEvent(stream, ds.ev, 0);
         if (he != hipSuccess) { err = std::string("upload: ") + hipGetErrorString(he); return SV_EDEVICE; }
     }
-    const double plan_ms = prep_ms;
     st = launch(1, D1, o_items1, o_recs1, o_cnt1);
     if (st != SV_OK) return st;
     he = launch_multi_sum(reinterpret_cast<const void*>(D1 + o_tasks), (uint32_t)tasks.size(), stream);
     if (he != hipSuccess) { err = std::string("reduction launch: ") + hipGetErrorString(he); return SV_EDEVICE; }
-    std::vector<double> out(nout, 0.0);
-    uint32_t errflag[2] = {0, 0};
-    he = hipMemcpyAsync(out.data(), S1 + o_out, nout * sizeof(double), hipMemcpyDeviceToHost, stream);
+    // results (outputs, then the two wait-error flags) into the slot's pinned buffer
+    const size_t rbytes = nout * sizeof(double) + 2 * sizeof(uint32_t);
+    if (sl.res.bytes < rbytes) {
+        if (sl.res.p) (void)hipHostFree(sl.res.p);
+        sl.res.p = nullptr;
+        sl.res.bytes = 0;
+        const size_t want = align_up(rbytes + rbytes / 4, (size_t)1 << 16);
+        if (hipHostMalloc(&sl.res.p, want, hipHostMallocDefault) == hipSuccess) sl.res.bytes = want;
+        else sl.res.p = nullptr;
+    }
+    unsigned char* rp = nullptr;
+    if (sl.res.p) {
+        rp = reinterpret_cast<unsigned char*>(sl.res.p);
+    } else {
+        job.outv.assign((rbytes + sizeof(double) - 1) / sizeof(double), 0.0);
+        rp = reinterpret_cast<unsigned char*>(job.outv.data());
+    }
+    double* outp_h = reinterpret_cast<double*>(rp);
+    uint32_t* flags_h = reinterpret_cast<uint32_t*>(rp + nout * sizeof(double));
+    flags_h[0] = flags_h[1] = 0;
+    he = hipMemcpyAsync(outp_h, S1 + o_out, nout * sizeof(double), hipMemcpyDeviceToHost, stream);
     for (int ph = 0; ph < 2; ++ph)
         if (he == hipSuccess && !recs[ph].empty())
-            he = hipMemcpyAsync(&errflag[ph], BA[ph].err, 4, hipMemcpyDeviceToHost, stream);
-    if (he == hipSuccess) he = hipStreamSynchronize(stream);
+            he = hipMemcpyAsync(&flags_h[ph], BA[ph].err, 4, hipMemcpyDeviceToHost, stream);
+    if (he == hipSuccess && !sl.done) he = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+    if (he == hipSuccess) he = hipEventRecord(sl.done, stream);
     if (he != hipSuccess) { err = std::string("batch: ") + hipGetErrorString(he); return SV_EDEVICE; }
-    if (errflag[0] || errflag[1]) { err = "persistent batch: a dependency wait exceeded its time budget"; return SV_EDEVICE; }
-    size_t goff = 0;
+    job.nout = nout;
+    job.out = outp_h;
+    job.errflag = flags_h;
+    job.nparams.resize((size_t)count);
+    job.pb.resize((size_t)count);
     for (int i = 0; i < count; ++i) {
-        if (energies) energies[i] = out[i];
-        if (grad) {
-            const int np = items[i].circuit->n_params;
-            for (int p = 0; p < np; ++p) grads[goff + p] = 0.0;
-            const EncodedPlan& B = H[i].pb->ep;
-            for (int s = 0; s < B.ngrad_total; ++s)
-                grads[goff + B.grad_param[s]] += B.grad_scale[s] * out[gslot0[i] + s];
-            goff += (size_t)np;
-        }
+        job.nparams[i] = items[i].circuit->n_params;
+        if (grad) job.pb[i] = H[i].pb;
     }
-    if (stats) {
-        std::memset(stats, 0, sizeof(*stats));
-        for (int i = 0; i < count; ++i) {
-            stats->gates_in += items[i].circuit->n_gates;
-            stats->passes += (int32_t)H[i].pf->ep.passes.size() + (grad ? (int32_t)H[i].pb->ep.passes.size() : 0);
-            stats->alu_ops += H[i].pf->ep.alu_ops + (grad ? H[i].pb->ep.alu_ops : 0.0);
-        }
-        stats->launches = (recs[0].empty() ? 0 : 1) + (recs[1].empty() ? 0 : 1) + 1;
-        stats->plan_ms = plan_ms;
-        double bytes = 0.0;
-        for (int ph = 0; ph < 2; ++ph)
-            for (const BRec& r : recs[ph])
-                bytes += (double)ab * std::ldexp(1.0, items[r.item].circuit->n_qubits) * (r.kind == BK_BWD ? 4.0 : 2.0);
-        stats->hbm_bytes = bytes;
+    job.gslot0 = gslot0;
+    sv_stats& sts = job.stats;
+    std::memset(&sts, 0, sizeof(sts));
+    for (int i = 0; i < count; ++i) {
+        sts.gates_in += items[i].circuit->n_gates;
+        sts.passes += (int32_t)H[i].pf->ep.passes.size() + (grad ? (int32_t)H[i].pb->ep.passes.size() : 0);
+        sts.alu_ops += H[i].pf->ep.alu_ops + (grad ? H[i].pb->ep.alu_ops : 0.0);
     }
+    sts.launches = (recs[0].empty() ? 0 : 1) + (recs[1].empty() ? 0 : 1) + 1;
+    sts.plan_ms = prep_ms;
+    double bytes = 0.0;
+    for (int ph = 0; ph < 2; ++ph)
+        for (const BRec& r : recs[ph])
+            bytes += (double)ab * std::ldexp(1.0, items[r.item].circuit->n_qubits) * (r.kind == BK_BWD ? 4.0 : 2.0);
+    sts.hbm_bytes = bytes;
+    guard.keep = true;
     return SV_OK;
+}
+
+// Wait for a launched job, turn its reduced outputs into energies and
+// gradients (the backward plans' slot order and scale factors), release its
+// slot.  energies / grads may be NULL when not wanted.
+sv_status batch_finish(BatchJob& job, double* energies, double* grads, sv_stats* stats, std::string& err) {
+    if (job.immediate) {
+        if (energies && job.want_e) std::copy(job.e.begin(), job.e.end(), energies);
+        if (grads && job.grad) std::copy(job.g.begin(), job.g.end(), grads);
+        if (stats) *stats = job.stats;
+        return SV_OK;
+    }
+    Slot* sl = nullptr;
+    hipStream_t up = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_stage_mu);
+        DevState& ds = g_dev[job.dev];
+        sl = &ds.slot[job.slot];
+        up = ds.up;
+    }
+    sv_status st = SV_OK;
+    const hipError_t he = hipEventSynchronize(sl->done);
+    if (he != hipSuccess) {
+        err = std::string("batch: ") + hipGetErrorString(he);
+        st = SV_EDEVICE;
+    } else if (job.errflag[0] || job.errflag[1]) {
+        err = "persistent batch: a dependency wait exceeded its time budget";
+        st = SV_EDEVICE;
+    } else {
+        size_t goff = 0;
+        for (int i = 0; i < job.count; ++i) {
+            if (energies && job.want_e) energies[i] = job.out[i];
+            if (job.grad && grads) {
+                const int np = job.nparams[i];
+                for (int p = 0; p < np; ++p) grads[goff + p] = 0.0;
+                const EncodedPlan& B = job.pb[i]->ep;
+                for (int k = 0; k < B.ngrad_total; ++k)
+                    grads[goff + B.grad_param[k]] += B.grad_scale[k] * job.out[job.gslot0[i] + k];
+                goff += (size_t)np;
+            }
+        }
+        if (stats) *stats = job.stats;
+    }
+    if (st != SV_OK) {
+        (void)hipStreamSynchronize(job.stream);
+        if (up) (void)hipStreamSynchronize(up);
+    }
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    sl->busy = false;
+    return st;
+}
+
+sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dtype dtype, hipStream_t stream,
+                               int32_t flags, double* energies, double* grads, const sv_opts* opts,
+                               sv_stats* stats, std::string& err, const GeomTable* geoms) {
+    if ((flags & SV_BATCH_GRAD) && (!energies || !grads)) { err = "energies and grads are required"; return SV_EINVAL; }
+    BatchJob job;
+    const sv_status st = batch_launch(count, items, dtype, stream, flags, energies != nullptr, opts, err, geoms, job);
+    if (st != SV_OK) return st;
+    return batch_finish(job, energies, grads, stats, err);
+}
+
+// Opaque jobs for the asynchronous entry points.
+sv_status batch_launch_async(int32_t count, const sv_batch_item* items, sv_dtype dtype, hipStream_t stream,
+                             int32_t flags, const sv_opts* opts, std::string& err, const GeomTable* geoms,
+                             void** job_out) {
+    auto job = std::make_unique<BatchJob>();
+    const sv_status st = batch_launch(count, items, dtype, stream, flags, (flags & SV_BATCH_ENERGY) != 0, opts, err,
+                                      geoms, *job);
+    if (st != SV_OK) return st;
+    *job_out = job.release();
+    return SV_OK;
+}
+
+sv_status batch_finish_async(void* job, double* energies, double* grads, sv_stats* stats, std::string& err) {
+    std::unique_ptr<BatchJob> j(static_cast<BatchJob*>(job));
+    if (j->grad && (!energies || !grads)) {
+        // still wait for the job and release its slot
+        std::string ignore;
+        (void)batch_finish(*j, nullptr, nullptr, nullptr, ignore);
+        err = "energies and grads are required";
+        return SV_EINVAL;
+    }
+    if (j->want_e && !energies) {
+        std::string ignore;
+        (void)batch_finish(*j, nullptr, nullptr, nullptr, ignore);
+        err = "energies is NULL";
+        return SV_EINVAL;
+    }
+    return batch_finish(*j, energies, grads, stats, err);
 }
 
 }  // namespace svmi

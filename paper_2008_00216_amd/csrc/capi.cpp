@@ -26,6 +26,10 @@ namespace svmi {
 sv_status run_batch_persistent(int32_t count, const sv_batch_item* items, sv_dtype dtype, hipStream_t stream,
                                int32_t flags, double* energies, double* grads, const sv_opts* opts,
                                sv_stats* stats, std::string& err, const GeomTable* geoms);
+sv_status batch_launch_async(int32_t count, const sv_batch_item* items, sv_dtype dtype, hipStream_t stream,
+                             int32_t flags, const sv_opts* opts, std::string& err, const GeomTable* geoms,
+                             void** job_out);
+sv_status batch_finish_async(void* job, double* energies, double* grads, sv_stats* stats, std::string& err);
 bool batch_tuned_table(int dtype, bool grad, GeomTable& out);
 bool batch_tuned_lookup(int dtype, bool grad, int n, BatchGeom& g);
 sv_status tune_batch(int32_t count, const sv_batch_item* items, sv_dtype dtype, hipStream_t stream, int32_t flags,
@@ -1323,6 +1327,38 @@ sv_status sv_apply_batch(int32_t count, const sv_batch_item* items, sv_dtype dty
                            batch_tuned_table(dtype, (flags & SV_BATCH_GRAD) != 0, tuned);
     sv_status st = run_batch_persistent(count, items, dtype, reinterpret_cast<hipStream_t>(hip_stream), flags,
                                         energies, grads, opts, stats, err, use_tuned ? &tuned : nullptr);
+    if (st != SV_OK) {
+        (void)hipGetLastError();
+        return fail(st, err);
+    }
+    return SV_OK;
+}
+
+sv_status sv_apply_batch_async(int32_t count, const sv_batch_item* items, sv_dtype dtype, void* hip_stream,
+                               int32_t flags, const sv_opts* opts, sv_batch_job* job) {
+    g_err.clear();
+    if (!job) return fail(SV_EINVAL, "job is NULL");
+    *job = nullptr;
+    std::string err;
+    GeomTable tuned;
+    const bool use_tuned = opts && opts->batch_tuned &&
+                           batch_tuned_table(dtype, (flags & SV_BATCH_GRAD) != 0, tuned);
+    void* j = nullptr;
+    sv_status st = batch_launch_async(count, items, dtype, reinterpret_cast<hipStream_t>(hip_stream), flags, opts,
+                                      err, use_tuned ? &tuned : nullptr, &j);
+    if (st != SV_OK) {
+        (void)hipGetLastError();
+        return fail(st, err);
+    }
+    *job = reinterpret_cast<sv_batch_job>(j);
+    return SV_OK;
+}
+
+sv_status sv_batch_finish(sv_batch_job job, double* energies, double* grads, sv_stats* stats) {
+    g_err.clear();
+    if (!job) return fail(SV_EINVAL, "job is NULL");
+    std::string err;
+    sv_status st = batch_finish_async(reinterpret_cast<void*>(job), energies, grads, stats, err);
     if (st != SV_OK) {
         (void)hipGetLastError();
         return fail(st, err);

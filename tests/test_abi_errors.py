@@ -140,6 +140,30 @@ def test_batch_item_validation():
     assert r == EINVAL and "NULL" in err
 
 
+def test_async_batch_validation():
+    """sv_apply_batch_async validates like sv_apply_batch before anything is
+    queued, and returns no job on error; sv_batch_finish rejects a NULL job."""
+    circ = m.CircuitABI(W.layered_param_circuit(6, 2, 1))
+    pr = np.zeros(circ.n_params)
+    items = (m.SvBatchItem * 1)()
+    items[0].circuit = ctypes.pointer(circ.c)
+    items[0].params = pr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    items[0].d_state = FAKE
+    items[0].observable = None
+    job = ctypes.c_void_p(123)
+    # energies of a forward batch need observables
+    r = lib.sv_apply_batch_async(1, items, m.SV_C64, None, m.BATCH_FORWARD | m.BATCH_ENERGY, None, ctypes.byref(job))
+    assert r == EINVAL and "observable" in lib.sv_last_error().decode()
+    assert job.value is None
+    items[0].d_state = FAKE + 8
+    r = lib.sv_apply_batch_async(1, items, m.SV_C64, None, m.BATCH_FORWARD, None, ctypes.byref(job))
+    assert r == EINVAL and "aligned" in lib.sv_last_error().decode()
+    r = lib.sv_apply_batch_async(1, items, m.SV_C64, None, m.BATCH_FORWARD, None, None)
+    assert r == EINVAL and "job" in lib.sv_last_error().decode()
+    r = lib.sv_batch_finish(None, None, None, None)
+    assert r == EINVAL and "job" in lib.sv_last_error().decode()
+
+
 def test_entry_points_reject_null_context():
     d = ctypes.c_double()
     for f, args in (("sv_init", (None, 0, 0)), ("sv_expect", (None, None, ctypes.byref(d))),

@@ -89,6 +89,41 @@ def test_batch_planned_up_front_matches_overlapped():
     assert len(e) == 0
 
 
+def test_async_batch_matches_sync_and_pipelines():
+    """sv_apply_batch_async + sv_batch_finish give what sv_apply_batch gives,
+    bit for bit (forward with energies, and gradients); two jobs on the same
+    states can be in flight at once (the stream orders them), a third is
+    refused until one is finished."""
+    m = lib()
+    circs = small_batch(18, 950)
+    params = [W.uniform_params(1, c.n_params, 960 + i)[0] for i, c in enumerate(circs)]
+    obs = [W.z_sum(c.n) for c in circs]
+    states = [torch.empty(1 << c.n, dtype=torch.complex64, device="cuda") for c in circs]
+    lams = [torch.empty_like(t) for t in states]
+    e0, g0, _ = m.apply_batch(circs, params, states, obs, lambdas=lams, grad=True, init_zero=True)
+    ef, _, _ = m.apply_batch(circs, params, states, obs, grad=False, init_zero=True)
+    j1 = m.apply_batch_async(circs, params, states, obs, lambdas=lams, grad=True, init_zero=True)
+    j2 = m.apply_batch_async(circs, params, states, obs, lambdas=lams, grad=True, init_zero=True)
+    with pytest.raises(m.SvError) as ex:
+        m.apply_batch_async(circs, params, states, obs, lambdas=lams, grad=True, init_zero=True)
+    assert "in flight" in str(ex.value)
+    e1, g1, st1 = j1.finish()
+    j3 = m.apply_batch_async(circs, params, states, obs, grad=False, init_zero=True, energies=True)
+    e2, g2, _ = j2.finish()
+    e3, _, _ = j3.finish()
+    assert st1["launches"] == 3
+    assert np.array_equal(e0, e1) and np.array_equal(e0, e2)
+    for i in range(len(circs)):
+        assert np.array_equal(g0[i], g1[i]) and np.array_equal(g0[i], g2[i])
+    # the last job on these states was the forward batch
+    assert np.array_equal(ef, e3)
+    for i, c in enumerate(circs):
+        ref = oracle.simulate(c, params[i])
+        assert np.max(np.abs(to_host(states[i]) - ref)) < 1e-5
+    with pytest.raises(RuntimeError):
+        j1.finish()
+
+
 def test_batch_long_circuits_gradients():
     """Long circuits (30-40 layers, one or two tile passes each) in one
     persistent launch: gradients finite and equal to the shift rule."""
