@@ -98,6 +98,8 @@ def parse():
     p.add_argument("--threads", type=int, default=0)
     p.add_argument("--jit", type=int, default=0, help="plan-specialised kernels: 0 auto, 1 always, -1 never")
     p.add_argument("--no-tune", action="store_true", help="skip the tile-geometry autotuner")
+    p.add_argument("--plan-beam", type=int, default=0,
+                   help="planner beam width over the passes' local sets (0 = library default, 1 = greedy)")
     return p.parse_args()
 
 
@@ -530,7 +532,7 @@ def sample_leg(s, W, np, n, shots=1 << 20, reps=3):
             "hbm_frac_whole_call": moved / dt / 1e9 / HBM_PEAK_GBS, "linear_xeb_8192": xeb}
 
 
-def c128_leg(sv, W, torch, steps=2):
+def c128_leg(sv, W, torch, steps=2, beam=0):
     """The same kind of sweep in complex128: the 32-qubit 4x8 grid circuit
     with 40 cycles (64 GiB state), default options, tile passes timed with
     HIP events.  FP64 arithmetic issues at the same lane rate as FP32, and
@@ -538,7 +540,7 @@ def c128_leg(sv, W, torch, steps=2):
     HBM roofline."""
     circ = W.grid_circuit(4, 8, 40, seed=1005)
     n = circ.n
-    s = sv.StateVector(n, torch.complex128, opts=sv.make_opts(timing=1))
+    s = sv.StateVector(n, torch.complex128, opts=sv.make_opts(timing=1, plan_beam=beam))
     cabi = sv.CircuitABI(circ)
     s.init("zero_deferred")
     st, _ = s.apply_norm(cabi)                         # warm-up: plan, compile
@@ -889,16 +891,16 @@ def main():
         print(json.dumps(batch_leg(sv, W, torch, np, tune_file=args.batch_tune_file)), flush=True)
         return
     if args.c128_only:
-        print(json.dumps(c128_leg(sv, W, torch)), flush=True)
+        print(json.dumps(c128_leg(sv, W, torch, beam=args.plan_beam)), flush=True)
         return
 
     cols = args.qubits // 3
     circ = W.grid_circuit(3, cols, args.cycles, seed=1002)
     n = circ.n
     # host planning time of the circuit (IR, reordering, encoding), uncached
-    plan_ms_host = sv.plan_info(circ, torch.complex64)["plan_ms"]
+    plan_ms_host = sv.plan_info(circ, torch.complex64, opts=sv.make_opts(plan_beam=args.plan_beam))["plan_ms"]
     opts = sv.make_opts(timing=1, structured=args.structured, tile_bits=args.tile_bits,
-                        low_bits=args.low_bits, threads=args.threads, jit=args.jit)
+                        low_bits=args.low_bits, threads=args.threads, jit=args.jit, plan_beam=args.plan_beam)
     s = sv.StateVector(n, torch.complex64, opts=opts)
     cabi = sv.CircuitABI(circ)
     st = None
@@ -990,7 +992,7 @@ def main():
     out["plain_method"] = plain_leg(sv, W, torch)
     progress("copy ceiling and plain-method leg done")
     if not args.no_c128:
-        out["c128"] = c128_leg(sv, W, torch)
+        out["c128"] = c128_leg(sv, W, torch, beam=args.plan_beam)
         progress(f"c128 leg: {out['c128']['ms_per_step']:.1f} ms per step")
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(sv, W, torch, np)

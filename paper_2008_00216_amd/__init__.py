@@ -68,7 +68,8 @@ class SvOpts(ctypes.Structure):
                 ("low_bits", ctypes.c_int32), ("plain", ctypes.c_int32), ("threads", ctypes.c_int32),
                 ("product_init", ctypes.c_int32), ("structured", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("jit", ctypes.c_int32), ("max_work_mib", ctypes.c_int32),
-                ("batch_tuned", ctypes.c_int32), ("paper", ctypes.c_int32)]
+                ("batch_tuned", ctypes.c_int32), ("paper", ctypes.c_int32),
+                ("plan_beam", ctypes.c_int32)]
 
 
 class SvStats(ctypes.Structure):

@@ -126,6 +126,7 @@ PlanCfg batch_cfg(int dtype, bool two, int n, const BatchGeom& g) {
     if (p.T - p.L > kMaxHigh) p.L = p.T - kMaxHigh;
     p.nt = 256;
     p.two = two;
+    p.beam = std::max(1, g.beam);
     return p;
 }
 
@@ -137,7 +138,8 @@ std::shared_ptr<PlanKeyed> get_batch_plan(const sv_circuit* c, const std::vector
     const PlanCfg cfg = batch_cfg(dtype, two, c->n_qubits, g);
     const uint64_t key = circuit_hash(c, 0x9e3779b97f4a7c15ull ^ ((uint64_t)dtype << 8) ^ ((uint64_t)two << 12) ^
                                              ((uint64_t)bo.structured << 16) ^ ((uint64_t)(uint32_t)bo.fuse_k << 20) ^
-                                             ((uint64_t)cfg.T << 28) ^ ((uint64_t)cfg.L << 34) ^ ir_signature(ir));
+                                             ((uint64_t)cfg.T << 28) ^ ((uint64_t)cfg.L << 34) ^
+                                             ((uint64_t)cfg.beam << 40) ^ ir_signature(ir));
     {
         std::lock_guard<std::mutex> lk(g_plan_mu);
         auto it = g_plans.find(key);
@@ -198,6 +200,7 @@ sv_status batch_launch(int32_t count, const sv_batch_item* items, sv_dtype dtype
     if (count < 0) { err = "count < 0"; return SV_EINVAL; }
     if (count > 0 && !items) { err = "items is NULL"; return SV_EINVAL; }
     if (dtype != SV_C64 && dtype != SV_C128) { err = "dtype must be SV_C64 or SV_C128"; return SV_EINVAL; }
+    if (opts && (opts->plan_beam < 0 || opts->plan_beam > 64)) { err = "plan_beam must be 0..64"; return SV_EINVAL; }
     const bool grad = (flags & SV_BATCH_GRAD) != 0;
     if (grad) want_e = true;
     job.count = count;
@@ -255,6 +258,7 @@ sv_status batch_launch(int32_t count, const sv_batch_item* items, sv_dtype dtype
             auto gi = geoms->find(items[i].circuit->n_qubits);
             if (gi != geoms->end()) g = gi->second;
         }
+        g.beam = opts && opts->plan_beam > 0 ? opts->plan_beam : 1;
         return g;
     };
     // Gates wider than a register phase (input gates of more than 4 qubits,

@@ -181,6 +181,10 @@ PlanCfg cfg_for(const sv_ctx_s* c, bool two) {
     p.nt = nt;
     p.max_fuse_k = c->opts.max_fuse_k > 0 ? c->opts.max_fuse_k : 4;
     p.two = two;
+    // complex64 passes are ALU-bound: past 8 a wider search packs more work
+    // into fewer passes without saving time; complex128 passes are held by
+    // memory, so every pass saved counts
+    p.beam = c->opts.plan_beam > 0 ? c->opts.plan_beam : (c64 ? 8 : 16);
     return p;
 }
 
@@ -190,7 +194,8 @@ uint64_t opts_key(const sv_ctx_s* c, bool two, bool pinit) {
     k ^= ((uint64_t)c->opts.max_fuse_k << 1) ^ ((uint64_t)c->opts.tile_bits << 9) ^
          ((uint64_t)c->opts.low_bits << 17) ^ ((uint64_t)c->opts.plain << 25) ^
          ((uint64_t)c->opts.threads << 27) ^ ((uint64_t)c->opts.structured << 40) ^
-         ((uint64_t)two << 42) ^ ((uint64_t)pinit << 43) ^ ((uint64_t)(c->opts.jit + 2) << 45);
+         ((uint64_t)two << 42) ^ ((uint64_t)pinit << 43) ^ ((uint64_t)(c->opts.jit + 2) << 45) ^
+         ((uint64_t)c->opts.plan_beam << 48);
     return k;
 }
 
@@ -789,6 +794,7 @@ sv_status sv_create(sv_ctx* out, int32_t n, sv_dtype dt, int32_t batch, void* d_
     c->acct.cap = (size_t)c->opts.max_work_mib << 20;
     if (c->opts.max_fuse_k < 0 || c->opts.max_fuse_k > 6) { delete c; return fail(SV_EINVAL, "max_fuse_k must be 0..6"); }
     if (c->opts.tile_bits < 0 || c->opts.tile_bits > kMaxTileBits) { delete c; return fail(SV_EINVAL, "tile_bits must be 0..14"); }
+    if (c->opts.plan_beam < 0 || c->opts.plan_beam > 64) { delete c; return fail(SV_EINVAL, "plan_beam must be 0..64"); }
     static std::once_flag once;
     static hipError_t attr_err = hipSuccess;
     std::call_once(once, [] { attr_err = tile_pass_set_attrs(160 * 1024); });
@@ -817,6 +823,7 @@ sv_status sv_set_opts(sv_ctx c, const sv_opts* o) {
     if (!c || !o) return fail(SV_EINVAL, "ctx or opts is NULL");
     if (o->max_fuse_k < 0 || o->max_fuse_k > 6) return fail(SV_EINVAL, "max_fuse_k must be 0..6");
     if (o->tile_bits < 0 || o->tile_bits > kMaxTileBits) return fail(SV_EINVAL, "tile_bits must be 0..14");
+    if (o->plan_beam < 0 || o->plan_beam > 64) return fail(SV_EINVAL, "plan_beam must be 0..64");
     if (o->max_work_mib < 0) return fail(SV_EINVAL, "max_work_mib must be >= 0");
     if (o->paper < 0 || o->paper > 2) return fail(SV_EINVAL, "paper must be 0, 1 or 2");
     c->opts = *o;
@@ -1223,6 +1230,7 @@ sv_status sv_plan_info(const sv_circuit* circ, sv_dtype dtype, int32_t adjoint, 
     c.dtype = dtype;
     c.batch = 1;
     if (opts) c.opts = *opts; else sv_opts_default(&c.opts);
+    if (c.opts.plan_beam < 0 || c.opts.plan_beam > 64) return fail(SV_EINVAL, "plan_beam must be 0..64");
     c.known_zero = !adjoint;
     std::vector<double> params((size_t)std::max(1, circ->n_params), 0.0);
     std::vector<IRGate> ir;
@@ -1271,6 +1279,7 @@ sv_status sv_plan_trace(const sv_circuit* circ, const double* params, sv_dtype d
     c.dtype = dtype;
     c.batch = 1;
     if (opts) c.opts = *opts; else sv_opts_default(&c.opts);
+    if (c.opts.plan_beam < 0 || c.opts.plan_beam > 64) return fail(SV_EINVAL, "plan_beam must be 0..64");
     if (c.opts.paper) {
         // the paper's plan: one line per kind cluster (bitmasks in binary,
         // qubit n-1 first) and the circuit gates it applies, in order

@@ -125,6 +125,7 @@ struct BatchGeom {
     int fuse_k = 4;
     int T = 0;
     int L = 0;
+    int beam = 1;   // planner beam width (not tuned)
 };
 using GeomTable = std::map<int, BatchGeom>;   // width -> choice
 
@@ -137,6 +138,7 @@ struct PlanCfg {
     int nt = 512;                // threads per workgroup
     int max_fuse_k = 4;
     bool two = false;            // adjoint sweep (psi and lambda)
+    int beam = 1;                // width of the local-set beam search (1 = greedy per pass)
 };
 
 // Pool recipe: what goes into each pool slot (computed per call).

@@ -8,9 +8,11 @@
 // set S of local qubits, a gate is executable in the pass when it is
 // unobstructed and either diagonal with 8th-root phases (any qubits: the
 // kernel knows every amplitude's full index) or all its qubits are in S.  The
-// planner picks S by greedy demand and then a swap-based local search on the
-// number of gates executed.  Register phases inside a pass are chosen the
-// same way over 4-subsets of the local bits.
+// greedy S of a pass comes from demand and then a swap-based local search on
+// the number of gates executed; a beam search over whole sequences of such
+// sets (the greedy set and its best single swaps at every step) then looks
+// for fewer passes.  Register phases inside a pass are chosen the same way
+// over 4-subsets of the local bits.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -375,6 +377,186 @@ void trace_form(std::string* tr, const Form& F) {
 
 }  // namespace
 
+// Local set S of one pass (|S| = T, the L low bits always local): the qubits
+// of the leading unobstructed gates, filled up with the qubits that have the
+// most pending local work, then improved by swapping one high local qubit
+// for one non-local qubit while the scan score grows.
+uint64_t greedy_local_set(const std::vector<int>& rem, const std::vector<GInfo>& inf, int n, int T, int L) {
+    const uint64_t all = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
+    uint64_t S = (1ull << L) - 1ull;
+    {
+        uint64_t bND = 0, bD = 0;
+        for (int id : rem) {
+            const GInfo& g = inf[id];
+            if (g.cls == C_FREE) {
+                if (g.qm & bND) bD |= g.qm;
+                continue;
+            }
+            const uint64_t blk = g.diag ? bND : (bND | bD);
+            if (g.cls == C_LOCAL && !(g.qm & blk) && popc(S | g.qm) <= T) {
+                S |= g.qm;
+                continue;
+            }
+            if (g.diag) bD |= g.qm; else bND |= g.qm;
+            if ((bND & all) == all || popc(S) >= T) break;
+        }
+        if (popc(S) < T) {
+            std::vector<int> cnt((size_t)n, 0);
+            for (int id : rem)
+                if (inf[id].cls == C_LOCAL)
+                    for (int q = 0; q < n; ++q) if ((inf[id].qm >> q) & 1) cnt[q]++;
+            while (popc(S) < T) {
+                int best = -1;
+                for (int q = 0; q < n; ++q)
+                    if (!((S >> q) & 1) && (best < 0 || cnt[q] > cnt[best])) best = q;
+                if (best < 0) break;
+                S |= 1ull << best;
+            }
+        }
+    }
+    double best = scan(rem, inf, S, all, nullptr);
+    for (int round = 0; round < 6 && T < n; ++round) {
+        bool improved = false;
+        uint64_t bestS = S;
+        for (int a = L; a < n; ++a) {
+            if (!((S >> a) & 1)) continue;
+            for (int b = L; b < n; ++b) {
+                if ((S >> b) & 1) continue;
+                const uint64_t S2 = (S & ~(1ull << a)) | (1ull << b);
+                const double sc = scan(rem, inf, S2, all, nullptr);
+                if (sc > best + 1e-9) { best = sc; bestS = S2; improved = true; }
+            }
+        }
+        S = bestS;
+        if (!improved) break;
+    }
+    return S;
+}
+
+// Gates executed by a pass over local set S, in circuit order.  At most
+// kMaxGradPerPass gradient reductions per pass (their per-wave partials live
+// in LDS); a prefix of the executable list in circuit order is closed under
+// dependencies, so the rest waits for a later pass.
+std::vector<int> executable(const std::vector<IRGate>& ir, const std::vector<GInfo>& inf,
+                            const std::vector<int>& rem, uint64_t S, uint64_t all) {
+    std::vector<int> ex;
+    scan(rem, inf, S, all, &ex);
+    int ng = 0;
+    for (size_t e = 0; e < ex.size(); ++e)
+        if (ir[ex[e]].grad && ++ng > kMaxGradPerPass) {
+            ex.resize(e);
+            break;
+        }
+    return ex;
+}
+
+// Steps that remain after executing `ex` (a pass), or after the plain step of
+// the leading gate when `ex` is empty.
+std::vector<int> remove_executed(const std::vector<int>& rem, const std::vector<int>& ex, size_t nir) {
+    std::vector<int> nr;
+    if (ex.empty()) {
+        nr.assign(rem.begin() + 1, rem.end());
+        return nr;
+    }
+    std::vector<char> done(nir, 0);
+    for (int id : ex) done[id] = 1;
+    nr.reserve(rem.size() - ex.size());
+    for (int id : rem) if (!done[id]) nr.push_back(id);
+    return nr;
+}
+
+// Beam search over sequences of local sets.  The greedy choice maximises the
+// work of the current pass only, and a pass that takes a little less can
+// leave the rest of the circuit in fewer passes.  Every search state is a
+// list of remaining gates after some number of steps; its children are the
+// greedy set and the best single swaps away from it (by the scan score of the
+// current pass), and after each step the `width` states with the least
+// remaining gate weight survive (duplicates merged).  The first sequence that
+// empties the list wins; the greedy sequence is the fallback, so the result
+// never has more steps than greedy planning.  Returns one local set per step
+// (a plain step's entry is the set that found nothing to execute).
+std::vector<uint64_t> beam_local_sets(const std::vector<IRGate>& ir, const std::vector<GInfo>& inf,
+                                      const std::vector<int>& rem0, int n, int T, int L, int width) {
+    const uint64_t all = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
+    const int kids = std::max(2, std::min(width, 4));
+    struct Node {
+        std::vector<int> rem;
+        std::vector<uint64_t> seq;
+        double left = 0.0;
+        uint64_t hash = 0;
+    };
+    auto finish = [&](Node& nd) {
+        double w = 0.0;
+        uint64_t h = 1469598103934665603ull;
+        for (int id : nd.rem) {
+            w += inf[id].w;
+            h = (h ^ (uint64_t)id) * 1099511628211ull;
+        }
+        nd.left = w;
+        nd.hash = h ^ (uint64_t)nd.rem.size();
+    };
+    // greedy sequence: the fallback and the bound
+    std::vector<uint64_t> greedy;
+    {
+        std::vector<int> r = rem0;
+        while (!r.empty()) {
+            const uint64_t S = greedy_local_set(r, inf, n, T, L);
+            greedy.push_back(S);
+            r = remove_executed(r, executable(ir, inf, r, S, all), ir.size());
+        }
+    }
+    std::vector<Node> beam(1);
+    beam[0].rem = rem0;
+    finish(beam[0]);
+    while (!beam.empty() && beam[0].seq.size() + 1 < greedy.size()) {
+        std::vector<Node> next;
+        for (const Node& nd : beam) {
+            const uint64_t S0 = greedy_local_set(nd.rem, inf, n, T, L);
+            std::vector<std::pair<double, uint64_t>> cand;
+            cand.push_back({scan(nd.rem, inf, S0, all, nullptr) + 1e-6, S0});
+            if (!executable(ir, inf, nd.rem, S0, all).empty() && T < n) {
+                for (int a = L; a < n; ++a) {
+                    if (!((S0 >> a) & 1)) continue;
+                    for (int b = L; b < n; ++b) {
+                        if ((S0 >> b) & 1) continue;
+                        const uint64_t S2 = (S0 & ~(1ull << a)) | (1ull << b);
+                        cand.push_back({scan(nd.rem, inf, S2, all, nullptr), S2});
+                    }
+                }
+            }
+            std::stable_sort(cand.begin(), cand.end(),
+                             [](const std::pair<double, uint64_t>& x, const std::pair<double, uint64_t>& y) {
+                                 return x.first > y.first;
+                             });
+            int taken = 0;
+            for (const auto& c : cand) {
+                if (taken == kids) break;
+                const std::vector<int> ex = executable(ir, inf, nd.rem, c.second, all);
+                if (ex.empty() && c.second != S0) continue;
+                Node ch;
+                ch.rem = remove_executed(nd.rem, ex, ir.size());
+                ch.seq = nd.seq;
+                ch.seq.push_back(c.second);
+                if (ch.rem.empty()) return ch.seq;
+                finish(ch);
+                next.push_back(std::move(ch));
+                ++taken;
+            }
+        }
+        std::stable_sort(next.begin(), next.end(), [](const Node& x, const Node& y) { return x.left < y.left; });
+        std::vector<Node> keep;
+        for (Node& nd : next) {
+            if ((int)keep.size() == width) break;
+            bool dup = false;
+            for (const Node& k : keep)
+                if (k.hash == nd.hash && k.rem == nd.rem) { dup = true; break; }
+            if (!dup) keep.push_back(std::move(nd));
+        }
+        beam.swap(keep);
+    }
+    return greedy;
+}
+
 void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, EncodedPlan& out, std::string* tr) {
     out = EncodedPlan();
     out.cfg = cfg;
@@ -410,70 +592,16 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
     int scale_p = 0;
     const int scale_every = cfg.two ? kScaleEveryAdjoint : kScaleEvery;
 
+    // local sets of the tile passes, chosen ahead by a beam search over whole
+    // pass sequences (an empty list: greedy per pass)
+    const std::vector<uint64_t> seq = cfg.beam > 1 ? beam_local_sets(ir, inf, rem, n, T, L, cfg.beam)
+                                                   : std::vector<uint64_t>();
+    size_t it = 0;
     while (!rem.empty()) {
         // ---- choose the local set S (|S| = T, low bits always local)
-        uint64_t S = low;
-        {
-            uint64_t bND = 0, bD = 0;
-            for (int id : rem) {
-                const GInfo& g = inf[id];
-                if (g.cls == C_FREE) {
-                    if (g.qm & bND) bD |= g.qm;
-                    continue;
-                }
-                const uint64_t blk = g.diag ? bND : (bND | bD);
-                if (g.cls == C_LOCAL && !(g.qm & blk) && popc(S | g.qm) <= T) {
-                    S |= g.qm;
-                    continue;
-                }
-                if (g.diag) bD |= g.qm; else bND |= g.qm;
-                if ((bND & all) == all || popc(S) >= T) break;
-            }
-            // fill up with qubits that have pending local work, then any
-            if (popc(S) < T) {
-                std::vector<int> cnt((size_t)n, 0);
-                for (int id : rem)
-                    if (inf[id].cls == C_LOCAL)
-                        for (int q = 0; q < n; ++q) if ((inf[id].qm >> q) & 1) cnt[q]++;
-                while (popc(S) < T) {
-                    int best = -1;
-                    for (int q = 0; q < n; ++q)
-                        if (!((S >> q) & 1) && (best < 0 || cnt[q] > cnt[best])) best = q;
-                    if (best < 0) break;
-                    S |= 1ull << best;
-                }
-            }
-        }
-        double best = scan(rem, inf, S, all, nullptr);
-        // local search: swap one high local qubit for one non-local qubit
-        for (int round = 0; round < 6 && T < n; ++round) {
-            bool improved = false;
-            uint64_t bestS = S;
-            for (int a = L; a < n; ++a) {
-                if (!((S >> a) & 1)) continue;
-                for (int b = L; b < n; ++b) {
-                    if ((S >> b) & 1) continue;
-                    const uint64_t S2 = (S & ~(1ull << a)) | (1ull << b);
-                    const double sc = scan(rem, inf, S2, all, nullptr);
-                    if (sc > best + 1e-9) { best = sc; bestS = S2; improved = true; }
-                }
-            }
-            S = bestS;
-            if (!improved) break;
-        }
-        std::vector<int> ex;
-        scan(rem, inf, S, all, &ex);
-        // at most kMaxGradPerPass gradient reductions per pass (their per-wave
-        // partials live in LDS); a prefix of the executable list in circuit
-        // order is closed under dependencies, so the rest waits for a later pass
-        {
-            int ng = 0;
-            for (size_t e = 0; e < ex.size(); ++e)
-                if (ir[ex[e]].grad && ++ng > kMaxGradPerPass) {
-                    ex.resize(e);
-                    break;
-                }
-        }
+        const uint64_t S = it < seq.size() ? seq[it] : greedy_local_set(rem, inf, n, T, L);
+        ++it;
+        std::vector<int> ex = executable(ir, inf, rem, S, all);
         if (ex.empty()) {
             // the frontier is a gate wider than a register phase: plain kernel
             const int id = rem[0];

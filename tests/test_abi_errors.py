@@ -48,6 +48,7 @@ def test_create_rejects(kw, msg):
 @pytest.mark.parametrize("field, value, msg", [
     ("max_fuse_k", 7, "max_fuse_k"), ("max_fuse_k", -1, "max_fuse_k"),
     ("tile_bits", 15, "tile_bits"), ("max_work_mib", -1, "max_work_mib"),
+    ("plan_beam", 65, "plan_beam"), ("plan_beam", -1, "plan_beam"),
 ])
 def test_create_rejects_options(field, value, msg):
     st, err = create(opts=m.make_opts(**{field: value}))

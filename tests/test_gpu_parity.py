@@ -210,6 +210,20 @@ def test_tile_geometries(tile_bits, low_bits):
         check_close(got[0], ref, dtype, f"T={tile_bits} L={low_bits}")
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("beam", [1, 2, 16])
+def test_planner_beam_widths(dtype, beam):
+    # different local-set sequences (15 passes greedily, 13 with a beam)
+    # and the interpreted and plan-specialised kernels give the oracle's state
+    c = W.random_circuit(16, 220, seed=97, mat_k=(2, 3))
+    p = W.uniform_params(1, c.n_params, 93)[0]
+    psi0 = W.random_state(16, 94)
+    ref = oracle.simulate(c, p, psi0=psi0)
+    for jit in (-1, 1):
+        got, st = run(c, psi0, dtype, params=p, tile_bits=8, low_bits=3, plan_beam=beam, jit=jit)
+        check_close(got[0], ref, dtype, f"beam={beam} jit={jit} passes={st['passes']}")
+
+
 def test_line_circuit_gate_by_gate_c128():
     c = W.line_circuit()
     ref = oracle.simulate(c)

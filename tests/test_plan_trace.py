@@ -178,3 +178,57 @@ def test_permutation_gates_are_register_permutations(seed):
     # adjoint plans too (inverse gates in reverse order)
     tr_b = m.plan_trace(c, None, opts=m.make_opts(tile_bits=7, low_bits=3), adjoint=True)
     assert sum(1 for l in tr_b.splitlines() if l.startswith("PERM ")) == nperm
+
+
+@pytest.mark.parametrize("beam", [1, 2, 8, 32])
+def test_beam_searched_local_sets_keep_the_state(beam):
+    # Sec. 4.5: any choice of local sets is a valid reordering; the beam
+    # search only changes which gates share a pass
+    m = lib()
+    c = W.grid_circuit(3, 5, 16, seed=91)
+    tr = _check(m, c, tile_bits=7, low_bits=3, plan_beam=beam)
+    assert tr.count("PASS") > 1
+    # 12 passes greedily, 10 with the beam search at width 8
+    c2 = W.random_circuit(10, 150, seed=97, mat_k=(2, 3))
+    p = W.uniform_params(1, c2.n_params, 93)[0]
+    _check(m, c2, p, tile_bits=6, low_bits=2, psi0=W.random_state(10, 94), plan_beam=beam)
+
+
+def test_beam_search_never_adds_passes():
+    m = lib()
+    import torch
+    cases = [(W.grid_circuit(3, 5, 16, seed=91), 7, 3), (W.grid_circuit(4, 4, 20, seed=95), 8, 3),
+             (W.random_circuit(12, 200, seed=96, mat_k=(2, 3)), 7, 3), (W.grid33(), 13, 4)]
+    fewer = 0
+    for c, tb, lb in cases:
+        for dt in (torch.complex64, torch.complex128):
+            greedy = m.plan_info(c, dt, opts=m.make_opts(tile_bits=tb, low_bits=lb, plan_beam=1))["passes"]
+            for beam in (2, 8, 16):
+                p = m.plan_info(c, dt, opts=m.make_opts(tile_bits=tb, low_bits=lb, plan_beam=beam))["passes"]
+                assert p <= greedy, (c.n, tb, beam, p, greedy)
+                fewer += p < greedy
+    # the 3x11 grid of 33 qubits at 2^13-amplitude tiles: 22 greedy passes
+    assert m.plan_info(W.grid33(), opts=m.make_opts(tile_bits=13, low_bits=4, plan_beam=8))["passes"] < 22
+    assert fewer > 0
+
+
+@pytest.mark.parametrize("beam", [2, 8])
+def test_beam_searched_adjoint_plan_matches_the_oracle(beam):
+    m = lib()
+    # 6 passes greedily, 5 with the beam search at width 8
+    c = W.random_circuit(10, 160, seed=97, ops=("H", "SQRTX", "SQRTY", "T", "S", "CZ", "RY", "RZ", "RX", "CP"),
+                         param_frac=1.0)
+    p = W.uniform_params(1, c.n_params, 98)[0]
+    h = W.pauli_sum([(1.0, {0: "Z", 5: "Z"}), (0.5, {7: "X"}), (-0.3, {2: "Y", 9: "Z"})])
+    opts = m.make_opts(tile_bits=6, low_bits=2, plan_beam=beam)
+    tr = m.plan_trace(c, p, adjoint=True, opts=opts)
+    assert tr.count("PASS") > 1
+    if beam == 8:
+        greedy = m.plan_info(c, adjoint=True, opts=m.make_opts(tile_bits=6, low_bits=2, plan_beam=1))["passes"]
+        assert m.plan_info(c, adjoint=True, opts=opts)["passes"] < greedy
+    psi0 = W.random_state(10, 99)
+    fwd = oracle.simulate(c, p, psi0=psi0)
+    (back, _), grads = evaluate(tr, 10, fwd, apply_pauli_sum(fwd, 10, h))
+    assert np.max(np.abs(back - psi0)) < 1e-12
+    ref = oracle.grad_param_shift(c, p, h, psi0)
+    np.testing.assert_allclose(np.array([grads[i] for i in range(c.n_params)]), ref, atol=1e-11)
