@@ -369,7 +369,7 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def batch_leg(sv, W, torch, np, count=512, tune_file=None):
+def batch_leg(sv, W, torch, np, count=512, tune_file=None, beam=0):
     """512 circuits, n ~ U{10..22}, 20..60 layers (RY + a random gate per qubit
     + CZ), observable sum Z_i: energies and adjoint gradients of all of them
     in one persistent launch, against the same work one circuit at a time."""
@@ -381,8 +381,9 @@ def batch_leg(sv, W, torch, np, count=512, tune_file=None):
     states = [torch.empty(1 << c.n, dtype=torch.complex64, device="cuda") for c in circs]
     lams = [torch.empty_like(t) for t in states]
     progress(f"batch: {count} circuits generated")
+    bopts = sv.make_opts(plan_beam=beam)
     if tune_file is None:
-        e, g, st = sv.apply_batch(circs, params, states, obs, lambdas=lams, grad=True, init_zero=True)
+        e, g, st = sv.apply_batch(circs, params, states, obs, lambdas=lams, grad=True, init_zero=True, opts=bopts)
         torch.cuda.synchronize()
         progress("batch: first persistent launch done (plans built)")
     reps = 3
@@ -390,20 +391,20 @@ def batch_leg(sv, W, torch, np, count=512, tune_file=None):
     if tune_file is None:
         t0 = time.perf_counter()
         for _ in range(reps):
-            e, g, st = sv.apply_batch(circs, params, states, obs, lambdas=lams, grad=True, init_zero=True)
+            e, g, st = sv.apply_batch(circs, params, states, obs, lambdas=lams, grad=True, init_zero=True, opts=bopts)
         torch.cuda.synchronize()
         t_default = (time.perf_counter() - t0) / reps
         progress(f"batch: {t_default * 1e3:.1f} ms per launch with the default geometry")
         # per-width fusion mode and tile geometry by measurement
         t0 = time.perf_counter()
-        ntuned = sv.tune_batch(circs, params, states, obs, lambdas=lams, grad=True)
+        ntuned = sv.tune_batch(circs, params, states, obs, lambdas=lams, grad=True, opts=bopts)
         t_tune = time.perf_counter() - t0
     else:
         # choices of an earlier sv_tune_batch run, read from its file
         ntuned, t_tune = -1, 0.0
     widths = sorted({c.n for c in circs_py})
     tuning = {int(w): sv.batch_tuning(w, grad=True) for w in widths}
-    topts = sv.make_opts(batch_tuned=1)
+    topts = sv.make_opts(batch_tuned=1, plan_beam=beam)
     e, g, st = sv.apply_batch(circs, params, states, obs, lambdas=lams, grad=True, init_zero=True, opts=topts)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -532,7 +533,7 @@ def sample_leg(s, W, np, n, shots=1 << 20, reps=3):
             "hbm_frac_whole_call": moved / dt / 1e9 / HBM_PEAK_GBS, "linear_xeb_8192": xeb}
 
 
-def c128_leg(sv, W, torch, steps=2, beam=0):
+def c128_leg(sv, W, torch, steps=2, beam=0, geometry=(0, 0, 0)):
     """The same kind of sweep in complex128: the 32-qubit 4x8 grid circuit
     with 40 cycles (64 GiB state), default options, tile passes timed with
     HIP events.  FP64 arithmetic issues at the same lane rate as FP32, and
@@ -540,7 +541,8 @@ def c128_leg(sv, W, torch, steps=2, beam=0):
     HBM roofline."""
     circ = W.grid_circuit(4, 8, 40, seed=1005)
     n = circ.n
-    s = sv.StateVector(n, torch.complex128, opts=sv.make_opts(timing=1, plan_beam=beam))
+    kw = dict(zip(("tile_bits", "low_bits", "threads"), geometry))
+    s = sv.StateVector(n, torch.complex128, opts=sv.make_opts(timing=1, plan_beam=beam, **kw))
     cabi = sv.CircuitABI(circ)
     s.init("zero_deferred")
     st, _ = s.apply_norm(cabi)                         # warm-up: plan, compile
@@ -888,10 +890,11 @@ def main():
         print(json.dumps(sf_leg(sv, W, torch, np)), flush=True)
         return
     if args.batch_only:
-        print(json.dumps(batch_leg(sv, W, torch, np, tune_file=args.batch_tune_file)), flush=True)
+        print(json.dumps(batch_leg(sv, W, torch, np, tune_file=args.batch_tune_file, beam=args.plan_beam)), flush=True)
         return
     if args.c128_only:
-        print(json.dumps(c128_leg(sv, W, torch, beam=args.plan_beam)), flush=True)
+        print(json.dumps(c128_leg(sv, W, torch, beam=args.plan_beam,
+                                  geometry=(args.tile_bits, args.low_bits, args.threads))), flush=True)
         return
 
     cols = args.qubits // 3
@@ -998,7 +1001,7 @@ def main():
         out["adjoint"] = adjoint_leg(sv, W, torch, np)
         progress("adjoint leg done")
     if not args.no_batch:
-        out["batch"] = batch_leg(sv, W, torch, np)
+        out["batch"] = batch_leg(sv, W, torch, np, beam=args.plan_beam)
     if not args.no_sf:
         out["schroedinger_feynman"] = sf_leg(sv, W, torch, np)
         progress("Schroedinger-Feynman leg done")

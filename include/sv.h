@@ -137,11 +137,12 @@ typedef struct {
                               LDS-staged chunks); 0 = tile passes (default) */
     int32_t plan_beam;     /* tile-pass planner (Sec. 4.5 reordering): width of the beam search
                               over the sequence of the passes' local qubit sets, 1..64; 1 = the
-                              greedy set of each pass alone.  0 = default: 8 (SV_C64) or 16
-                              (SV_C128) for contexts, 1 for the items of sv_apply_batch.  Any
-                              width gives the same state up to rounding; a wider search costs
-                              host planning time (about 0.1 s at width 8 for 1 900 gates on 33
-                              qubits) and never yields more passes than width 1 */
+                              greedy set of each pass alone.  0 = default: 8, or 16 for SV_C128
+                              contexts.  Any width gives the same state up to rounding; a wider
+                              search costs host planning time (about 0.1 s at width 8 for 1 900
+                              gates on 33 qubits, about 1.7x the greedy planning of a batch item;
+                              plans are cached by circuit structure) and never yields more
+                              passes than width 1 */
 } sv_opts;
 
 typedef struct {

@@ -258,7 +258,7 @@ sv_status batch_launch(int32_t count, const sv_batch_item* items, sv_dtype dtype
             auto gi = geoms->find(items[i].circuit->n_qubits);
             if (gi != geoms->end()) g = gi->second;
         }
-        g.beam = opts && opts->plan_beam > 0 ? opts->plan_beam : 1;
+        g.beam = opts && opts->plan_beam > 0 ? opts->plan_beam : 8;
         return g;
     };
     // Gates wider than a register phase (input gates of more than 4 qubits,

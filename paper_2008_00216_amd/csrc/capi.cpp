@@ -910,7 +910,8 @@ sv_status sv_tune(sv_ctx c, const sv_circuit* circ, const double* params, sv_opt
     const sv_opts base = c->opts;
     uint64_t key = circuit_hash(circ, 0x5a17ull ^ ((uint64_t)c->dtype << 3) ^ ((uint64_t)c->batch << 8) ^
                                           ((uint64_t)c->n << 40) ^ ((uint64_t)base.structured << 50) ^
-                                          ((uint64_t)(base.jit + 2) << 52) ^ ((uint64_t)base.max_fuse_k << 56));
+                                          ((uint64_t)(base.jit + 2) << 52) ^ ((uint64_t)base.max_fuse_k << 56) ^
+                                          ((uint64_t)base.plan_beam * 0x9e3779b97f4a7c15ull));
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         if (g_tune.empty()) {   // results of earlier processes

@@ -125,7 +125,7 @@ struct BatchGeom {
     int fuse_k = 4;
     int T = 0;
     int L = 0;
-    int beam = 1;   // planner beam width (not tuned)
+    int beam = 8;   // planner beam width (not tuned)
 };
 using GeomTable = std::map<int, BatchGeom>;   // width -> choice
 
