@@ -438,10 +438,13 @@ void fill_stats(sv_stats* st, const sv_ctx_s* c, const CachedPlan& cp, const sv_
 struct PauliPack {
     std::vector<unsigned char> buf;
     size_t ox = 0, og = 0, oz = 0, oc = 0, oph = 0;
+    size_t ogm = 0, ohz = 0, ohc = 0, ohm = 0;   // tiled lambda = H psi tables (hpsi)
+    bool hpsi = false;
     uint32_t ng = 0;
 };
 
-sv_status pack_pauli(const sv_ctx_s* c, const sv_pauli_sum* h, PauliPack& pk) {
+// hpsi: also the tables of the tiled lambda = H psi kernel.
+sv_status pack_pauli(const sv_ctx_s* c, const sv_pauli_sum* h, PauliPack& pk, bool hpsi = false) {
     if (!h || h->n_terms < 0) return fail(SV_EINVAL, "observable is NULL or has n_terms < 0");
     if (h->n_terms > 0 && (!h->coeff || !h->x_mask || !h->z_mask)) return fail(SV_EINVAL, "observable arrays are NULL");
     const uint64_t qm = c->n >= 64 ? ~0ull : ((1ull << c->n) - 1ull);
@@ -469,18 +472,53 @@ sv_status pack_pauli(const sv_ctx_s* c, const sv_pauli_sum* h, PauliPack& pk) {
         }
     }
     g0.push_back((uint32_t)z.size());
+    // tiled-kernel order: per group the even-exponent terms, then the odd
+    std::vector<uint32_t> gm, hm;
+    std::vector<uint64_t> hz;
+    std::vector<double> hc;
+    if (hpsi) {
+        for (size_t g = 0; g < ng; ++g) {
+            for (int odd = 0; odd < 2; ++odd) {
+                if (odd) gm.push_back((uint32_t)hz.size());
+                for (uint32_t t = g0[g]; t < g0[g + 1]; ++t) {
+                    if ((int)(ph[t] & 1) != odd) continue;
+                    hz.push_back(z[t]);
+                    hc.push_back(ph[t] >= 2 ? -cf[t] : cf[t]);
+                    uint32_t m = 0;
+                    for (uint32_t k = 0; k < 8; ++k)
+                        m |= (uint32_t)(__builtin_popcountll((z[t] >> 8) & 7ull & k) & 1) << k;
+                    hm.push_back(m);
+                }
+            }
+        }
+    }
+    pk.hpsi = hpsi;
     pk.ox = 0;
     pk.og = align_up(pk.ox + ng * 8, 64);
     pk.oz = align_up(pk.og + (ng + 1) * 4, 64);
     pk.oc = align_up(pk.oz + nt * 8, 64);
     pk.oph = align_up(pk.oc + nt * 8, 64);
-    const size_t tot = align_up(pk.oph + nt * 4 + 64, 64);
+    size_t end = pk.oph + nt * 4;
+    if (hpsi) {
+        pk.ogm = align_up(end, 64);
+        pk.ohz = align_up(pk.ogm + ng * 4, 64);
+        pk.ohc = align_up(pk.ohz + nt * 8, 64);
+        pk.ohm = align_up(pk.ohc + nt * 8, 64);
+        end = pk.ohm + nt * 4;
+    }
+    const size_t tot = align_up(end + 64, 64);
     pk.buf.assign(tot, 0);
     std::memcpy(pk.buf.data() + pk.ox, xs.data(), ng * 8);
     std::memcpy(pk.buf.data() + pk.og, g0.data(), (ng + 1) * 4);
     std::memcpy(pk.buf.data() + pk.oz, z.data(), nt * 8);
     std::memcpy(pk.buf.data() + pk.oc, cf.data(), nt * 8);
     std::memcpy(pk.buf.data() + pk.oph, ph.data(), nt * 4);
+    if (hpsi) {
+        std::memcpy(pk.buf.data() + pk.ogm, gm.data(), ng * 4);
+        std::memcpy(pk.buf.data() + pk.ohz, hz.data(), nt * 8);
+        std::memcpy(pk.buf.data() + pk.ohc, hc.data(), nt * 8);
+        std::memcpy(pk.buf.data() + pk.ohm, hm.data(), nt * 4);
+    }
     pk.ng = (uint32_t)ng;
     return SV_OK;
 }
@@ -494,12 +532,18 @@ PauliDev pauli_at(const PauliPack& pk, unsigned char* d) {
     pd.c = reinterpret_cast<const double*>(d + pk.oc);
     pd.ph = reinterpret_cast<const uint32_t*>(d + pk.oph);
     pd.ngroup = pk.ng;
+    if (pk.hpsi) {
+        pd.gm = reinterpret_cast<const uint32_t*>(d + pk.ogm);
+        pd.hz = reinterpret_cast<const uint64_t*>(d + pk.ohz);
+        pd.hc = reinterpret_cast<const double*>(d + pk.ohc);
+        pd.hm = reinterpret_cast<const uint32_t*>(d + pk.ohm);
+    }
     return pd;
 }
 
-sv_status upload_pauli(sv_ctx_s* c, const sv_pauli_sum* h, PauliDev& pd) {
+sv_status upload_pauli(sv_ctx_s* c, const sv_pauli_sum* h, PauliDev& pd, bool hpsi = false) {
     PauliPack pk;
-    sv_status st = pack_pauli(c, h, pk);
+    sv_status st = pack_pauli(c, h, pk, hpsi);
     if (st != SV_OK) return st;
     HIPCHK(c->pauli.ensure(pk.buf.size()));
     HIPCHK(hipMemcpyAsync(c->pauli.p, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice, c->stream));
@@ -1151,7 +1195,7 @@ sv_status sv_adjoint_grad(sv_ctx c, const sv_circuit* circ, const double* params
     for (int64_t i = 0; params && i < (int64_t)c->batch * circ->n_params; ++i)
         if (!std::isfinite(params[i])) return fail(SV_EINVAL, "non-finite parameter");
     PauliDev pd{};
-    sv_status st = upload_pauli(c, h, pd);
+    sv_status st = upload_pauli(c, h, pd, true);
     if (st != SV_OK) return st;
     // forward sweep (folds leading one-qubit gates when the state is |0...0>)
     st = apply_internal(c, circ, params, stats);

@@ -90,6 +90,15 @@ struct PauliDev {
     const double* c;          // coefficient per term
     const uint32_t* ph;       // i^{|x&z|} exponent per term
     uint32_t ngroup;
+    // Tables of the tiled lambda = H psi kernel (null unless requested).
+    // Within each group the terms with an even phase exponent come first,
+    // up to gm[g]; per term in that order: hz = z mask, hc = coefficient
+    // times the real sign of i^ph (so the term is hc, or i hc for odd ph),
+    // hm bit k (k < 8) = parity of (z >> 8) & k.
+    const uint32_t* gm;
+    const uint64_t* hz;
+    const double* hc;
+    const uint32_t* hm;
 };
 hipError_t launch_reduce(int dtype, int kind, const void* a, const void* b, uint64_t bstride,
                          int batch, int n, const PauliDev* pd, int gen, uint64_t gmask,

@@ -114,3 +114,32 @@ def test_long_single_pass_adjoint(jit):
     sel = list(range(0, c.n_params, 23))
     np.testing.assert_allclose(g[0][sel], ref[sel], atol=2e-4)
     assert abs(e[0] - oracle.expect(oracle.simulate(c, p[0]), h)) < 2e-4
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+@pytest.mark.parametrize("n", [10, 11, 13, 16])
+def test_lambda_tiles_rich_observable(dtype, n):
+    # lambda = H psi runs by tiles of 2^11 amplitudes from n = 11 on: X masks
+    # below, across and above the tile, several terms per X mask with even
+    # and odd phase exponents (X, Y), Z on lane, tile and block bits, and an
+    # identity term; n = 10 keeps the untiled kernel
+    m = lib()
+    hi = n - 1
+    terms = [(0.7, {}), (1.0, {0: "Z", 9: "Z"}), (-0.4, {8: "Z", hi: "Z"}), (0.25, {3: "X"}), (0.6, {3: "Y"}),
+             (-0.35, {3: "Y", 10 % n: "Z"}), (0.45, {9: "X", 5: "Z"}), (0.3, {hi: "X"}), (-0.2, {hi: "Y", 2: "Z"}),
+             (0.15, {0: "X", hi: "X"}), (0.5, {1: "Y", (hi + 1) // 2: "Y"}), (-0.55, {7: "X", 8: "Y", hi: "Z"})]
+    h = W.pauli_sum(terms)
+    ops = ("H", "SQRTX", "T", "CZ", "RX", "RY", "RZ", "CP")
+    c = W.random_circuit(n, 60, 300 + n, ops=ops, param_frac=1.0)
+    B = 2
+    th = W.uniform_params(B, c.n_params, 301 + n)
+    psi0 = np.stack([round_c64(W.random_state(n, 302 + n + b)) for b in range(B)])
+    t = to_dev(psi0, dtype)
+    s = m.StateVector(n, dtype, batch=B, tensor=t)
+    e, g = s.adjoint_grad(c, th, h)
+    for b in range(B):
+        e_ref = oracle.energy(c, th[b], h, psi0[b])
+        assert abs(e[b] - e_ref) < TOL[dtype], (b, e[b], e_ref)
+        if b == 0:
+            g_ref = oracle.grad_param_shift(c, th[b], h, psi0[b])
+            np.testing.assert_allclose(g[b], g_ref, atol=TOL[dtype])
