@@ -474,8 +474,14 @@ std::vector<IRGate> build_ir(const sv_circuit* c, const double* params, const Bu
         for (int i = 0; i < c->n_gates; ++i)
             if (!consumed[i]) in.push_back(make_ir(c, i, params, o, false));
     } else {
+        // Each parametric gate exp(-i theta G / 2) commutes with its
+        // generator G, so Im <lambda|G|psi> has the same value before and
+        // after the gate's inverse is applied to both states.  The gradient
+        // term goes after it: the inverse takes over the pending phases on
+        // its qubits (Sec. 4.3), and the term then finds none there.
         for (int i = c->n_gates - 1; i >= 0; --i) {
             const sv_gate& g = c->gates[i];
+            in.push_back(make_ir(c, i, params, o, true));
             if (g.param >= 0) {
                 IRGate gr;
                 gr.grad = 1;
@@ -487,7 +493,6 @@ std::vector<IRGate> build_ir(const sv_circuit* c, const double* params, const Bu
                 gr.src = i;
                 in.push_back(gr);
             }
-            in.push_back(make_ir(c, i, params, o, true));
         }
     }
     if (!o.fuse) return in;

@@ -857,7 +857,11 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
                     out.alu_ops += (real ? 4.0 : 8.0) * (double)(1ull << n) * (cfg.two ? 2 : 1);
                     continue;
                 }
-                if (pending.depends(g.qmask())) flush(false);
+                // A diagonal gate, or a gradient term whose generator is
+                // diagonal, commutes with the pending diagonal phases (which
+                // psi and lambda share), so those stay pending
+                const bool commutes = g.kind == K_DIAGG || (g.grad && (g.gen == GEN_Z || g.gen == GEN_P11));
+                if (!commutes && pending.depends(g.qmask())) flush(false);
                 if (g.grad) {
                     uint32_t mask = 0;
                     for (int t = 0; t < g.k; ++t) mask |= 1u << slot_of_q[t];
