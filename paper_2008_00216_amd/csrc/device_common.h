@@ -104,6 +104,36 @@ __device__ __forceinline__ double lane_f64(double v, int l) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// DPP moves into the rows of ROW_MASK only (the lanes of the other rows read
+// 0), of a float and of both halves of a double.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_rows(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_rows(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes of a wave (all lanes active), complete in lane 63
+// only: each row of 16 lanes is summed (swaps within quads, rotations by 4
+// and 8 lanes), then row 1 adds the sum of row 0 and row 3 that of row 2
+// (row_bcast:15), and rows 2 and 3 add the sum of rows 0 and 1
+// (row_bcast:31).  No lane reads; the lanes of the other rows add 0.
+template <class T>
+__device__ __forceinline__ T wave_sum_lane63(T v) {
+    v += dpp_rows<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+    v += dpp_rows<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+    v += dpp_rows<0x124, 0xF>(v);   // row_ror:4
+    v += dpp_rows<0x128, 0xF>(v);   // row_ror:8
+    v += dpp_rows<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_rows<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 // Sum over the 64 lanes of a wave (all lanes active), in every lane: each
 // row of 16 lanes is summed with DPP (swaps within quads, then rotations by 4
 // and 8 lanes), and the four row sums are read with readlane.  No LDS round

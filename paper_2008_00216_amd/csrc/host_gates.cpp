@@ -476,14 +476,15 @@ std::vector<IRGate> build_ir(const sv_circuit* c, const double* params, const Bu
     } else {
         // Each parametric gate exp(-i theta G / 2) commutes with its
         // generator G, so Im <lambda|G|psi> has the same value before and
-        // after the gate's inverse is applied to both states.  The gradient
-        // term goes after it: the inverse takes over the pending phases on
-        // its qubits (Sec. 4.3), and the term then finds none there.
+        // after the gate's inverse is applied to both states.  With the
+        // structured forms the term goes after it: the inverse takes over the
+        // pending phases on its qubits (Sec. 4.3), and the term then finds
+        // none there.  With dense blocks it goes before, where it does not
+        // separate the inverse from the gates applied next on its qubits.
         for (int i = c->n_gates - 1; i >= 0; --i) {
             const sv_gate& g = c->gates[i];
-            in.push_back(make_ir(c, i, params, o, true));
+            IRGate gr;
             if (g.param >= 0) {
-                IRGate gr;
                 gr.grad = 1;
                 gr.kind = K_DENSE;
                 gr.k = g.nq;
@@ -491,8 +492,10 @@ std::vector<IRGate> build_ir(const sv_circuit* c, const double* params, const Bu
                 gr.param = g.param;
                 gr.gen = gen_of(g.op);
                 gr.src = i;
-                in.push_back(gr);
+                if (!o.structured) in.push_back(gr);
             }
+            in.push_back(make_ir(c, i, params, o, true));
+            if (g.param >= 0 && o.structured) in.push_back(gr);
         }
     }
     if (!o.fuse) return in;

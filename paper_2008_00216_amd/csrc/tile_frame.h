@@ -224,12 +224,12 @@ struct TileFrame {
         }
     }
 
-    // wave-reduced gradient partial into the per-wave slot
-    __device__ __forceinline__ void grad_add(uint32_t slot, double v) const {
-        v = wave_sum_(v);
-        if ((tid & 63u) == 0) red[slot * NW + (tid >> 6)] += v;
+    // Gradient partial summed over the wave in the state's precision (DPP
+    // only, the sum lands in lane 63), then added in FP64 to the per-wave slot.
+    __device__ __forceinline__ void grad_add(uint32_t slot, R v) const {
+        v = wave_sum_lane63(v);
+        if ((tid & 63u) == 63u) red[slot * NW + (tid >> 6)] += (double)v;
     }
-    __device__ __forceinline__ static double wave_sum_(double v) { return wave_sum64(v); }
 
     // Gradient partials of this tile and the scatter back to HBM.
     template <class HP>

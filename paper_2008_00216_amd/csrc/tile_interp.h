@@ -131,18 +131,18 @@ __device__ __forceinline__ void d1t_dispatch_u(V2<R>* a, uint32_t slot, cptr_t<V
 }
 
 template <class R, uint32_t GEN>
-__device__ __forceinline__ double grad1_dispatch(const V2<R>* p, const V2<R>* l, uint32_t mask) {
+__device__ __forceinline__ R grad1_dispatch(const V2<R>* p, const V2<R>* l, uint32_t mask) {
     switch (mask) {
         case 1: return op_grad1<R, 0, GEN>(p, l);
         case 2: return op_grad1<R, 1, GEN>(p, l);
         case 4: return op_grad1<R, 2, GEN>(p, l);
         case 8: return op_grad1<R, 3, GEN>(p, l);
-        default: return 0.0;
+        default: return R(0);
     }
 }
 
 template <class R>
-__device__ __forceinline__ double grad_dispatch(const V2<R>* p, const V2<R>* l, uint32_t gen, uint32_t mask) {
+__device__ __forceinline__ R grad_dispatch(const V2<R>* p, const V2<R>* l, uint32_t gen, uint32_t mask) {
     switch (gen) {
         case GEN_X: return grad1_dispatch<R, GEN_X>(p, l, mask);
         case GEN_Y: return grad1_dispatch<R, GEN_Y>(p, l, mask);
@@ -156,7 +156,7 @@ __device__ __forceinline__ double grad_dispatch(const V2<R>* p, const V2<R>* l, 
         case 9: return op_grad11<R, 9>(p, l);
         case 10: return op_grad11<R, 10>(p, l);
         case 12: return op_grad11<R, 12>(p, l);
-        default: return 0.0;
+        default: return R(0);
     }
 }
 

@@ -359,10 +359,10 @@ __device__ __forceinline__ void op_phase8(V2<R>* a, V2<R>* l, uint32_t e0, const
 // ---- adjoint gradient terms -----------------------------------------------
 // Im <lambda|G|psi> over the 16 register amplitudes, G = X, Y or Z on slot
 // S.  The thread's products are accumulated with fused multiply-adds in the
-// state's precision (two chains) and returned as a double; the sum of these
-// partials over the 2^n / 16 register groups of the state is taken in FP64.
+// state's precision (two chains); the frame sums these partials over the
+// wave in the same precision, and the wave sums over the state in FP64.
 template <class R, int S, uint32_t GEN>
-__device__ __forceinline__ double op_grad1(const V2<R>* p, const V2<R>* l) {
+__device__ __forceinline__ R op_grad1(const V2<R>* p, const V2<R>* l) {
     R acc[2] = {R(0), R(0)};
     int c = 0;
 #pragma unroll
@@ -385,12 +385,12 @@ __device__ __forceinline__ double op_grad1(const V2<R>* p, const V2<R>* l) {
             a = fma_(-l1.x, p1.y, a); a = fma_(l1.y, p1.x, a);
         }
     }
-    return (double)acc[0] + (double)acc[1];
+    return acc[0] + acc[1];
 }
 
 // Generator -2 |11><11| on the two slots of MASK (controlled phase).
 template <class R, int MASK>
-__device__ __forceinline__ double op_grad11(const V2<R>* p, const V2<R>* l) {
+__device__ __forceinline__ R op_grad11(const V2<R>* p, const V2<R>* l) {
     R acc = R(0);
 #pragma unroll
     for (int i = 0; i < 16; ++i)
@@ -398,7 +398,7 @@ __device__ __forceinline__ double op_grad11(const V2<R>* p, const V2<R>* l) {
             acc = fma_(l[i].x, p[i].y, acc);
             acc = fma_(-l[i].y, p[i].x, acc);
         }
-    return -2.0 * (double)acc;
+    return R(-2) * acc;
 }
 
 // Exact permutation on register slots (OP_PERM): KIND 1 = X on slot SA,
