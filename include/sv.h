@@ -391,8 +391,10 @@ sv_status sv_batch_finish(sv_batch_job job, double* energies, double* grads, sv_
  * measurement, and the fusion width): for every width among the items, times
  * one persistent launch of that width's items under candidate fusion modes
  * (butterflies with lazily applied phases; dense blocks of 2, 3 or 4
- * qubits), then 2^T-amplitude tiles (T = 11..13) and 2^L-amplitude segments
- * (L = 3..5) around the best, keeping a change only when it is more than
+ * qubits), then 2^T-amplitude tiles from T = 11 up to the default size (a
+ * larger tile for one width would raise the LDS of every workgroup of a
+ * mixed launch) and 2^L-amplitude segments (L = 3..5) around the best,
+ * keeping a change only when it is more than
  * 3 % faster.  The choices are remembered per (dtype, direction, width) in
  * the process and in $SVMI_BATCH_TUNE_CACHE (default
  * /tmp/svmi-batch-tune.txt); sv_apply_batch uses them when opts.batch_tuned

@@ -983,12 +983,15 @@ sv_status tune_batch(int32_t count, const sv_batch_item* items, sv_dtype dtype, 
             consider(g);
         }
         if (w > 10) {
-            const int tmax = (dtype == SV_C128 && grad) ? 12 : 13;
+            // Tiles no larger than the default: the launch gives every
+            // workgroup the LDS of its largest tile, so a larger tile for one
+            // width (faster when that width is timed alone) would cut the
+            // occupancy of all the others in a mixed batch.
+            const int tdef = dtype == SV_C64 ? 12 : (grad ? 11 : 12);
             const BatchGeom base = best;
-            for (int T = 11; T <= std::min(tmax, w) && st == SV_OK; ++T) {
+            for (int T = 11; T < std::min(tdef, w + 1) && st == SV_OK; ++T) {
                 BatchGeom g = base;
                 g.T = T;
-                if (T == (dtype == SV_C64 ? 12 : (grad ? 11 : 12))) continue;   // the default, timed above
                 consider(g);
             }
             const BatchGeom base2 = best;
