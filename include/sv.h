@@ -418,8 +418,9 @@ sv_status sv_timing(sv_ctx ctx, double* tile_ms, int64_t* tile_launches, double*
 
 /* Tile-geometry autotuner (the block-size choice of Sec. 5.1, made by
  * measurement): applies `circuit` once per candidate geometry -- 2^T-amplitude
- * tiles for T in {12, 13} (c64) or {11, 12} (c128), 2^L-amplitude contiguous
- * segments for L in {4, 5} -- to the context's state, times the second of two
+ * tiles for T in {12, 13, 14} (c64; 14 from 14 qubits on, one 128 KiB workgroup
+ * per CU) or {11, 12} (c128), 2^L-amplitude contiguous segments for L in
+ * {4, 5} -- to the context's state, times the second of two
  * sweeps with HIP events, and keeps the fastest in the context's options
  * (tile_bits, low_bits, threads).  The state's content is destroyed:
  * initialise it afterwards.  Results are remembered per (width, dtype, batch,

@@ -1034,6 +1034,10 @@ sv_status sv_tune(sv_ctx c, const sv_circuit* circ, const double* params, sv_opt
     const int t_hi = c64 ? 13 : 12;
     for (int T = t_hi - 1; T <= t_hi; ++T)
         for (int L = 4; L <= 5; ++L) cand.push_back({T, L, (c64 && T == 13) ? 512 : 256});
+    // complex64 also 2^14-amplitude tiles: 128 KiB of LDS, one workgroup
+    // per CU, fewer passes
+    if (c64 && c->n >= 14)
+        for (int L = 4; L <= 5; ++L) cand.push_back({14, L, 512});
     {   // defined values for the timing sweeps
         sv_status is = sv_init(c, SV_INIT_UNIFORM, 0);
         if (is != SV_OK) return is;
