@@ -2,6 +2,7 @@
 #pragma once
 #include <complex>
 #include <cstdint>
+#include <functional>
 #include <map>
 #include <string>
 #include <vector>
@@ -203,6 +204,10 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
 void plan_plain(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, EncodedPlan& out);
 
 // Fill the pool (state dtype, batch-major when it varies) from the recipes.
+// fn(i) for i in [0, n) on a persistent pool of host threads (the caller
+// takes part); runs inline when the pool is busy with another loop.
+void host_parallel_for(int n, const std::function<void(int)>& fn);
+
 void fill_pool(const EncodedPlan& p, const std::vector<IRGate>& ir, int batch,
                std::vector<unsigned char>& pool_bytes);
 

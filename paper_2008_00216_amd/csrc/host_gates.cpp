@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstring>
 #include <sstream>
+#include <stdexcept>
 
 #include "host.h"
 
@@ -470,9 +471,27 @@ std::vector<IRGate> build_ir(const sv_circuit* c, const double* params, const Bu
         }
     }
 
+    // The gates' matrices for many parameter sets are computed in parallel
+    // (make_ir is independent per gate); errors are reported in gate order.
+    std::vector<IRGate> made;
+    if (o.batch >= 8 && c->n_gates >= 16) {
+        made.resize((size_t)c->n_gates);
+        std::vector<std::string> errs((size_t)c->n_gates);
+        host_parallel_for(c->n_gates, [&](int i) {
+            if (consumed[i]) return;
+            try {
+                made[i] = make_ir(c, i, params, o, o.backward);
+            } catch (const std::exception& e) {
+                errs[i] = e.what();
+            }
+        });
+        for (int i = 0; i < c->n_gates; ++i)
+            if (!errs[i].empty()) throw std::runtime_error(errs[i]);
+    }
+    auto gate_ir = [&](int i) { return made.empty() ? make_ir(c, i, params, o, o.backward) : std::move(made[i]); };
     if (!o.backward) {
         for (int i = 0; i < c->n_gates; ++i)
-            if (!consumed[i]) in.push_back(make_ir(c, i, params, o, false));
+            if (!consumed[i]) in.push_back(gate_ir(i));
     } else {
         // Each parametric gate exp(-i theta G / 2) commutes with its
         // generator G, so Im <lambda|G|psi> has the same value before and
@@ -494,7 +513,7 @@ std::vector<IRGate> build_ir(const sv_circuit* c, const double* params, const Bu
                 gr.src = i;
                 if (!o.structured) in.push_back(gr);
             }
-            in.push_back(make_ir(c, i, params, o, true));
+            in.push_back(gate_ir(i));
             if (g.param >= 0 && o.structured) in.push_back(gr);
         }
     }

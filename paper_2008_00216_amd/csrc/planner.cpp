@@ -1093,7 +1093,7 @@ void fill_pool_t(const EncodedPlan& p, const std::vector<IRGate>& ir, int batch,
     R* base = reinterpret_cast<R*>(bytes.data());
     const double c = std::sqrt(0.5);
     const cd tab[8] = {cd(1, 0), cd(c, c), cd(0, 1), cd(-c, c), cd(-1, 0), cd(-c, -c), cd(0, -1), cd(c, -c)};
-    for (int b = 0; b < nb; ++b) {
+    auto fill_one = [&](int b) {
         R* pb = base + (size_t)b * p.pool_size * 2;
         for (const Recipe& rc : p.recipes) {
             R* dst = pb + rc.off * 2;
@@ -1188,6 +1188,12 @@ void fill_pool_t(const EncodedPlan& p, const std::vector<IRGate>& ir, int batch,
                 }
             }
         }
+    };
+    // the states' pools are independent: many parameter sets fill in parallel
+    if (nb >= 8 && (size_t)nb * p.recipes.size() >= 4096) {
+        host_parallel_for(nb, fill_one);
+    } else {
+        for (int b = 0; b < nb; ++b) fill_one(b);
     }
 }
 }  // namespace
