@@ -10,6 +10,8 @@
 #include <thread>
 #include <vector>
 
+#include <unistd.h>
+
 #include "host.h"
 
 namespace svmi {
@@ -18,24 +20,27 @@ namespace {
 
 class WorkerPool {
 public:
-    WorkerPool() {
+    WorkerPool() : pid_(getpid()) {
         const unsigned hw = std::thread::hardware_concurrency();
         const unsigned k = std::min(7u, hw > 1 ? hw - 1 : 0u);
-        for (unsigned i = 0; i < k; ++i) th_.emplace_back([this] { work(); });
+        for (unsigned i = 0; i < k; ++i) th_->emplace_back([this] { work(); });
     }
     ~WorkerPool() {
+        if (getpid() != pid_) return;   // forked child: the threads are not here (the list leaks)
         {
             std::lock_guard<std::mutex> l(mu_);
             stop_ = true;
         }
         cv_.notify_all();
-        for (std::thread& t : th_) t.join();
+        for (std::thread& t : *th_) t.join();
+        delete th_;
     }
     // fn(i) for every i in [0, n); returns when every call has returned and
     // every worker has left this loop
     void run(int n, const std::function<void(int)>& fn) {
+        // a forked child has the pool's state but not its threads
         std::unique_lock<std::mutex> busy(run_mu_, std::try_to_lock);
-        if (!busy.owns_lock() || th_.empty() || n < 2) {
+        if (!busy.owns_lock() || th_->empty() || n < 2 || getpid() != pid_) {
             for (int i = 0; i < n; ++i) fn(i);
             return;
         }
@@ -50,7 +55,7 @@ public:
         cv_.notify_all();
         for (int i = next_++; i < n; i = next_++) fn(i);
         std::unique_lock<std::mutex> l(mu_);
-        done_.wait(l, [&] { return finished_ == (int)th_.size(); });
+        done_.wait(l, [&] { return finished_ == (int)th_->size(); });
         fn_ = nullptr;
     }
 
@@ -67,10 +72,11 @@ private:
             l.unlock();
             for (int i = next_++; i < n; i = next_++) (*f)(i);
             l.lock();
-            if (++finished_ == (int)th_.size()) done_.notify_all();
+            if (++finished_ == (int)th_->size()) done_.notify_all();
         }
     }
-    std::vector<std::thread> th_;
+    const pid_t pid_;
+    std::vector<std::thread>* th_ = new std::vector<std::thread>;
     std::mutex run_mu_, mu_;
     std::condition_variable cv_, done_;
     const std::function<void(int)>* fn_ = nullptr;
