@@ -567,7 +567,7 @@ std::vector<IRGate> build_ir(const sv_circuit* c, const double* params, const Bu
                     f.kind = K_DENSE; f.perm = PK_NONE; f.param = -1; f.gen = 0; f.skind = 0;
                     f.src = h.src;
                     alive[oi] = 0;
-                    out.push_back(f);
+                    out.push_back(std::move(f));
                     alive.push_back(1);
                     open[q] = (int)out.size() - 1;
                     open_diag[q] = 0;
@@ -581,10 +581,10 @@ std::vector<IRGate> build_ir(const sv_circuit* c, const double* params, const Bu
                     continue;
                 }
             }
-            out.push_back(g);
+            open_diag[q] = is_diag(g);
+            out.push_back(std::move(g));   // `in` is not read again
             alive.push_back(1);
             open[q] = (int)out.size() - 1;
-            open_diag[q] = is_diag(g);
             blocked[q] = 0;
             continue;
         }
@@ -597,7 +597,7 @@ std::vector<IRGate> build_ir(const sv_circuit* c, const double* params, const Bu
         // A diagonal one-qubit gate that cannot fuse (structured mode T) must
         // still keep later dense gates from jumping over it.
         if (g.k == 1 && g.kind != K_DENSE) open[g.q[0]] = -1;
-        out.push_back(g);
+        out.push_back(std::move(g));
         alive.push_back(1);
     }
     std::vector<IRGate> res;
