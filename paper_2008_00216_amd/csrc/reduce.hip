@@ -7,6 +7,7 @@
 #include <algorithm>
 
 #include "device_common.h"
+#include "hpsi_tile.h"
 #include "kernels.h"
 
 namespace svmi {
@@ -184,105 +185,19 @@ __global__ __launch_bounds__(kRB) void k_hpsi(const V2<R>* __restrict__ psi, V2<
 
 // lambda = H psi by tiles of 2^11 consecutive amplitudes (n >= 11), the
 // same sum as k_hpsi with the work per wave cut to a few instructions per
-// amplitude.  Thread `tid` holds amplitudes t0 + k 256 + tid (k < 8) of its
-// block's tile t0, and the tile sits in LDS, so a group whose x mask stays
-// below bit 11 reads its partners there; other groups load them from global
-// memory.  For a group with mask x the partner of amplitude k has index
-// jx = (t0 ^ x) with bits 8..10 xor k and bits 0..7 = (tid ^ x) & 255, so the
-// sign (-1)^{|z & jx|} of a term splits into a per-lane factor (bits 0..7),
-// a compile-time factor per k (bits 8..10, the table hm) and a block-uniform
-// factor (bits >= 8 of t0 ^ x).  Per group the terms add up to one complex
-// diagonal value D_k per amplitude, and lambda gains D_k times the partner.
-// Accumulation is FP64; lambda is rounded once, and the block's FP64 partial
-// of Re <psi|lambda> goes to epart[state * gridDim.x + block].
-constexpr int kHB = 11;
-constexpr int kHK = (1 << kHB) / kRB;
-
-__device__ __forceinline__ double flip_sign(double v, uint32_t bit) {
-    return __longlong_as_double(__double_as_longlong(v) ^ ((long long)(bit & 1u) << 63));
-}
-
+// amplitude (hpsi_tile11).  The block's FP64 partial of Re <psi|lambda>
+// (lambda before rounding) goes to epart[state * gridDim.x + block].
 template <class R>
 __global__ __launch_bounds__(kRB) void k_hpsi_tile(const V2<R>* __restrict__ psi, V2<R>* __restrict__ lam,
                                                    uint64_t bstride, PauliDev pd, double* __restrict__ epart) {
     __shared__ V2<R> tile[1 << kHB];
     __shared__ double sh[kRB / 64];
-    const uint32_t tid = threadIdx.x;
     const uint32_t b = blockIdx.y;
     const uint64_t t0 = (uint64_t)blockIdx.x << kHB;
-    const V2<R>* p = psi + (uint64_t)b * bstride;
-    V2<R> v[kHK];
-#pragma unroll
-    for (int k = 0; k < kHK; ++k) {
-        v[k] = p[t0 + (uint32_t)k * kRB + tid];
-        tile[k * kRB + tid] = v[k];
-    }
-    __syncthreads();
-    double lr[kHK], li[kHK];
-#pragma unroll
-    for (int k = 0; k < kHK; ++k) { lr[k] = 0.0; li[k] = 0.0; }
-    const cptr_t<uint64_t> X = cptr(pd.x);
-    const cptr_t<uint32_t> G0 = cptr(pd.g0);
-    const cptr_t<uint32_t> GM = cptr(pd.gm);
-    const cptr_t<uint64_t> HZ = cptr(pd.hz);
-    const cptr_t<double> HC = cptr(pd.hc);
-    const cptr_t<uint32_t> HM = cptr(pd.hm);
-    for (uint32_t g = 0; g < pd.ngroup; ++g) {
-        const uint64_t x = X[g];
-        V2<R> w[kHK];
-        if (x == 0) {
-#pragma unroll
-            for (int k = 0; k < kHK; ++k) w[k] = v[k];
-        } else if ((x >> kHB) == 0) {
-#pragma unroll
-            for (int k = 0; k < kHK; ++k) w[k] = tile[((uint32_t)k * kRB + tid) ^ (uint32_t)x];
-        } else {
-#pragma unroll
-            for (int k = 0; k < kHK; ++k) w[k] = p[(t0 + (uint32_t)k * kRB + tid) ^ x];
-        }
-        const uint32_t xl = (tid ^ (uint32_t)x) & 255u;
-        const uint64_t xu = (t0 ^ x) & ~255ull;
-        double dr[kHK], di[kHK];
-#pragma unroll
-        for (int k = 0; k < kHK; ++k) { dr[k] = 0.0; di[k] = 0.0; }
-        const uint32_t ta = G0[g], tm = GM[g], te = G0[g + 1];
-        for (uint32_t t = ta; t < tm; ++t) {
-            const uint64_t z = HZ[t];
-            const double c = HC[t];
-            const uint32_t pm = HM[t];
-            const uint32_t u = (uint32_t)__popcll(z & xu);
-            const uint32_t lp = (uint32_t)__popc(xl & (uint32_t)z);
-            const double ls = __longlong_as_double((long long)(0x3FF00000u | (lp << 31)) << 32);
-#pragma unroll
-            for (int k = 0; k < kHK; ++k) dr[k] = fma(ls, flip_sign(c, (pm >> k) ^ u), dr[k]);
-        }
-        for (uint32_t t = tm; t < te; ++t) {
-            const uint64_t z = HZ[t];
-            const double c = HC[t];
-            const uint32_t pm = HM[t];
-            const uint32_t u = (uint32_t)__popcll(z & xu);
-            const uint32_t lp = (uint32_t)__popc(xl & (uint32_t)z);
-            const double ls = __longlong_as_double((long long)(0x3FF00000u | (lp << 31)) << 32);
-#pragma unroll
-            for (int k = 0; k < kHK; ++k) di[k] = fma(ls, flip_sign(c, (pm >> k) ^ u), di[k]);
-        }
-#pragma unroll
-        for (int k = 0; k < kHK; ++k) {
-            const double wr = w[k].x, wi = w[k].y;
-            lr[k] = fma(dr[k], wr, fma(-di[k], wi, lr[k]));
-            li[k] = fma(dr[k], wi, fma(di[k], wr, li[k]));
-        }
-    }
-    V2<R>* out = lam + (uint64_t)b * bstride + t0;
-    double e = 0.0;
-#pragma unroll
-    for (int k = 0; k < kHK; ++k) {
-        out[(uint32_t)k * kRB + tid] = V2<R>{R(lr[k]), R(li[k])};
-        e += (double)v[k].x * lr[k] + (double)v[k].y * li[k];
-    }
+    const double e = hpsi_tile11<R>(psi + (uint64_t)b * bstride, lam + (uint64_t)b * bstride, t0, pd, tile, false);
     if (epart) {
         const double s = block_sum(e, sh);
-        if (tid == 0) epart[(uint64_t)b * gridDim.x + blockIdx.x] = s;
+        if (threadIdx.x == 0) epart[(uint64_t)b * gridDim.x + blockIdx.x] = s;
     }
 }
 
