@@ -64,6 +64,27 @@ def test_batch_adjoint_gradients(dtype):
         np.testing.assert_allclose(g1[0], g[i], atol=tol)
 
 
+@pytest.mark.parametrize("beam", [1, 8])
+def test_batch_plan_beam_widths(beam):
+    # items wider than the 2^12-amplitude tile take several passes, whose
+    # local sets differ with the planner's beam width (68 forward passes in
+    # all greedily, 64 at width 8); every width gives the oracle's energies
+    # and gradients
+    m = lib()
+    circs = W.batch_circuits(10, n_lo=15, n_hi=18, l_lo=20, l_hi=30, seed0=910)
+    params = [W.uniform_params(1, c.n_params, 950 + i)[0] for i, c in enumerate(circs)]
+    obs = [W.z_sum(c.n) if i % 2 else W.ansatz_observable(c.n) for i, c in enumerate(circs)]
+    states = [torch.empty(1 << c.n, dtype=torch.complex64, device="cuda") for c in circs]
+    lams = [torch.empty_like(s) for s in states]
+    e, g, _ = m.apply_batch(circs, params, states, obs, lambdas=lams, grad=True, init_zero=True,
+                            opts=m.make_opts(plan_beam=beam))
+    for i, c in enumerate(circs):
+        assert abs(e[i] - oracle.energy(c, params[i], obs[i])) < 2e-4, (beam, i)
+        which = list(range(0, c.n_params, max(1, c.n_params // 3)))
+        ref = oracle.grad_param_shift(c, params[i], obs[i], which=which)
+        np.testing.assert_allclose(g[i][which], ref, atol=2e-4)
+
+
 def test_batch_planned_up_front_matches_overlapped():
     """With max_work_mib set, both directions are planned before the first
     launch; otherwise the backward plans are built while the forward launch
