@@ -646,8 +646,9 @@ def sf_leg(sv, W, torch, np, reps=3, amplitudes=4096):
             "first_call_s": t_first, "passes": st["passes"], "launches": st["launches"],
             "roofline_hbm": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(gbs / HBM_PEAK_GBS, 4),
-                             "note": "algorithmic bytes of every half-width pass, doubling copy and path "
-                                     "contraction / whole call"},
+                             "note": "algorithmic bytes of every half-width pass (a pass that reads a doubled "
+                                     "half state counts a full read), of the doubling copies not read by a "
+                                     "pass, and of the path contraction / whole call"},
             "full_schroedinger_s": t_full, "speedup_vs_full_schroedinger": t_full / t,
             "max_abs_diff_vs_full_schroedinger_c64": float(np.max(np.abs(got - full))),
             "fp64_check": dict(_err_vs_fp64(got22, want, 22),

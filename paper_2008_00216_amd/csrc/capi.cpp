@@ -179,6 +179,7 @@ struct sv_ctx_s {
     sv_opts opts{};
     bool known_zero = false;
     bool zero_pending = false;   // |0..0> requested but not yet written
+    uint64_t in_mask = 0;        // next sweep: the state is copies of its part with these bits clear
     WorkAcct acct;               // declared before every DevBuf: outlives them
     std::unordered_map<uint64_t, std::unique_ptr<CachedPlan>> cache;
     DevBuf pool, red_part, red_out, pauli, gpart, gout, pinit;
@@ -313,6 +314,7 @@ struct InitTables {
     const double* lo = nullptr;
     const double* hi = nullptr;
     uint32_t nlo = 0;
+    uint64_t in_mask = 0;   // TileArgs::in_mask of the first pass
 };
 
 // Execute a plan on psi (and lambda when `lam` is non-null).  With
@@ -363,6 +365,7 @@ sv_status run_plan(sv_ctx_s* c, CachedPlan& cp, const std::vector<IRGate>& ir, v
                     a.init_hi = init.hi;
                     a.init_nlo = init.nlo;
                 }
+                if (si == 0) a.in_mask = init.in_mask;
                 if (norm_in_pass && si + 1 == e.steps.size()) {
                     norm_ntile = 1ull << (c->n - P.T);
                     HIPCHK(c->npart.ensure((size_t)c->batch * norm_ntile * sizeof(double)));
@@ -607,7 +610,13 @@ sv_status upload_pauli(sv_ctx_s* c, const sv_pauli_sum* h, PauliDev& pd, bool hp
 
 // Write a pending |0...0> (sv_init(ZERO) is deferred so that a following
 // product-state initialisation does not stream the state twice).
+sv_status write_input_copy(sv_ctx_s* c);
+
 sv_status materialise(sv_ctx_s* c) {
+    if (c->in_mask) {
+        sv_status st = write_input_copy(c);
+        if (st != SV_OK) return st;
+    }
     if (!c->zero_pending) return SV_OK;
     HIPCHK(launch_init(c->dtype, c->state, 1ull << c->n, c->batch, c->n, 1, 0, 0.0, c->stream));
     c->zero_pending = false;
@@ -776,15 +785,54 @@ sv_status apply_paper(sv_ctx_s* c, const sv_circuit* circ, const double* params,
     return SV_OK;
 }
 
+// Write the copies that c->in_mask stands for (the part with the mask's bit
+// clear into the part with it set; one bit).
+sv_status write_input_copy(sv_ctx_s* c) {
+    const uint64_t m = c->in_mask;
+    c->in_mask = 0;
+    if (!m) return SV_OK;
+    const size_t half = (size_t)m * amp_bytes(c->dtype);
+    for (int b = 0; b < c->batch; ++b) {
+        unsigned char* st = reinterpret_cast<unsigned char*>(c->state) + (size_t)b * (c->state_bytes / c->batch);
+        HIPCHK(launch_copy(st, st + half, half, c->stream));
+    }
+    return SV_OK;
+}
+
 sv_status apply_internal(sv_ctx_s* c, const sv_circuit* circ, const double* params, sv_stats* stats,
                          double* norm_out = nullptr) {
-    if (c->opts.paper) return apply_paper(c, circ, params, stats, norm_out);
+    if (c->opts.paper) {
+        sv_status ws = write_input_copy(c);
+        if (ws != SV_OK) return ws;
+        return apply_paper(c, circ, params, stats, norm_out);
+    }
     std::vector<IRGate> ir;
     ProductInit pi;
     CachedPlan* cp = nullptr;
     double plan_ms = 0.0;
     sv_status st = get_plan(c, circ, params, false, ir, pi, cp, plan_ms);
     if (st != SV_OK) return st;
+    // a pending input copy is read by the first pass when that pass is a tile
+    // pass with the copy's bit among its local bits (then every tile reads only
+    // amplitudes it writes); otherwise it is written first
+    uint64_t in_mask = 0;
+    if (c->in_mask) {
+        const EncodedPlan& e = cp->ep;
+        bool fused = !pi.used && !e.steps.empty() && e.steps.front().type == ST_TILE;
+        if (fused) {
+            const DPass& P0 = e.passes[e.steps.front().pass];
+            uint64_t local = (1ull << P0.L) - 1ull;
+            for (uint32_t t = 0; t < P0.H; ++t) local |= 1ull << P0.hpos[t];
+            fused = (c->in_mask & ~local) == 0;
+        }
+        if (fused) {
+            in_mask = c->in_mask;
+            c->in_mask = 0;
+        } else {
+            st = write_input_copy(c);
+            if (st != SV_OK) return st;
+        }
+    }
     if (!pi.used) {
         st = materialise(c);
         if (st != SV_OK) return st;
@@ -811,6 +859,7 @@ sv_status apply_internal(sv_ctx_s* c, const sv_circuit* circ, const double* para
                                        c->stream));
         }
     }
+    init.in_mask = in_mask;
     st = run_plan(c, *cp, ir, c->state, nullptr, nullptr, 0, init, norm_out);
     if (st != SV_OK) return st;
     c->known_zero = false;
@@ -823,6 +872,20 @@ sv_status apply_internal(sv_ctx_s* c, const sv_circuit* circ, const double* para
 namespace svmi {
 
 sv_status sf_fail(sv_status st, const std::string& msg) { return fail(st, msg); }
+
+// The next sweep of c starts from copies of the state's part with its top
+// qubit `bit` clear (the part with it set is not read): the Schroedinger-Feynman
+// doubling of a half state at a path bit, left to the sweep's first pass
+// when it can read it.  Any other use of the state writes the copy first.
+sv_status set_input_copy(sv_ctx c, int bit) {
+    if (!c || bit != c->n - 1) return fail(SV_EINVAL, "set_input_copy: bad context or bit (the top qubit only)");
+    if (c->in_mask) {
+        sv_status st = write_input_copy(c);
+        if (st != SV_OK) return st;
+    }
+    c->in_mask = 1ull << bit;
+    return SV_OK;
+}
 
 // Plan (and compile, where specialised kernels apply) the forward sweep of
 // `circ` on context c without launching it, so that the plans of many
@@ -934,6 +997,7 @@ sv_status sv_init(sv_ctx c, int32_t kind, uint64_t basis_index) {
     if (kind != SV_INIT_ZERO && kind != SV_INIT_BASIS && kind != SV_INIT_UNIFORM && kind != SV_INIT_ZERO_DEFERRED)
         return fail(SV_EINVAL, "unknown init kind");
     if (kind == SV_INIT_BASIS && basis_index >= (1ull << c->n)) return fail(SV_EINVAL, "basis index out of range");
+    c->in_mask = 0;   // the state is overwritten
     const double v = kind == SV_INIT_UNIFORM ? std::ldexp(1.0, -c->n / 2) * ((c->n & 1) ? std::sqrt(0.5) : 1.0) : 0.0;
     if (kind == SV_INIT_ZERO_DEFERRED) {
         c->zero_pending = true;
@@ -1056,6 +1120,7 @@ sv_status sv_tune(sv_ctx c, const sv_circuit* circ, const double* params, sv_opt
         c->opts.timing = 0;
         c->known_zero = false;
         c->zero_pending = false;
+        c->in_mask = 0;
         st = apply_internal(c, circ, params, nullptr);   // plans and compiles
         if (st != SV_OK) break;
         if (hipEventRecord(e0, c->stream) != hipSuccess) { st = fail(SV_EDEVICE, "event record failed"); break; }
@@ -1096,7 +1161,12 @@ sv_status sv_copy_state(sv_ctx dst, sv_ctx src) {
     const char* lo_s = static_cast<const char*>(src->state);
     if (lo_d < lo_s + src->state_bytes && lo_s < lo_d + dst->state_bytes)
         return fail(SV_EINVAL, "state buffers overlap");
+    if (src->in_mask) {
+        sv_status ws = write_input_copy(src);
+        if (ws != SV_OK) return ws;
+    }
     if (src->stream != dst->stream) HIPCHK(hipStreamSynchronize(src->stream));
+    dst->in_mask = 0;
     if (src->zero_pending) {
         // |0..0> not yet written: the copy is deferred the same way
         dst->zero_pending = true;

@@ -45,6 +45,7 @@
 namespace svmi {
 sv_status sf_fail(sv_status st, const std::string& msg);
 sv_status prepare_apply(sv_ctx c, const sv_circuit* circ, const double* params);
+sv_status set_input_copy(sv_ctx c, int bit);
 }
 
 namespace {
@@ -485,13 +486,21 @@ sv_status sv_sf_amplitudes(sv_sf f, const double* params, int64_t count, const u
     for (int s = 0; s < 2; ++s) {
         sv_status st = SV_OK;
         for (int w = 0; w <= m; ++w) {
-            if (w > 0) {
-                const size_t bytes = ((size_t)1 << (p.nS[s] + w - 1)) * ab;
-                he = svmi::launch_copy(f->work + f->off[s], f->work + f->off[s] + bytes, bytes, f->stream);
-                if (he != hipSuccess) return hip_fail("path doubling copy", he);
-                if (stats) { stats->hbm_bytes += 2.0 * (double)bytes; stats->launches += 1; }
-            }
             const SideCirc& sc = p.pre[s][(size_t)w];
+            if (w > 0) {
+                if (!sc.gates.empty()) {
+                    // the segment's sweep reads the lower half for both halves
+                    // when its first pass holds the new ancilla locally, and
+                    // writes the copy first otherwise
+                    st = svmi::set_input_copy(f->ctx[s][(size_t)w], p.nS[s] + w - 1);
+                    if (st != SV_OK) return st;
+                } else {
+                    const size_t bytes = ((size_t)1 << (p.nS[s] + w - 1)) * ab;
+                    he = svmi::launch_copy(f->work + f->off[s], f->work + f->off[s] + bytes, bytes, f->stream);
+                    if (he != hipSuccess) return hip_fail("path doubling copy", he);
+                    if (stats) { stats->hbm_bytes += 2.0 * (double)bytes; stats->launches += 1; }
+                }
+            }
             if (sc.gates.empty() && w > 0) continue;
             sv_circuit cv = sc.view(p.nS[s] + w, p.n_params);
             sv_stats ss{};

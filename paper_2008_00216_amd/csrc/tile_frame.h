@@ -33,6 +33,16 @@ struct TileArgs {
     // One-state passes: when set, the pass also writes the FP64 sum of
     // |psi_j|^2 over each tile it stores, at norm_part[state * tiles + tile].
     double* norm_part;
+    // One-state passes: index bits that read as 0 on input (the state is
+    // taken as copies of its part with those bits clear, written by the pass
+    // in full).  The bits must be tile-local, so that a tile reads only what
+    // it writes.  0 = none.
+    uint64_t in_mask;
+};
+
+template <bool B>
+struct BoolTag {
+    static constexpr bool value = B;
 };
 
 __device__ __forceinline__ uint32_t ins0(uint32_t x, uint32_t p) {
@@ -142,9 +152,12 @@ struct TileFrame {
         const uint32_t nchunk = NA / APC;
         ot = map_local(APC * tid, L, H, hpos);
         const bool pinit = !TWO && A.init_lo != nullptr;   // uniform over the grid
+        const uint64_t imask = TWO ? 0ull : A.in_mask;     // uniform
         // 16-byte chunks in flight per thread before the first wait: all 16 of
         // a complex128 tile's share (one state), else 8
         constexpr int KB = (sizeof(V) == 16 && !TWO) ? 16 : 8;
+        // (two copies of the loop: the input mask costs nothing when unused)
+        auto gather = [&](auto masked) {
         for (uint32_t c0 = 0; c0 < nchunk; c0 += KB * NT) {
             u32x4 va[KB];
             u32x4 vb[TWO ? KB : 1];
@@ -153,7 +166,8 @@ struct TileFrame {
                 const uint32_t c = c0 + j * NT + tid;
                 if (c < nchunk) {
                     const uint64_t gi = base + ot + map_local(APC * (c0 + j * NT), L, H, hpos);
-                    if (pinit) va[j] = product_chunk(A, gi);
+                    if constexpr (decltype(masked)::value) va[j] = gload(reinterpret_cast<const u32x4*>(psi + (gi & ~imask)));
+                    else if (pinit) va[j] = product_chunk(A, gi);
                     else va[j] = gload(reinterpret_cast<const u32x4*>(psi + gi));
                     if constexpr (TWO) vb[j] = gload(reinterpret_cast<const u32x4*>(lam + gi));
                 }
@@ -168,6 +182,9 @@ struct TileFrame {
                 }
             }
         }
+        };
+        if (imask) gather(BoolTag<true>{});
+        else gather(BoolTag<false>{});
         __syncthreads();
 
         // per-tile form parts: Lambda_c (local bits whose nonlocal partner sum
