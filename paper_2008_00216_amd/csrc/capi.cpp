@@ -251,7 +251,8 @@ bool use_plain(const sv_ctx_s* c) { return c->opts.plain != 0 || c->n < 4; }
 // Build (or fetch) the plan for a circuit; builds the IR with the current
 // parameters in `ir` and the product-init tables in `pi`.
 sv_status get_plan(sv_ctx_s* c, const sv_circuit* circ, const double* params, bool two,
-                   std::vector<IRGate>& ir, ProductInit& pi, CachedPlan*& out, double& plan_ms) {
+                   std::vector<IRGate>& ir, ProductInit& pi, CachedPlan*& out, double& plan_ms,
+                   uint64_t first_pin = 0) {
     BuildOpts bo;
     bo.batch = c->batch;
     bo.structured = c->opts.structured != 0 && !use_plain(c);
@@ -264,7 +265,10 @@ sv_status get_plan(sv_ctx_s* c, const sv_circuit* circ, const double* params, bo
     } catch (const std::exception& e) {
         return fail(SV_EINVAL, std::string("IR build failed: ") + e.what());
     }
-    const uint64_t key = circuit_hash(circ, opts_key(c, two, bo.product_init) ^ ir_signature(ir));
+    PlanCfg cfg = cfg_for(c, two);
+    cfg.first_pin = two || use_plain(c) ? 0ull : first_pin;
+    const uint64_t key = circuit_hash(circ, opts_key(c, two, bo.product_init) ^ ir_signature(ir) ^
+                                                (cfg.first_pin * 0x9e3779b97f4a7c15ull));
     auto it = c->cache.find(key);
     plan_ms = 0.0;
     if (it != c->cache.end()) {
@@ -275,8 +279,8 @@ sv_status get_plan(sv_ctx_s* c, const sv_circuit* circ, const double* params, bo
     auto cp = std::make_unique<CachedPlan>();
     cp->dev.acct = &c->acct;
     try {
-        if (use_plain(c)) plan_plain(ir, c->n, cfg_for(c, two), cp->ep);
-        else plan_fused(ir, c->n, cfg_for(c, two), cp->ep);
+        if (use_plain(c)) plan_plain(ir, c->n, cfg, cp->ep);
+        else plan_fused(ir, c->n, cfg, cp->ep);
     } catch (const std::exception& e) {
         return fail(SV_EUNSUPPORTED, std::string("planning failed: ") + e.what());
     }
@@ -810,7 +814,7 @@ sv_status apply_internal(sv_ctx_s* c, const sv_circuit* circ, const double* para
     ProductInit pi;
     CachedPlan* cp = nullptr;
     double plan_ms = 0.0;
-    sv_status st = get_plan(c, circ, params, false, ir, pi, cp, plan_ms);
+    sv_status st = get_plan(c, circ, params, false, ir, pi, cp, plan_ms, c->in_mask);
     if (st != SV_OK) return st;
     // a pending input copy is read by the first pass when that pass is a tile
     // pass with the copy's bit among its local bits (then every tile reads only
@@ -884,13 +888,17 @@ sv_status set_input_copy(sv_ctx c, int bit) {
         if (st != SV_OK) return st;
     }
     c->in_mask = 1ull << bit;
+    c->zero_pending = false;
+    c->known_zero = false;
     return SV_OK;
 }
 
 // Plan (and compile, where specialised kernels apply) the forward sweep of
 // `circ` on context c without launching it, so that the plans of many
 // contexts can be prepared from several host threads before they run.
-sv_status prepare_apply(sv_ctx c, const sv_circuit* circ, const double* params) {
+// `first_pin`: qubits the first tile pass holds locally (the qubit of a
+// doubling that the sweep will read, as set_input_copy leaves it; 0: none).
+sv_status prepare_apply(sv_ctx c, const sv_circuit* circ, const double* params, uint64_t first_pin) {
     if (!c) return fail(SV_EINVAL, "ctx is NULL");
     std::string v = validate_circuit(circ, c->n);
     if (!v.empty()) return fail(SV_EINVAL, v);
@@ -898,7 +906,7 @@ sv_status prepare_apply(sv_ctx c, const sv_circuit* circ, const double* params) 
     ProductInit pi;
     CachedPlan* cp = nullptr;
     double plan_ms = 0.0;
-    sv_status st = get_plan(c, circ, params, false, ir, pi, cp, plan_ms);
+    sv_status st = get_plan(c, circ, params, false, ir, pi, cp, plan_ms, first_pin);
     if (st != SV_OK) return st;
     return ensure_jit(c, *cp, false);
 }

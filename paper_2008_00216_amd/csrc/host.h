@@ -140,6 +140,7 @@ struct PlanCfg {
     int max_fuse_k = 4;
     bool two = false;            // adjoint sweep (psi and lambda)
     int beam = 1;                // width of the local-set beam search (1 = greedy per pass)
+    uint64_t first_pin = 0;      // qubits the first tile pass must hold locally
 };
 
 // Pool recipe: what goes into each pool slot (computed per call).

@@ -475,8 +475,31 @@ std::vector<int> remove_executed(const std::vector<int>& rem, const std::vector<
 // empties the list wins; the greedy sequence is the fallback, so the result
 // never has more steps than greedy planning.  Returns one local set per step
 // (a plain step's entry is the set that found nothing to execute).
+// S with every qubit of `pin` made local, each in place of the unpinned high
+// qubit whose loss leaves the most gate weight executable.
+uint64_t pin_set(uint64_t S, uint64_t pin, const std::vector<int>& rem, const std::vector<GInfo>& inf, int n,
+                 int L) {
+    const uint64_t all = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
+    pin &= all;
+    for (int b = 0; b < n; ++b) {
+        if (!((pin >> b) & 1) || ((S >> b) & 1)) continue;
+        uint64_t bestS = S;
+        double bw = -1.0;
+        for (int a = L; a < n; ++a) {
+            if (!((S >> a) & 1) || ((pin >> a) & 1)) continue;
+            const uint64_t S2 = (S & ~(1ull << a)) | (1ull << b);
+            const double w = scan(rem, inf, S2, all, nullptr);
+            if (w > bw) { bw = w; bestS = S2; }
+        }
+        if (bw < 0.0) break;   // every high qubit is pinned
+        S = bestS;
+    }
+    return S;
+}
+
 std::vector<uint64_t> beam_local_sets(const std::vector<IRGate>& ir, const std::vector<GInfo>& inf,
-                                      const std::vector<int>& rem0, int n, int T, int L, int width) {
+                                      const std::vector<int>& rem0, int n, int T, int L, int width,
+                                      uint64_t pin) {
     const uint64_t all = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
     const int kids = std::max(2, std::min(width, 4));
     struct Node {
@@ -500,7 +523,8 @@ std::vector<uint64_t> beam_local_sets(const std::vector<IRGate>& ir, const std::
     {
         std::vector<int> r = rem0;
         while (!r.empty()) {
-            const uint64_t S = greedy_local_set(r, inf, n, T, L);
+            uint64_t S = greedy_local_set(r, inf, n, T, L);
+            if (greedy.empty()) S = pin_set(S, pin, r, inf, n, L);
             greedy.push_back(S);
             r = remove_executed(r, executable(ir, inf, r, S, all), ir.size());
         }
@@ -511,12 +535,14 @@ std::vector<uint64_t> beam_local_sets(const std::vector<IRGate>& ir, const std::
     while (!beam.empty() && beam[0].seq.size() + 1 < greedy.size()) {
         std::vector<Node> next;
         for (const Node& nd : beam) {
-            const uint64_t S0 = greedy_local_set(nd.rem, inf, n, T, L);
+            const bool first = nd.seq.empty();
+            uint64_t S0 = greedy_local_set(nd.rem, inf, n, T, L);
+            if (first) S0 = pin_set(S0, pin, nd.rem, inf, n, L);
             std::vector<std::pair<double, uint64_t>> cand;
             cand.push_back({scan(nd.rem, inf, S0, all, nullptr) + 1e-6, S0});
             if (!executable(ir, inf, nd.rem, S0, all).empty() && T < n) {
                 for (int a = L; a < n; ++a) {
-                    if (!((S0 >> a) & 1)) continue;
+                    if (!((S0 >> a) & 1) || (first && ((pin >> a) & 1))) continue;
                     for (int b = L; b < n; ++b) {
                         if ((S0 >> b) & 1) continue;
                         const uint64_t S2 = (S0 & ~(1ull << a)) | (1ull << b);
@@ -594,12 +620,14 @@ void plan_fused(const std::vector<IRGate>& ir, int n, const PlanCfg& cfg, Encode
 
     // local sets of the tile passes, chosen ahead by a beam search over whole
     // pass sequences (an empty list: greedy per pass)
-    const std::vector<uint64_t> seq = cfg.beam > 1 ? beam_local_sets(ir, inf, rem, n, T, L, cfg.beam)
+    const std::vector<uint64_t> seq = cfg.beam > 1 ? beam_local_sets(ir, inf, rem, n, T, L, cfg.beam, cfg.first_pin)
                                                    : std::vector<uint64_t>();
     size_t it = 0;
     while (!rem.empty()) {
-        // ---- choose the local set S (|S| = T, low bits always local)
-        const uint64_t S = it < seq.size() ? seq[it] : greedy_local_set(rem, inf, n, T, L);
+        // ---- choose the local set S (|S| = T, low bits always local; the
+        // first pass also holds the pinned qubits)
+        uint64_t S = it < seq.size() ? seq[it] : greedy_local_set(rem, inf, n, T, L);
+        if (it == 0) S = pin_set(S, cfg.first_pin, rem, inf, n, L);
         ++it;
         std::vector<int> ex = executable(ir, inf, rem, S, all);
         if (ex.empty()) {

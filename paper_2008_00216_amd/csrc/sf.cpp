@@ -44,7 +44,7 @@
 
 namespace svmi {
 sv_status sf_fail(sv_status st, const std::string& msg);
-sv_status prepare_apply(sv_ctx c, const sv_circuit* circ, const double* params);
+sv_status prepare_apply(sv_ctx c, const sv_circuit* circ, const double* params, uint64_t first_pin);
 sv_status set_input_copy(sv_ctx c, int bit);
 }
 
@@ -450,13 +450,17 @@ sv_status sv_sf_amplitudes(sv_sf f, const double* params, int64_t count, const u
         // plan (and compile) every segment of both halves up front, several
         // contexts at a time, instead of one after the other as they run
         if (p.has_suffix()) fill_slots(p, 0, params);
-        struct Task { sv_ctx c; sv_circuit cv; };
+        // a segment after a doubling is planned with its path qubit local in
+        // the first pass, which then reads the doubling instead of a copy
+        struct Task { sv_ctx c; sv_circuit cv; uint64_t pin; };
         std::vector<Task> tasks;
         for (int s = 0; s < 2; ++s) {
             for (int w = 0; w <= m; ++w)
                 if (!p.pre[s][(size_t)w].gates.empty() || w == 0)
-                    tasks.push_back({f->ctx[s][(size_t)w], p.pre[s][(size_t)w].view(p.nS[s] + w, p.n_params)});
-            if (p.has_suffix()) tasks.push_back({f->ctx[s][(size_t)m], p.suf[s].view(p.nS[s] + m, p.n_params)});
+                    tasks.push_back({f->ctx[s][(size_t)w], p.pre[s][(size_t)w].view(p.nS[s] + w, p.n_params),
+                                     w > 0 ? 1ull << (p.nS[s] + w - 1) : 0ull});
+            if (p.has_suffix())
+                tasks.push_back({f->ctx[s][(size_t)m], p.suf[s].view(p.nS[s] + m, p.n_params), 0ull});
         }
         std::vector<sv_status> res(tasks.size(), SV_OK);
         std::vector<std::string> msg(tasks.size());
@@ -473,7 +477,7 @@ sv_status sv_sf_amplitudes(sv_sf f, const double* params, int64_t count, const u
                         if (next >= tasks.size()) return;
                         i = next++;
                     }
-                    res[i] = svmi::prepare_apply(tasks[i].c, &tasks[i].cv, params);
+                    res[i] = svmi::prepare_apply(tasks[i].c, &tasks[i].cv, params, tasks[i].pin);
                     if (res[i] != SV_OK) msg[i] = sv_last_error();
                 }
             });
