@@ -614,11 +614,11 @@ sv_status upload_pauli(sv_ctx_s* c, const sv_pauli_sum* h, PauliDev& pd, bool hp
 
 // Write a pending |0...0> (sv_init(ZERO) is deferred so that a following
 // product-state initialisation does not stream the state twice).
-sv_status write_input_copy(sv_ctx_s* c);
+sv_status write_input_copy(sv_ctx_s* c, sv_stats* stats);
 
 sv_status materialise(sv_ctx_s* c) {
     if (c->in_mask) {
-        sv_status st = write_input_copy(c);
+        sv_status st = write_input_copy(c, nullptr);
         if (st != SV_OK) return st;
     }
     if (!c->zero_pending) return SV_OK;
@@ -791,7 +791,9 @@ sv_status apply_paper(sv_ctx_s* c, const sv_circuit* circ, const double* params,
 
 // Write the copies that c->in_mask stands for (the part with the mask's bit
 // clear into the part with it set; one bit).
-sv_status write_input_copy(sv_ctx_s* c) {
+// The launches and algorithmic bytes of the copies are added to `stats`
+// when it is given.
+sv_status write_input_copy(sv_ctx_s* c, sv_stats* stats = nullptr) {
     const uint64_t m = c->in_mask;
     c->in_mask = 0;
     if (!m) return SV_OK;
@@ -800,15 +802,27 @@ sv_status write_input_copy(sv_ctx_s* c) {
         unsigned char* st = reinterpret_cast<unsigned char*>(c->state) + (size_t)b * (c->state_bytes / c->batch);
         HIPCHK(launch_copy(st, st + half, half, c->stream));
     }
+    if (stats) {
+        stats->launches += c->batch;
+        stats->hbm_bytes += 2.0 * (double)half * (double)c->batch;
+    }
     return SV_OK;
 }
 
 sv_status apply_internal(sv_ctx_s* c, const sv_circuit* circ, const double* params, sv_stats* stats,
                          double* norm_out = nullptr) {
+    sv_stats copies{};   // a pending input copy written before the sweep
+    auto add_copies = [&]() {
+        if (!stats) return;
+        stats->launches += copies.launches;
+        stats->hbm_bytes += copies.hbm_bytes;
+    };
     if (c->opts.paper) {
-        sv_status ws = write_input_copy(c);
+        sv_status ws = write_input_copy(c, &copies);
         if (ws != SV_OK) return ws;
-        return apply_paper(c, circ, params, stats, norm_out);
+        ws = apply_paper(c, circ, params, stats, norm_out);
+        if (ws == SV_OK) add_copies();
+        return ws;
     }
     std::vector<IRGate> ir;
     ProductInit pi;
@@ -833,7 +847,7 @@ sv_status apply_internal(sv_ctx_s* c, const sv_circuit* circ, const double* para
             in_mask = c->in_mask;
             c->in_mask = 0;
         } else {
-            st = write_input_copy(c);
+            st = write_input_copy(c, &copies);
             if (st != SV_OK) return st;
         }
     }
@@ -868,6 +882,7 @@ sv_status apply_internal(sv_ctx_s* c, const sv_circuit* circ, const double* para
     if (st != SV_OK) return st;
     c->known_zero = false;
     fill_stats(stats, c, *cp, circ, plan_ms, pi.folded, pi.used, init_fused);
+    add_copies();
     return SV_OK;
 }
 
