@@ -43,6 +43,23 @@ def test_grid_column_cut_all_paths_in_memory(dtype):
     check_close(got, ref, dtype, f"S-F grid 4x5, {info['n_cross']} cross gates")
 
 
+def test_doublings_are_read_by_the_next_pass():
+    # every segment after a cross gate is planned with its path qubit local
+    # in its first pass, which reads the doubled half from the half with that
+    # qubit clear: no doubling copy is launched, and the amplitudes still
+    # match the full sweep
+    m = lib()
+    c = W.grid_circuit(2, 9, 10, seed=33)
+    mask = column_mask(2, 9, 4)
+    ref = oracle.simulate(c)
+    got, st, info = all_amplitudes(m, c, mask, torch.complex64)
+    assert info["n_cross"] >= 4 and info["n_outer"] == 0
+    extra = st["launches"] - st["passes"]
+    print(f"S-F 2x9: {info['n_cross']} cross gates, {st['passes']} passes, {st['launches']} launches")
+    assert extra <= 2, f"{extra} launches besides the passes (init and contraction expected)"
+    check_close(got, ref, torch.complex64, "S-F 2x9 with fused doublings")
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_enumerated_path_bits_match(dtype):
     m = lib()
